@@ -1,0 +1,857 @@
+/*
+ * FP64 CPU oracle for the strength-SPH hot path of
+ * "SPH in pkdgrav3 for Shock Physics Simulations. II. Shear Strength"
+ * (Meier, Reinhardt, Jutzi, Potter, Stadel; arXiv 2603.19764).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path may link, load or
+ * call this file: only the test-suite, the smoke check and the CPU-baseline
+ * leg of the benchmark use it.  It shares no code, header, table or helper
+ * with the GPU library.
+ *
+ * Design rules of this file
+ *   - plain C99, every value in IEEE double, built with -ffp-contract=off so
+ *     that no expression is fused into an FMA;
+ *   - neighbours are found by brute force over all j for every target i
+ *     (O(N^2)), with the strict criterion r^2 < H^2 on the FP64 squared
+ *     separation ((dx*dx + dy*dy) + dz*dz), dx = x_i - x_j;
+ *   - every sum runs over ascending j, so the result does not depend on the
+ *     number of OpenMP threads;
+ *   - each function names the passage of the paper it writes out.  Where the
+ *     paper is silent the reading used is stated at the function.
+ *
+ * Readings of the paper used here (paper passage in brackets):
+ *   K1  kernel support H = 2h for the Wendland C2 kernel [sec. 3, kernel and
+ *       neighbour number; Density_estimate eq.].
+ *   K2  the self term j = i is part of the density sum and of the sum in the
+ *       grad-h term Omega [Density_estimate eq.; Omega eq. of sec. 2.1].
+ *   K3  the artificial-viscosity constants alpha, beta, epsilon are inputs
+ *       (Paper I holds their values; this paper does not print them).
+ *   K4  the hydrodynamic du/dt is the compatible form
+ *       du_i/dt|_H = P_i/(Omega_i rho_i^2) sum_j m_j v_ij . grad_i W_ij(h_i);
+ *       the paper uses the entropy-conserving scheme of Paper I instead,
+ *       whose formula is not in this paper [sec. 2.1 last paragraph].
+ *   K5  the rotation term of the stress rate is rot_sign * (R S - S R).
+ *       rot_sign = +1 is the objective (co-rotational) Jaumann rate the
+ *       paper says it adopts; rot_sign = -1 reproduces the index order as
+ *       printed in Deviatoric_Stress_derivative eq. and in the five
+ *       component equations, which equals S R - R S [sec. 2.2].
+ *   K6  a correction tensor whose inverse is singular (|det| below
+ *       1e-12 |C^-1|_F^3, or fewer than 4 neighbours) is replaced by the
+ *       identity, and counted [Correction_Tensor eq.; paper silent].
+ *   K7  the EOS is Tillotson; temperature is T = T_ref + u / c_v; the sound
+ *       speed follows c^2 = (dP/drho)_u + P/rho^2 (dP/du)_rho, floored at
+ *       c_min [sec. 2.3 uses EOSlib / M-ANEOS, which are not available].
+ *   K8  the thermal-softening factor is clamped at zero for T >= T_melt,
+ *       and strength switched off for a material means Gamma = 0, Y = 0.
+ *   K9  time integration: single global step, kick-drift-kick with the
+ *       predictor of Predict_S eq. applied to v, u and S; the closing kick
+ *       is followed by the plastic rescaling, the opening kick is not
+ *       [sec. 2.4].
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define OR_PI 3.14159265358979323846
+
+/* ----------------------------------------------------------------------- */
+/* Parameter blocks (own definitions; the GPU library has its own).        */
+/* ----------------------------------------------------------------------- */
+typedef struct {
+    /* Tillotson EOS */
+    double rho0, A, B, E0, Eiv, Ecv, a, b, alpha, beta;
+    /* temperature model and sound-speed floor */
+    double cv, T_ref, c_min;
+    /* shear modulus: > 0 constant, otherwise Poisson route with nu */
+    double shear_modulus, nu;
+    /* Collins yield and thermal softening */
+    double Y0, Ym, mu_i, mu_d, xi, T_melt;
+    int32_t strength_on, thermal_softening_on;
+} or_material;
+
+typedef struct {
+    double av_alpha, av_beta, av_eps, eta_C, rot_sign;
+    double g[3];
+    double box[3];          /* periodic box lengths; 0 = open along that axis */
+    int32_t use_correction; /* 1: G = F C, 0: G = F                            */
+    int32_t omega_one;      /* 1: Omega = 1; 0: Omega as defined               */
+} or_params;
+
+/* ----------------------------------------------------------------------- */
+/* Wendland C2 kernel in 3D, support H = 2h (reading K1).                  */
+/*   W(r,h)      = 21/(2 pi H^3) (1-q)^4 (1+4q),  q = r/H < 1               */
+/*   grad_i W    = K(r,h) x_ij,  K = -210/(pi H^5) (1-q)^3                  */
+/*   dW/dh       = -21/(pi H^4) (1-q)^3 (3 + 9q - 32 q^2)                   */
+/* ----------------------------------------------------------------------- */
+double or_W(double r, double h)
+{
+    double H = 2.0 * h;
+    double q = r / H;
+    if (q >= 1.0) return 0.0;
+    double t = 1.0 - q;
+    return 21.0 / (2.0 * OR_PI * H * H * H) * (t * t * t * t) * (1.0 + 4.0 * q);
+}
+
+double or_K(double r, double h)
+{
+    double H = 2.0 * h;
+    double q = r / H;
+    if (q >= 1.0) return 0.0;
+    double t = 1.0 - q;
+    return -210.0 / (OR_PI * H * H * H * H * H) * (t * t * t);
+}
+
+double or_dWdh(double r, double h)
+{
+    double H = 2.0 * h;
+    double q = r / H;
+    if (q >= 1.0) return 0.0;
+    double t = 1.0 - q;
+    return -21.0 / (OR_PI * H * H * H * H) * (t * t * t) * (3.0 + 9.0 * q - 32.0 * q * q);
+}
+
+/* Squared separation of i and j with dx = x_i - x_j (minimum image along
+ * periodic axes), summed as ((dx*dx + dy*dy) + dz*dz). */
+static double sep2(const double *x, const double *y, const double *z,
+                   int64_t i, int64_t j, const double *box, double d[3])
+{
+    double dx = x[i] - x[j];
+    double dy = y[i] - y[j];
+    double dz = z[i] - z[j];
+    if (box[0] > 0.0) dx -= box[0] * nearbyint(dx / box[0]);
+    if (box[1] > 0.0) dy -= box[1] * nearbyint(dy / box[1]);
+    if (box[2] > 0.0) dz -= box[2] * nearbyint(dz / box[2]);
+    d[0] = dx; d[1] = dy; d[2] = dz;
+    return dx * dx + dy * dy + dz * dz;
+}
+
+static double supp2(double h) { double H = 2.0 * h; return H * H; }
+
+/* ----------------------------------------------------------------------- */
+/* Neighbour sets by brute force.                                          */
+/*   density set  D_i = { j != i : r^2 < H_i^2 }  (plus the self term)      */
+/*   pair set     N_i = { j != i : r^2 < max(H_i^2, H_j^2) }                */
+/* The pair set is the set over which both kernels W(h_i), W(h_j) of the   */
+/* symmetrised sums (acceleration eq., Velocity_Gradient eq.) may be       */
+/* non-zero.                                                                */
+/* ----------------------------------------------------------------------- */
+
+/* Count |N_i| for every target. */
+void or_pair_counts(int64_t n, const double *x, const double *y, const double *z,
+                    const double *h, const or_params *p,
+                    int64_t nt, const int64_t *tar, int64_t *cnt)
+{
+    #pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t k = 0; k < nt; ++k) {
+        int64_t i = tar[k];
+        double Hi2 = supp2(h[i]);
+        int64_t c = 0;
+        double d[3];
+        for (int64_t j = 0; j < n; ++j) {
+            if (j == i) continue;
+            double r2 = sep2(x, y, z, i, j, p->box, d);
+            double Hj2 = supp2(h[j]);
+            if (r2 < (Hi2 > Hj2 ? Hi2 : Hj2)) ++c;
+        }
+        cnt[k] = c;
+    }
+}
+
+/* Fill the pair lists (CSR rows given by off[k]..off[k+1]) in ascending j,
+ * with dflag = 1 when j is also in the density set of i. */
+void or_pair_lists(int64_t n, const double *x, const double *y, const double *z,
+                   const double *h, const or_params *p,
+                   int64_t nt, const int64_t *tar, const int64_t *off,
+                   int64_t *nbr, uint8_t *dflag)
+{
+    #pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t k = 0; k < nt; ++k) {
+        int64_t i = tar[k];
+        double Hi2 = supp2(h[i]);
+        int64_t c = off[k];
+        double d[3];
+        for (int64_t j = 0; j < n; ++j) {
+            if (j == i) continue;
+            double r2 = sep2(x, y, z, i, j, p->box, d);
+            double Hj2 = supp2(h[j]);
+            if (r2 < (Hi2 > Hj2 ? Hi2 : Hj2)) {
+                nbr[c] = j;
+                dflag[c] = (uint8_t)(r2 < Hi2);
+                ++c;
+            }
+        }
+    }
+}
+
+/* ----------------------------------------------------------------------- */
+/* Density and grad-h term (sec. 2.1, Density_estimate eq. and the Omega   */
+/* eq. that follows it):                                                   */
+/*   rho_i   = sum_j m_j W(r_ij, h_i)                                      */
+/*   Omega_i = 1 + h_i/(3 rho_i) sum_j m_j dW(r_ij, h_i)/dh_i              */
+/* The sums run over j in D_i and the self term j = i (reading K2).        */
+/* ----------------------------------------------------------------------- */
+void or_density(int64_t n, const double *x, const double *y, const double *z,
+                const double *m, const double *h, const or_params *p,
+                int64_t nt, const int64_t *tar, double *rho, double *omega)
+{
+    #pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t k = 0; k < nt; ++k) {
+        int64_t i = tar[k];
+        double Hi2 = supp2(h[i]);
+        double sum_w = 0.0, sum_dh = 0.0;
+        double d[3];
+        for (int64_t j = 0; j < n; ++j) {
+            double r;
+            if (j == i) {
+                r = 0.0;
+            } else {
+                double r2 = sep2(x, y, z, i, j, p->box, d);
+                if (!(r2 < Hi2)) continue;
+                r = sqrt(r2);
+            }
+            sum_w += m[j] * or_W(r, h[i]);
+            sum_dh += m[j] * or_dWdh(r, h[i]);
+        }
+        rho[i] = sum_w;
+        omega[i] = p->omega_one ? 1.0 : 1.0 + h[i] / (3.0 * sum_w) * sum_dh;
+    }
+}
+
+/* ----------------------------------------------------------------------- */
+/* Tillotson equation of state (reading K7).                               */
+/*   eta = rho/rho0, mu = eta - 1, w = u/(E0 eta^2) + 1, z = 1/eta - 1      */
+/*   compressed or cold (eta >= 1 or u <= Eiv):                             */
+/*      Pc = (a + b/w) rho u + A mu + B mu^2                                */
+/*   hot expanded (eta < 1 and u >= Ecv):                                   */
+/*      Pe = a rho u + (b rho u / w + A mu exp(-beta z)) exp(-alpha z^2)    */
+/*   otherwise the linear blend in u of Pe and Pc.                          */
+/* Sound speed from the partial derivatives of the active branch.           */
+/* ----------------------------------------------------------------------- */
+static void till_compressed(const or_material *M, double rho, double u,
+                            double *P, double *dPdrho, double *dPdu)
+{
+    double eta = rho / M->rho0;
+    double mu = eta - 1.0;
+    double w = u / (M->E0 * eta * eta) + 1.0;
+    *P = (M->a + M->b / w) * rho * u + M->A * mu + M->B * mu * mu;
+    /* dw/drho = -2 (w-1)/rho,  dw/du = (w-1)/u = 1/(E0 eta^2) */
+    *dPdrho = M->a * u + M->b * u / w + 2.0 * M->b * u * (w - 1.0) / (w * w)
+            + (M->A + 2.0 * M->B * mu) / M->rho0;
+    *dPdu = M->a * rho + M->b * rho / w
+          - M->b * rho * u / (w * w) / (M->E0 * eta * eta);
+}
+
+static void till_expanded(const or_material *M, double rho, double u,
+                          double *P, double *dPdrho, double *dPdu)
+{
+    double eta = rho / M->rho0;
+    double mu = eta - 1.0;
+    double w = u / (M->E0 * eta * eta) + 1.0;
+    double z = 1.0 / eta - 1.0;
+    double eb = exp(-M->beta * z);
+    double ea = exp(-M->alpha * z * z);
+    double brace = M->b * rho * u / w + M->A * mu * eb;
+    *P = M->a * rho * u + brace * ea;
+    /* dz/drho = -rho0/rho^2 */
+    double dz = -M->rho0 / (rho * rho);
+    double dbrace = M->b * u / w + 2.0 * M->b * u * (w - 1.0) / (w * w)
+                  + M->A / M->rho0 * eb + M->A * mu * eb * (-M->beta) * dz;
+    *dPdrho = M->a * u + dbrace * ea + brace * ea * (-2.0 * M->alpha * z) * dz;
+    *dPdu = M->a * rho + ea * (M->b * rho / w
+          - M->b * rho * u / (w * w) / (M->E0 * eta * eta));
+}
+
+void or_tillotson(const or_material *M, double rho, double u,
+                  double *P_out, double *c_out, double *dPdrho_out, double *dPdu_out)
+{
+    double eta = rho / M->rho0;
+    double P, dPdrho, dPdu;
+    if (eta >= 1.0 || u <= M->Eiv) {
+        till_compressed(M, rho, u, &P, &dPdrho, &dPdu);
+    } else if (u >= M->Ecv) {
+        till_expanded(M, rho, u, &P, &dPdrho, &dPdu);
+    } else {
+        double Pc, Pe, dc_r, de_r, dc_u, de_u;
+        till_compressed(M, rho, u, &Pc, &dc_r, &dc_u);
+        till_expanded(M, rho, u, &Pe, &de_r, &de_u);
+        double span = M->Ecv - M->Eiv;
+        P = ((u - M->Eiv) * Pe + (M->Ecv - u) * Pc) / span;
+        dPdrho = ((u - M->Eiv) * de_r + (M->Ecv - u) * dc_r) / span;
+        dPdu = ((u - M->Eiv) * de_u + Pe + (M->Ecv - u) * dc_u - Pc) / span;
+    }
+    double c2 = dPdrho + P / (rho * rho) * dPdu;
+    double c = c2 > 0.0 ? sqrt(c2) : 0.0;
+    if (c < M->c_min) c = M->c_min;
+    *P_out = P;
+    *c_out = c;
+    if (dPdrho_out) *dPdrho_out = dPdrho;
+    if (dPdu_out) *dPdu_out = dPdu;
+}
+
+/* ----------------------------------------------------------------------- */
+/* Yield strength (sec. 2.3):                                               */
+/*   Y_i = Y0 + mu_i P / (1 + mu_i P / (Ym - Y0))   intact, P clipped >= 0  */
+/*   Y_d = mu_d P                                    damaged                */
+/*   Y   = min(Y_i, Y_d)                                                    */
+/*   Y  <- Y tanh(xi (T_melt/T - 1))                 thermal softening      */
+/* ----------------------------------------------------------------------- */
+double or_yield(const or_material *M, double P, double T)
+{
+    if (!M->strength_on) return 0.0;
+    double Pp = P > 0.0 ? P : 0.0;
+    double Yi = M->Y0 + M->mu_i * Pp / (1.0 + M->mu_i * Pp / (M->Ym - M->Y0));
+    double Yd = M->mu_d * Pp;
+    double Y = Yi < Yd ? Yi : Yd;
+    if (M->thermal_softening_on) {
+        double s = tanh(M->xi * (M->T_melt / T - 1.0));
+        Y *= (s > 0.0 ? s : 0.0);            /* reading K8 */
+    }
+    return Y;
+}
+
+/* Shear modulus (sec. 2.2): constant, or Gamma = 3(1-2nu)/(2(1+nu)) K with
+ * K = rho c^2. */
+double or_shear_modulus(const or_material *M, double rho, double c)
+{
+    if (!M->strength_on) return 0.0;
+    if (M->shear_modulus > 0.0) return M->shear_modulus;
+    double K = rho * c * c;
+    return 3.0 * (1.0 - 2.0 * M->nu) / (2.0 * (1.0 + M->nu)) * K;
+}
+
+/* Per-particle state after the density: P, c, T, Y, Gamma. */
+void or_state(int64_t nt, const int64_t *tar, const double *rho, const double *u,
+              const int32_t *mat, const or_material *mats,
+              double *P, double *c, double *T, double *Y, double *Gam)
+{
+    #pragma omp parallel for schedule(static)
+    for (int64_t k = 0; k < nt; ++k) {
+        int64_t i = tar[k];
+        const or_material *M = &mats[mat[i]];
+        double Pi, ci;
+        or_tillotson(M, rho[i], u[i], &Pi, &ci, NULL, NULL);
+        double Ti = M->T_ref + u[i] / M->cv;
+        P[i] = Pi;
+        c[i] = ci;
+        T[i] = Ti;
+        Y[i] = or_yield(M, Pi, Ti);
+        Gam[i] = or_shear_modulus(M, rho[i], ci);
+    }
+}
+
+/* ----------------------------------------------------------------------- */
+/* Deviatoric stress: 5 stored components (xx, yy, xy, xz, yz), with       */
+/* S_zz = -S_xx - S_yy (sec. 2.2, matrix form of the stress tensor).       */
+/* ----------------------------------------------------------------------- */
+static void S_full(const double s5[5], double S[3][3])
+{
+    S[0][0] = s5[0]; S[1][1] = s5[1]; S[2][2] = -s5[0] - s5[1];
+    S[0][1] = S[1][0] = s5[2];
+    S[0][2] = S[2][0] = s5[3];
+    S[1][2] = S[2][1] = s5[4];
+}
+
+/* J2 = 1/2 S:S over the full tensor (sec. 2.3). */
+double or_J2(const double s5[5])
+{
+    double S[3][3];
+    S_full(s5, S);
+    double ss = 0.0;
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b)
+            ss += S[a][b] * S[a][b];
+    return 0.5 * ss;
+}
+
+/* Plastic rescaling S -> f S, f = min(Y / sqrt(J2), 1) (sec. 2.3,
+ * Deviatoric_stress_rescaling eq.).  Operates on one particle. */
+void or_plastic_return(double s5[5], double Y)
+{
+    double J2 = or_J2(s5);
+    if (J2 > 0.0) {
+        double f = Y / sqrt(J2);
+        if (f < 1.0)
+            for (int k = 0; k < 5; ++k) s5[k] *= f;
+    }
+}
+
+/* Array form: S is component-major (5 rows of length n). */
+void or_plastic_return_all(int64_t n, int64_t nt, const int64_t *tar, double *S,
+                           const double *Y)
+{
+    #pragma omp parallel for schedule(static)
+    for (int64_t k = 0; k < nt; ++k) {
+        int64_t i = tar[k];
+        double s5[5];
+        for (int c = 0; c < 5; ++c) s5[c] = S[c * n + i];
+        or_plastic_return(s5, Y[i]);
+        for (int c = 0; c < 5; ++c) S[c * n + i] = s5[c];
+    }
+}
+
+/* ----------------------------------------------------------------------- */
+/* Velocity gradient with correction tensor (sec. 2.2,                     */
+/* Velocity_Gradient, Correction_Tensor and Corrected_Gradients eqs.):     */
+/*   F^ab    = -1/2 sum_j m_j v_ij^a (d_b W_ij(h_i)/(Om_i rho_i)            */
+/*                                  + d_b W_ij(h_j)/(Om_j rho_j))           */
+/*   (C^-1)^ab = the same sum with x_ij^a in place of v_ij^a                */
+/*   G^ab    = F^ag C^gb                                                    */
+/* with d_b W_ij(h) = K(r,h) x_ij^b.  G, Cinv and F are 9 rows of length n  */
+/* (row-major component index 3a+b).                                        */
+/* ----------------------------------------------------------------------- */
+static int inverse3(const double A[3][3], double Ainv[3][3], double *det_out)
+{
+    double c00 = A[1][1] * A[2][2] - A[1][2] * A[2][1];
+    double c01 = A[1][2] * A[2][0] - A[1][0] * A[2][2];
+    double c02 = A[1][0] * A[2][1] - A[1][1] * A[2][0];
+    double det = A[0][0] * c00 + A[0][1] * c01 + A[0][2] * c02;
+    *det_out = det;
+    if (det == 0.0) return 0;
+    double id = 1.0 / det;
+    Ainv[0][0] = c00 * id;
+    Ainv[1][0] = c01 * id;
+    Ainv[2][0] = c02 * id;
+    Ainv[0][1] = (A[0][2] * A[2][1] - A[0][1] * A[2][2]) * id;
+    Ainv[1][1] = (A[0][0] * A[2][2] - A[0][2] * A[2][0]) * id;
+    Ainv[2][1] = (A[0][1] * A[2][0] - A[0][0] * A[2][1]) * id;
+    Ainv[0][2] = (A[0][1] * A[1][2] - A[0][2] * A[1][1]) * id;
+    Ainv[1][2] = (A[0][2] * A[1][0] - A[0][0] * A[1][2]) * id;
+    Ainv[2][2] = (A[0][0] * A[1][1] - A[0][1] * A[1][0]) * id;
+    return 1;
+}
+
+void or_gradients(int64_t n, const double *x, const double *y, const double *z,
+                  const double *vx, const double *vy, const double *vz,
+                  const double *m, const double *h, const double *rho,
+                  const double *omega, const or_params *p,
+                  int64_t nt, const int64_t *tar,
+                  double *G, double *Cinv_out, double *F_out, int64_t *n_singular)
+{
+    int64_t nsing = 0;
+    #pragma omp parallel for schedule(dynamic, 16) reduction(+:nsing)
+    for (int64_t k = 0; k < nt; ++k) {
+        int64_t i = tar[k];
+        double F[3][3] = {{0}}, Ci[3][3] = {{0}};
+        double Hi2 = supp2(h[i]);
+        double wi = 1.0 / (omega[i] * rho[i]);
+        int64_t cnt = 0;
+        double d[3];
+        for (int64_t j = 0; j < n; ++j) {
+            if (j == i) continue;
+            double r2 = sep2(x, y, z, i, j, p->box, d);
+            double Hj2 = supp2(h[j]);
+            if (!(r2 < (Hi2 > Hj2 ? Hi2 : Hj2))) continue;
+            ++cnt;
+            double r = sqrt(r2);
+            double Ki = or_K(r, h[i]);
+            double Kj = or_K(r, h[j]);
+            double wj = 1.0 / (omega[j] * rho[j]);
+            double v[3] = { vx[i] - vx[j], vy[i] - vy[j], vz[i] - vz[j] };
+            for (int a = 0; a < 3; ++a) {
+                for (int b = 0; b < 3; ++b) {
+                    double gw = Ki * d[b] * wi + Kj * d[b] * wj;
+                    F[a][b] -= 0.5 * m[j] * v[a] * gw;
+                    Ci[a][b] -= 0.5 * m[j] * d[a] * gw;
+                }
+            }
+        }
+        double C[3][3];
+        int ok = 0;
+        if (p->use_correction) {
+            double fro = 0.0;
+            for (int a = 0; a < 3; ++a)
+                for (int b = 0; b < 3; ++b) fro += Ci[a][b] * Ci[a][b];
+            fro = sqrt(fro);
+            double det;
+            ok = inverse3(Ci, C, &det);
+            if (!ok || cnt < 4 || fabs(det) < 1e-12 * fro * fro * fro) ok = 0;
+            if (!ok) ++nsing;                                 /* reading K6 */
+        }
+        if (!ok) {
+            for (int a = 0; a < 3; ++a)
+                for (int b = 0; b < 3; ++b) C[a][b] = (a == b) ? 1.0 : 0.0;
+        }
+        for (int a = 0; a < 3; ++a) {
+            for (int b = 0; b < 3; ++b) {
+                double g = 0.0;
+                for (int c = 0; c < 3; ++c) g += F[a][c] * C[c][b];
+                G[(3 * a + b) * n + i] = g;
+                if (Cinv_out) Cinv_out[(3 * a + b) * n + i] = Ci[a][b];
+                if (F_out) F_out[(3 * a + b) * n + i] = F[a][b];
+            }
+        }
+    }
+    if (n_singular) *n_singular = nsing;
+}
+
+/* ----------------------------------------------------------------------- */
+/* Stress rate, tensor form (sec. 2.2, Deviatoric_Stress_derivative eq.,   */
+/* Strain_rate_tensor and Rotation_rate_tensor from G):                     */
+/*   eps = (G + G^T)/2,  R = (G - G^T)/2                                    */
+/*   dS  = 2 Gamma (eps - tr(eps)/3 I) + rot_sign (R S - S R)   (K5)        */
+/* Also returns the rate of the strain-rate invariant 1/2 eps:eps (end of   */
+/* sec. 2.4).                                                               */
+/* ----------------------------------------------------------------------- */
+void or_stress_rate_one(const double G9[9], const double s5[5], double Gam,
+                        double rot_sign, double ds5[5], double *eps2_rate)
+{
+    double S[3][3], E[3][3], R[3][3], D[3][3];
+    S_full(s5, S);
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+            E[a][b] = 0.5 * (G9[3 * a + b] + G9[3 * b + a]);
+            R[a][b] = 0.5 * (G9[3 * a + b] - G9[3 * b + a]);
+        }
+    double tr = E[0][0] + E[1][1] + E[2][2];
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+            double rs = 0.0, sr = 0.0;
+            for (int c = 0; c < 3; ++c) {
+                rs += R[a][c] * S[c][b];
+                sr += S[a][c] * R[c][b];
+            }
+            D[a][b] = 2.0 * Gam * (E[a][b] - (a == b ? tr / 3.0 : 0.0))
+                    + rot_sign * (rs - sr);
+        }
+    ds5[0] = D[0][0]; ds5[1] = D[1][1]; ds5[2] = D[0][1]; ds5[3] = D[0][2]; ds5[4] = D[1][2];
+    if (eps2_rate) {
+        double ee = 0.0;
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) ee += E[a][b] * E[a][b];
+        *eps2_rate = 0.5 * ee;
+    }
+}
+
+/* The five component equations as printed at the end of sec. 2.2, written
+ * out term by term.  Used by tests only, to show that they equal the tensor
+ * form with rot_sign = -1. */
+void or_stress_rate_printed(const double G9[9], const double s5[5], double Gam, double ds5[5])
+{
+#define GG(a, b) G9[3 * (a) + (b)]
+    const int X = 0, Y = 1, Z = 2;
+    double Sxx = s5[0], Syy = s5[1], Sxy = s5[2], Sxz = s5[3], Syz = s5[4];
+    ds5[0] = Sxy * (GG(Y, X) - GG(X, Y)) + Sxz * (GG(Z, X) - GG(X, Z))
+           - 2.0 / 3.0 * Gam * (GG(Y, Y) + GG(Z, Z) - 2.0 * GG(X, X));
+    ds5[1] = Sxy * (GG(X, Y) - GG(Y, X)) + Syz * (GG(Z, Y) - GG(Y, Z))
+           - 2.0 / 3.0 * Gam * (GG(X, X) + GG(Z, Z) - 2.0 * GG(Y, Y));
+    ds5[2] = Gam * (GG(X, Y) + GG(Y, X))
+           + 0.5 * (Sxx * (GG(X, Y) - GG(Y, X)) + Syy * (GG(Y, X) - GG(X, Y))
+                    + Syz * (GG(Z, X) - GG(X, Z)) + Sxz * (GG(Z, Y) - GG(Y, Z)));
+    ds5[3] = Gam * (GG(X, Z) + GG(Z, X))
+           + 0.5 * ((Sxx + Syy) * (GG(X, Z) - GG(Z, X)) + Sxx * (GG(X, Z) - GG(Z, X))
+                    + Syz * (GG(Y, X) - GG(X, Y)) + Sxy * (GG(Y, Z) - GG(Z, Y)));
+    ds5[4] = Gam * (GG(Y, Z) + GG(Z, Y))
+           + 0.5 * ((Sxx + Syy) * (GG(Y, Z) - GG(Z, Y)) + Sxz * (GG(X, Y) - GG(Y, X))
+                    + Sxy * (GG(X, Z) - GG(Z, X)) + Syy * (GG(Y, Z) - GG(Z, Y)));
+#undef GG
+}
+
+/* Array form of the tensor stress rate. */
+void or_stress_rate(int64_t n, int64_t nt, const int64_t *tar, const double *G,
+                    const double *S, const double *Gam, double rot_sign,
+                    double *dS, double *eps2_rate)
+{
+    #pragma omp parallel for schedule(static)
+    for (int64_t k = 0; k < nt; ++k) {
+        int64_t i = tar[k];
+        double g9[9], s5[5], d5[5], e2;
+        for (int c = 0; c < 9; ++c) g9[c] = G[c * n + i];
+        for (int c = 0; c < 5; ++c) s5[c] = S[c * n + i];
+        or_stress_rate_one(g9, s5, Gam[i], rot_sign, d5, &e2);
+        for (int c = 0; c < 5; ++c) dS[c * n + i] = d5[c];
+        if (eps2_rate) eps2_rate[i] = e2;
+    }
+}
+
+/* ----------------------------------------------------------------------- */
+/* Accelerations, internal-energy rate and CFL time step (sec. 2.1 and     */
+/* 2.2: hydrodynamic acceleration, artificial viscosity Pi_ij with mu_ij,  */
+/* AV_heating eq., the strength terms of the acceleration and energy       */
+/* equations, and courant_condition eq. of sec. 2.4):                      */
+/*  dv_i/dt = - sum_j m_j [P_i/(Om_i rho_i^2) dW(h_i) + P_j/(..)_j dW(h_j)] */
+/*            - sum_j m_j Pi_ij dWbar                                       */
+/*            + sum_j m_j [S_i/(Om_i rho_i^2) . dW(h_i) + S_j/(..)_j . dW(h_j)]*/
+/*            + g                                                            */
+/*  du_i/dt = P_i/(Om_i rho_i^2) sum_j m_j v_ij . dW(h_i)       (K4)         */
+/*            + 1/2 sum_j m_j Pi_ij v_ij . dWbar                             */
+/*            - S_i/(Om_i rho_i^2) : sum_j m_j v_ij (x) dW(h_i)              */
+/*  dt_i    = eta_C min_j h_i / ((1 + 0.6 alpha) c_i + 0.6 beta |min(0,mu_ij)|)*/
+/* AV acts only when v_ij . x_ij < 0; bars are arithmetic means of i and j. */
+/* ----------------------------------------------------------------------- */
+void or_forces(int64_t n, const double *x, const double *y, const double *z,
+               const double *vx, const double *vy, const double *vz,
+               const double *m, const double *h, const double *rho,
+               const double *omega, const double *P, const double *cs,
+               const double *S, const or_params *p,
+               int64_t nt, const int64_t *tar,
+               double *ax, double *ay, double *az, double *dudt, double *dt)
+{
+    const double al = p->av_alpha, be = p->av_beta, eps = p->av_eps;
+    #pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t k = 0; k < nt; ++k) {
+        int64_t i = tar[k];
+        double Si[3][3], s5[5];
+        for (int c = 0; c < 5; ++c) s5[c] = S[c * n + i];
+        S_full(s5, Si);
+        double Hi2 = supp2(h[i]);
+        double oi = omega[i] * rho[i] * rho[i];
+        double acc_H[3] = {0, 0, 0}, acc_S[3] = {0, 0, 0}, acc_V[3] = {0, 0, 0};
+        double du_H = 0.0, du_S = 0.0, du_V = 0.0;
+        double denom_max = (1.0 + 0.6 * al) * cs[i];
+        double d[3];
+        for (int64_t j = 0; j < n; ++j) {
+            if (j == i) continue;
+            double r2 = sep2(x, y, z, i, j, p->box, d);
+            double Hj2 = supp2(h[j]);
+            if (!(r2 < (Hi2 > Hj2 ? Hi2 : Hj2))) continue;
+            double r = sqrt(r2);
+            double Ki = or_K(r, h[i]);
+            double Kj = or_K(r, h[j]);
+            double oj = omega[j] * rho[j] * rho[j];
+            double Sj[3][3], t5[5];
+            for (int c = 0; c < 5; ++c) t5[c] = S[c * n + j];
+            S_full(t5, Sj);
+            double v[3] = { vx[i] - vx[j], vy[i] - vy[j], vz[i] - vz[j] };
+            double dWi[3] = { Ki * d[0], Ki * d[1], Ki * d[2] };
+            double dWj[3] = { Kj * d[0], Kj * d[1], Kj * d[2] };
+            /* hydrodynamic pressure term */
+            for (int a = 0; a < 3; ++a)
+                acc_H[a] -= m[j] * (P[i] / oi * dWi[a] + P[j] / oj * dWj[a]);
+            /* deviatoric stress term */
+            for (int a = 0; a < 3; ++a) {
+                double sum = 0.0;
+                for (int b = 0; b < 3; ++b)
+                    sum += Si[a][b] / oi * dWi[b] + Sj[a][b] / oj * dWj[b];
+                acc_S[a] += m[j] * sum;
+            }
+            /* energy: compatible hydro part and strength part, kernel h_i */
+            double vdw = v[0] * dWi[0] + v[1] * dWi[1] + v[2] * dWi[2];
+            du_H += P[i] / oi * m[j] * vdw;
+            {
+                double ss = 0.0;
+                for (int a = 0; a < 3; ++a)
+                    for (int b = 0; b < 3; ++b)
+                        ss += Si[a][b] / oi * m[j] * v[a] * dWi[b];
+                du_S -= ss;
+            }
+            /* artificial viscosity */
+            double vr = v[0] * d[0] + v[1] * d[1] + v[2] * d[2];
+            double hb = 0.5 * (h[i] + h[j]);
+            double mu = hb * vr / (r2 + eps * hb * hb);
+            if (vr < 0.0) {
+                double cb = 0.5 * (cs[i] + cs[j]);
+                double rb = 0.5 * (rho[i] + rho[j]);
+                double Pi = (-al * cb * mu + be * mu * mu) / rb;
+                double dWb[3];
+                for (int a = 0; a < 3; ++a) dWb[a] = 0.5 * (dWi[a] + dWj[a]);
+                for (int a = 0; a < 3; ++a) acc_V[a] -= m[j] * Pi * dWb[a];
+                du_V += 0.5 * m[j] * Pi * (v[0] * dWb[0] + v[1] * dWb[1] + v[2] * dWb[2]);
+            }
+            double mneg = mu < 0.0 ? -mu : 0.0;
+            double den = (1.0 + 0.6 * al) * cs[i] + 0.6 * be * mneg;
+            if (den > denom_max) denom_max = den;
+        }
+        ax[i] = acc_H[0] + acc_S[0] + acc_V[0] + p->g[0];
+        ay[i] = acc_H[1] + acc_S[1] + acc_V[1] + p->g[1];
+        az[i] = acc_H[2] + acc_S[2] + acc_V[2] + p->g[2];
+        dudt[i] = du_H + du_S + du_V;
+        dt[i] = p->eta_C * h[i] / denom_max;
+    }
+}
+
+/* ----------------------------------------------------------------------- */
+/* Full state integrator (used by multi-step tests).                        */
+/* ----------------------------------------------------------------------- */
+typedef struct {
+    int64_t n;
+    double *x, *y, *z;          /* positions at the current time            */
+    double *vx, *vy, *vz;       /* velocity at the half step                */
+    double *u;                  /* internal energy at the half step         */
+    double *S;                  /* deviatoric stress at the half step, 5n   */
+    double *ax, *ay, *az;       /* derivatives of the last evaluation       */
+    double *dudt, *dS;          /* dS is 5n                                  */
+    double *eps2;               /* accumulated strain-rate invariant        */
+    const double *m, *h;
+    const int32_t *mat;
+    const uint8_t *fixed;
+    /* outputs of the last evaluation */
+    double *rho, *omega, *P, *cs, *T, *Y, *Gam, *G, *dt_i;
+    double dt;                  /* current global step                       */
+    int64_t n_singular, pairs;
+} or_state_t;
+
+/* One derivative evaluation at the current positions with the predicted
+ * velocity vp, energy up and stress Sp (Sp is rescaled in place). */
+static void eval_derivs(or_state_t *s, const or_material *mats, const or_params *p,
+                        const double *vpx, const double *vpy, const double *vpz,
+                        const double *up, double *Sp, int64_t *tar, double *e2rate)
+{
+    int64_t n = s->n;
+    or_density(n, s->x, s->y, s->z, s->m, s->h, p, n, tar, s->rho, s->omega);
+    or_state(n, tar, s->rho, up, s->mat, mats, s->P, s->cs, s->T, s->Y, s->Gam);
+    or_plastic_return_all(n, n, tar, Sp, s->Y);
+    or_gradients(n, s->x, s->y, s->z, vpx, vpy, vpz, s->m, s->h, s->rho, s->omega, p,
+                 n, tar, s->G, NULL, NULL, &s->n_singular);
+    or_stress_rate(n, n, tar, s->G, Sp, s->Gam, p->rot_sign, s->dS, e2rate);
+    or_forces(n, s->x, s->y, s->z, vpx, vpy, vpz, s->m, s->h, s->rho, s->omega,
+              s->P, s->cs, Sp, p, n, tar, s->ax, s->ay, s->az, s->dudt, s->dt_i);
+    int64_t *cnt = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
+    or_pair_counts(n, s->x, s->y, s->z, s->h, p, n, tar, cnt);
+    int64_t tot = 0;
+    for (int64_t i = 0; i < n; ++i) tot += cnt[i];
+    free(cnt);
+    s->pairs = tot;
+}
+
+static double min_dt(const or_state_t *s)
+{
+    double d = INFINITY;
+    for (int64_t i = 0; i < s->n; ++i)
+        if (!s->fixed[i] && s->dt_i[i] < d) d = s->dt_i[i];
+    return d;
+}
+
+/* Initial evaluation at t = 0 (predicted values = current values), choice
+ * of the first step from the CFL condition (or dt_fixed > 0), and the
+ * first opening kick. */
+void or_init(or_state_t *s, const or_material *mats, const or_params *p, double dt_fixed)
+{
+    int64_t n = s->n;
+    int64_t *tar = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
+    for (int64_t i = 0; i < n; ++i) tar[i] = i;
+    double *Sp = (double *)malloc(sizeof(double) * 5 * (size_t)n);
+    double *e2 = (double *)malloc(sizeof(double) * (size_t)n);
+    memcpy(Sp, s->S, sizeof(double) * 5 * (size_t)n);
+    eval_derivs(s, mats, p, s->vx, s->vy, s->vz, s->u, Sp, tar, e2);
+    s->dt = dt_fixed > 0.0 ? dt_fixed : min_dt(s);
+    double hd = 0.5 * s->dt;
+    for (int64_t i = 0; i < n; ++i) {
+        if (s->fixed[i]) continue;
+        s->vx[i] += hd * s->ax[i];
+        s->vy[i] += hd * s->ay[i];
+        s->vz[i] += hd * s->az[i];
+        s->u[i] += hd * s->dudt[i];
+        for (int c = 0; c < 5; ++c) s->S[c * n + i] = Sp[c * n + i] + hd * s->dS[c * n + i];
+    }
+    free(Sp); free(e2); free(tar);
+}
+
+/* One step of the kick-drift-kick scheme with the predictor of
+ * Predict_S eq. (reading K9).  On entry v, u, S hold the half-step values
+ * and a, dudt, dS the derivatives of the previous evaluation. */
+void or_step(or_state_t *s, const or_material *mats, const or_params *p, double dt_fixed)
+{
+    int64_t n = s->n;
+    double dt = s->dt, hd = 0.5 * dt;
+    int64_t *tar = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
+    for (int64_t i = 0; i < n; ++i) tar[i] = i;
+    double *vpx = (double *)malloc(sizeof(double) * (size_t)n);
+    double *vpy = (double *)malloc(sizeof(double) * (size_t)n);
+    double *vpz = (double *)malloc(sizeof(double) * (size_t)n);
+    double *up = (double *)malloc(sizeof(double) * (size_t)n);
+    double *Sp = (double *)malloc(sizeof(double) * 5 * (size_t)n);
+    double *e2 = (double *)malloc(sizeof(double) * (size_t)n);
+    /* drift */
+    for (int64_t i = 0; i < n; ++i) {
+        if (s->fixed[i]) continue;
+        s->x[i] += dt * s->vx[i];
+        s->y[i] += dt * s->vy[i];
+        s->z[i] += dt * s->vz[i];
+    }
+    /* predictor: half step with the previous derivatives */
+    for (int64_t i = 0; i < n; ++i) {
+        if (s->fixed[i]) {
+            vpx[i] = s->vx[i]; vpy[i] = s->vy[i]; vpz[i] = s->vz[i]; up[i] = s->u[i];
+            for (int c = 0; c < 5; ++c) Sp[c * n + i] = s->S[c * n + i];
+            continue;
+        }
+        vpx[i] = s->vx[i] + hd * s->ax[i];
+        vpy[i] = s->vy[i] + hd * s->ay[i];
+        vpz[i] = s->vz[i] + hd * s->az[i];
+        up[i] = s->u[i] + hd * s->dudt[i];
+        for (int c = 0; c < 5; ++c) Sp[c * n + i] = s->S[c * n + i] + hd * s->dS[c * n + i];
+    }
+    eval_derivs(s, mats, p, vpx, vpy, vpz, up, Sp, tar, e2);
+    /* closing kick to the full step, rescaling of S */
+    for (int64_t i = 0; i < n; ++i) {
+        if (s->fixed[i]) continue;
+        s->vx[i] += hd * s->ax[i];
+        s->vy[i] += hd * s->ay[i];
+        s->vz[i] += hd * s->az[i];
+        s->u[i] += hd * s->dudt[i];
+        double s5[5];
+        for (int c = 0; c < 5; ++c) s5[c] = s->S[c * n + i] + hd * s->dS[c * n + i];
+        or_plastic_return(s5, s->Y[i]);
+        for (int c = 0; c < 5; ++c) s->S[c * n + i] = s5[c];
+        s->eps2[i] += dt * e2[i];
+    }
+    /* next step, opening kick (no rescaling) */
+    double dtn = dt_fixed > 0.0 ? dt_fixed : min_dt(s);
+    double hn = 0.5 * dtn;
+    for (int64_t i = 0; i < n; ++i) {
+        if (s->fixed[i]) continue;
+        s->vx[i] += hn * s->ax[i];
+        s->vy[i] += hn * s->ay[i];
+        s->vz[i] += hn * s->az[i];
+        s->u[i] += hn * s->dudt[i];
+        for (int c = 0; c < 5; ++c) s->S[c * n + i] += hn * s->dS[c * n + i];
+    }
+    s->dt = dtn;
+    free(vpx); free(vpy); free(vpz); free(up); free(Sp); free(e2); free(tar);
+}
+
+/* ----------------------------------------------------------------------- */
+/* Array helpers for the tests.                                             */
+/* ----------------------------------------------------------------------- */
+void or_kernel_arr(int64_t n, const double *r, const double *h,
+                   double *W, double *K, double *dWdh)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        if (W) W[i] = or_W(r[i], h[i]);
+        if (K) K[i] = or_K(r[i], h[i]);
+        if (dWdh) dWdh[i] = or_dWdh(r[i], h[i]);
+    }
+}
+
+void or_tillotson_arr(const or_material *M, int64_t n, const double *rho, const double *u,
+                      double *P, double *c, double *dPdrho, double *dPdu)
+{
+    for (int64_t i = 0; i < n; ++i)
+        or_tillotson(M, rho[i], u[i], &P[i], &c[i], dPdrho ? &dPdrho[i] : NULL,
+                     dPdu ? &dPdu[i] : NULL);
+}
+
+void or_yield_arr(const or_material *M, int64_t n, const double *P, const double *T, double *Y)
+{
+    for (int64_t i = 0; i < n; ++i) Y[i] = or_yield(M, P[i], T[i]);
+}
+
+/* Rows of 9 (G) and 5 (S) per entry, entry-major. */
+void or_stress_rate_rows(int64_t n, const double *G, const double *S, const double *Gam,
+                         double rot_sign, int32_t printed, double *dS, double *e2)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        if (printed)
+            or_stress_rate_printed(&G[9 * i], &S[5 * i], Gam[i], &dS[5 * i]);
+        else
+            or_stress_rate_one(&G[9 * i], &S[5 * i], Gam[i], rot_sign, &dS[5 * i],
+                               e2 ? &e2[i] : NULL);
+    }
+}
+
+void or_plastic_return_rows(int64_t n, double *S, const double *Y)
+{
+    for (int64_t i = 0; i < n; ++i) or_plastic_return(&S[5 * i], Y[i]);
+}
+
+/* y_pred = y + 1/2 dt dy for non-fixed entries (Predict_S eq. applied to a
+ * component-major array of ncomp rows). */
+void or_predict(int64_t n, int32_t ncomp, const uint8_t *fixed, double dt,
+                const double *y, const double *dy, double *out)
+{
+    for (int c = 0; c < ncomp; ++c)
+        for (int64_t i = 0; i < n; ++i)
+            out[c * n + i] = (fixed && fixed[i]) ? y[c * n + i]
+                                                 : y[c * n + i] + 0.5 * dt * dy[c * n + i];
+}

@@ -1,0 +1,223 @@
+"""Seeded synthetic inputs for the strength-SPH hot path.
+
+This module only lays out particles and draws random numbers; it holds none
+of the method's arithmetic (no kernel, EOS, yield or force formula).  Both the
+GPU path and the CPU oracle take their inputs from here.
+
+A workload is a dict of numpy arrays in SI units:
+  x, y, z, vx, vy, vz, m, h, u   float64 (n,)
+  S                              float64 (5, n)   components xx, yy, xy, xz, yz
+  mat                            int32 (n,)       index into ``mats``
+  fixed                          uint8 (n,)       1 = boundary particle, never integrated
+plus ``mats`` (list of material dicts), ``params`` (dict) and ``name``.
+
+Material parameters are inputs of a workload.  Tillotson constants are the
+published basalt and granite sets; the strength constants follow the
+workload descriptions (pressure-dependent Collins yield, Drucker-Prager
+friction for the granular column).
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+# Tillotson basalt (Benz & Asphaug 1999) and granite (Melosh 1989) constants.
+_BASALT_EOS = dict(rho0=2700.0, A=26.7e9, B=26.7e9, E0=487.0e6, Eiv=4.72e6, Ecv=18.2e6,
+                   a=0.5, b=1.5, alpha=5.0, beta=5.0)
+_GRANITE_EOS = dict(rho0=2680.0, A=18.0e9, B=18.0e9, E0=16.0e6, Eiv=3.5e6, Ecv=18.0e6,
+                    a=0.5, b=1.3, alpha=5.0, beta=5.0)
+
+
+def _cmin(eos):
+    # sound-speed floor: one tenth of the linear bulk sound speed sqrt(A/rho0)
+    return 0.1 * math.sqrt(eos["A"] / eos["rho0"])
+
+
+def basalt_c1() -> dict:
+    """Basalt with constant shear modulus 22.7 GPa, Collins yield Y0 = 10 MPa,
+    Ym = 3.5 GPa, mu_i = 1.5, mu_d = 0.8, thermal softening xi = 1.2,
+    T_melt = 1373 K."""
+    e = dict(_BASALT_EOS)
+    return dict(e, cv=800.0, T_ref=300.0, c_min=_cmin(e), shear_modulus=22.7e9, nu=0.25,
+                Y0=10.0e6, Ym=3.5e9, mu_i=1.5, mu_d=0.8, xi=1.2, T_melt=1373.0,
+                strength_on=1, thermal_softening_on=1)
+
+
+def granular_c2() -> dict:
+    """Granular basalt (rho0 = 2600): zero cohesion, friction tan(30 deg), shear
+    modulus from the bulk modulus with nu = 0.25, no thermal softening."""
+    e = dict(_BASALT_EOS, rho0=2600.0)
+    return dict(e, cv=800.0, T_ref=300.0, c_min=_cmin(e), shear_modulus=0.0, nu=0.25,
+                Y0=0.0, Ym=3.5e9, mu_i=2.0, mu_d=math.tan(math.radians(30.0)), xi=1.2,
+                T_melt=1373.0, strength_on=1, thermal_softening_on=0)
+
+
+def granite_c3() -> dict:
+    """Granite with Collins yield (Y0 = 0, Ym = 3.5 GPa, mu_i = 2.0, mu_d = 0.8),
+    thermal softening xi = 1.2, T_melt = 1373 K, Poisson-route shear modulus."""
+    e = dict(_GRANITE_EOS)
+    return dict(e, cv=800.0, T_ref=300.0, c_min=_cmin(e), shear_modulus=0.0, nu=0.25,
+                Y0=0.0, Ym=3.5e9, mu_i=2.0, mu_d=0.8, xi=1.2, T_melt=1373.0,
+                strength_on=1, thermal_softening_on=1)
+
+
+def fluid(mat: dict) -> dict:
+    """The same material with strength switched off."""
+    return dict(mat, strength_on=0)
+
+
+def default_params(**kw) -> dict:
+    """Monaghan artificial viscosity alpha = 1, beta = 2, epsilon = 0.01;
+    Courant factor 0.3; objective Jaumann rotation sign; correction tensor on."""
+    p = dict(av_alpha=1.0, av_beta=2.0, av_eps=0.01, eta_C=0.3, rot_sign=1.0,
+             g=(0.0, 0.0, 0.0), box=(0.0, 0.0, 0.0), use_correction=1, omega_one=0)
+    p.update(kw)
+    return p
+
+
+def _empty(n):
+    return dict(vx=np.zeros(n), vy=np.zeros(n), vz=np.zeros(n), u=np.zeros(n),
+                S=np.zeros((5, n)), mat=np.zeros(n, dtype=np.int32),
+                fixed=np.zeros(n, dtype=np.uint8))
+
+
+def lattice(nx, ny, nz, spacing, origin=(0.0, 0.0, 0.0)):
+    """Cubic lattice of cell centres, x fastest."""
+    i = np.arange(nx, dtype=np.float64)
+    j = np.arange(ny, dtype=np.float64)
+    k = np.arange(nz, dtype=np.float64)
+    Z, Y, X = np.meshgrid(k, j, i, indexing="ij")
+    return (origin[0] + (X.ravel() + 0.5) * spacing,
+            origin[1] + (Y.ravel() + 0.5) * spacing,
+            origin[2] + (Z.ravel() + 0.5) * spacing)
+
+
+def c1_block(n_side: int = 16, variant: str = "", seed_pos: int = 1, seed_vel: int = 2,
+             seed_S: int = 3) -> dict:
+    """Single strength step workload: n_side^3 particles on a cubic lattice of
+    spacing 1 m, positions jittered uniformly by +/-0.05 m, m = 2700 kg,
+    h = 1.3 m, u = 1e4 J/kg, v = (1e-2 y, 0, 0) + N(0, (1e-3 m/s)^2) per
+    component, S = 0.  Variants: "s" draws S ~ N(0, (10 MPa)^2) per component,
+    "y" draws S ~ N(0, (200 MPa)^2) so that the plastic rescaling is active."""
+    sp = 1.0
+    x, y, z = lattice(n_side, n_side, n_side, sp)
+    n = x.size
+    rng = np.random.Generator(np.random.PCG64(seed_pos))
+    jit = rng.uniform(-0.05 * sp, 0.05 * sp, size=(3, n))
+    x, y, z = x + jit[0], y + jit[1], z + jit[2]
+    w = _empty(n)
+    rv = np.random.Generator(np.random.PCG64(seed_vel))
+    noise = rv.normal(0.0, 1e-3, size=(3, n))
+    w.update(x=x, y=y, z=z, m=np.full(n, 2700.0 * sp ** 3), h=np.full(n, 1.3 * sp),
+             u=np.full(n, 1.0e4))
+    w["vx"] = 1e-2 * y + noise[0]
+    w["vy"] = noise[1]
+    w["vz"] = noise[2]
+    if variant:
+        sig = {"s": 10.0e6, "y": 200.0e6}[variant]
+        rs = np.random.Generator(np.random.PCG64(seed_S))
+        w["S"] = rs.normal(0.0, sig, size=(5, n))
+    w.update(mats=[basalt_c1()], params=default_params(),
+             name=f"c1_{n_side}^3{('_' + variant) if variant else ''}")
+    return w
+
+
+def c2_column(scale: float = 1.0) -> dict:
+    """Granular column: a 0.2 x 0.1 x 0.05 m block (x length, y height, z
+    width) on a cubic lattice of spacing 1.70998 mm (117 x 58 x 29 =
+    196,794 mobile particles, no jitter), rho0 = 2600 kg/m^3, u = 0, v = 0,
+    S = 0, on a floor of 4 layers of fixed particles below y = 0 spanning
+    x in [-0.02, 0.42] m and the block's width; g = (0, -9.81, 0).
+
+    ``scale`` < 1 shrinks every extent (same spacing) for small test copies."""
+    sp = 1.70998e-3
+    nx = int(round(0.2 * scale / sp))
+    ny = int(round(0.1 * scale / sp))
+    nz = int(round(0.05 * scale / sp))
+    bx, by, bz = lattice(nx, ny, nz, sp)
+    i0 = int(math.floor(-0.02 * scale / sp))
+    i1 = int(math.ceil(0.42 * scale / sp))
+    fx, fy, fz = lattice(i1 - i0, 4, nz, sp, origin=(i0 * sp, -4 * sp, 0.0))
+    x = np.concatenate([bx, fx])
+    y = np.concatenate([by, fy])
+    z = np.concatenate([bz, fz])
+    n = x.size
+    w = _empty(n)
+    w["fixed"][bx.size:] = 1
+    w.update(x=x, y=y, z=z, m=np.full(n, 2600.0 * sp ** 3), h=np.full(n, 1.3 * sp))
+    w.update(mats=[granular_c2()], params=default_params(g=(0.0, -9.81, 0.0)),
+             name=f"c2_column_{bx.size}+{fx.size}fixed", n_mobile=int(bx.size))
+    return w
+
+
+def stratified_ball(n_target: int, radius: float, seed: int):
+    """Glass-like points in a ball: one uniform random point per cubic cell of
+    a lattice whose spacing gives ~n_target points inside the ball, followed
+    by three passes that push close pairs apart (a relaxed random packing)."""
+    sp = radius * (4.0 / 3.0 * math.pi / n_target) ** (1.0 / 3.0)
+    nside = int(math.ceil(2 * radius / sp)) + 2
+    rng = np.random.Generator(np.random.PCG64(seed))
+    c = (np.arange(nside) - nside / 2.0) * sp
+    Z, Y, X = np.meshgrid(c, c, c, indexing="ij")
+    P = np.stack([X.ravel(), Y.ravel(), Z.ravel()], axis=1)
+    P = P + rng.uniform(0.0, sp, size=P.shape)
+    P = P[np.einsum("ij,ij->i", P, P) < radius * radius]
+    try:
+        from scipy.spatial import cKDTree
+        for _ in range(3):
+            tree = cKDTree(P)
+            pairs = tree.query_pairs(0.8 * sp, output_type="ndarray")
+            if pairs.size == 0:
+                break
+            d = P[pairs[:, 0]] - P[pairs[:, 1]]
+            r = np.sqrt(np.einsum("ij,ij->i", d, d)) + 1e-12 * sp
+            push = (0.5 * (0.8 * sp - r) / r)[:, None] * d * 0.5
+            np.add.at(P, pairs[:, 0], push)
+            np.add.at(P, pairs[:, 1], -push)
+    except ImportError:  # pragma: no cover - scipy is part of the image
+        pass
+    return P, sp
+
+
+def c3_impact(n_target: int = 1_000_000, n_proj: int = 100_000, seed: int = 4) -> dict:
+    """Two-sphere impact: granite target of radius 50 km with ~n_target
+    particles and a projectile of equal particle mass with ~n_proj particles,
+    glass-like arrangement, h = 1.3 spacing; projectile centre at
+    (R_t + R_p)(-cos 45, sin 45, 0) from the target centre moving at
+    (3000, 0, 0) m/s; u = 0, S = 0, gravity off."""
+    Rt = 50.0e3
+    mat = granite_c3()
+    Pt, sp = stratified_ball(n_target, Rt, seed)
+    Rp = Rt * (n_proj / n_target) ** (1.0 / 3.0)
+    Pp, _ = stratified_ball(n_proj, Rp, seed + 1000)
+    d = (Rt + Rp + 0.5 * sp)
+    off = np.array([-d * math.cos(math.radians(45)), d * math.sin(math.radians(45)), 0.0])
+    Pp = Pp + off
+    P = np.concatenate([Pt, Pp])
+    n = P.shape[0]
+    w = _empty(n)
+    mass = mat["rho0"] * sp ** 3
+    w.update(x=P[:, 0].copy(), y=P[:, 1].copy(), z=P[:, 2].copy(), m=np.full(n, mass),
+             h=np.full(n, 1.3 * sp))
+    w["vx"][Pt.shape[0]:] = 3000.0
+    w.update(mats=[mat], params=default_params(), name=f"c3_impact_{Pt.shape[0]}+{Pp.shape[0]}",
+             n_target=int(Pt.shape[0]))
+    return w
+
+
+def random_cloud(n: int, seed: int, h_spread: float = 0.0, box: float = 6.0) -> dict:
+    """Small random set for parity edge cases: n uniform points in a cube of
+    side ``box`` m (mean spacing ~1 m for box^3 ~ n), h = 1.3 m times a factor
+    drawn from U(1 - h_spread, 1 + h_spread), random velocity, energy and
+    stress of C1 magnitudes."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    P = rng.uniform(0.0, box, size=(3, n))
+    w = _empty(n)
+    hs = 1.3 * (1.0 + h_spread * rng.uniform(-1.0, 1.0, size=n))
+    w.update(x=P[0].copy(), y=P[1].copy(), z=P[2].copy(), m=np.full(n, 2700.0), h=hs,
+             u=rng.uniform(5e3, 2e4, size=n))
+    w["vx"], w["vy"], w["vz"] = rng.normal(0.0, 0.05, size=(3, n))
+    w["S"] = rng.normal(0.0, 20.0e6, size=(5, n))
+    w.update(mats=[basalt_c1()], params=default_params(), name=f"cloud_{n}_{seed}")
+    return w
