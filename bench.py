@@ -1,0 +1,194 @@
+"""Benchmark of the strength-SPH step on one MI355X.
+
+Workload: the granular column (196,794 mobile particles in a 0.2 x 0.1 x 0.05 m
+block on a 4-layer floor of 29,928 fixed particles, cubic lattice spacing
+1.70998 mm, h = 1.3 spacing, Drucker-Prager friction tan 30 deg, g = 9.81),
+advanced with the FP32 cell-relative pair arithmetic; the same steps in the
+plain FP64 path are timed next to it.  One step = neighbour search (cell
+sort + pair sets), reorder of the state, predictor, density + EOS + yield,
+stress predict and rescale, corrected gradients, stress rate, forces, CFL
+minimum, kicks.  Metric: ordered neighbour pairs per second,
+sum_steps sum_i |N_i| / wall time.
+
+Prints one JSON line.  ``--gpus N`` with N > 1 is not supported (one GPU).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK_FP32_VALU = 157.3e12   # MI355X FP32 vector, published
+PEAK_FP64_VALU = 78.6e12    # MI355X FP64 vector, published
+PEAK_HBM = 8.0e12
+
+# Algorithmic flops per ordered pair of the forces pass (FMA = 2, sqrt = 1),
+# counted from the pair term of the kernel without the artificial-viscosity
+# branch: separation (9 in float incl. the cell shift, 3 in double), r^2 (5),
+# sqrt (1), kernel factors t_i^3, t_j^3 (8), (K A)_i x and (K A)_j x (30),
+# momentum sum (15), v_ij (3), energy term (8), v_ij . x_ij (5).
+FLOPS_FORCES_PAIR = {1: 84, 0: 78}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def run_steps(w, prec, steps, warmup, use_graph, timing=True):
+    import torch
+    from paper_2603_19764_amd import sph
+
+    n = int(w["x"].size)
+    ctx = sph.Context(n, max_neighbors=128, max_cells=1 << 22)
+    st = sph.State(w)
+    mats, prm = w["mats"], w["params"]
+    sph.sph_init(ctx, st, mats, prm, prec)
+    for _ in range(warmup):
+        sph.sph_step(ctx, st, mats, prm, prec)
+    torch.cuda.synchronize()
+    ctx.check(sph.lib().sph_sync_status(ctx.h, None))
+    graph = None
+    if use_graph:
+        # the state buffers flip every step: capture two steps per replay
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            sph.sph_step(ctx, st, mats, prm, prec)
+            sph.sph_step(ctx, st, mats, prm, prec)
+        torch.cuda.current_stream().wait_stream(s)
+        torch.cuda.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            sph.sph_step(ctx, st, mats, prm, prec)
+            sph.sph_step(ctx, st, mats, prm, prec)
+        graph.replay()
+        torch.cuda.synchronize()
+    if timing and not use_graph:
+        sph.sph_timing(ctx, True)
+    p0 = sph.sph_pair_count(ctx)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    if use_graph:
+        for _ in range(steps // 2):
+            graph.replay()
+    else:
+        for _ in range(steps):
+            sph.sph_step(ctx, st, mats, prm, prec)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    p1 = sph.sph_pair_count(ctx)
+    ctx.check(sph.lib().sph_sync_status(ctx.h, None))
+    k_steps = (steps // 2) * 2 if use_graph else steps
+    kern = {}
+    if timing and not use_graph:
+        for name, kid in (("build", 0), ("density", 1), ("gradients", 2), ("forces", 3)):
+            kern[name] = sph.sph_timing_read(ctx, kid)
+        sph.sph_timing(ctx, False)
+    out = dict(seconds=t1 - t0, steps=k_steps, pairs=p1 - p0, kernels=kern, n=n)
+    del graph
+    ctx.close()
+    return out
+
+
+def cpu_baseline(w, budget_s=15.0):
+    """The FP64 oracle on a bounded sample of the same workload: the full
+    derivative chain (brute-force pair sets, density + EOS for the pair-set
+    closure, gradients, stress rate, forces) for randomly chosen target
+    particles.  Rate = ordered pairs of the targets per second."""
+    from oracle import oracle
+
+    st = {k: w[k] for k in ("x", "y", "z", "m", "h", "mat", "vx", "vy", "vz", "u", "S")}
+    n = w["x"].size
+    rng = np.random.default_rng(123)
+    oracle.lib()
+    ntar = 8
+    t_used = 0.0
+    while True:
+        tar = np.sort(rng.choice(n, ntar, replace=False))
+        t0 = time.perf_counter()
+        oracle.derivs(st, w["mats"], w["params"], tar)
+        dt = time.perf_counter() - t0
+        if dt > 0.25 * budget_s or ntar >= n:
+            break
+        t_used += dt
+        ntar = int(min(n, ntar * max(2.0, min(8.0, 0.5 * budget_s / max(dt, 1e-3)))))
+    off, _, _ = oracle.pair_lists(w["x"], w["y"], w["z"], w["h"], w["params"], tar)
+    pairs = int(off[-1])
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return dict(value=pairs / dt, unit="pairs/s", cores=threads, kind="oracle",
+                sample=f"{ntar} random targets of the {n}-particle column, full FP64 derivative "
+                       f"chain with brute-force O(N^2) neighbour search, {pairs} target pairs in "
+                       f"{dt:.2f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--graph", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(--gpus must be 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2603_19764_amd import inputs
+
+    torch.cuda.set_device(0)
+    w = inputs.c2_column()
+    log(f"workload {w['name']}: n={w['x'].size}")
+    r32 = run_steps(w, 1, args.steps, args.warmup, bool(args.graph))
+    log(f"fp32: {r32['seconds']:.3f} s for {r32['steps']} steps, {r32['pairs']} pairs")
+    r64 = None
+    if not args.no_fp64:
+        r64 = run_steps(w, 0, max(args.steps // 4, 2), args.warmup, bool(args.graph))
+        log(f"fp64: {r64['seconds']:.3f} s for {r64['steps']} steps, {r64['pairs']} pairs")
+    value = r32["pairs"] / r32["seconds"]
+    ms_step = 1e3 * r32["seconds"] / r32["steps"]
+    roof = None
+    if r32["kernels"]:
+        ms, cnt = r32["kernels"]["forces"]
+        avg_s = ms / cnt * 1e-3
+        pairs_per_launch = r32["pairs"] / r32["steps"]
+        achieved = FLOPS_FORCES_PAIR[1] * pairs_per_launch / avg_s
+        roof = dict(bound="alu", achieved=achieved / 1e12, peak=PEAK_FP32_VALU / 1e12,
+                    unit="TFLOP/s", frac=achieved / PEAK_FP32_VALU, traffic=None,
+                    kernel="k_forces<8,fp32>", avg_launch_us=avg_s * 1e6,
+                    kernels_us={k: (v[0] / v[1] * 1e3 if v[1] else None)
+                                for k, v in r32["kernels"].items()})
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(w)
+    line = {
+        "metric": "SPH strength-step pair interactions/s (FP32 vs FP64 plain, 1 GPU) at 1e-5 rel err",
+        "value": value, "unit": "pairs/s", "n_gpus": 1, "steps": r32["steps"],
+        "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32 pair terms, f64 state",
+        "data": "synthetic",
+        "config": {"workload": "granular column collapse, 196794 mobile + 29928 fixed particles, "
+                               "FP32 cell-relative pair loop, Drucker-Prager tan 30, g = 9.81",
+                   "particles": r32["n"], "pairs_per_step": r32["pairs"] / r32["steps"],
+                   "graph": bool(args.graph)},
+        "fp64_plain": None if r64 is None else {
+            "value": r64["pairs"] / r64["seconds"], "ms_per_step": 1e3 * r64["seconds"] / r64["steps"],
+            "steps": r64["steps"]},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,320 @@
+/*
+ * sph.h -- C-ABI of the MI355X (gfx950) strength-SPH hot path.
+ *
+ * Method: "SPH in pkdgrav3 for Shock Physics Simulations. II. Shear
+ * Strength" (Meier et al., arXiv 2603.19764), sec. 2: kernel-sum density
+ * with grad-h term (sec. 2.1), Cauchy stress with deviatoric part and
+ * Jaumann rate (sec. 2.2), corrected velocity gradient (Velocity_Gradient,
+ * Correction_Tensor, Corrected_Gradients eqs.), Collins yield with thermal
+ * softening and plastic rescaling (sec. 2.3), momentum and energy equations
+ * with the full stress tensor and Monaghan artificial viscosity (sec. 2.1,
+ * 2.2), predictor-corrector time integration of S (sec. 2.4).
+ *
+ * Conventions that hold for every entry point
+ *   - All array arguments are DEVICE pointers owned by the caller, in
+ *     structure-of-arrays layout: one row of n values per component.
+ *     Deviatoric stress S has 5 rows (xx, yy, xy, xz, yz) with
+ *     S_zz = -S_xx - S_yy; the velocity gradient G has 9 rows, row 3a+b
+ *     holding dv^a/dx^b.  Rows of a multi-row array are n_stride = n
+ *     elements apart.
+ *   - Every call is asynchronous on `stream` (a hipStream_t; NULL is the
+ *     null stream) and allocates nothing; a call sequence can be captured
+ *     into a hipGraph.  Scalars that change from step to step (the time
+ *     step) are read from device memory for that reason.
+ *   - Argument errors are returned synchronously (SPH_EINVAL, SPH_ESTATE,
+ *     SPH_ECAPACITY).  Conditions found on the device (neighbour list
+ *     overflow, cell table overflow) raise a device flag that
+ *     sph_sync_status() reports after synchronising the stream.
+ *   - After sph_build_cells the pair passes expect every per-particle array
+ *     in the cell order the call produced: the caller permutes its arrays
+ *     with sph_reorder (perm[k] = input index of the k-th particle).
+ *   - sph_ctx owns only internal scratch (cell tables, sorted positions,
+ *     neighbour lists), sized once by sph_create.  One ctx per stream.
+ *   - No exception crosses the boundary; sph_last_error() describes the
+ *     last failure of a ctx.
+ */
+#ifndef SPH_ABI_H_
+#define SPH_ABI_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sph_ctx sph_ctx;
+typedef void *sph_stream; /* hipStream_t */
+
+typedef enum {
+    SPH_OK = 0,
+    SPH_EINVAL = 1,     /* bad argument (null pointer, size out of range)        */
+    SPH_EHIP = 2,       /* a HIP runtime call failed                              */
+    SPH_ENOMEM = 3,     /* device allocation failed in sph_create                 */
+    SPH_ECAPACITY = 4,  /* n above the ctx capacity, or a device-side overflow    */
+    SPH_ENONFINITE = 5, /* non-finite value met by a kernel                       */
+    SPH_ESTATE = 6      /* call out of order (pair pass before sph_build_cells)   */
+} sph_status;
+
+/* Arithmetic of the pair passes.  SPH_FP64: every pair term in IEEE double on
+ * absolute positions.  SPH_FP32_CELLREL: pair terms in float on positions
+ * stored relative to the origin of each particle's cell, per-particle
+ * epilogues (EOS, yield, correction-tensor inverse, stress update, kicks) in
+ * double.  Neighbour sets are the same in both (FP64 test). */
+typedef enum { SPH_FP64 = 0, SPH_FP32_CELLREL = 1 } sph_precision;
+
+/* Material parameters (sec. 2.2 shear modulus, sec. 2.3 yield; Tillotson
+ * EOS constants since EOSlib tables are not part of this library). */
+typedef struct {
+    double rho0, A, B, E0, Eiv, Ecv, a, b, alpha, beta; /* Tillotson              */
+    double cv, T_ref, c_min;      /* T = T_ref + u/cv; sound-speed floor          */
+    double shear_modulus, nu;     /* > 0: constant; otherwise 3(1-2nu)/(2(1+nu)) rho c^2 */
+    double Y0, Ym, mu_i, mu_d, xi, T_melt; /* Collins yield, thermal softening    */
+    int32_t strength_on, thermal_softening_on;
+} sph_material;
+
+/* Run parameters: Monaghan AV (sec. 2.1), Courant factor (courant_condition
+ * eq.), rotation sign of the Jaumann term (+1: R S - S R, the objective
+ * rate; -1: the index order as printed), external gravity, correction
+ * tensor switch (Corrected_Gradients eq.), Omega = 1 switch. */
+typedef struct {
+    double av_alpha, av_beta, av_eps, eta_C, rot_sign;
+    double g[3];
+    int32_t use_correction_tensor, omega_one;
+} sph_params;
+
+/* ---------------------------------------------------------------- context */
+
+/* Create a context on device `device` for up to `capacity` particles, at
+ * most `max_neighbors` pair-set members per particle, a cell table of at
+ * most `max_cells` entries (summed over runs) and `max_runs` independent
+ * particle sets.  capacity <= 2^26.  Returns SPH_ENOMEM if the scratch does
+ * not fit. */
+sph_status sph_create(sph_ctx **ctx, int64_t capacity, int32_t max_neighbors,
+                      int64_t max_cells, int32_t max_runs, int32_t device);
+sph_status sph_destroy(sph_ctx *ctx);
+const char *sph_last_error(const sph_ctx *ctx);
+
+/* Synchronise `stream` and report (then clear) device-side flags:
+ * SPH_ECAPACITY after a neighbour-list or cell-table overflow. */
+sph_status sph_sync_status(sph_ctx *ctx, sph_stream stream);
+
+/* ---------------------------------------------------- neighbour search (a1) */
+
+/* Bin particles into a uniform cell grid per run, sort them by the Morton
+ * key of their cell, and build the pair sets
+ *    N_i = { j != i : |x_i - x_j|^2 < max((2h_i)^2, (2h_j)^2) }
+ * (support H = 2h; the density set uses (2h_i)^2 alone and is flagged per
+ * entry).  The squared separation is ((dx dx + dy dy) + dz dz) in IEEE double
+ * with no fused operation, dx = x_i - x_j, so membership is exact.
+ *   x, y, z, h : n input positions and smoothing lengths (input order)
+ *   run_start  : n_runs + 1 host integers, particles of run r occupy
+ *                [run_start[r], run_start[r+1]) in input order; NULL means
+ *                one run.  Runs never interact.
+ *   cell_min   : lower bound of the cell edge; the edge used per run is
+ *                max(cell_min, 2 max h) (grown if the table would overflow)
+ *   perm_out   : n int32, perm_out[k] = input index of sorted particle k
+ * Errors: SPH_EINVAL (null pointer, n < 0), SPH_ECAPACITY (n > capacity or
+ * n_runs > max_runs); device overflow of the lists is reported later by
+ * sph_sync_status. */
+sph_status sph_build_cells(sph_ctx *ctx, int64_t n, const double *x, const double *y,
+                           const double *z, const double *h, int32_t n_runs,
+                           const int64_t *run_start, double cell_min, int32_t *perm_out,
+                           sph_stream stream);
+
+/* Permute `nfields` arrays: dst[f][k] = src[f][perm[k]] for k < n, each
+ * element `elem_bytes[f]` bytes (4 or 8) and rows[f] rows of n elements.
+ * src and dst must not overlap.  Pointer arrays are host arrays of at most
+ * 64 entries. */
+sph_status sph_reorder(sph_ctx *ctx, int64_t n, const int32_t *perm, int32_t nfields,
+                       const void *const *src, void *const *dst, const int32_t *elem_bytes,
+                       const int32_t *rows, sph_stream stream);
+
+/* Export the pair sets of the last build as CSR in sorted order:
+ * offsets (n+1, int64), nbr (sorted index of j), dflag (1 if j is in the
+ * density set of i).  nbr/dflag must hold offsets[n] entries; pass NULL for
+ * nbr and dflag to get offsets only.  Test and diagnostic use. */
+sph_status sph_neighbors_csr(sph_ctx *ctx, int64_t *offsets, int32_t *nbr, uint8_t *dflag,
+                             sph_stream stream);
+
+/* Copy (asynchronously, on `stream`) the running total of ordered pairs
+ * sum_i |N_i|, accumulated over every build since sph_create, into the
+ * device uint64 *out. */
+sph_status sph_pair_count(sph_ctx *ctx, uint64_t *out, sph_stream stream);
+
+/* ---------------------------------------------------------- density (a2) */
+
+/* rho_i = sum_j m_j W(r_ij, h_i) over the density set and the self term;
+ * Omega_i = 1 + h_i/(3 rho_i) sum_j m_j dW(r_ij, h_i)/dh_i (sec. 2.1,
+ * Density_estimate eq. and the grad-h term), Wendland C2 kernel with
+ * support 2h.  Epilogue per particle in double: Tillotson P and c with
+ * energy u, T = T_ref + u/cv, yield Y = min(Y_i, Y_d) with the thermal
+ * softening factor (sec. 2.3), shear modulus Gamma (sec. 2.2).
+ *   m, h, u, mat : sorted inputs (mat indexes mats[0..n_materials))
+ *   outputs      : rho, omega, P, cs, T, Y, Gmod, n doubles each. */
+sph_status sph_density(sph_ctx *ctx, int64_t n, const double *m, const double *h,
+                       const double *u, const int32_t *mat, const sph_material *mats,
+                       int32_t n_materials, const sph_params *prm, sph_precision prec,
+                       double *rho, double *omega, double *P, double *cs, double *T,
+                       double *Y, double *Gmod, sph_stream stream);
+
+/* --------------------------------------------------------- gradients (a4) */
+
+/* F_i = -1/2 sum_j m_j v_ij (x) (dW_ij(h_i)/(Omega_i rho_i) + dW_ij(h_j)/(Omega_j rho_j)),
+ * C_i^-1 the same sum with x_ij in place of v_ij, G_i = F_i C_i
+ * (Velocity_Gradient, Correction_Tensor, Corrected_Gradients eqs.).  The
+ * 3x3 inverse is taken in double from the adjugate; a singular C^-1
+ * (|det| < 1e-12 |C^-1|_F^3 or fewer than 4 neighbours) or
+ * use_correction_tensor = 0 gives C = identity.
+ *   vx, vy, vz : sorted (predicted) velocities;  rho, omega from sph_density
+ *   G          : 9 rows of n doubles;  n_singular: device int64 counter,
+ *                incremented by the number of singular particles (may be NULL). */
+sph_status sph_gradients(sph_ctx *ctx, int64_t n, const double *vx, const double *vy,
+                         const double *vz, const double *m, const double *h,
+                         const double *rho, const double *omega, const sph_params *prm,
+                         sph_precision prec, double *G, int64_t *n_singular,
+                         sph_stream stream);
+
+/* --------------------------------------------------- stress update (a3, a5, a7) */
+
+enum {
+    SPH_STRESS_PREDICT = 1, /* S_pred = f(S_half + dt/2 Sdot), f = min(Y/sqrt(J2), 1)    */
+    SPH_STRESS_RATE = 2,    /* Sdot = 2 Gamma (eps - tr(eps)/3) + rot_sign (R S_pred - S_pred R) */
+    SPH_STRESS_KICK = 4,    /* S_half = f(S_half + dt/2 Sdot) + dt_next/2 Sdot; eps2 += dt eps:eps/2 */
+    SPH_STRESS_OPEN = 8     /* S_half = S_pred + dt_next/2 Sdot (first opening kick of a run)      */
+};
+
+/* Per-particle stress phases of sec. 2.4 (Predict_S eq., the closing and
+ * opening kicks) and the stress rate of Deviatoric_Stress_derivative eq.
+ * with eps = (G + G^T)/2, R = (G - G^T)/2.  `phase` is one of the values
+ * above.  dt and dt_next point to device doubles.  Fixed particles are left
+ * untouched.  Arrays: S_half, S_pred, Sdot 5 rows; G 9 rows; Y, Gmod, eps2
+ * one row; fixed (int32 0/1) may be NULL. */
+sph_status sph_stress_update(sph_ctx *ctx, int32_t phase, int64_t n, const double *dt,
+                             const double *dt_next, const double *G, const double *Y,
+                             const double *Gmod, const int32_t *fixed, const sph_params *prm,
+                             double *S_half, double *S_pred, double *Sdot, double *eps2,
+                             sph_stream stream);
+
+/* ------------------------------------------------------------ forces (a6) */
+
+/* a_i = sum_j m_j (K_i A_i + K_j A_j) x_ij with A = (-P I + S)/(Omega rho^2) and
+ * grad_i W_ij(h) = K(r,h) x_ij (momentum equation of sec. 2.2), minus the
+ * Monaghan AV term with the mean kernel gradient for approaching pairs
+ * (sec. 2.1), plus g.  du_i/dt = -A_i : sum_j m_j v_ij (x) grad_i W_ij(h_i)
+ * (compatible hydro term plus the strength term of the energy equation)
+ * plus the AV heating of AV_heating eq.  dt_cfl_i = eta_C min_j
+ * h_i/((1+0.6 alpha) c_i + 0.6 beta |min(0, mu_ij)|) (courant_condition eq.).
+ *   S : predicted, rescaled deviatoric stress (5 rows);  outputs n doubles. */
+sph_status sph_forces_stress(sph_ctx *ctx, int64_t n, const double *vx, const double *vy,
+                             const double *vz, const double *m, const double *h,
+                             const double *rho, const double *omega, const double *P,
+                             const double *cs, const double *S, const sph_params *prm,
+                             sph_precision prec, double *ax, double *ay, double *az,
+                             double *dudt, double *dt_cfl, sph_stream stream);
+
+/* ------------------------------------------------------ kicks and drift (a7) */
+
+enum {
+    SPH_KD_DRIFT = 1,   /* x += dt v_half                                          */
+    SPH_KD_PREDICT = 2, /* v_pred = v_half + dt/2 a, u_pred = u_half + dt/2 dudt   */
+    SPH_KD_KICK = 4,    /* v_half += dt/2 a + dt_next/2 a, same for u              */
+    SPH_KD_OPEN = 8     /* v_half += dt_next/2 a, same for u (start of a run)      */
+};
+
+/* Kick-drift-kick updates of sec. 2.4 for positions, velocities and
+ * energies; fixed particles are left untouched.  dt, dt_next are device
+ * doubles.  v_pred/u_pred are written by SPH_KD_PREDICT only. */
+sph_status sph_kick_drift(sph_ctx *ctx, int32_t phase, int64_t n, const double *dt,
+                          const double *dt_next, const int32_t *fixed, double *x, double *y,
+                          double *z, double *vx, double *vy, double *vz, double *u,
+                          const double *ax, const double *ay, const double *az,
+                          const double *dudt, double *vpx, double *vpy, double *vpz,
+                          double *up, sph_stream stream);
+
+/* dt_out = min over non-fixed particles of dt_cfl (device double). */
+sph_status sph_dt_min(sph_ctx *ctx, int64_t n, const double *dt_cfl, const int32_t *fixed,
+                      double *dt_out, sph_stream stream);
+
+/* Conservation diagnostics (device doubles, 13 values): sum m a (3),
+ * sum m x x a (3), sum m (v . a + dudt), sum m v (3), sum m x x v (3). */
+sph_status sph_diagnostics(sph_ctx *ctx, int64_t n, const double *x, const double *y,
+                           const double *z, const double *vx, const double *vy,
+                           const double *vz, const double *m, const double *ax,
+                           const double *ay, const double *az, const double *dudt,
+                           double *out13, sph_stream stream);
+
+/* ------------------------------------------------------- whole step (a1-a8) */
+
+/* Rows of the persistent double state buffer (each row n_cap doubles).
+ * v, u and S hold half-step values, a, dudt and Sdot the derivatives of the
+ * last evaluation. */
+enum {
+    SPH_X = 0, SPH_Y, SPH_Z, SPH_VX, SPH_VY, SPH_VZ, SPH_U,
+    SPH_S = 7,                      /* 5 rows */
+    SPH_AX = 12, SPH_AY, SPH_AZ, SPH_DUDT,
+    SPH_SDOT = 16,                  /* 5 rows */
+    SPH_M = 21, SPH_H, SPH_EPS2,
+    SPH_NF64 = 24
+};
+/* Rows of the persistent int32 state buffer: material id, particle id (any
+ * caller label, carried through the sorts), fixed flag (0/1), run id. */
+enum { SPH_MAT = 0, SPH_ID, SPH_FIXED, SPH_RUN, SPH_NI32 = 4 };
+
+/* Rows of the work buffer (each n_cap doubles) written by sph_step. */
+enum {
+    SPH_W_RHO = 0, SPH_W_OMEGA, SPH_W_P, SPH_W_CS, SPH_W_T, SPH_W_Y, SPH_W_GMOD,
+    SPH_W_VP = 7,                   /* 3 rows */
+    SPH_W_UP = 10,
+    SPH_W_SP = 11,                  /* 5 rows */
+    SPH_W_G = 16,                   /* 9 rows */
+    SPH_W_DT = 25,
+    SPH_W_PERM = 26,                /* int32 view of one row */
+    SPH_NW = 27
+};
+
+typedef struct {
+    int64_t n, n_cap;            /* particles, row stride                         */
+    double *f64[2];              /* two buffers of SPH_NF64 x n_cap doubles; [cur] holds the state */
+    int32_t *i32[2];             /* two buffers of SPH_NI32 x n_cap int32          */
+    double *work;                /* SPH_NW x n_cap doubles                          */
+    double *dt;                  /* device double: step of the coming drift         */
+    double *dt_next;             /* device double scratch                           */
+    int64_t *n_singular;         /* device counter (may be NULL)                    */
+    int32_t cur;                 /* 0 or 1; flipped by every sph_step               */
+    int32_t n_runs;
+    const int64_t *run_start;    /* host, n_runs + 1 (NULL: one run)                */
+    double cell_min;
+    double dt_max;               /* > 0: upper bound of the step                    */
+} sph_state;
+
+/* Start a run: neighbour search and reorder (buffers flip), derivatives at
+ * the current state (predicted values = current values, S rescaled),
+ * *dt = min dt_cfl (capped by dt_max) and the first opening kick. */
+sph_status sph_init(sph_ctx *ctx, sph_state *st, const sph_material *mats, int32_t n_materials,
+                    const sph_params *prm, sph_precision prec, sph_stream stream);
+
+/* One step: drift, neighbour search and reorder (buffers flip), predictor,
+ * density + EOS + yield, stress predict and rescale, gradients, stress rate,
+ * forces, closing kick with rescale, next step from the CFL minimum, opening
+ * kick.  All on `stream`, no host synchronisation. */
+sph_status sph_step(sph_ctx *ctx, sph_state *st, const sph_material *mats, int32_t n_materials,
+                    const sph_params *prm, sph_precision prec, sph_stream stream);
+
+/* ------------------------------------------------------ kernel timing */
+
+/* Pass kernels whose launches can be timed with HIP events. */
+enum { SPH_T_BUILD = 0, SPH_T_DENSITY, SPH_T_GRADIENTS, SPH_T_FORCES, SPH_T_COUNT };
+
+/* enable = 1: from now on record a pair of hipEvents on the launch stream
+ * around every launch of the kernels above and reset the totals; 0: stop.
+ * Not for use while a stream is being captured into a graph. */
+sph_status sph_timing(sph_ctx *ctx, int32_t enable);
+
+/* Synchronise the recorded events and return the summed duration (ms) and
+ * the number of timed launches of kernel `which` since sph_timing(ctx, 1). */
+sph_status sph_timing_read(sph_ctx *ctx, int32_t which, double *total_ms, int64_t *launches);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SPH_ABI_H_ */

@@ -1,0 +1,617 @@
+// C-ABI entry points of the strength-SPH library: argument checks, context
+// scratch, and the whole-step sequence of sec. 2.4 built from the pass
+// launches.  Everything is asynchronous on the caller's stream.
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <vector>
+
+#include "sph_internal.h"
+
+struct sph_ctx {
+    sph::Ctx c;
+    std::vector<int64_t> run_cache;  // host copy of the run layout on the device
+};
+
+namespace sph {
+
+void set_error(Ctx *ctx, const char *fmt, ...) {
+    if (!ctx) return;
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(ctx->err, sizeof(ctx->err), fmt, ap);
+    va_end(ap);
+}
+
+sph_status launch_copy_scalar(Ctx *ctx, const double *src, double *dst, hipStream_t s);
+sph_status launch_copy_u64(Ctx *ctx, const unsigned long long *src, unsigned long long *dst,
+                           hipStream_t s);
+
+static hipEvent_t take_event(Ctx *ctx) {
+    if (!ctx->t_pool.empty()) {
+        hipEvent_t e = ctx->t_pool.back();
+        ctx->t_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Fold recorded pairs of kernel w into the totals (oldest first); keep at
+// most `keep` pending pairs.
+static void fold_events(Ctx *ctx, int w, size_t keep) {
+    auto &v = ctx->t_pending[w];
+    size_t drop = v.size() > keep ? v.size() - keep : 0;
+    for (size_t k = 0; k < drop; ++k) {
+        float ms = 0.f;
+        if (hipEventSynchronize(v[k].second) == hipSuccess &&
+            hipEventElapsedTime(&ms, v[k].first, v[k].second) == hipSuccess) {
+            ctx->t_ms[w] += ms;
+            ctx->t_count[w] += 1;
+        }
+        ctx->t_pool.push_back(v[k].first);
+        ctx->t_pool.push_back(v[k].second);
+    }
+    v.erase(v.begin(), v.begin() + drop);
+}
+
+TimedLaunch::TimedLaunch(Ctx *c, int w, hipStream_t st) : ctx(c), which(w), s(st) {
+    if (!ctx->timing) return;
+    a = take_event(ctx);
+    b = take_event(ctx);
+    if (a && b) (void)hipEventRecord(a, s);
+}
+
+TimedLaunch::~TimedLaunch() {
+    if (!ctx->timing || !a || !b) return;
+    (void)hipEventRecord(b, s);
+    ctx->t_pending[which].push_back({a, b});
+    if (ctx->t_pending[which].size() > 4096) fold_events(ctx, which, 2048);
+}
+
+}  // namespace sph
+
+using namespace sph;
+
+#define CHECK_CTX()                                     \
+    do {                                                \
+        if (!h) return SPH_EINVAL;                      \
+    } while (0)
+#define REQUIRE(cond, code, ...)                        \
+    do {                                                \
+        if (!(cond)) {                                  \
+            set_error(&h->c, __VA_ARGS__);              \
+            return code;                                \
+        }                                               \
+    } while (0)
+
+static hipStream_t S(sph_stream s) { return (hipStream_t)s; }
+
+extern "C" {
+
+sph_status sph_create(sph_ctx **out, int64_t capacity, int32_t max_neighbors, int64_t max_cells,
+                      int32_t max_runs, int32_t device) {
+    if (!out) return SPH_EINVAL;
+    *out = nullptr;
+    if (capacity < 1 || capacity > (int64_t)kIdxMask + 1 || max_neighbors < 1 ||
+        max_neighbors > 4096 || max_cells < 1 || max_cells > (int64_t)1 << 30 || max_runs < 1 ||
+        max_runs > 32767)
+        return SPH_EINVAL;
+    sph_ctx *h = new (std::nothrow) sph_ctx();
+    if (!h) return SPH_ENOMEM;
+    Ctx *ctx = &h->c;
+    ctx->device = device;
+    ctx->capacity = capacity;
+    ctx->max_nbr = max_neighbors;
+    ctx->max_cells = max_cells;
+    ctx->max_runs = max_runs;
+    if (hipSetDevice(device) != hipSuccess) {
+        delete h;
+        return SPH_EINVAL;
+    }
+    int cu = 0;
+    if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cu > 0)
+        ctx->num_cu = cu;
+    size_t cap = (size_t)capacity;
+    struct A {
+        void **p;
+        size_t bytes;
+    } allocs[] = {
+        {(void **)&ctx->key, cap * 4},
+        {(void **)&ctx->slot, cap * 4},
+        {(void **)&ctx->perm, cap * 4},
+        {(void **)&ctx->skey, cap * 4},
+        {(void **)&ctx->cell_count, ((size_t)max_cells + 1) * 4},
+        {(void **)&ctx->cell_start, ((size_t)max_cells + 1) * 4},
+        {(void **)&ctx->posh64, cap * sizeof(double4)},
+        {(void **)&ctx->posh32, cap * sizeof(float4)},
+        {(void **)&ctx->cellc, cap * 4},
+        {(void **)&ctx->runid, cap * 2},
+        {(void **)&ctx->nbr, cap * (size_t)max_neighbors * 4},
+        {(void **)&ctx->ncount, cap * 4},
+        {(void **)&ctx->grid, (size_t)max_runs * sizeof(GridDesc)},
+        {(void **)&ctx->bbox_part, (size_t)max_runs * kBBoxBlocks * sizeof(BBox)},
+        {(void **)&ctx->run_p, ((size_t)max_runs + 1) * 4},
+        {(void **)&ctx->total_keys, 4},
+        {(void **)&ctx->scan_part, (kScanBlocks + 1) * 8},
+        {(void **)&ctx->flags, FLAG_COUNT * 4},
+        {(void **)&ctx->pairs, 8},
+        {(void **)&ctx->dtbits, 8},
+        {(void **)&ctx->diag, 256 * 13 * 8},
+        {(void **)&ctx->rec, cap * 128},
+        {(void **)&ctx->gsum, cap * 15 * 8},
+    };
+    for (auto &a : allocs) {
+        if (hipMalloc(a.p, a.bytes) != hipSuccess) {
+            sph_destroy(h);
+            return SPH_ENOMEM;
+        }
+    }
+    ctx->mats = new Mat[kMaxMaterials];
+    if (hipMemset(ctx->flags, 0, FLAG_COUNT * 4) != hipSuccess ||
+        hipMemset(ctx->pairs, 0, 8) != hipSuccess ||
+        hipMemset(ctx->ncount, 0, cap * 4) != hipSuccess) {
+        sph_destroy(h);
+        return SPH_EHIP;
+    }
+    *out = h;
+    return SPH_OK;
+}
+
+sph_status sph_destroy(sph_ctx *h) {
+    if (!h) return SPH_EINVAL;
+    Ctx *ctx = &h->c;
+    void *ptrs[] = {ctx->key,  ctx->slot,      ctx->perm,   ctx->skey,    ctx->cell_count,
+                    ctx->cell_start, ctx->posh64, ctx->posh32, ctx->cellc, ctx->runid,
+                    ctx->nbr,  ctx->ncount,    ctx->grid,   ctx->bbox_part, ctx->run_p,
+                    ctx->total_keys, ctx->scan_part, ctx->flags, ctx->pairs, ctx->dtbits,
+                    ctx->diag, ctx->rec,       ctx->gsum};
+    for (void *p : ptrs)
+        if (p) (void)hipFree(p);
+    for (int w = 0; w < SPH_T_COUNT; ++w) {
+        for (auto &pr : ctx->t_pending[w]) {
+            (void)hipEventDestroy(pr.first);
+            (void)hipEventDestroy(pr.second);
+        }
+    }
+    for (hipEvent_t e : ctx->t_pool) (void)hipEventDestroy(e);
+    delete[] ctx->mats;
+    delete h;
+    return SPH_OK;
+}
+
+const char *sph_last_error(const sph_ctx *h) { return h ? h->c.err : "null context"; }
+
+sph_status sph_sync_status(sph_ctx *h, sph_stream stream) {
+    CHECK_CTX();
+    Ctx *ctx = &h->c;
+    SPH_HIP(hipStreamSynchronize(S(stream)));
+    int32_t fl[FLAG_COUNT];
+    SPH_HIP(hipMemcpy(fl, ctx->flags, sizeof(fl), hipMemcpyDeviceToHost));
+    SPH_HIP(hipMemset(ctx->flags, 0, sizeof(fl)));
+    if (fl[FLAG_NBR_OVERFLOW]) {
+        set_error(ctx, "pair list overflow: a particle has more than %d neighbours", ctx->max_nbr);
+        return SPH_ECAPACITY;
+    }
+    if (fl[FLAG_CELL_OVERFLOW]) {
+        set_error(ctx, "cell table overflow: more than %lld cells", (long long)ctx->max_cells);
+        return SPH_ECAPACITY;
+    }
+    if (fl[FLAG_NONFINITE]) {
+        set_error(ctx, "non-finite value");
+        return SPH_ENONFINITE;
+    }
+    return SPH_OK;
+}
+
+static sph_status upload_runs(sph_ctx *h, int64_t n, int32_t nr, const int64_t *run_start,
+                              hipStream_t s) {
+    Ctx *ctx = &h->c;
+    std::vector<int64_t> rs(nr + 1);
+    if (run_start) {
+        for (int r = 0; r <= nr; ++r) rs[r] = run_start[r];
+    } else {
+        rs[0] = 0;
+        rs[1] = n;
+    }
+    if (rs[0] != 0 || rs[nr] != n) {
+        set_error(ctx, "run_start must start at 0 and end at n");
+        return SPH_EINVAL;
+    }
+    for (int r = 0; r < nr; ++r)
+        if (rs[r + 1] < rs[r]) {
+            set_error(ctx, "run_start must be non-decreasing");
+            return SPH_EINVAL;
+        }
+    if (rs != h->run_cache) {
+        std::vector<int32_t> rp(nr + 1);
+        for (int r = 0; r <= nr; ++r) rp[r] = (int32_t)rs[r];
+        SPH_HIP(hipMemcpyAsync(ctx->run_p, rp.data(), rp.size() * 4, hipMemcpyHostToDevice, s));
+        SPH_HIP(hipStreamSynchronize(s));
+        h->run_cache = rs;
+    }
+    return SPH_OK;
+}
+
+sph_status sph_build_cells(sph_ctx *h, int64_t n, const double *x, const double *y,
+                           const double *z, const double *hh, int32_t n_runs,
+                           const int64_t *run_start, double cell_min, int32_t *perm_out,
+                           sph_stream stream) {
+    CHECK_CTX();
+    REQUIRE(n >= 0, SPH_EINVAL, "n < 0");
+    REQUIRE(n <= h->c.capacity, SPH_ECAPACITY, "n = %lld exceeds capacity %lld", (long long)n,
+            (long long)h->c.capacity);
+    REQUIRE(n == 0 || (x && y && z && hh && perm_out), SPH_EINVAL, "null array");
+    if (!run_start) n_runs = 1;
+    REQUIRE(n_runs >= 1 && n_runs <= h->c.max_runs, SPH_ECAPACITY, "n_runs out of range");
+    REQUIRE(cell_min >= 0.0, SPH_EINVAL, "cell_min < 0");
+    sph_status st = upload_runs(h, n, n_runs, run_start, S(stream));
+    if (st != SPH_OK) return st;
+    return launch_build_cells(&h->c, n, x, y, z, hh, n_runs, run_start, cell_min, perm_out,
+                              S(stream));
+}
+
+sph_status sph_reorder(sph_ctx *h, int64_t n, const int32_t *perm, int32_t nfields,
+                       const void *const *src, void *const *dst, const int32_t *elem_bytes,
+                       const int32_t *rows, sph_stream stream) {
+    CHECK_CTX();
+    REQUIRE(n >= 0 && n <= h->c.capacity, SPH_EINVAL, "n out of range");
+    REQUIRE(nfields >= 0 && nfields <= 64, SPH_EINVAL, "nfields out of range");
+    if (n == 0 || nfields == 0) return SPH_OK;
+    REQUIRE(perm && src && dst && elem_bytes, SPH_EINVAL, "null argument");
+    for (int f = 0; f < nfields; ++f) {
+        REQUIRE(src[f] && dst[f], SPH_EINVAL, "null field %d", f);
+        REQUIRE(elem_bytes[f] == 4 || elem_bytes[f] == 8, SPH_EINVAL, "elem_bytes must be 4 or 8");
+        REQUIRE(!rows || (rows[f] >= 1 && rows[f] <= 16), SPH_EINVAL, "rows out of range");
+        REQUIRE(src[f] != dst[f], SPH_EINVAL, "src and dst overlap");
+    }
+    return launch_reorder(&h->c, n, perm, nfields, src, dst, elem_bytes, rows, S(stream));
+}
+
+sph_status sph_neighbors_csr(sph_ctx *h, int64_t *offsets, int32_t *nbr, uint8_t *dflag,
+                             sph_stream stream) {
+    CHECK_CTX();
+    REQUIRE(h->c.n_built >= 0, SPH_ESTATE, "no neighbour search yet");
+    REQUIRE(offsets, SPH_EINVAL, "null offsets");
+    return launch_csr(&h->c, offsets, nbr, dflag, S(stream));
+}
+
+sph_status sph_pair_count(sph_ctx *h, uint64_t *out, sph_stream stream) {
+    CHECK_CTX();
+    REQUIRE(out, SPH_EINVAL, "null argument");
+    return launch_copy_u64(&h->c, h->c.pairs, (unsigned long long *)out, S(stream));
+}
+
+static sph_status check_built(sph_ctx *h, int64_t n) {
+    REQUIRE(h->c.n_built >= 0, SPH_ESTATE, "pair pass before sph_build_cells");
+    REQUIRE(n == h->c.n_built, SPH_ESTATE, "n = %lld differs from the last build (%lld)",
+            (long long)n, (long long)h->c.n_built);
+    return SPH_OK;
+}
+
+static sph_status set_mats(sph_ctx *h, const sph_material *mats, int32_t nmat) {
+    REQUIRE(mats && nmat >= 1 && nmat <= 8, SPH_EINVAL, "need 1..8 materials");
+    for (int k = 0; k < nmat; ++k) {
+        const sph_material &m = mats[k];
+        REQUIRE(m.rho0 > 0 && m.E0 > 0 && m.cv > 0 && m.Ecv > m.Eiv, SPH_EINVAL,
+                "material %d: invalid Tillotson or temperature constants", k);
+        REQUIRE(!m.strength_on || m.Ym > m.Y0, SPH_EINVAL, "material %d: Ym must exceed Y0", k);
+        h->c.mats[k].m = m;
+    }
+    return SPH_OK;
+}
+
+sph_status sph_density(sph_ctx *h, int64_t n, const double *m, const double *hh,
+                       const double *u, const int32_t *mat, const sph_material *mats,
+                       int32_t n_materials, const sph_params *prm, sph_precision prec,
+                       double *rho, double *omega, double *P, double *cs, double *T, double *Y,
+                       double *Gmod, sph_stream stream) {
+    CHECK_CTX();
+    sph_status st = check_built(h, n);
+    if (st != SPH_OK) return st;
+    REQUIRE(prm && (prec == SPH_FP64 || prec == SPH_FP32_CELLREL), SPH_EINVAL, "bad params");
+    REQUIRE(n == 0 || (m && hh && u && rho && omega && P && cs && T && Y && Gmod), SPH_EINVAL,
+            "null array");
+    st = set_mats(h, mats, n_materials);
+    if (st != SPH_OK) return st;
+    return launch_density(&h->c, n, m, hh, u, mat, n_materials, prm, prec, rho, omega, P, cs, T,
+                          Y, Gmod, S(stream));
+}
+
+sph_status sph_gradients(sph_ctx *h, int64_t n, const double *vx, const double *vy,
+                         const double *vz, const double *m, const double *hh, const double *rho,
+                         const double *omega, const sph_params *prm, sph_precision prec,
+                         double *G, int64_t *n_singular, sph_stream stream) {
+    CHECK_CTX();
+    sph_status st = check_built(h, n);
+    if (st != SPH_OK) return st;
+    REQUIRE(prm && (prec == SPH_FP64 || prec == SPH_FP32_CELLREL), SPH_EINVAL, "bad params");
+    REQUIRE(n == 0 || (vx && vy && vz && m && hh && rho && omega && G), SPH_EINVAL, "null array");
+    return launch_gradients(&h->c, n, vx, vy, vz, m, hh, rho, omega, prm, prec, G, n_singular,
+                            S(stream));
+}
+
+sph_status sph_stress_update(sph_ctx *h, int32_t phase, int64_t n, const double *dt,
+                             const double *dt_next, const double *G, const double *Y,
+                             const double *Gmod, const int32_t *fixed, const sph_params *prm,
+                             double *S_half, double *S_pred, double *Sdot, double *eps2,
+                             sph_stream stream) {
+    CHECK_CTX();
+    REQUIRE(n >= 0 && n <= h->c.capacity, SPH_EINVAL, "n out of range");
+    REQUIRE(prm, SPH_EINVAL, "null params");
+    if (n == 0) return SPH_OK;
+    switch (phase) {
+        case SPH_STRESS_PREDICT:
+            REQUIRE(dt && Y && S_half && S_pred && Sdot, SPH_EINVAL, "null array");
+            break;
+        case SPH_STRESS_RATE:
+            REQUIRE(G && Gmod && S_pred && Sdot, SPH_EINVAL, "null array");
+            break;
+        case SPH_STRESS_KICK:
+            REQUIRE(dt && dt_next && Y && S_half && Sdot && (!eps2 || G), SPH_EINVAL, "null array");
+            break;
+        case SPH_STRESS_OPEN:
+            REQUIRE(dt_next && S_half && S_pred && Sdot, SPH_EINVAL, "null array");
+            break;
+        default:
+            REQUIRE(false, SPH_EINVAL, "unknown stress phase %d", phase);
+    }
+    return launch_stress(&h->c, phase, n, dt, dt_next, G, Y, Gmod, fixed, prm, S_half, S_pred,
+                         Sdot, eps2, S(stream));
+}
+
+sph_status sph_forces_stress(sph_ctx *h, int64_t n, const double *vx, const double *vy,
+                             const double *vz, const double *m, const double *hh,
+                             const double *rho, const double *omega, const double *P,
+                             const double *cs, const double *Sd, const sph_params *prm,
+                             sph_precision prec, double *ax, double *ay, double *az,
+                             double *dudt, double *dt_cfl, sph_stream stream) {
+    CHECK_CTX();
+    sph_status st = check_built(h, n);
+    if (st != SPH_OK) return st;
+    REQUIRE(prm && (prec == SPH_FP64 || prec == SPH_FP32_CELLREL), SPH_EINVAL, "bad params");
+    REQUIRE(n == 0 || (vx && vy && vz && m && hh && rho && omega && P && cs && Sd && ax && ay &&
+                       az && dudt && dt_cfl),
+            SPH_EINVAL, "null array");
+    return launch_forces(&h->c, n, vx, vy, vz, m, hh, rho, omega, P, cs, Sd, prm, prec, ax, ay, az,
+                         dudt, dt_cfl, S(stream));
+}
+
+sph_status sph_kick_drift(sph_ctx *h, int32_t phase, int64_t n, const double *dt,
+                          const double *dt_next, const int32_t *fixed, double *x, double *y,
+                          double *z, double *vx, double *vy, double *vz, double *u,
+                          const double *ax, const double *ay, const double *az,
+                          const double *dudt, double *vpx, double *vpy, double *vpz,
+                          double *up, sph_stream stream) {
+    CHECK_CTX();
+    REQUIRE(n >= 0 && n <= h->c.capacity, SPH_EINVAL, "n out of range");
+    if (n == 0) return SPH_OK;
+    switch (phase) {
+        case SPH_KD_DRIFT:
+            REQUIRE(dt && x && y && z && vx && vy && vz, SPH_EINVAL, "null array");
+            break;
+        case SPH_KD_PREDICT:
+            REQUIRE(dt && vx && vy && vz && u && ax && ay && az && dudt && vpx && vpy && vpz && up,
+                    SPH_EINVAL, "null array");
+            break;
+        case SPH_KD_KICK:
+            REQUIRE(dt && dt_next && vx && vy && vz && u && ax && ay && az && dudt, SPH_EINVAL,
+                    "null array");
+            break;
+        case SPH_KD_OPEN:
+            REQUIRE(dt_next && vx && vy && vz && u && ax && ay && az && dudt, SPH_EINVAL,
+                    "null array");
+            break;
+        default:
+            REQUIRE(false, SPH_EINVAL, "unknown kick/drift phase %d", phase);
+    }
+    return launch_kick_drift(&h->c, phase, n, dt, dt_next, fixed, x, y, z, vx, vy, vz, u, ax, ay,
+                             az, dudt, vpx, vpy, vpz, up, S(stream));
+}
+
+sph_status sph_dt_min(sph_ctx *h, int64_t n, const double *dt_cfl, const int32_t *fixed,
+                      double *dt_out, sph_stream stream) {
+    CHECK_CTX();
+    REQUIRE(n >= 0 && n <= h->c.capacity, SPH_EINVAL, "n out of range");
+    REQUIRE(dt_out && (n == 0 || dt_cfl), SPH_EINVAL, "null array");
+    return launch_dt_min(&h->c, n, dt_cfl, fixed, 0.0, dt_out, S(stream));
+}
+
+sph_status sph_diagnostics(sph_ctx *h, int64_t n, const double *x, const double *y,
+                           const double *z, const double *vx, const double *vy, const double *vz,
+                           const double *m, const double *ax, const double *ay, const double *az,
+                           const double *dudt, double *out13, sph_stream stream) {
+    CHECK_CTX();
+    REQUIRE(n >= 0 && n <= h->c.capacity, SPH_EINVAL, "n out of range");
+    REQUIRE(out13 && (n == 0 || (x && y && z && vx && vy && vz && m && ax && ay && az && dudt)),
+            SPH_EINVAL, "null array");
+    return launch_diag(&h->c, n, x, y, z, vx, vy, vz, m, ax, ay, az, dudt, out13, S(stream));
+}
+
+// ------------------------------------------------------------ whole step
+struct Rows {
+    double *f[SPH_NF64];
+    int32_t *i[SPH_NI32];
+    double *w[SPH_NW];
+};
+
+static Rows rows_of(const sph_state *st, int buf) {
+    Rows r;
+    for (int k = 0; k < SPH_NF64; ++k) r.f[k] = st->f64[buf] + (size_t)k * st->n_cap;
+    for (int k = 0; k < SPH_NI32; ++k) r.i[k] = st->i32[buf] + (size_t)k * st->n_cap;
+    for (int k = 0; k < SPH_NW; ++k) r.w[k] = st->work + (size_t)k * st->n_cap;
+    return r;
+}
+
+static sph_status check_state(sph_ctx *h, const sph_state *st) {
+    REQUIRE(st, SPH_EINVAL, "null state");
+    REQUIRE(st->n >= 0 && st->n <= st->n_cap && st->n <= h->c.capacity, SPH_ECAPACITY,
+            "state size out of range");
+    REQUIRE(st->f64[0] && st->f64[1] && st->i32[0] && st->i32[1] && st->work && st->dt &&
+                st->dt_next,
+            SPH_EINVAL, "null state buffer");
+    REQUIRE(st->cur == 0 || st->cur == 1, SPH_EINVAL, "cur must be 0 or 1");
+    return SPH_OK;
+}
+
+// Derivatives at the current (sorted) state: density, EOS, stress predict +
+// rescale, gradients, stress rate, forces, CFL minimum into *dt_next.
+static sph_status eval(sph_ctx *h, const sph_state *st, const Rows &R, int32_t nmat,
+                       const sph_params *prm, sph_precision prec, hipStream_t s) {
+    const int64_t n = st->n, nc = st->n_cap;
+    Ctx *ctx = &h->c;
+    (void)nc;
+    sph_status e;
+    const int32_t *fixed = R.i[SPH_FIXED];
+    if ((e = launch_density(ctx, n, R.f[SPH_M], R.f[SPH_H], R.w[SPH_W_UP], R.i[SPH_MAT], nmat,
+                            prm, prec, R.w[SPH_W_RHO], R.w[SPH_W_OMEGA], R.w[SPH_W_P],
+                            R.w[SPH_W_CS], R.w[SPH_W_T], R.w[SPH_W_Y], R.w[SPH_W_GMOD], s)))
+        return e;
+    if ((e = launch_stress(ctx, SPH_STRESS_PREDICT, n, st->dt, st->dt_next, nullptr,
+                           R.w[SPH_W_Y], nullptr, fixed, prm, R.f[SPH_S], R.w[SPH_W_SP],
+                           R.f[SPH_SDOT], nullptr, s)))
+        return e;
+    if ((e = launch_gradients(ctx, n, R.w[SPH_W_VP], R.w[SPH_W_VP + 1], R.w[SPH_W_VP + 2],
+                              R.f[SPH_M], R.f[SPH_H], R.w[SPH_W_RHO], R.w[SPH_W_OMEGA], prm, prec,
+                              R.w[SPH_W_G], st->n_singular, s)))
+        return e;
+    if ((e = launch_stress(ctx, SPH_STRESS_RATE, n, st->dt, st->dt_next, R.w[SPH_W_G],
+                           R.w[SPH_W_Y], R.w[SPH_W_GMOD], fixed, prm, R.f[SPH_S], R.w[SPH_W_SP],
+                           R.f[SPH_SDOT], nullptr, s)))
+        return e;
+    if ((e = launch_forces(ctx, n, R.w[SPH_W_VP], R.w[SPH_W_VP + 1], R.w[SPH_W_VP + 2],
+                           R.f[SPH_M], R.f[SPH_H], R.w[SPH_W_RHO], R.w[SPH_W_OMEGA], R.w[SPH_W_P],
+                           R.w[SPH_W_CS], R.w[SPH_W_SP], prm, prec, R.f[SPH_AX], R.f[SPH_AY],
+                           R.f[SPH_AZ], R.f[SPH_DUDT], R.w[SPH_W_DT], s)))
+        return e;
+    return launch_dt_min(ctx, n, R.w[SPH_W_DT], fixed, st->dt_max, st->dt_next, s);
+}
+
+static sph_status sort_state(sph_ctx *h, sph_state *st, hipStream_t s) {
+    Ctx *ctx = &h->c;
+    const int64_t n = st->n;
+    const int cur = st->cur, alt = 1 - cur;
+    Rows A = rows_of(st, cur), B = rows_of(st, alt);
+    int32_t *perm = (int32_t *)A.w[SPH_W_PERM];
+    sph_status e = sph_build_cells(h, n, A.f[SPH_X], A.f[SPH_Y], A.f[SPH_Z], A.f[SPH_H],
+                                   st->run_start ? st->n_runs : 1, st->run_start, st->cell_min,
+                                   perm, (sph_stream)s);
+    if (e) return e;
+    const void *src[SPH_NF64 + SPH_NI32];
+    void *dst[SPH_NF64 + SPH_NI32];
+    int32_t eb[SPH_NF64 + SPH_NI32];
+    int nf = 0;
+    for (int k = 0; k < SPH_NF64; ++k, ++nf) {
+        src[nf] = A.f[k];
+        dst[nf] = B.f[k];
+        eb[nf] = 8;
+    }
+    for (int k = 0; k < SPH_NI32; ++k, ++nf) {
+        src[nf] = A.i[k];
+        dst[nf] = B.i[k];
+        eb[nf] = 4;
+    }
+    e = launch_reorder(ctx, n, perm, nf, src, dst, eb, nullptr, s);
+    if (e) return e;
+    st->cur = alt;
+    return SPH_OK;
+}
+
+sph_status sph_init(sph_ctx *h, sph_state *st, const sph_material *mats, int32_t n_materials,
+                    const sph_params *prm, sph_precision prec, sph_stream stream) {
+    CHECK_CTX();
+    sph_status e = check_state(h, st);
+    if (e) return e;
+    REQUIRE(prm, SPH_EINVAL, "null params");
+    if ((e = set_mats(h, mats, n_materials))) return e;
+    hipStream_t s = S(stream);
+    Ctx *ctx = &h->c;
+    const int64_t n = st->n;
+    if ((e = sort_state(h, st, s))) return e;
+    Rows R = rows_of(st, st->cur);
+    const int32_t *fixed = R.i[SPH_FIXED];
+    SPH_HIP(hipMemsetAsync(st->dt, 0, 8, s));
+    // predicted values are the current ones: v, u as they are, S rescaled
+    // (PREDICT with the derivative rows cleared)
+    for (int k = 0; k < 5; ++k)
+        SPH_HIP(hipMemsetAsync(R.f[SPH_SDOT + k], 0, n * 8, s));
+    for (int k = 0; k < 3; ++k)
+        SPH_HIP(hipMemcpyAsync(R.w[SPH_W_VP + k], R.f[SPH_VX + k], n * 8, hipMemcpyDeviceToDevice, s));
+    SPH_HIP(hipMemcpyAsync(R.w[SPH_W_UP], R.f[SPH_U], n * 8, hipMemcpyDeviceToDevice, s));
+    if ((e = eval(h, st, R, n_materials, prm, prec, s))) return e;
+    if ((e = launch_copy_scalar(ctx, st->dt_next, st->dt, s))) return e;
+    if ((e = launch_kick_drift(ctx, SPH_KD_OPEN, n, st->dt, st->dt, fixed, R.f[SPH_X], R.f[SPH_Y],
+                               R.f[SPH_Z], R.f[SPH_VX], R.f[SPH_VY], R.f[SPH_VZ], R.f[SPH_U],
+                               R.f[SPH_AX], R.f[SPH_AY], R.f[SPH_AZ], R.f[SPH_DUDT], nullptr,
+                               nullptr, nullptr, nullptr, s)))
+        return e;
+    return launch_stress(ctx, SPH_STRESS_OPEN, n, st->dt, st->dt, nullptr, nullptr, nullptr,
+                         fixed, prm, R.f[SPH_S], R.w[SPH_W_SP], R.f[SPH_SDOT], nullptr, s);
+}
+
+sph_status sph_step(sph_ctx *h, sph_state *st, const sph_material *mats, int32_t n_materials,
+                    const sph_params *prm, sph_precision prec, sph_stream stream) {
+    CHECK_CTX();
+    sph_status e = check_state(h, st);
+    if (e) return e;
+    REQUIRE(prm, SPH_EINVAL, "null params");
+    if ((e = set_mats(h, mats, n_materials))) return e;
+    hipStream_t s = S(stream);
+    Ctx *ctx = &h->c;
+    const int64_t n = st->n;
+    {
+        Rows R = rows_of(st, st->cur);
+        if ((e = launch_kick_drift(ctx, SPH_KD_DRIFT, n, st->dt, st->dt, R.i[SPH_FIXED],
+                                   R.f[SPH_X], R.f[SPH_Y], R.f[SPH_Z], R.f[SPH_VX], R.f[SPH_VY],
+                                   R.f[SPH_VZ], nullptr, nullptr, nullptr, nullptr, nullptr,
+                                   nullptr, nullptr, nullptr, nullptr, s)))
+            return e;
+    }
+    if ((e = sort_state(h, st, s))) return e;
+    Rows R = rows_of(st, st->cur);
+    const int32_t *fixed = R.i[SPH_FIXED];
+    if ((e = launch_kick_drift(ctx, SPH_KD_PREDICT, n, st->dt, st->dt, fixed, nullptr, nullptr,
+                               nullptr, R.f[SPH_VX], R.f[SPH_VY], R.f[SPH_VZ], R.f[SPH_U],
+                               R.f[SPH_AX], R.f[SPH_AY], R.f[SPH_AZ], R.f[SPH_DUDT],
+                               R.w[SPH_W_VP], R.w[SPH_W_VP + 1], R.w[SPH_W_VP + 2], R.w[SPH_W_UP],
+                               s)))
+        return e;
+    if ((e = eval(h, st, R, n_materials, prm, prec, s))) return e;
+    if ((e = launch_kick_drift(ctx, SPH_KD_KICK, n, st->dt, st->dt_next, fixed, nullptr, nullptr,
+                               nullptr, R.f[SPH_VX], R.f[SPH_VY], R.f[SPH_VZ], R.f[SPH_U],
+                               R.f[SPH_AX], R.f[SPH_AY], R.f[SPH_AZ], R.f[SPH_DUDT], nullptr,
+                               nullptr, nullptr, nullptr, s)))
+        return e;
+    if ((e = launch_stress(ctx, SPH_STRESS_KICK, n, st->dt, st->dt_next, R.w[SPH_W_G],
+                           R.w[SPH_W_Y], R.w[SPH_W_GMOD], fixed, prm, R.f[SPH_S], R.w[SPH_W_SP],
+                           R.f[SPH_SDOT], R.f[SPH_EPS2], s)))
+        return e;
+    return launch_copy_scalar(ctx, st->dt_next, st->dt, s);
+}
+
+sph_status sph_timing(sph_ctx *h, int32_t enable) {
+    CHECK_CTX();
+    Ctx *ctx = &h->c;
+    for (int w = 0; w < SPH_T_COUNT; ++w) {
+        fold_events(ctx, w, 0);
+        ctx->t_ms[w] = 0.0;
+        ctx->t_count[w] = 0;
+    }
+    ctx->timing = enable != 0;
+    return SPH_OK;
+}
+
+sph_status sph_timing_read(sph_ctx *h, int32_t which, double *total_ms, int64_t *launches) {
+    CHECK_CTX();
+    REQUIRE(which >= 0 && which < SPH_T_COUNT, SPH_EINVAL, "unknown kernel id");
+    REQUIRE(total_ms && launches, SPH_EINVAL, "null argument");
+    Ctx *ctx = &h->c;
+    fold_events(ctx, which, 0);
+    *total_ms = ctx->t_ms[which];
+    *launches = ctx->t_count[which];
+    return SPH_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,595 @@
+// Neighbour search of the strength-SPH hot path on gfx950: uniform cell
+// grid per run, counting sort of particles by the Morton key of their cell,
+// and the exact pair sets N_i built from LDS-staged candidate tiles.
+//
+// Pair set (symmetrised sums of the acceleration and Velocity_Gradient
+// eqs.): N_i = { j != i : r_ij^2 < max((2h_i)^2, (2h_j)^2) }, kernel support
+// H = 2h; density set: r_ij^2 < (2h_i)^2 (Density_estimate eq.).
+#include <stdarg.h>
+#include <stdio.h>
+
+#include "sph_internal.h"
+
+namespace sph {
+
+// ------------------------------------------------------------- utilities
+__global__ void k_fill_i32(int32_t *p, int32_t v, int64_t n) {
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n;
+         k += (int64_t)gridDim.x * blockDim.x)
+        p[k] = v;
+}
+
+// Zero the first *len entries of p (len read on the device).
+__global__ void k_zero_dev_len(int32_t *p, const int32_t *len) {
+    int64_t n = *len;
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n;
+         k += (int64_t)gridDim.x * blockDim.x)
+        p[k] = 0;
+}
+
+sph_status launch_fill_i32(Ctx *ctx, int32_t *p, int32_t v, int64_t n, hipStream_t s) {
+    if (n <= 0) return SPH_OK;
+    int blocks = (int)((n + 255) / 256);
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_fill_i32, dim3(blocks), dim3(256), 0, s, p, v, n);
+    SPH_HIP(hipGetLastError());
+    return SPH_OK;
+}
+
+// ------------------------------------------------ exclusive scan (device length)
+// out[k] = sum_{l<k} in[l] for k <= len (out[len] = total).  Three phases:
+// per-block sums over contiguous chunks, scan of the block sums, rescan.
+template <typename Tin, typename Tout>
+__global__ void k_scan_reduce(const Tin *in, const int64_t *len_dev, const int32_t *len32_dev,
+                              int64_t len_host, int64_t *part) {
+    int64_t len = len_dev ? *len_dev : (len32_dev ? (int64_t)*len32_dev : len_host);
+    int64_t chunk = (len + gridDim.x - 1) / gridDim.x;
+    int64_t a = blockIdx.x * chunk, b = a + chunk < len ? a + chunk : len;
+    int64_t s = 0;
+    for (int64_t k = a + threadIdx.x; k < b; k += blockDim.x) s += (int64_t)in[k];
+    __shared__ int64_t red[256];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ void k_scan_top(int64_t *part, int nb) {
+    // single block of 1024 threads, nb <= 1024: exclusive scan in place
+    __shared__ int64_t sh[1024];
+    int t = threadIdx.x;
+    int64_t v = t < nb ? part[t] : 0;
+    sh[t] = v;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {
+        int64_t add = t >= o ? sh[t - o] : 0;
+        __syncthreads();
+        sh[t] += add;
+        __syncthreads();
+    }
+    if (t < nb) part[t] = sh[t] - v;
+    if (t == nb - 1) part[nb] = sh[t];
+}
+
+template <typename Tin, typename Tout>
+__global__ void k_scan_final(const Tin *in, Tout *out, const int64_t *len_dev,
+                             const int32_t *len32_dev, int64_t len_host, const int64_t *part) {
+    int64_t len = len_dev ? *len_dev : (len32_dev ? (int64_t)*len32_dev : len_host);
+    int64_t chunk = (len + gridDim.x - 1) / gridDim.x;
+    int64_t a = blockIdx.x * chunk, b = a + chunk < len ? a + chunk : len;
+    __shared__ int64_t sh[256];
+    int64_t carry = part[blockIdx.x];
+    for (int64_t base = a; base < b; base += blockDim.x) {
+        int64_t k = base + threadIdx.x;
+        int64_t v = k < b ? (int64_t)in[k] : 0;
+        sh[threadIdx.x] = v;
+        __syncthreads();
+        for (int o = 1; o < 256; o <<= 1) {
+            int64_t add = threadIdx.x >= (unsigned)o ? sh[threadIdx.x - o] : 0;
+            __syncthreads();
+            sh[threadIdx.x] += add;
+            __syncthreads();
+        }
+        if (k < b) out[k] = (Tout)(carry + sh[threadIdx.x] - v);
+        int64_t tot = sh[255];
+        __syncthreads();
+        carry += tot;
+    }
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) out[len] = (Tout)part[gridDim.x];
+}
+
+template <typename Tin, typename Tout>
+static sph_status scan(Ctx *ctx, const Tin *in, Tout *out, const int32_t *len32_dev,
+                       int64_t len_host, hipStream_t s) {
+    const int nb = kScanBlocks;
+    hipLaunchKernelGGL((k_scan_reduce<Tin, Tout>), dim3(nb), dim3(256), 0, s, in,
+                       (const int64_t *)nullptr, len32_dev, len_host, ctx->scan_part);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, ctx->scan_part, nb);
+    hipLaunchKernelGGL((k_scan_final<Tin, Tout>), dim3(nb), dim3(256), 0, s, in, out,
+                       (const int64_t *)nullptr, len32_dev, len_host, ctx->scan_part);
+    SPH_HIP(hipGetLastError());
+    return SPH_OK;
+}
+
+// ------------------------------------------------------------ grid set-up
+__device__ __forceinline__ int run_of(const int32_t *run_p, int nr, int64_t k) {
+    int lo = 0, hi = nr;  // run_p[lo] <= k < run_p[hi]
+    while (hi - lo > 1) {
+        int mid = (lo + hi) >> 1;
+        if (run_p[mid] <= k) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+__global__ void k_bbox(const double *x, const double *y, const double *z, const double *h,
+                       const int32_t *run_p, BBox *part) {
+    int r = blockIdx.y;
+    int64_t a = run_p[r], b = run_p[r + 1];
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    double hm = 0.0;
+    for (int64_t k = a + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < b;
+         k += (int64_t)gridDim.x * blockDim.x) {
+        double v[3] = {x[k], y[k], z[k]};
+        for (int d = 0; d < 3; ++d) {
+            lo[d] = fmin(lo[d], v[d]);
+            hi[d] = fmax(hi[d], v[d]);
+        }
+        hm = fmax(hm, h[k]);
+    }
+    __shared__ double sh[7][256];
+    for (int d = 0; d < 3; ++d) {
+        sh[d][threadIdx.x] = lo[d];
+        sh[3 + d][threadIdx.x] = hi[d];
+    }
+    sh[6][threadIdx.x] = hm;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < (unsigned)o) {
+            for (int d = 0; d < 3; ++d) {
+                sh[d][threadIdx.x] = fmin(sh[d][threadIdx.x], sh[d][threadIdx.x + o]);
+                sh[3 + d][threadIdx.x] = fmax(sh[3 + d][threadIdx.x], sh[3 + d][threadIdx.x + o]);
+            }
+            sh[6][threadIdx.x] = fmax(sh[6][threadIdx.x], sh[6][threadIdx.x + o]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        BBox bb;
+        for (int d = 0; d < 3; ++d) {
+            bb.lo[d] = sh[d][0];
+            bb.hi[d] = sh[3 + d][0];
+        }
+        bb.hmax = sh[6][0];
+        part[r * kBBoxBlocks + blockIdx.x] = bb;
+    }
+}
+
+__device__ static int bits_for(int n) {
+    int b = 0;
+    while ((1 << b) < n) ++b;
+    return b;
+}
+
+// One thread: per-run grids that fit the cell table.
+__global__ void k_grid(const BBox *part, const int32_t *run_p, int nr, double cell_min,
+                       int64_t max_cells, GridDesc *grid, int32_t *total_keys, int32_t *flags) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double grow = 1.0;
+    for (int attempt = 0; attempt < 200; ++attempt) {
+        int64_t total = 0;
+        for (int r = 0; r < nr; ++r) {
+            BBox bb = part[r * kBBoxBlocks];
+            for (int b = 1; b < kBBoxBlocks; ++b) {
+                BBox o = part[r * kBBoxBlocks + b];
+                for (int d = 0; d < 3; ++d) {
+                    bb.lo[d] = fmin(bb.lo[d], o.lo[d]);
+                    bb.hi[d] = fmax(bb.hi[d], o.hi[d]);
+                }
+                bb.hmax = fmax(bb.hmax, o.hmax);
+            }
+            GridDesc g;
+            g.p0 = run_p[r];
+            g.p1 = run_p[r + 1];
+            if (g.p1 <= g.p0) {  // empty run
+                for (int d = 0; d < 3; ++d) { bb.lo[d] = 0.0; bb.hi[d] = 0.0; }
+                bb.hmax = 0.0;
+            }
+            // Edge at least the largest support 2h (so every pair lies in the
+            // 27-cell stencil), slightly enlarged so that rounding of
+            // (x - origin)/L can never separate a pair by two cells.
+            double L = fmax(cell_min, 2.0 * bb.hmax) * grow * (1.0 + 1.0 / 1099511627776.0);
+            if (!(L > 0.0)) L = 1.0;
+            int dims[3];
+            for (int d = 0; d < 3; ++d) {
+                double ext = bb.hi[d] - bb.lo[d];
+                if (ext / L > (double)((1 << kMaxMortonBits) - 2)) L = ext / (double)((1 << kMaxMortonBits) - 2);
+            }
+            for (int d = 0; d < 3; ++d) {
+                double ext = bb.hi[d] - bb.lo[d];
+                int nd = (int)floor(ext / L) + 1;
+                dims[d] = nd < 1 ? 1 : nd;
+            }
+            g.ox = bb.lo[0]; g.oy = bb.lo[1]; g.oz = bb.lo[2];
+            g.L = L;
+            g.invL = 1.0 / L;
+            g.L32 = (float)L;
+            g.nx = dims[0]; g.ny = dims[1]; g.nz = dims[2];
+            g.bx = bits_for(dims[0]); g.by = bits_for(dims[1]); g.bz = bits_for(dims[2]);
+            g.key_count = 1 << (g.bx + g.by + g.bz);
+            g.key_off = (int32_t)total;
+            total += g.key_count;
+            grid[r] = g;
+        }
+        if (total <= max_cells) {
+            *total_keys = (int32_t)total;
+            return;
+        }
+        grow *= 1.25;
+    }
+    flags[FLAG_CELL_OVERFLOW] = 1;
+    *total_keys = 0;
+}
+
+__device__ __forceinline__ void cell_of(const GridDesc &g, double x, double y, double z,
+                                        int &cx, int &cy, int &cz) {
+    cx = (int)floor((x - g.ox) * g.invL);
+    cy = (int)floor((y - g.oy) * g.invL);
+    cz = (int)floor((z - g.oz) * g.invL);
+    cx = cx < 0 ? 0 : (cx >= g.nx ? g.nx - 1 : cx);
+    cy = cy < 0 ? 0 : (cy >= g.ny ? g.ny - 1 : cy);
+    cz = cz < 0 ? 0 : (cz >= g.nz ? g.nz - 1 : cz);
+}
+
+__global__ void k_keys(int64_t n, const double *x, const double *y, const double *z,
+                       const int32_t *run_p, int nr, const GridDesc *grid,
+                       const int32_t *total_keys, uint32_t *key, int32_t *slot,
+                       int32_t *cell_count) {
+    int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    if (*total_keys == 0) {  // table overflow: flagged, produce a valid (empty) permutation
+        key[k] = 0;
+        slot[k] = 0;
+        return;
+    }
+    int r = nr > 1 ? run_of(run_p, nr, k) : 0;
+    GridDesc g = grid[r];
+    int cx, cy, cz;
+    cell_of(g, x[k], y[k], z[k], cx, cy, cz);
+    uint32_t kk = (uint32_t)g.key_off + morton(cx, cy, cz, g.bx, g.by, g.bz);
+    key[k] = kk;
+    slot[k] = atomicAdd(&cell_count[kk], 1);
+}
+
+__global__ void k_scatter(int64_t n, const uint32_t *key, const int32_t *slot,
+                          const int32_t *cell_start, const int32_t *total_keys, int32_t *perm) {
+    int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    if (*total_keys == 0) {
+        perm[k] = (int32_t)k;
+        return;
+    }
+    perm[cell_start[key[k]] + slot[k]] = (int32_t)k;
+}
+
+// Arrival order inside a cell depends on atomics; sorting each cell's
+// members by input index makes the permutation deterministic.
+__global__ void k_cellsort(const int32_t *cell_start, const int32_t *cell_count,
+                           const int32_t *total_keys, int32_t *perm) {
+    int64_t nk = *total_keys;
+    for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < nk;
+         c += (int64_t)gridDim.x * blockDim.x) {
+        int cnt = cell_count[c];
+        if (cnt < 2) continue;
+        int32_t *a = perm + cell_start[c];
+        for (int i = 1; i < cnt; ++i) {
+            int32_t v = a[i];
+            int j = i - 1;
+            while (j >= 0 && a[j] > v) {
+                a[j + 1] = a[j];
+                --j;
+            }
+            a[j + 1] = v;
+        }
+    }
+}
+
+// Sorted copies of positions and h, cell-relative float offsets, packed
+// cell coordinates, run id, sorted keys; perm copied out for the caller.
+__global__ void k_gather(int64_t n, const int32_t *perm, const double *x, const double *y,
+                         const double *z, const double *h, const uint32_t *key,
+                         const int32_t *run_p, int nr, const GridDesc *grid,
+                         double4 *posh64, float4 *posh32, uint32_t *cellc, int16_t *runid,
+                         uint32_t *skey, int32_t *perm_out) {
+    int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    int32_t o = perm[p];
+    double xo = x[o], yo = y[o], zo = z[o], ho = h[o];
+    int r = nr > 1 ? run_of(run_p, nr, p) : 0;
+    GridDesc g = grid[r];
+    int cx, cy, cz;
+    cell_of(g, xo, yo, zo, cx, cy, cz);
+    posh64[p] = make_double4(xo, yo, zo, ho);
+    double dx = (xo - g.ox) - (double)cx * g.L;
+    double dy = (yo - g.oy) - (double)cy * g.L;
+    double dz = (zo - g.oz) - (double)cz * g.L;
+    posh32[p] = make_float4((float)dx, (float)dy, (float)dz, (float)ho);
+    cellc[p] = (uint32_t)cx | ((uint32_t)cy << 10) | ((uint32_t)cz << 20);
+    runid[p] = (int16_t)r;
+    skey[p] = key[o];
+    if (perm_out) perm_out[p] = o;
+}
+
+// ------------------------------------------------------ pair-set builder
+// One wave per work-group.  The work-group owns a contiguous range of
+// sorted particles; for each cell it meets it stages the candidates of the
+// 27 neighbour cells in LDS (chunks of kTile), then tests every (i, j)
+// combination of the cell's particles in a flattened loop so that all 64
+// lanes stay busy, and appends hits to i's list in candidate order (ballot
+// + mbcnt compaction): the lists are deterministic.
+constexpr int kTile = 256;
+constexpr int kIBatch = 64;
+
+__global__ __launch_bounds__(64) void k_build_pairs(
+    int64_t n, const double4 *__restrict__ posh64, const uint32_t *__restrict__ skey,
+    const uint32_t *__restrict__ cellc, const int16_t *__restrict__ runid,
+    const GridDesc *__restrict__ grid, const int32_t *__restrict__ cell_start,
+    const int32_t *__restrict__ cell_count, const int32_t *total_keys, uint32_t *nbr,
+    int32_t *ncount, int32_t K, int32_t *flags, unsigned long long *pairs) {
+    __shared__ double4 tile[kTile];
+    __shared__ uint32_t tj[kTile];
+    __shared__ double4 ipos[kIBatch];
+    __shared__ int32_t icnt[kIBatch];
+    __shared__ int32_t st_start[27];
+    __shared__ int32_t st_off[28];
+
+    const int lane = threadIdx.x;
+    const uint32_t wg = xcd_block(blockIdx.x, gridDim.x);
+    const int64_t p_begin = n * (int64_t)wg / gridDim.x;
+    const int64_t p_end = n * (int64_t)(wg + 1) / gridDim.x;
+    if (*total_keys == 0) {  // table overflow (flagged): leave empty, valid lists
+        for (int64_t q = p_begin + lane; q < p_end; q += kWave) ncount[q] = 0;
+        return;
+    }
+    unsigned long long my_pairs = 0;
+
+    int64_t p = p_begin;
+    while (p < p_end) {
+        const uint32_t key = skey[p];
+        const int64_t cs = cell_start[key];
+        const int64_t ce = cs + cell_count[key];
+        const int64_t i_lo = p;
+        const int64_t i_hi = ce < p_end ? ce : p_end;
+        if (i_hi <= i_lo) {  // inconsistent cell table: never loop without progress
+            for (int64_t q = p + lane; q < p_end; q += kWave) ncount[q] = 0;
+            if (lane == 0) atomicOr(&flags[FLAG_CELL_OVERFLOW], 2);
+            break;
+        }
+        // ---- stencil: 27 neighbour cells (lane t handles cell t)
+        const uint32_t cc = cellc[p];
+        const int r = runid[p];
+        const GridDesc g = grid[r];
+        int cnt_t = 0, start_t = 0;
+        if (lane < 27) {
+            int dx = lane % 3 - 1, dy = (lane / 3) % 3 - 1, dz = lane / 9 - 1;
+            int cx = (int)(cc & 1023u) + dx;
+            int cy = (int)((cc >> 10) & 1023u) + dy;
+            int cz = (int)((cc >> 20) & 1023u) + dz;
+            if (cx >= 0 && cx < g.nx && cy >= 0 && cy < g.ny && cz >= 0 && cz < g.nz) {
+                uint32_t kk = (uint32_t)g.key_off + morton(cx, cy, cz, g.bx, g.by, g.bz);
+                start_t = cell_start[kk];
+                cnt_t = cell_count[kk];
+            }
+        }
+        // inclusive scan of the 27 counts across the wave
+        int incl = cnt_t;
+#pragma unroll
+        for (int o = 1; o < 32; o <<= 1) {
+            int v = __shfl_up(incl, o);
+            if (lane >= o) incl += v;
+        }
+        __syncthreads();
+        if (lane < 27) {
+            st_start[lane] = start_t;
+            st_off[lane + 1] = incl;
+        }
+        if (lane == 0) st_off[0] = 0;
+        __syncthreads();
+        const int T = st_off[27];
+
+        for (int64_t ib = i_lo; ib < i_hi; ib += kIBatch) {
+            const int ni = (int)((i_hi - ib) < kIBatch ? (i_hi - ib) : kIBatch);
+            if (lane < ni) {
+                double4 q = posh64[ib + lane];
+                double H = 2.0 * q.w;
+                ipos[lane] = make_double4(q.x, q.y, q.z, __dmul_rn(H, H));
+                icnt[lane] = 0;
+            }
+            for (int c0 = 0; c0 < T; c0 += kTile) {
+                const int nS = (T - c0) < kTile ? (T - c0) : kTile;
+                __syncthreads();
+                for (int s = lane; s < nS; s += kWave) {
+                    int gidx = c0 + s;
+                    int lo = 0, hi = 27;
+                    while (hi - lo > 1) {
+                        int mid = (lo + hi) >> 1;
+                        if (st_off[mid] <= gidx) lo = mid; else hi = mid;
+                    }
+                    int j = st_start[lo] + (gidx - st_off[lo]);
+                    double4 q = posh64[j];
+                    double H = 2.0 * q.w;
+                    tile[s] = make_double4(q.x, q.y, q.z, __dmul_rn(H, H));
+                    tj[s] = (uint32_t)j | ((uint32_t)lo << kCodeShift);
+                }
+                __syncthreads();
+                const int total = ni * nS;
+                const int adv_i = kWave / nS, adv_s = kWave % nS;
+                int il = lane / nS, s = lane % nS;
+                for (int f0 = 0; f0 < total; f0 += kWave) {
+                    const bool valid = f0 + lane < total;
+                    bool hit = false, dfl = false;
+                    uint32_t e = 0;
+                    if (valid) {
+                        double4 pi = ipos[il];
+                        double4 pj = tile[s];
+                        e = tj[s];
+                        double r2 = sep2_exact(pi.x, pi.y, pi.z, pj.x, pj.y, pj.z);
+                        int64_t j = e & kIdxMask;
+                        hit = (j != ib + il) && (r2 < fmax(pi.w, pj.w));
+                        dfl = r2 < pi.w;
+                    }
+                    const uint64_t m = __ballot(hit);
+                    const int below = __builtin_amdgcn_mbcnt_hi(
+                        (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+                    int first = lane - s;
+                    first = first < 0 ? 0 : first;
+                    const int below_first = __shfl(below, first);
+                    const int rank = below - below_first;
+                    const int base = valid ? icnt[il] : 0;
+                    if (hit) {
+                        int idx = base + rank;
+                        if (idx < K) nbr[(ib + il) * (int64_t)K + idx] = e | (dfl ? kDensityBit : 0u);
+                    }
+                    const bool last = valid && (s == nS - 1 || lane == kWave - 1 || f0 + lane == total - 1);
+                    if (last) icnt[il] = base + rank + (hit ? 1 : 0);
+                    s += adv_s;
+                    il += adv_i;
+                    if (s >= nS) {
+                        s -= nS;
+                        ++il;
+                    }
+                }
+            }
+            __syncthreads();
+            if (lane < ni) {
+                int c = icnt[lane];
+                ncount[ib + lane] = c < K ? c : K;
+                if (c > K) atomicOr(&flags[FLAG_NBR_OVERFLOW], 1);
+                my_pairs += (unsigned long long)c;
+            }
+            __syncthreads();
+        }
+        p = i_hi;
+    }
+    // wave sum of the pair count, one atomic per work-group
+    unsigned long long v = my_pairs;
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    if (lane == 0 && v) atomicAdd(pairs, v);
+}
+
+sph_status launch_build_cells(Ctx *ctx, int64_t n, const double *x, const double *y,
+                              const double *z, const double *h, int32_t nr,
+                              const int64_t *run_start, double cell_min, int32_t *perm_out,
+                              hipStream_t s) {
+    (void)run_start;
+    if (n == 0) {
+        ctx->n_built = 0;
+        ctx->n_runs_built = nr;
+        return SPH_OK;
+    }
+    const int tb = 256;
+    const int nb = (int)((n + tb - 1) / tb);
+    hipLaunchKernelGGL(k_bbox, dim3(kBBoxBlocks, nr), dim3(256), 0, s, x, y, z, h, ctx->run_p,
+                       ctx->bbox_part);
+    hipLaunchKernelGGL(k_grid, dim3(1), dim3(64), 0, s, ctx->bbox_part, ctx->run_p, nr, cell_min,
+                       ctx->max_cells, ctx->grid, ctx->total_keys, ctx->flags);
+    hipLaunchKernelGGL(k_zero_dev_len, dim3(1024), dim3(256), 0, s, ctx->cell_count,
+                       ctx->total_keys);
+    hipLaunchKernelGGL(k_keys, dim3(nb), dim3(tb), 0, s, n, x, y, z, ctx->run_p, nr, ctx->grid,
+                       ctx->total_keys, ctx->key, ctx->slot, ctx->cell_count);
+    sph_status st = scan<int32_t, int32_t>(ctx, ctx->cell_count, ctx->cell_start,
+                                           ctx->total_keys, 0, s);
+    if (st != SPH_OK) return st;
+    hipLaunchKernelGGL(k_scatter, dim3(nb), dim3(tb), 0, s, n, ctx->key, ctx->slot,
+                       ctx->cell_start, ctx->total_keys, ctx->perm);
+    hipLaunchKernelGGL(k_cellsort, dim3(1024), dim3(256), 0, s, ctx->cell_start, ctx->cell_count,
+                       ctx->total_keys, ctx->perm);
+    hipLaunchKernelGGL(k_gather, dim3(nb), dim3(tb), 0, s, n, ctx->perm, x, y, z, h, ctx->key,
+                       ctx->run_p, nr, ctx->grid, ctx->posh64, ctx->posh32, ctx->cellc,
+                       ctx->runid, ctx->skey, perm_out);
+    int64_t wgs = (n + 31) / 32;
+    if (wgs > 65536) wgs = 65536;
+    {
+        TimedLaunch tl(ctx, SPH_T_BUILD, s);
+        hipLaunchKernelGGL(k_build_pairs, dim3((unsigned)wgs), dim3(64), 0, s, n, ctx->posh64,
+                           ctx->skey, ctx->cellc, ctx->runid, ctx->grid, ctx->cell_start,
+                           ctx->cell_count, ctx->total_keys, ctx->nbr, ctx->ncount, ctx->max_nbr,
+                           ctx->flags, ctx->pairs);
+    }
+    SPH_HIP(hipGetLastError());
+    ctx->n_built = n;
+    ctx->n_runs_built = nr;
+    return SPH_OK;
+}
+
+// ----------------------------------------------------------------- reorder
+struct ReorderArgs {
+    const void *src[32];
+    void *dst[32];
+    int32_t eb[32];
+    int32_t nf;
+};
+
+__global__ void k_reorder(int64_t n, const int32_t *__restrict__ perm, ReorderArgs a) {
+    int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const int64_t o = perm[k];
+    for (int f = 0; f < a.nf; ++f) {
+        if (a.eb[f] == 8)
+            ((double *)a.dst[f])[k] = ((const double *)a.src[f])[o];
+        else
+            ((int32_t *)a.dst[f])[k] = ((const int32_t *)a.src[f])[o];
+    }
+}
+
+sph_status launch_reorder(Ctx *ctx, int64_t n, const int32_t *perm, int32_t nf,
+                          const void *const *src, void *const *dst, const int32_t *eb,
+                          const int32_t *rows, hipStream_t s) {
+    if (n == 0) return SPH_OK;
+    ReorderArgs a;
+    a.nf = 0;
+    const int nb = (int)((n + 255) / 256);
+    for (int f = 0; f < nf; ++f) {
+        int nrow = rows ? rows[f] : 1;
+        for (int r = 0; r < nrow; ++r) {
+            a.src[a.nf] = (const char *)src[f] + (size_t)r * n * eb[f];
+            a.dst[a.nf] = (char *)dst[f] + (size_t)r * n * eb[f];
+            a.eb[a.nf] = eb[f];
+            if (++a.nf == 32) {
+                hipLaunchKernelGGL(k_reorder, dim3(nb), dim3(256), 0, s, n, perm, a);
+                a.nf = 0;
+            }
+        }
+    }
+    if (a.nf) hipLaunchKernelGGL(k_reorder, dim3(nb), dim3(256), 0, s, n, perm, a);
+    SPH_HIP(hipGetLastError());
+    return SPH_OK;
+}
+
+// ----------------------------------------------------------- CSR export
+__global__ void k_csr(int64_t n, const uint32_t *nbr, const int32_t *ncount, int32_t K,
+                      const int64_t *off, int32_t *out, uint8_t *dfl) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int64_t o = off[i];
+    for (int k = 0; k < ncount[i]; ++k) {
+        uint32_t e = nbr[i * (int64_t)K + k];
+        out[o + k] = (int32_t)(e & kIdxMask);
+        if (dfl) dfl[o + k] = (uint8_t)(e >> 31);
+    }
+}
+
+sph_status launch_csr(Ctx *ctx, int64_t *off, int32_t *nbr, uint8_t *dflag, hipStream_t s) {
+    int64_t n = ctx->n_built;
+    sph_status st = scan<int32_t, int64_t>(ctx, ctx->ncount, off, nullptr, n, s);
+    if (st != SPH_OK) return st;
+    if (nbr && n > 0)
+        hipLaunchKernelGGL(k_csr, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, ctx->nbr,
+                           ctx->ncount, ctx->max_nbr, off, nbr, dflag);
+    SPH_HIP(hipGetLastError());
+    return SPH_OK;
+}
+
+}  // namespace sph

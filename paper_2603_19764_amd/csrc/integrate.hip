@@ -1,0 +1,268 @@
+// Per-particle phases of the strength-SPH step on gfx950 (HBM-bound
+// streams, one thread per particle, all in double): predictor and plastic
+// rescaling of the deviatoric stress (Predict_S eq., Deviatoric_stress_
+// rescaling eq.), Jaumann stress rate (Deviatoric_Stress_derivative eq.),
+// closing and opening kicks (sec. 2.4), drift, global time step from the
+// CFL condition, and conservation diagnostics.
+#include "sph_internal.h"
+
+namespace sph {
+
+// S -> f S, f = min(Y / sqrt(J2), 1), J2 = 1/2 S:S over the full tensor.
+__device__ __forceinline__ void plastic_return(double s[5], double Y) {
+    const double szz = -s[0] - s[1];
+    const double J2 = 0.5 * (s[0] * s[0] + s[1] * s[1] + szz * szz) + s[2] * s[2] +
+                      s[3] * s[3] + s[4] * s[4];
+    if (J2 > 0.0) {
+        const double f = Y / sqrt(J2);
+        if (f < 1.0)
+            for (int c = 0; c < 5; ++c) s[c] *= f;
+    }
+}
+
+__global__ void k_stress(int32_t phase, int64_t n, const double *__restrict__ dtp,
+                         const double *__restrict__ dtnp, const double *__restrict__ G,
+                         const double *__restrict__ Y, const double *__restrict__ Gmod,
+                         const int32_t *__restrict__ fixed, double rot, double *S_half,
+                         double *S_pred, double *Sdot, double *eps2) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const bool fx = fixed && fixed[i];
+    if (phase == SPH_STRESS_PREDICT) {
+        const double hd = 0.5 * *dtp;
+        double s[5];
+        for (int c = 0; c < 5; ++c)
+            s[c] = fx ? S_half[c * n + i] : S_half[c * n + i] + hd * Sdot[c * n + i];
+        plastic_return(s, Y[i]);
+        for (int c = 0; c < 5; ++c) S_pred[c * n + i] = s[c];
+    } else if (phase == SPH_STRESS_RATE) {
+        double g[9];
+        for (int c = 0; c < 9; ++c) g[c] = G[c * n + i];
+        const double sxx = S_pred[i], syy = S_pred[n + i], sxy = S_pred[2 * n + i],
+                     sxz = S_pred[3 * n + i], syz = S_pred[4 * n + i];
+        const double S[3][3] = {{sxx, sxy, sxz}, {sxy, syy, syz}, {sxz, syz, -sxx - syy}};
+        double E[3][3], R[3][3];
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) {
+                E[a][b] = 0.5 * (g[3 * a + b] + g[3 * b + a]);
+                R[a][b] = 0.5 * (g[3 * a + b] - g[3 * b + a]);
+            }
+        const double tr3 = (E[0][0] + E[1][1] + E[2][2]) / 3.0;
+        const double gm = Gmod[i];
+        const int ia[5] = {0, 1, 0, 0, 1}, ib[5] = {0, 1, 1, 2, 2};
+        for (int c = 0; c < 5; ++c) {
+            const int a = ia[c], b = ib[c];
+            double rs = 0.0, sr = 0.0;
+            for (int k = 0; k < 3; ++k) {
+                rs += R[a][k] * S[k][b];
+                sr += S[a][k] * R[k][b];
+            }
+            Sdot[c * n + i] = 2.0 * gm * (E[a][b] - (a == b ? tr3 : 0.0)) + rot * (rs - sr);
+        }
+    } else if (phase == SPH_STRESS_KICK) {
+        if (fx) return;
+        const double dt = *dtp, hd = 0.5 * dt, hn = 0.5 * *dtnp;
+        double s[5], d[5];
+        for (int c = 0; c < 5; ++c) {
+            d[c] = Sdot[c * n + i];
+            s[c] = S_half[c * n + i] + hd * d[c];
+        }
+        plastic_return(s, Y[i]);
+        for (int c = 0; c < 5; ++c) S_half[c * n + i] = s[c] + hn * d[c];
+        if (eps2) {
+            double ee = 0.0;
+            for (int a = 0; a < 3; ++a)
+                for (int b = 0; b < 3; ++b) {
+                    const double e = 0.5 * (G[(3 * a + b) * n + i] + G[(3 * b + a) * n + i]);
+                    ee += e * e;
+                }
+            eps2[i] += dt * (0.5 * ee);
+        }
+    } else {  // opening kick from the predicted stress (start of a run)
+        if (fx) return;
+        const double hn = 0.5 * *dtnp;
+        for (int c = 0; c < 5; ++c) S_half[c * n + i] = S_pred[c * n + i] + hn * Sdot[c * n + i];
+    }
+}
+
+sph_status launch_stress(Ctx *ctx, int32_t phase, int64_t n, const double *dt,
+                         const double *dt_next, const double *G, const double *Y,
+                         const double *Gmod, const int32_t *fixed, const sph_params *prm,
+                         double *S_half, double *S_pred, double *Sdot, double *eps2,
+                         hipStream_t s) {
+    if (n == 0) return SPH_OK;
+    hipLaunchKernelGGL(k_stress, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, phase, n, dt,
+                       dt_next, G, Y, Gmod, fixed, prm->rot_sign, S_half, S_pred, Sdot, eps2);
+    SPH_HIP(hipGetLastError());
+    return SPH_OK;
+}
+
+__global__ void k_kick_drift(int32_t phase, int64_t n, const double *__restrict__ dtp,
+                             const double *__restrict__ dtnp, const int32_t *__restrict__ fixed,
+                             double *x, double *y, double *z, double *vx, double *vy,
+                             double *vz, double *u, const double *ax, const double *ay,
+                             const double *az, const double *dudt, double *vpx, double *vpy,
+                             double *vpz, double *up) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const bool fx = fixed && fixed[i];
+    if (phase == SPH_KD_DRIFT) {
+        if (fx) return;
+        const double dt = *dtp;
+        x[i] += dt * vx[i];
+        y[i] += dt * vy[i];
+        z[i] += dt * vz[i];
+    } else if (phase == SPH_KD_PREDICT) {
+        const double hd = fx ? 0.0 : 0.5 * *dtp;
+        if (fx) {
+            vpx[i] = vx[i]; vpy[i] = vy[i]; vpz[i] = vz[i]; up[i] = u[i];
+        } else {
+            vpx[i] = vx[i] + hd * ax[i];
+            vpy[i] = vy[i] + hd * ay[i];
+            vpz[i] = vz[i] + hd * az[i];
+            up[i] = u[i] + hd * dudt[i];
+        }
+    } else if (phase == SPH_KD_KICK) {
+        if (fx) return;
+        const double hd = 0.5 * *dtp, hn = 0.5 * *dtnp;
+        vx[i] = (vx[i] + hd * ax[i]) + hn * ax[i];
+        vy[i] = (vy[i] + hd * ay[i]) + hn * ay[i];
+        vz[i] = (vz[i] + hd * az[i]) + hn * az[i];
+        u[i] = (u[i] + hd * dudt[i]) + hn * dudt[i];
+    } else {  // opening kick only (start of a run)
+        if (fx) return;
+        const double hn = 0.5 * *dtnp;
+        vx[i] += hn * ax[i];
+        vy[i] += hn * ay[i];
+        vz[i] += hn * az[i];
+        u[i] += hn * dudt[i];
+    }
+}
+
+sph_status launch_kick_drift(Ctx *ctx, int32_t phase, int64_t n, const double *dt,
+                             const double *dt_next, const int32_t *fixed, double *x, double *y,
+                             double *z, double *vx, double *vy, double *vz, double *u,
+                             const double *ax, const double *ay, const double *az,
+                             const double *dudt, double *vpx, double *vpy, double *vpz,
+                             double *up, hipStream_t s) {
+    if (n == 0) return SPH_OK;
+    hipLaunchKernelGGL(k_kick_drift, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, phase, n,
+                       dt, dt_next, fixed, x, y, z, vx, vy, vz, u, ax, ay, az, dudt, vpx, vpy,
+                       vpz, up);
+    SPH_HIP(hipGetLastError());
+    return SPH_OK;
+}
+
+// ------------------------------------------------------------ dt minimum
+// Positive doubles order like their bit patterns, so an integer atomicMin on
+// the bits is an exact, order-independent minimum.
+__global__ void k_dt_init(unsigned long long *bits) { *bits = 0x7ff0000000000000ull; }
+
+__global__ void k_dt_reduce(int64_t n, const double *__restrict__ dtc,
+                            const int32_t *__restrict__ fixed, unsigned long long *bits) {
+    unsigned long long best = 0x7ff0000000000000ull;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        if (fixed && fixed[i]) continue;
+        const double d = dtc[i];
+        if (d > 0.0) {
+            const unsigned long long b = (unsigned long long)__double_as_longlong(d);
+            best = b < best ? b : best;
+        }
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        const unsigned long long v = __shfl_xor(best, o);
+        best = v < best ? v : best;
+    }
+    if ((threadIdx.x % kWave) == 0 && best != 0x7ff0000000000000ull) atomicMin(bits, best);
+}
+
+__global__ void k_dt_final(const unsigned long long *bits, double cap, double *out) {
+    double d = __longlong_as_double((long long)*bits);
+    if (cap > 0.0 && !(d <= cap)) d = cap;
+    *out = d;
+}
+
+sph_status launch_dt_min(Ctx *ctx, int64_t n, const double *dtc, const int32_t *fixed,
+                         double cap, double *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_dt_init, dim3(1), dim3(1), 0, s, ctx->dtbits);
+    if (n > 0) {
+        int nb = (int)((n + 255) / 256);
+        nb = nb > 1024 ? 1024 : nb;
+        hipLaunchKernelGGL(k_dt_reduce, dim3(nb), dim3(256), 0, s, n, dtc, fixed, ctx->dtbits);
+    }
+    hipLaunchKernelGGL(k_dt_final, dim3(1), dim3(1), 0, s, ctx->dtbits, cap, out);
+    SPH_HIP(hipGetLastError());
+    return SPH_OK;
+}
+
+__global__ void k_copy_scalar(const double *src, double *dst) { *dst = *src; }
+
+// ------------------------------------------------------------ diagnostics
+constexpr int kDiagBlocks = 256;
+__global__ void k_diag(int64_t n, const double *x, const double *y, const double *z,
+                       const double *vx, const double *vy, const double *vz, const double *m,
+                       const double *ax, const double *ay, const double *az, const double *du,
+                       double *part) {
+    double acc[13] = {0};
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const double mi = m[i];
+        const double X[3] = {x[i], y[i], z[i]}, V[3] = {vx[i], vy[i], vz[i]},
+                     A[3] = {ax[i], ay[i], az[i]};
+        for (int d = 0; d < 3; ++d) acc[d] += mi * A[d];
+        acc[3] += mi * (X[1] * A[2] - X[2] * A[1]);
+        acc[4] += mi * (X[2] * A[0] - X[0] * A[2]);
+        acc[5] += mi * (X[0] * A[1] - X[1] * A[0]);
+        acc[6] += mi * (V[0] * A[0] + V[1] * A[1] + V[2] * A[2] + du[i]);
+        for (int d = 0; d < 3; ++d) acc[7 + d] += mi * V[d];
+        acc[10] += mi * (X[1] * V[2] - X[2] * V[1]);
+        acc[11] += mi * (X[2] * V[0] - X[0] * V[2]);
+        acc[12] += mi * (X[0] * V[1] - X[1] * V[0]);
+    }
+    __shared__ double sh[13][256];
+    for (int k = 0; k < 13; ++k) sh[k][threadIdx.x] = acc[k];
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < (unsigned)o)
+            for (int k = 0; k < 13; ++k) sh[k][threadIdx.x] += sh[k][threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x < 13) part[blockIdx.x * 13 + threadIdx.x] = sh[threadIdx.x][0];
+}
+
+__global__ void k_diag_final(const double *part, double *out) {
+    const int k = threadIdx.x;
+    if (k >= 13) return;
+    double s = 0.0;
+    for (int b = 0; b < kDiagBlocks; ++b) s += part[b * 13 + k];
+    out[k] = s;
+}
+
+sph_status launch_diag(Ctx *ctx, int64_t n, const double *x, const double *y, const double *z,
+                       const double *vx, const double *vy, const double *vz, const double *m,
+                       const double *ax, const double *ay, const double *az,
+                       const double *dudt, double *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_diag, dim3(kDiagBlocks), dim3(256), 0, s, n, x, y, z, vx, vy, vz, m, ax,
+                       ay, az, dudt, ctx->diag);
+    hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(64), 0, s, ctx->diag, out);
+    SPH_HIP(hipGetLastError());
+    return SPH_OK;
+}
+
+__global__ void k_copy_u64(const unsigned long long *src, unsigned long long *dst) { *dst = *src; }
+
+sph_status launch_copy_u64(Ctx *ctx, const unsigned long long *src, unsigned long long *dst,
+                           hipStream_t s) {
+    hipLaunchKernelGGL(k_copy_u64, dim3(1), dim3(1), 0, s, src, dst);
+    SPH_HIP(hipGetLastError());
+    return SPH_OK;
+}
+
+sph_status launch_copy_scalar(Ctx *ctx, const double *src, double *dst, hipStream_t s) {
+    hipLaunchKernelGGL(k_copy_scalar, dim3(1), dim3(1), 0, s, src, dst);
+    SPH_HIP(hipGetLastError());
+    return SPH_OK;
+}
+
+}  // namespace sph

@@ -1,0 +1,230 @@
+// Internal declarations of the gfx950 strength-SPH library (not installed).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <utility>
+#include <vector>
+
+#include "../../include/sph.h"
+
+namespace sph {
+
+// ------------------------------------------------------------------ limits
+constexpr int kWave = 64;
+constexpr int kIdxBits = 26;                       // neighbour entry: j index bits
+constexpr uint32_t kIdxMask = (1u << kIdxBits) - 1;
+constexpr int kCodeShift = kIdxBits;               // 5 bits: stencil cell 0..26
+constexpr uint32_t kDensityBit = 1u << 31;         // j is in the density set of i
+constexpr int kMaxMortonBits = 10;                 // per axis
+constexpr int kNumXcd = 8;                         // MI355X: 8 XCDs, round-robin dispatch
+
+// Flags raised on the device (ctx->flags[...]).
+enum { FLAG_NBR_OVERFLOW = 0, FLAG_CELL_OVERFLOW = 1, FLAG_NONFINITE = 2, FLAG_COUNT = 4 };
+
+// Uniform cell grid of one run.
+struct GridDesc {
+    double ox, oy, oz;      // origin
+    double L, invL;         // cell edge
+    float L32;              // cell edge in float (cell-relative pair arithmetic)
+    int32_t nx, ny, nz;     // cells per axis
+    int32_t bx, by, bz;     // Morton bits per axis
+    int32_t key_off;        // first key of this run in the global cell table
+    int32_t key_count;      // 2^(bx+by+bz)
+    int32_t p0, p1;         // particle range of the run (input order == sorted order by run)
+};
+
+struct BBox {
+    double lo[3], hi[3], hmax;
+};
+
+// Material block as the kernels read it (copy of the ABI struct).
+struct Mat {
+    sph_material m;
+};
+
+struct Ctx {
+    int device = 0;
+    int64_t capacity = 0;
+    int32_t max_nbr = 0;
+    int64_t max_cells = 0;
+    int32_t max_runs = 0;
+    int32_t num_cu = 256;
+    // scratch (device)
+    uint32_t *key = nullptr;        // capacity: cell key, input order
+    int32_t *slot = nullptr;        // capacity: arrival rank within the cell
+    int32_t *perm = nullptr;        // capacity: sorted -> input
+    uint32_t *skey = nullptr;       // capacity: cell key, sorted order
+    int32_t *cell_count = nullptr;  // max_cells + 1
+    int32_t *cell_start = nullptr;  // max_cells + 1
+    double4 *posh64 = nullptr;      // capacity: (x, y, z, h) sorted
+    float4 *posh32 = nullptr;       // capacity: (dx, dy, dz, h) relative to the cell origin
+    uint32_t *cellc = nullptr;      // capacity: packed cell coordinates (10 bits each) + run in bits 30..
+    int16_t *runid = nullptr;       // capacity: run of the sorted particle
+    uint32_t *nbr = nullptr;        // capacity * max_nbr entries
+    int32_t *ncount = nullptr;      // capacity
+    GridDesc *grid = nullptr;       // max_runs
+    BBox *bbox_part = nullptr;      // max_runs * kBBoxBlocks
+    int32_t *run_p = nullptr;       // max_runs + 1 particle offsets (device copy)
+    int32_t *total_keys = nullptr;  // 1
+    int64_t *scan_part = nullptr;   // scan partials (kScanBlocks + 1)
+    int32_t *flags = nullptr;       // FLAG_COUNT
+    unsigned long long *pairs = nullptr;  // accumulated ordered pairs
+    unsigned long long *dtbits = nullptr; // scratch for dt min
+    double *diag = nullptr;         // 16 doubles
+    // pair-pass records
+    void *rec = nullptr;            // capacity * 128 bytes
+    double *gsum = nullptr;         // capacity * 15 (gradient raw sums)
+    Mat *mats = nullptr;            // up to kMaxMaterials
+    // kernel timing (host side): event pairs recorded around pass kernels
+    bool timing = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> t_pending[SPH_T_COUNT];
+    std::vector<hipEvent_t> t_pool;
+    double t_ms[SPH_T_COUNT] = {0};
+    int64_t t_count[SPH_T_COUNT] = {0};
+    // host state
+    int64_t n_built = -1;           // particles of the last build
+    int32_t n_runs_built = 0;
+    char err[512] = {0};
+};
+
+constexpr int kBBoxBlocks = 64;
+constexpr int kScanBlocks = 1024;
+constexpr int kMaxMaterials = 16;
+
+// --------------------------------------------------------- device helpers
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+// Block index remapped so that consecutive logical blocks run on the same
+// XCD (hardware dispatches block b to XCD b % 8): XCD x gets a contiguous
+// range of logical blocks.  Bijective for any grid size.
+__device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t nb) {
+    uint32_t q = nb / kNumXcd, r = nb % kNumXcd;
+    uint32_t x = b % kNumXcd, k = b / kNumXcd;
+    return x * q + (x < r ? x : r) + k;
+}
+
+// Interleave cell coordinates into a Morton key with per-axis bit counts.
+__device__ __forceinline__ uint32_t morton(uint32_t cx, uint32_t cy, uint32_t cz,
+                                           int bx, int by, int bz) {
+    uint32_t key = 0;
+    int pos = 0;
+    int mb = bx > by ? bx : by;
+    mb = mb > bz ? mb : bz;
+    for (int l = 0; l < mb; ++l) {
+        if (l < bx) key |= ((cx >> l) & 1u) << pos++;
+        if (l < by) key |= ((cy >> l) & 1u) << pos++;
+        if (l < bz) key |= ((cz >> l) & 1u) << pos++;
+    }
+    return key;
+}
+
+// Squared separation with no contraction: ((dx*dx + dy*dy) + dz*dz).
+__device__ __forceinline__ double sep2_exact(double xi, double yi, double zi, double xj,
+                                             double yj, double zj) {
+    double dx = __dsub_rn(xi, xj);
+    double dy = __dsub_rn(yi, yj);
+    double dz = __dsub_rn(zi, zj);
+    return __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)), __dmul_rn(dz, dz));
+}
+
+// Sum over groups of L consecutive lanes (L a power of two <= 64); every
+// lane of the group receives the group sum.
+template <int L>
+__device__ __forceinline__ float group_sum(float v) {
+#pragma unroll
+    for (int o = L / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, L);
+    return v;
+}
+template <int L>
+__device__ __forceinline__ double group_sum(double v) {
+#pragma unroll
+    for (int o = L / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, L);
+    return v;
+}
+template <int L>
+__device__ __forceinline__ float group_min(float v) {
+#pragma unroll
+    for (int o = L / 2; o > 0; o >>= 1) v = fminf(v, __shfl_xor(v, o, L));
+    return v;
+}
+template <int L>
+__device__ __forceinline__ double group_max(double v) {
+#pragma unroll
+    for (int o = L / 2; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, L));
+    return v;
+}
+template <int L>
+__device__ __forceinline__ float group_max(float v) {
+#pragma unroll
+    for (int o = L / 2; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, L));
+    return v;
+}
+
+// ------------------------------------------------------------ host helpers
+#define SPH_HIP(expr)                                                          \
+    do {                                                                       \
+        hipError_t _e = (expr);                                                \
+        if (_e != hipSuccess) {                                                \
+            set_error(ctx, "%s: %s", #expr, hipGetErrorString(_e));            \
+            return SPH_EHIP;                                                   \
+        }                                                                      \
+    } while (0)
+
+void set_error(Ctx *ctx, const char *fmt, ...);
+
+// Timing bracket around a pass kernel launch (no-op unless enabled).
+struct TimedLaunch {
+    Ctx *ctx;
+    int which;
+    hipStream_t s;
+    hipEvent_t a = nullptr, b = nullptr;
+    TimedLaunch(Ctx *c, int w, hipStream_t st);
+    ~TimedLaunch();
+};
+
+// Launch helpers implemented in the .hip files.
+sph_status launch_build_cells(Ctx *ctx, int64_t n, const double *x, const double *y,
+                              const double *z, const double *h, int32_t n_runs,
+                              const int64_t *run_start, double cell_min, int32_t *perm_out,
+                              hipStream_t s);
+sph_status launch_reorder(Ctx *ctx, int64_t n, const int32_t *perm, int32_t nf,
+                          const void *const *src, void *const *dst, const int32_t *eb,
+                          const int32_t *rows, hipStream_t s);
+sph_status launch_csr(Ctx *ctx, int64_t *off, int32_t *nbr, uint8_t *dflag, hipStream_t s);
+sph_status launch_density(Ctx *ctx, int64_t n, const double *m, const double *h,
+                          const double *u, const int32_t *mat, int32_t nmat,
+                          const sph_params *prm, sph_precision prec, double *rho,
+                          double *omega, double *P, double *cs, double *T, double *Y,
+                          double *Gmod, hipStream_t s);
+sph_status launch_gradients(Ctx *ctx, int64_t n, const double *vx, const double *vy,
+                            const double *vz, const double *m, const double *h,
+                            const double *rho, const double *omega, const sph_params *prm,
+                            sph_precision prec, double *G, int64_t *n_singular, hipStream_t s);
+sph_status launch_forces(Ctx *ctx, int64_t n, const double *vx, const double *vy,
+                         const double *vz, const double *m, const double *h, const double *rho,
+                         const double *omega, const double *P, const double *cs,
+                         const double *S, const sph_params *prm, sph_precision prec,
+                         double *ax, double *ay, double *az, double *dudt, double *dtc,
+                         hipStream_t s);
+sph_status launch_stress(Ctx *ctx, int32_t phase, int64_t n, const double *dt,
+                         const double *dt_next, const double *G, const double *Y,
+                         const double *Gmod, const int32_t *fixed, const sph_params *prm,
+                         double *S_half, double *S_pred, double *Sdot, double *eps2,
+                         hipStream_t s);
+sph_status launch_kick_drift(Ctx *ctx, int32_t phase, int64_t n, const double *dt,
+                             const double *dt_next, const int32_t *fixed, double *x, double *y,
+                             double *z, double *vx, double *vy, double *vz, double *u,
+                             const double *ax, const double *ay, const double *az,
+                             const double *dudt, double *vpx, double *vpy, double *vpz,
+                             double *up, hipStream_t s);
+sph_status launch_dt_min(Ctx *ctx, int64_t n, const double *dtc, const int32_t *fixed,
+                         double cap, double *out, hipStream_t s);
+sph_status launch_diag(Ctx *ctx, int64_t n, const double *x, const double *y, const double *z,
+                       const double *vx, const double *vy, const double *vz, const double *m,
+                       const double *ax, const double *ay, const double *az,
+                       const double *dudt, double *out, hipStream_t s);
+sph_status launch_fill_i32(Ctx *ctx, int32_t *p, int32_t v, int64_t n, hipStream_t s);
+
+}  // namespace sph
