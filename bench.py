@@ -30,12 +30,14 @@ PEAK_FP32_VALU = 157.3e12   # MI355X FP32 vector, published
 PEAK_FP64_VALU = 78.6e12    # MI355X FP64 vector, published
 PEAK_HBM = 8.0e12
 
-# Algorithmic flops per ordered pair of the forces pass (FMA = 2, sqrt = 1),
-# counted from the pair term of the kernel without the artificial-viscosity
-# branch: separation (9 in float incl. the cell shift, 3 in double), r^2 (5),
-# sqrt (1), kernel factors t_i^3, t_j^3 (8), (K A)_i x and (K A)_j x (30),
-# momentum sum (15), v_ij (3), energy term (8), v_ij . x_ij (5).
-FLOPS_FORCES_PAIR = {1: 84, 0: 78}
+# Algorithmic flops per ordered pair of the fused gradient + force sweep of
+# the step (FMA = 2, sqrt = 1), counted from the pair term without the
+# artificial-viscosity branch: separation (9 in float incl. the cell shift,
+# 3 in double), r^2 (5), sqrt (1), kernel factors t_i^3, t_j^3 (8), v_ij (3);
+# force part: (K A)_i x and (K A)_j x (30), momentum sum (15), energy term
+# (8), v_ij . x_ij (5); gradient part: pair weight (5), w x_ij (3),
+# C^-1 sums (12), F sums (18).
+FLOPS_PAIR = {1: 122, 0: 116}
 
 
 def log(*a):
@@ -89,7 +91,7 @@ def run_steps(w, prec, steps, warmup, use_graph, timing=True):
     k_steps = (steps // 2) * 2 if use_graph else steps
     kern = {}
     if timing and not use_graph:
-        for name, kid in (("build", 0), ("density", 1), ("gradients", 2), ("forces", 3)):
+        for name, kid in (("build", 0), ("density", 1), ("grad_forces", 3)):
             kern[name] = sph.sph_timing_read(ctx, kid)
         sph.sph_timing(ctx, False)
     out = dict(seconds=t1 - t0, steps=k_steps, pairs=p1 - p0, kernels=kern, n=n)
@@ -159,13 +161,13 @@ def main():
     ms_step = 1e3 * r32["seconds"] / r32["steps"]
     roof = None
     if r32["kernels"]:
-        ms, cnt = r32["kernels"]["forces"]
+        ms, cnt = r32["kernels"]["grad_forces"]
         avg_s = ms / cnt * 1e-3
         pairs_per_launch = r32["pairs"] / r32["steps"]
-        achieved = FLOPS_FORCES_PAIR[1] * pairs_per_launch / avg_s
+        achieved = FLOPS_PAIR[1] * pairs_per_launch / avg_s
         roof = dict(bound="alu", achieved=achieved / 1e12, peak=PEAK_FP32_VALU / 1e12,
                     unit="TFLOP/s", frac=achieved / PEAK_FP32_VALU, traffic=None,
-                    kernel="k_forces<8,fp32>", avg_launch_us=avg_s * 1e6,
+                    kernel="k_grad_forces<8,fp32>", avg_launch_us=avg_s * 1e6,
                     kernels_us={k: (v[0] / v[1] * 1e3 if v[1] else None)
                                 for k, v in r32["kernels"].items()})
     cpu = None

@@ -300,6 +300,32 @@ sph_status sph_init(sph_ctx *ctx, sph_state *st, const sph_material *mats, int32
 sph_status sph_step(sph_ctx *ctx, sph_state *st, const sph_material *mats, int32_t n_materials,
                     const sph_params *prm, sph_precision prec, sph_stream stream);
 
+/* ------------------------------------------------- Q_RD* proposal network */
+
+/* Multilayer perceptron 4 -> 64 -> 64 -> 1 (tanh, tanh, logistic) used to
+ * propose impact speeds when bracketing the catastrophic disruption threshold
+ * (the paper's Q_RD* bisection of sec. 3 is the fallback).  Float32 device
+ * arrays; parameters in one flat array of sph_mlp_num_params() = 4545 values
+ * laid out W1[64][4] b1[64] W2[64][64] b2[64] W3[64] b3.  These are for the
+ * batched scan driver, outside the per-step hot path. */
+int32_t sph_mlp_num_params(void);
+
+/* out[s] = network(X[s][0..3]) for s < batch; h1, h2 (batch x 64 each) keep
+ * the hidden activations for sph_mlp_backward (may be NULL otherwise). */
+sph_status sph_mlp_forward(int32_t batch, const float *X, const float *params, float *out,
+                           float *h1, float *h2, sph_stream stream);
+
+/* Gradient of (1/batch) sum_s (out_s - Y_s)^2 with respect to the parameters
+ * into grads (4545), from a forward pass with h1, h2 kept.  work: device
+ * scratch of batch * 129 floats.  Deterministic (fixed summation order). */
+sph_status sph_mlp_backward(int32_t batch, const float *X, const float *Y, const float *params,
+                            const float *out, const float *h1, const float *h2, float *work,
+                            float *grads, sph_stream stream);
+
+/* One bias-corrected Adam step (step >= 1) on params with moments m, v. */
+sph_status sph_mlp_adam(float *params, const float *grads, float *m, float *v, int32_t step,
+                        float lr, float beta1, float beta2, float eps, sph_stream stream);
+
 /* ------------------------------------------------------ kernel timing */
 
 /* Pass kernels whose launches can be timed with HIP events. */

@@ -24,7 +24,6 @@ void set_error(Ctx *ctx, const char *fmt, ...) {
     va_end(ap);
 }
 
-sph_status launch_copy_scalar(Ctx *ctx, const double *src, double *dst, hipStream_t s);
 sph_status launch_copy_u64(Ctx *ctx, const unsigned long long *src, unsigned long long *dst,
                            hipStream_t s);
 
@@ -122,6 +121,7 @@ sph_status sph_create(sph_ctx **out, int64_t capacity, int32_t max_neighbors, in
         {(void **)&ctx->key, cap * 4},
         {(void **)&ctx->slot, cap * 4},
         {(void **)&ctx->perm, cap * 4},
+        {(void **)&ctx->ptmp, cap * 4},
         {(void **)&ctx->skey, cap * 4},
         {(void **)&ctx->cell_count, ((size_t)max_cells + 1) * 4},
         {(void **)&ctx->cell_start, ((size_t)max_cells + 1) * 4},
@@ -140,7 +140,9 @@ sph_status sph_create(sph_ctx **out, int64_t capacity, int32_t max_neighbors, in
         {(void **)&ctx->pairs, 8},
         {(void **)&ctx->dtbits, 8},
         {(void **)&ctx->diag, 256 * 13 * 8},
-        {(void **)&ctx->rec, cap * 128},
+        {(void **)&ctx->rec_d, cap * 32},
+        {(void **)&ctx->rec_g, cap * 96},
+        {(void **)&ctx->rec_f, cap * 160},
         {(void **)&ctx->gsum, cap * 15 * 8},
     };
     for (auto &a : allocs) {
@@ -150,9 +152,13 @@ sph_status sph_create(sph_ctx **out, int64_t capacity, int32_t max_neighbors, in
         }
     }
     ctx->mats = new Mat[kMaxMaterials];
+    const unsigned long long inf_bits = 0x7ff0000000000000ull;
     if (hipMemset(ctx->flags, 0, FLAG_COUNT * 4) != hipSuccess ||
         hipMemset(ctx->pairs, 0, 8) != hipSuccess ||
-        hipMemset(ctx->ncount, 0, cap * 4) != hipSuccess) {
+        hipMemset(ctx->ncount, 0, cap * 4) != hipSuccess ||
+        hipMemset(ctx->total_keys, 0, 4) != hipSuccess ||
+        hipMemset(ctx->cell_count, 0, ((size_t)max_cells + 1) * 4) != hipSuccess ||
+        hipMemcpy(ctx->dtbits, &inf_bits, 8, hipMemcpyHostToDevice) != hipSuccess) {
         sph_destroy(h);
         return SPH_EHIP;
     }
@@ -163,11 +169,11 @@ sph_status sph_create(sph_ctx **out, int64_t capacity, int32_t max_neighbors, in
 sph_status sph_destroy(sph_ctx *h) {
     if (!h) return SPH_EINVAL;
     Ctx *ctx = &h->c;
-    void *ptrs[] = {ctx->key,  ctx->slot,      ctx->perm,   ctx->skey,    ctx->cell_count,
+    void *ptrs[] = {ctx->ptmp, ctx->key,  ctx->slot,      ctx->perm,   ctx->skey,    ctx->cell_count,
                     ctx->cell_start, ctx->posh64, ctx->posh32, ctx->cellc, ctx->runid,
                     ctx->nbr,  ctx->ncount,    ctx->grid,   ctx->bbox_part, ctx->run_p,
                     ctx->total_keys, ctx->scan_part, ctx->flags, ctx->pairs, ctx->dtbits,
-                    ctx->diag, ctx->rec,       ctx->gsum};
+                    ctx->diag, ctx->rec_d, ctx->rec_g, ctx->rec_f, ctx->gsum};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     for (int w = 0; w < SPH_T_COUNT; ++w) {
@@ -249,7 +255,8 @@ sph_status sph_build_cells(sph_ctx *h, int64_t n, const double *x, const double 
     REQUIRE(cell_min >= 0.0, SPH_EINVAL, "cell_min < 0");
     sph_status st = upload_runs(h, n, n_runs, run_start, S(stream));
     if (st != SPH_OK) return st;
-    return launch_build_cells(&h->c, n, x, y, z, hh, n_runs, run_start, cell_min, perm_out,
+    return launch_build_cells(&h->c, n, const_cast<double *>(x), const_cast<double *>(y),
+                              const_cast<double *>(z), hh, n_runs, cell_min, perm_out, nullptr,
                               S(stream));
 }
 
@@ -456,67 +463,82 @@ static sph_status check_state(sph_ctx *h, const sph_state *st) {
     return SPH_OK;
 }
 
-// Derivatives at the current (sorted) state: density, EOS, stress predict +
-// rescale, gradients, stress rate, forces, CFL minimum into *dt_next.
-static sph_status eval(sph_ctx *h, const sph_state *st, const Rows &R, int32_t nmat,
-                       const sph_params *prm, sph_precision prec, hipStream_t s) {
-    const int64_t n = st->n, nc = st->n_cap;
-    Ctx *ctx = &h->c;
-    (void)nc;
-    sph_status e;
-    const int32_t *fixed = R.i[SPH_FIXED];
-    if ((e = launch_density(ctx, n, R.f[SPH_M], R.f[SPH_H], R.w[SPH_W_UP], R.i[SPH_MAT], nmat,
-                            prm, prec, R.w[SPH_W_RHO], R.w[SPH_W_OMEGA], R.w[SPH_W_P],
-                            R.w[SPH_W_CS], R.w[SPH_W_T], R.w[SPH_W_Y], R.w[SPH_W_GMOD], s)))
-        return e;
-    if ((e = launch_stress(ctx, SPH_STRESS_PREDICT, n, st->dt, st->dt_next, nullptr,
-                           R.w[SPH_W_Y], nullptr, fixed, prm, R.f[SPH_S], R.w[SPH_W_SP],
-                           R.f[SPH_SDOT], nullptr, s)))
-        return e;
-    if ((e = launch_gradients(ctx, n, R.w[SPH_W_VP], R.w[SPH_W_VP + 1], R.w[SPH_W_VP + 2],
-                              R.f[SPH_M], R.f[SPH_H], R.w[SPH_W_RHO], R.w[SPH_W_OMEGA], prm, prec,
-                              R.w[SPH_W_G], st->n_singular, s)))
-        return e;
-    if ((e = launch_stress(ctx, SPH_STRESS_RATE, n, st->dt, st->dt_next, R.w[SPH_W_G],
-                           R.w[SPH_W_Y], R.w[SPH_W_GMOD], fixed, prm, R.f[SPH_S], R.w[SPH_W_SP],
-                           R.f[SPH_SDOT], nullptr, s)))
-        return e;
-    if ((e = launch_forces(ctx, n, R.w[SPH_W_VP], R.w[SPH_W_VP + 1], R.w[SPH_W_VP + 2],
-                           R.f[SPH_M], R.f[SPH_H], R.w[SPH_W_RHO], R.w[SPH_W_OMEGA], R.w[SPH_W_P],
-                           R.w[SPH_W_CS], R.w[SPH_W_SP], prm, prec, R.f[SPH_AX], R.f[SPH_AY],
-                           R.f[SPH_AZ], R.f[SPH_DUDT], R.w[SPH_W_DT], s)))
-        return e;
-    return launch_dt_min(ctx, n, R.w[SPH_W_DT], fixed, st->dt_max, st->dt_next, s);
-}
-
-static sph_status sort_state(sph_ctx *h, sph_state *st, hipStream_t s) {
+// Neighbour search (with the drift fused in when `drift`), then the
+// reorder of every state row into the other buffer with the predictor of v
+// and u fused in (predict = 0 at the start of a run: predicted = current).
+static sph_status search_and_sort(sph_ctx *h, sph_state *st, sph_precision prec, bool drift,
+                                  int32_t predict, hipStream_t s) {
     Ctx *ctx = &h->c;
     const int64_t n = st->n;
     const int cur = st->cur, alt = 1 - cur;
     Rows A = rows_of(st, cur), B = rows_of(st, alt);
-    int32_t *perm = (int32_t *)A.w[SPH_W_PERM];
-    sph_status e = sph_build_cells(h, n, A.f[SPH_X], A.f[SPH_Y], A.f[SPH_Z], A.f[SPH_H],
-                                   st->run_start ? st->n_runs : 1, st->run_start, st->cell_min,
-                                   perm, (sph_stream)s);
+    int32_t *perm = (int32_t *)B.w[SPH_W_PERM];
+    const int32_t nr = st->run_start ? st->n_runs : 1;
+    REQUIRE(nr >= 1 && nr <= ctx->max_runs, SPH_ECAPACITY, "n_runs out of range");
+    sph_status e = upload_runs(h, n, nr, st->run_start, s);
     if (e) return e;
-    const void *src[SPH_NF64 + SPH_NI32];
-    void *dst[SPH_NF64 + SPH_NI32];
-    int32_t eb[SPH_NF64 + SPH_NI32];
-    int nf = 0;
-    for (int k = 0; k < SPH_NF64; ++k, ++nf) {
-        src[nf] = A.f[k];
-        dst[nf] = B.f[k];
-        eb[nf] = 8;
+    BuildExtras ex;
+    if (drift) {
+        ex.dt = st->dt;
+        ex.vx = A.f[SPH_VX];
+        ex.vy = A.f[SPH_VY];
+        ex.vz = A.f[SPH_VZ];
+        ex.fixed = A.i[SPH_FIXED];
     }
-    for (int k = 0; k < SPH_NI32; ++k, ++nf) {
-        src[nf] = A.i[k];
-        dst[nf] = B.i[k];
-        eb[nf] = 4;
+    ex.m = A.f[SPH_M];  // the gather reads the unsorted state: records in sorted order
+    ex.f32 = prec == SPH_FP32_CELLREL;
+    if ((e = launch_build_cells(ctx, n, A.f[SPH_X], A.f[SPH_Y], A.f[SPH_Z], A.f[SPH_H], nr,
+                                st->cell_min, perm, &ex, s)))
+        return e;
+    StepRows r;
+    for (int k = 0; k < SPH_NF64; ++k) {
+        r.f_src[k] = A.f[k];
+        r.f_dst[k] = B.f[k];
     }
-    e = launch_reorder(ctx, n, perm, nf, src, dst, eb, nullptr, s);
-    if (e) return e;
+    for (int k = 0; k < SPH_NI32; ++k) {
+        r.i_src[k] = A.i[k];
+        r.i_dst[k] = B.i[k];
+    }
+    if ((e = launch_step_reorder(ctx, n, perm, r, st->dt, predict, B.w[SPH_W_VP],
+                                 B.w[SPH_W_VP + 1], B.w[SPH_W_VP + 2], B.w[SPH_W_UP], s)))
+        return e;
     st->cur = alt;
     return SPH_OK;
+}
+
+// Derivatives at the sorted state: density pass, per-particle state (EOS,
+// yield, stress predictor + rescaling, pass record), one sweep for the
+// gradient sums and the forces, gradient epilogue + stress rate, CFL minimum
+// into *dt_next.
+static sph_status eval(sph_ctx *h, const sph_state *st, const Rows &R, int32_t nmat,
+                       const sph_params *prm, sph_precision prec, int32_t predict,
+                       bool accumulate_eps2, hipStream_t s) {
+    const int64_t n = st->n;
+    Ctx *ctx = &h->c;
+    sph_status e;
+    const int32_t *fixed = R.i[SPH_FIXED];
+    if ((e = launch_density_pairs(ctx, n, prm, prec, R.w[SPH_W_RHO], R.w[SPH_W_OMEGA], s)))
+        return e;
+    if ((e = launch_step_state(ctx, n, prec, R.w[SPH_W_RHO], R.w[SPH_W_OMEGA], R.w[SPH_W_UP],
+                               R.w[SPH_W_VP], R.w[SPH_W_VP + 1], R.w[SPH_W_VP + 2], R.f[SPH_M],
+                               R.i[SPH_MAT], nmat, fixed, st->dt, predict, R.f[SPH_S],
+                               R.f[SPH_SDOT], R.w[SPH_W_P], R.w[SPH_W_CS], R.w[SPH_W_T],
+                               R.w[SPH_W_Y], R.w[SPH_W_GMOD], R.w[SPH_W_SP], s)))
+        return e;
+    if ((e = launch_grad_force_pairs(ctx, n, prm, prec, R.f[SPH_AX], R.f[SPH_AY], R.f[SPH_AZ],
+                                     R.f[SPH_DUDT], R.w[SPH_W_DT], s)))
+        return e;
+    if ((e = launch_step_grad_rate(ctx, n, prm, R.w[SPH_W_SP], R.w[SPH_W_GMOD], fixed, st->dt,
+                                   R.w[SPH_W_G], R.f[SPH_SDOT],
+                                   accumulate_eps2 ? R.f[SPH_EPS2] : nullptr, st->n_singular, s)))
+        return e;
+    return launch_dt_min(ctx, n, R.w[SPH_W_DT], fixed, st->dt_max, st->dt_next, s);
+}
+
+static void swap_dt(sph_state *st) {
+    double *t = st->dt;
+    st->dt = st->dt_next;
+    st->dt_next = t;
 }
 
 sph_status sph_init(sph_ctx *h, sph_state *st, const sph_material *mats, int32_t n_materials,
@@ -525,30 +547,20 @@ sph_status sph_init(sph_ctx *h, sph_state *st, const sph_material *mats, int32_t
     sph_status e = check_state(h, st);
     if (e) return e;
     REQUIRE(prm, SPH_EINVAL, "null params");
+    REQUIRE(prec == SPH_FP64 || prec == SPH_FP32_CELLREL, SPH_EINVAL, "bad precision");
     if ((e = set_mats(h, mats, n_materials))) return e;
     hipStream_t s = S(stream);
     Ctx *ctx = &h->c;
     const int64_t n = st->n;
-    if ((e = sort_state(h, st, s))) return e;
+    if ((e = search_and_sort(h, st, prec, false, 0, s))) return e;
     Rows R = rows_of(st, st->cur);
-    const int32_t *fixed = R.i[SPH_FIXED];
-    SPH_HIP(hipMemsetAsync(st->dt, 0, 8, s));
     // predicted values are the current ones: v, u as they are, S rescaled
-    // (PREDICT with the derivative rows cleared)
-    for (int k = 0; k < 5; ++k)
-        SPH_HIP(hipMemsetAsync(R.f[SPH_SDOT + k], 0, n * 8, s));
-    for (int k = 0; k < 3; ++k)
-        SPH_HIP(hipMemcpyAsync(R.w[SPH_W_VP + k], R.f[SPH_VX + k], n * 8, hipMemcpyDeviceToDevice, s));
-    SPH_HIP(hipMemcpyAsync(R.w[SPH_W_UP], R.f[SPH_U], n * 8, hipMemcpyDeviceToDevice, s));
-    if ((e = eval(h, st, R, n_materials, prm, prec, s))) return e;
-    if ((e = launch_copy_scalar(ctx, st->dt_next, st->dt, s))) return e;
-    if ((e = launch_kick_drift(ctx, SPH_KD_OPEN, n, st->dt, st->dt, fixed, R.f[SPH_X], R.f[SPH_Y],
-                               R.f[SPH_Z], R.f[SPH_VX], R.f[SPH_VY], R.f[SPH_VZ], R.f[SPH_U],
-                               R.f[SPH_AX], R.f[SPH_AY], R.f[SPH_AZ], R.f[SPH_DUDT], nullptr,
-                               nullptr, nullptr, nullptr, s)))
-        return e;
-    return launch_stress(ctx, SPH_STRESS_OPEN, n, st->dt, st->dt, nullptr, nullptr, nullptr,
-                         fixed, prm, R.f[SPH_S], R.w[SPH_W_SP], R.f[SPH_SDOT], nullptr, s);
+    if ((e = eval(h, st, R, n_materials, prm, prec, 0, false, s))) return e;
+    swap_dt(st);
+    return launch_step_kick(ctx, n, 1, st->dt, st->dt, R.i[SPH_FIXED], R.f[SPH_VX], R.f[SPH_VY],
+                            R.f[SPH_VZ], R.f[SPH_U], R.f[SPH_AX], R.f[SPH_AY], R.f[SPH_AZ],
+                            R.f[SPH_DUDT], R.f[SPH_S], R.w[SPH_W_SP], R.f[SPH_SDOT],
+                            R.w[SPH_W_Y], s);
 }
 
 sph_status sph_step(sph_ctx *h, sph_state *st, const sph_material *mats, int32_t n_materials,
@@ -557,38 +569,21 @@ sph_status sph_step(sph_ctx *h, sph_state *st, const sph_material *mats, int32_t
     sph_status e = check_state(h, st);
     if (e) return e;
     REQUIRE(prm, SPH_EINVAL, "null params");
+    REQUIRE(prec == SPH_FP64 || prec == SPH_FP32_CELLREL, SPH_EINVAL, "bad precision");
     if ((e = set_mats(h, mats, n_materials))) return e;
     hipStream_t s = S(stream);
     Ctx *ctx = &h->c;
     const int64_t n = st->n;
-    {
-        Rows R = rows_of(st, st->cur);
-        if ((e = launch_kick_drift(ctx, SPH_KD_DRIFT, n, st->dt, st->dt, R.i[SPH_FIXED],
-                                   R.f[SPH_X], R.f[SPH_Y], R.f[SPH_Z], R.f[SPH_VX], R.f[SPH_VY],
-                                   R.f[SPH_VZ], nullptr, nullptr, nullptr, nullptr, nullptr,
-                                   nullptr, nullptr, nullptr, nullptr, s)))
-            return e;
-    }
-    if ((e = sort_state(h, st, s))) return e;
+    if ((e = search_and_sort(h, st, prec, true, 1, s))) return e;
     Rows R = rows_of(st, st->cur);
-    const int32_t *fixed = R.i[SPH_FIXED];
-    if ((e = launch_kick_drift(ctx, SPH_KD_PREDICT, n, st->dt, st->dt, fixed, nullptr, nullptr,
-                               nullptr, R.f[SPH_VX], R.f[SPH_VY], R.f[SPH_VZ], R.f[SPH_U],
-                               R.f[SPH_AX], R.f[SPH_AY], R.f[SPH_AZ], R.f[SPH_DUDT],
-                               R.w[SPH_W_VP], R.w[SPH_W_VP + 1], R.w[SPH_W_VP + 2], R.w[SPH_W_UP],
-                               s)))
+    if ((e = eval(h, st, R, n_materials, prm, prec, 1, true, s))) return e;
+    if ((e = launch_step_kick(ctx, n, 0, st->dt, st->dt_next, R.i[SPH_FIXED], R.f[SPH_VX],
+                              R.f[SPH_VY], R.f[SPH_VZ], R.f[SPH_U], R.f[SPH_AX], R.f[SPH_AY],
+                              R.f[SPH_AZ], R.f[SPH_DUDT], R.f[SPH_S], R.w[SPH_W_SP],
+                              R.f[SPH_SDOT], R.w[SPH_W_Y], s)))
         return e;
-    if ((e = eval(h, st, R, n_materials, prm, prec, s))) return e;
-    if ((e = launch_kick_drift(ctx, SPH_KD_KICK, n, st->dt, st->dt_next, fixed, nullptr, nullptr,
-                               nullptr, R.f[SPH_VX], R.f[SPH_VY], R.f[SPH_VZ], R.f[SPH_U],
-                               R.f[SPH_AX], R.f[SPH_AY], R.f[SPH_AZ], R.f[SPH_DUDT], nullptr,
-                               nullptr, nullptr, nullptr, s)))
-        return e;
-    if ((e = launch_stress(ctx, SPH_STRESS_KICK, n, st->dt, st->dt_next, R.w[SPH_W_G],
-                           R.w[SPH_W_Y], R.w[SPH_W_GMOD], fixed, prm, R.f[SPH_S], R.w[SPH_W_SP],
-                           R.f[SPH_SDOT], R.f[SPH_EPS2], s)))
-        return e;
-    return launch_copy_scalar(ctx, st->dt_next, st->dt, s);
+    swap_dt(st);
+    return SPH_OK;
 }
 
 sph_status sph_timing(sph_ctx *h, int32_t enable) {

@@ -19,14 +19,6 @@ __global__ void k_fill_i32(int32_t *p, int32_t v, int64_t n) {
         p[k] = v;
 }
 
-// Zero the first *len entries of p (len read on the device).
-__global__ void k_zero_dev_len(int32_t *p, const int32_t *len) {
-    int64_t n = *len;
-    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n;
-         k += (int64_t)gridDim.x * blockDim.x)
-        p[k] = 0;
-}
-
 sph_status launch_fill_i32(Ctx *ctx, int32_t *p, int32_t v, int64_t n, hipStream_t s) {
     if (n <= 0) return SPH_OK;
     int blocks = (int)((n + 255) / 256);
@@ -39,77 +31,70 @@ sph_status launch_fill_i32(Ctx *ctx, int32_t *p, int32_t v, int64_t n, hipStream
 // ------------------------------------------------ exclusive scan (device length)
 // out[k] = sum_{l<k} in[l] for k <= len (out[len] = total).  Three phases:
 // per-block sums over contiguous chunks, scan of the block sums, rescan.
-template <typename Tin, typename Tout>
-__global__ void k_scan_reduce(const Tin *in, const int64_t *len_dev, const int32_t *len32_dev,
-                              int64_t len_host, int64_t *part) {
-    int64_t len = len_dev ? *len_dev : (len32_dev ? (int64_t)*len32_dev : len_host);
-    int64_t chunk = (len + gridDim.x - 1) / gridDim.x;
-    int64_t a = blockIdx.x * chunk, b = a + chunk < len ? a + chunk : len;
+template <typename Tin>
+__global__ void k_scan_reduce(const Tin *in, const int32_t *len32_dev, int64_t len_host,
+                              int64_t *part) {
+    const int64_t len = len32_dev ? (int64_t)*len32_dev : len_host;
+    const int64_t chunk = (len + gridDim.x - 1) / gridDim.x;
+    const int64_t a = blockIdx.x * chunk, b = a + chunk < len ? a + chunk : len;
     int64_t s = 0;
     for (int64_t k = a + threadIdx.x; k < b; k += blockDim.x) s += (int64_t)in[k];
     __shared__ int64_t red[256];
     red[threadIdx.x] = s;
     __syncthreads();
     for (int o = 128; o > 0; o >>= 1) {
-        if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        if (threadIdx.x < (unsigned)o) red[threadIdx.x] += red[threadIdx.x + o];
         __syncthreads();
     }
     if (threadIdx.x == 0) part[blockIdx.x] = red[0];
 }
 
-__global__ void k_scan_top(int64_t *part, int nb) {
-    // single block of 1024 threads, nb <= 1024: exclusive scan in place
-    __shared__ int64_t sh[1024];
-    int t = threadIdx.x;
-    int64_t v = t < nb ? part[t] : 0;
-    sh[t] = v;
+// Each block adds the totals of the blocks before it (a short reduction of
+// at most gridDim.x values, no inter-block signalling), then scans its chunk.
+template <typename Tin, typename Tout>
+__global__ void k_scan_final(const Tin *in, Tout *out, const int32_t *len32_dev, int64_t len_host,
+                             const int64_t *part) {
+    const int64_t len = len32_dev ? (int64_t)*len32_dev : len_host;
+    const int64_t chunk = (len + gridDim.x - 1) / gridDim.x;
+    const int64_t a = blockIdx.x * chunk, b = a + chunk < len ? a + chunk : len;
+    __shared__ int64_t sh[256];
+    int64_t pre = 0;
+    for (unsigned q = threadIdx.x; q < blockIdx.x; q += blockDim.x) pre += part[q];
+    sh[threadIdx.x] = pre;
     __syncthreads();
-    for (int o = 1; o < 1024; o <<= 1) {
-        int64_t add = t >= o ? sh[t - o] : 0;
-        __syncthreads();
-        sh[t] += add;
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < (unsigned)o) sh[threadIdx.x] += sh[threadIdx.x + o];
         __syncthreads();
     }
-    if (t < nb) part[t] = sh[t] - v;
-    if (t == nb - 1) part[nb] = sh[t];
-}
-
-template <typename Tin, typename Tout>
-__global__ void k_scan_final(const Tin *in, Tout *out, const int64_t *len_dev,
-                             const int32_t *len32_dev, int64_t len_host, const int64_t *part) {
-    int64_t len = len_dev ? *len_dev : (len32_dev ? (int64_t)*len32_dev : len_host);
-    int64_t chunk = (len + gridDim.x - 1) / gridDim.x;
-    int64_t a = blockIdx.x * chunk, b = a + chunk < len ? a + chunk : len;
-    __shared__ int64_t sh[256];
-    int64_t carry = part[blockIdx.x];
+    int64_t carry = sh[0];
+    __syncthreads();
     for (int64_t base = a; base < b; base += blockDim.x) {
-        int64_t k = base + threadIdx.x;
-        int64_t v = k < b ? (int64_t)in[k] : 0;
+        const int64_t k = base + threadIdx.x;
+        const int64_t v = k < b ? (int64_t)in[k] : 0;
         sh[threadIdx.x] = v;
         __syncthreads();
         for (int o = 1; o < 256; o <<= 1) {
-            int64_t add = threadIdx.x >= (unsigned)o ? sh[threadIdx.x - o] : 0;
+            const int64_t add = threadIdx.x >= (unsigned)o ? sh[threadIdx.x - o] : 0;
             __syncthreads();
             sh[threadIdx.x] += add;
             __syncthreads();
         }
         if (k < b) out[k] = (Tout)(carry + sh[threadIdx.x] - v);
-        int64_t tot = sh[255];
+        const int64_t tot = sh[255];
         __syncthreads();
         carry += tot;
     }
-    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) out[len] = (Tout)part[gridDim.x];
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) out[len] = (Tout)carry;
 }
 
 template <typename Tin, typename Tout>
 static sph_status scan(Ctx *ctx, const Tin *in, Tout *out, const int32_t *len32_dev,
                        int64_t len_host, hipStream_t s) {
     const int nb = kScanBlocks;
-    hipLaunchKernelGGL((k_scan_reduce<Tin, Tout>), dim3(nb), dim3(256), 0, s, in,
-                       (const int64_t *)nullptr, len32_dev, len_host, ctx->scan_part);
-    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, ctx->scan_part, nb);
-    hipLaunchKernelGGL((k_scan_final<Tin, Tout>), dim3(nb), dim3(256), 0, s, in, out,
-                       (const int64_t *)nullptr, len32_dev, len_host, ctx->scan_part);
+    hipLaunchKernelGGL((k_scan_reduce<Tin>), dim3(nb), dim3(256), 0, s, in, len32_dev, len_host,
+                       ctx->scan_part);
+    hipLaunchKernelGGL((k_scan_final<Tin, Tout>), dim3(nb), dim3(256), 0, s, in, out, len32_dev,
+                       len_host, ctx->scan_part);
     SPH_HIP(hipGetLastError());
     return SPH_OK;
 }
@@ -124,15 +109,36 @@ __device__ __forceinline__ int run_of(const int32_t *run_p, int nr, int64_t k) {
     return lo;
 }
 
-__global__ void k_bbox(const double *x, const double *y, const double *z, const double *h,
-                       const int32_t *run_p, BBox *part) {
-    int r = blockIdx.y;
-    int64_t a = run_p[r], b = run_p[r + 1];
+// Per-run bounding box and largest h (partials per block).  Also: optional
+// drift x += dt v of the non-fixed particles before binning, and zeroing of
+// the cell-count entries the previous build used (the only non-zero ones).
+__global__ void k_bbox(double *x, double *y, double *z, const double *h, const int32_t *run_p,
+                       BBox *part, int32_t *cell_count, const int32_t *total_keys_prev,
+                       const double *dtp, const double *vx, const double *vy, const double *vz,
+                       const int32_t *fixed) {
+    {
+        const int64_t nz = *total_keys_prev;
+        const int64_t nthr = (int64_t)gridDim.x * gridDim.y * blockDim.x;
+        for (int64_t k = ((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * blockDim.x + threadIdx.x;
+             k < nz; k += nthr)
+            cell_count[k] = 0;
+    }
+    const int r = blockIdx.y;
+    const int64_t a = run_p[r], b = run_p[r + 1];
+    const double dt = dtp ? *dtp : 0.0;
     double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
     double hm = 0.0;
     for (int64_t k = a + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < b;
          k += (int64_t)gridDim.x * blockDim.x) {
         double v[3] = {x[k], y[k], z[k]};
+        if (dtp && !(fixed && fixed[k])) {
+            v[0] += dt * vx[k];
+            v[1] += dt * vy[k];
+            v[2] += dt * vz[k];
+            x[k] = v[0];
+            y[k] = v[1];
+            z[k] = v[2];
+        }
         for (int d = 0; d < 3; ++d) {
             lo[d] = fmin(lo[d], v[d]);
             hi[d] = fmax(hi[d], v[d]);
@@ -173,23 +179,48 @@ __device__ static int bits_for(int n) {
     return b;
 }
 
-// One thread: per-run grids that fit the cell table.
-__global__ void k_grid(const BBox *part, const int32_t *run_p, int nr, double cell_min,
+// Per-run grids that fit the cell table.  The block first reduces each
+// run's bounding-box partials in parallel (into the first partial of the
+// run), then one thread sizes the grids.
+__global__ void k_grid(BBox *part, const int32_t *run_p, int nr, double cell_min,
                        int64_t max_cells, GridDesc *grid, int32_t *total_keys, int32_t *flags) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    __shared__ double sh[7][256];
+    for (int r = 0; r < nr; ++r) {
+        double v[7] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY, 0.0};
+        for (int b = threadIdx.x; b < kBBoxBlocks; b += blockDim.x) {
+            const BBox o = part[r * kBBoxBlocks + b];
+            for (int d = 0; d < 3; ++d) {
+                v[d] = fmin(v[d], o.lo[d]);
+                v[3 + d] = fmax(v[3 + d], o.hi[d]);
+            }
+            v[6] = fmax(v[6], o.hmax);
+        }
+        for (int d = 0; d < 7; ++d) sh[d][threadIdx.x] = v[d];
+        __syncthreads();
+        for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+            if (threadIdx.x < (unsigned)o) {
+                for (int d = 0; d < 3; ++d) sh[d][threadIdx.x] = fmin(sh[d][threadIdx.x], sh[d][threadIdx.x + o]);
+                for (int d = 3; d < 7; ++d) sh[d][threadIdx.x] = fmax(sh[d][threadIdx.x], sh[d][threadIdx.x + o]);
+            }
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) {
+            BBox bb;
+            for (int d = 0; d < 3; ++d) {
+                bb.lo[d] = sh[d][0];
+                bb.hi[d] = sh[3 + d][0];
+            }
+            bb.hmax = sh[6][0];
+            part[r * kBBoxBlocks] = bb;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x != 0) return;
     double grow = 1.0;
     for (int attempt = 0; attempt < 200; ++attempt) {
         int64_t total = 0;
         for (int r = 0; r < nr; ++r) {
             BBox bb = part[r * kBBoxBlocks];
-            for (int b = 1; b < kBBoxBlocks; ++b) {
-                BBox o = part[r * kBBoxBlocks + b];
-                for (int d = 0; d < 3; ++d) {
-                    bb.lo[d] = fmin(bb.lo[d], o.lo[d]);
-                    bb.hi[d] = fmax(bb.hi[d], o.hi[d]);
-                }
-                bb.hmax = fmax(bb.hmax, o.hmax);
-            }
             GridDesc g;
             g.p0 = run_p[r];
             g.p1 = run_p[r + 1];
@@ -204,12 +235,12 @@ __global__ void k_grid(const BBox *part, const int32_t *run_p, int nr, double ce
             if (!(L > 0.0)) L = 1.0;
             int dims[3];
             for (int d = 0; d < 3; ++d) {
-                double ext = bb.hi[d] - bb.lo[d];
+                const double ext = bb.hi[d] - bb.lo[d];
                 if (ext / L > (double)((1 << kMaxMortonBits) - 2)) L = ext / (double)((1 << kMaxMortonBits) - 2);
             }
             for (int d = 0; d < 3; ++d) {
-                double ext = bb.hi[d] - bb.lo[d];
-                int nd = (int)floor(ext / L) + 1;
+                const double ext = bb.hi[d] - bb.lo[d];
+                const int nd = (int)floor(ext / L) + 1;
                 dims[d] = nd < 1 ? 1 : nd;
             }
             g.ox = bb.lo[0]; g.oy = bb.lo[1]; g.oz = bb.lo[2];
@@ -247,53 +278,75 @@ __global__ void k_keys(int64_t n, const double *x, const double *y, const double
                        const int32_t *run_p, int nr, const GridDesc *grid,
                        const int32_t *total_keys, uint32_t *key, int32_t *slot,
                        int32_t *cell_count) {
-    int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (k >= n) return;
+    const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const bool valid = k < n;
     if (*total_keys == 0) {  // table overflow: flagged, produce a valid (empty) permutation
-        key[k] = 0;
-        slot[k] = 0;
+        if (valid) {
+            key[k] = 0;
+            slot[k] = 0;
+        }
         return;
     }
-    int r = nr > 1 ? run_of(run_p, nr, k) : 0;
-    GridDesc g = grid[r];
-    int cx, cy, cz;
-    cell_of(g, x[k], y[k], z[k], cx, cy, cz);
-    uint32_t kk = (uint32_t)g.key_off + morton(cx, cy, cz, g.bx, g.by, g.bz);
-    key[k] = kk;
-    slot[k] = atomicAdd(&cell_count[kk], 1);
+    uint32_t kk = 0xffffffffu;
+    if (valid) {
+        const int r = nr > 1 ? run_of(run_p, nr, k) : 0;
+        const GridDesc g = grid[r];
+        int cx, cy, cz;
+        cell_of(g, x[k], y[k], z[k], cx, cy, cz);
+        kk = (uint32_t)g.key_off + morton(cx, cy, cz, g.bx, g.by, g.bz);
+        key[k] = kk;
+    }
+    // One atomic per distinct key of the wave: lanes with equal keys take
+    // consecutive slots in lane order.
+    const int lane = threadIdx.x % kWave;
+    uint64_t todo = __ballot(valid);
+    int my_slot = 0;
+    while (todo) {
+        const int leader = __ffsll((long long)todo) - 1;
+        const uint32_t lk = __shfl(kk, leader);
+        const uint64_t peers = __ballot(valid && kk == lk);
+        int base = 0;
+        if (lane == leader) base = atomicAdd(&cell_count[lk], __popcll(peers));
+        base = __shfl(base, leader);
+        if (valid && kk == lk)
+            my_slot = base + __builtin_amdgcn_mbcnt_hi((uint32_t)(peers >> 32),
+                                                       __builtin_amdgcn_mbcnt_lo((uint32_t)peers, 0u));
+        todo &= ~peers;
+    }
+    if (valid) slot[k] = my_slot;
 }
 
 __global__ void k_scatter(int64_t n, const uint32_t *key, const int32_t *slot,
-                          const int32_t *cell_start, const int32_t *total_keys, int32_t *perm) {
-    int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+                          const int32_t *cell_start, const int32_t *total_keys, int32_t *out) {
+    const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (k >= n) return;
     if (*total_keys == 0) {
-        perm[k] = (int32_t)k;
+        out[k] = (int32_t)k;
         return;
     }
-    perm[cell_start[key[k]] + slot[k]] = (int32_t)k;
+    out[cell_start[key[k]] + slot[k]] = (int32_t)k;
 }
 
-// Arrival order inside a cell depends on atomics; sorting each cell's
-// members by input index makes the permutation deterministic.
-__global__ void k_cellsort(const int32_t *cell_start, const int32_t *cell_count,
-                           const int32_t *total_keys, int32_t *perm) {
-    int64_t nk = *total_keys;
-    for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < nk;
-         c += (int64_t)gridDim.x * blockDim.x) {
-        int cnt = cell_count[c];
-        if (cnt < 2) continue;
-        int32_t *a = perm + cell_start[c];
-        for (int i = 1; i < cnt; ++i) {
-            int32_t v = a[i];
-            int j = i - 1;
-            while (j >= 0 && a[j] > v) {
-                a[j + 1] = a[j];
-                --j;
-            }
-            a[j + 1] = v;
-        }
+// Arrival order inside a cell depends on atomics; placing each member at its
+// rank by input index makes the permutation deterministic.  One thread per
+// particle counts the members of its cell with a smaller input index.
+__global__ void k_cellrank(int64_t n, const int32_t *__restrict__ arrived,
+                           const uint32_t *__restrict__ key,
+                           const int32_t *__restrict__ cell_start,
+                           const int32_t *__restrict__ cell_count, const int32_t *total_keys,
+                           int32_t *__restrict__ perm) {
+    const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    const int32_t o = arrived[p];
+    if (*total_keys == 0) {
+        perm[p] = o;
+        return;
     }
+    const uint32_t kk = key[o];
+    const int32_t cs = cell_start[kk], c = cell_count[kk];
+    int rank = 0;
+    for (int l = 0; l < c; ++l) rank += arrived[cs + l] < o;
+    perm[cs + rank] = o;
 }
 
 // Sorted copies of positions and h, cell-relative float offsets, packed
@@ -302,7 +355,8 @@ __global__ void k_gather(int64_t n, const int32_t *perm, const double *x, const 
                          const double *z, const double *h, const uint32_t *key,
                          const int32_t *run_p, int nr, const GridDesc *grid,
                          double4 *posh64, float4 *posh32, uint32_t *cellc, int16_t *runid,
-                         uint32_t *skey, int32_t *perm_out) {
+                         uint32_t *skey, int32_t *perm_out, const double *m, void *rec_d,
+                         int32_t f32) {
     int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (p >= n) return;
     int32_t o = perm[p];
@@ -316,6 +370,12 @@ __global__ void k_gather(int64_t n, const int32_t *perm, const double *x, const 
     double dy = (yo - g.oy) - (double)cy * g.L;
     double dz = (zo - g.oz) - (double)cz * g.L;
     posh32[p] = make_float4((float)dx, (float)dy, (float)dz, (float)ho);
+    if (m) {  // density-pass record (p, m) of the sorted particle
+        if (f32)
+            ((float4 *)rec_d)[p] = make_float4((float)dx, (float)dy, (float)dz, (float)m[o]);
+        else
+            ((double4 *)rec_d)[p] = make_double4(xo, yo, zo, m[o]);
+    }
     cellc[p] = (uint32_t)cx | ((uint32_t)cy << 10) | ((uint32_t)cz << 20);
     runid[p] = (int16_t)r;
     skey[p] = key[o];
@@ -325,11 +385,15 @@ __global__ void k_gather(int64_t n, const int32_t *perm, const double *x, const 
 // ------------------------------------------------------ pair-set builder
 // One wave per work-group.  The work-group owns a contiguous range of
 // sorted particles; for each cell it meets it stages the candidates of the
-// 27 neighbour cells in LDS (chunks of kTile), then tests every (i, j)
-// combination of the cell's particles in a flattened loop so that all 64
-// lanes stay busy, and appends hits to i's list in candidate order (ballot
-// + mbcnt compaction): the lists are deterministic.
-constexpr int kTile = 256;
+// 27 neighbour cells in LDS (chunks of kTile, candidate order = stencil
+// order, then sorted index).  Each lane then holds one candidate of a
+// 64-wide column in registers while the wave walks over the cell's
+// particles i (read from LDS as a broadcast): one exact test per lane, a
+// ballot, and the hits are appended to i's list in candidate order at
+// offsets from mbcnt.  Per-particle counts live in lane q of a register
+// (readlane / writelane), so the loop carries no LDS round trip.  The lists
+// are deterministic.
+constexpr int kTile = 128;
 constexpr int kIBatch = 64;
 
 __global__ __launch_bounds__(64) void k_build_pairs(
@@ -338,10 +402,10 @@ __global__ __launch_bounds__(64) void k_build_pairs(
     const GridDesc *__restrict__ grid, const int32_t *__restrict__ cell_start,
     const int32_t *__restrict__ cell_count, const int32_t *total_keys, uint32_t *nbr,
     int32_t *ncount, int32_t K, int32_t *flags, unsigned long long *pairs) {
-    __shared__ double4 tile[kTile];
+    // candidate tile in structure-of-arrays form: lane-consecutive doubles
+    __shared__ double tx[kTile], ty[kTile], tz[kTile], tw[kTile];
     __shared__ uint32_t tj[kTile];
-    __shared__ double4 ipos[kIBatch];
-    __shared__ int32_t icnt[kIBatch];
+    __shared__ double4 ipos[kIBatch + 4];
     __shared__ int32_t st_start[27];
     __shared__ int32_t st_off[28];
 
@@ -369,25 +433,23 @@ __global__ __launch_bounds__(64) void k_build_pairs(
         }
         // ---- stencil: 27 neighbour cells (lane t handles cell t)
         const uint32_t cc = cellc[p];
-        const int r = runid[p];
-        const GridDesc g = grid[r];
+        const GridDesc g = grid[runid[p]];
         int cnt_t = 0, start_t = 0;
         if (lane < 27) {
-            int dx = lane % 3 - 1, dy = (lane / 3) % 3 - 1, dz = lane / 9 - 1;
-            int cx = (int)(cc & 1023u) + dx;
-            int cy = (int)((cc >> 10) & 1023u) + dy;
-            int cz = (int)((cc >> 20) & 1023u) + dz;
+            const int dx = lane % 3 - 1, dy = (lane / 3) % 3 - 1, dz = lane / 9 - 1;
+            const int cx = (int)(cc & 1023u) + dx;
+            const int cy = (int)((cc >> 10) & 1023u) + dy;
+            const int cz = (int)((cc >> 20) & 1023u) + dz;
             if (cx >= 0 && cx < g.nx && cy >= 0 && cy < g.ny && cz >= 0 && cz < g.nz) {
-                uint32_t kk = (uint32_t)g.key_off + morton(cx, cy, cz, g.bx, g.by, g.bz);
+                const uint32_t kk = (uint32_t)g.key_off + morton(cx, cy, cz, g.bx, g.by, g.bz);
                 start_t = cell_start[kk];
                 cnt_t = cell_count[kk];
             }
         }
-        // inclusive scan of the 27 counts across the wave
-        int incl = cnt_t;
+        int incl = cnt_t;  // inclusive scan of the 27 counts across the wave
 #pragma unroll
         for (int o = 1; o < 32; o <<= 1) {
-            int v = __shfl_up(incl, o);
+            const int v = __shfl_up(incl, o);
             if (lane >= o) incl += v;
         }
         __syncthreads();
@@ -402,72 +464,70 @@ __global__ __launch_bounds__(64) void k_build_pairs(
         for (int64_t ib = i_lo; ib < i_hi; ib += kIBatch) {
             const int ni = (int)((i_hi - ib) < kIBatch ? (i_hi - ib) : kIBatch);
             if (lane < ni) {
-                double4 q = posh64[ib + lane];
-                double H = 2.0 * q.w;
+                const double4 q = posh64[ib + lane];
+                const double H = 2.0 * q.w;
                 ipos[lane] = make_double4(q.x, q.y, q.z, __dmul_rn(H, H));
-                icnt[lane] = 0;
             }
+            int cnt_reg = 0;  // lane q: running count of particle ib + q
             for (int c0 = 0; c0 < T; c0 += kTile) {
                 const int nS = (T - c0) < kTile ? (T - c0) : kTile;
                 __syncthreads();
                 for (int s = lane; s < nS; s += kWave) {
-                    int gidx = c0 + s;
+                    const int gidx = c0 + s;
                     int lo = 0, hi = 27;
                     while (hi - lo > 1) {
-                        int mid = (lo + hi) >> 1;
+                        const int mid = (lo + hi) >> 1;
                         if (st_off[mid] <= gidx) lo = mid; else hi = mid;
                     }
-                    int j = st_start[lo] + (gidx - st_off[lo]);
-                    double4 q = posh64[j];
-                    double H = 2.0 * q.w;
-                    tile[s] = make_double4(q.x, q.y, q.z, __dmul_rn(H, H));
+                    const int j = st_start[lo] + (gidx - st_off[lo]);
+                    const double4 q = posh64[j];
+                    const double H = 2.0 * q.w;
+                    tx[s] = q.x;
+                    ty[s] = q.y;
+                    tz[s] = q.z;
+                    tw[s] = __dmul_rn(H, H);
                     tj[s] = (uint32_t)j | ((uint32_t)lo << kCodeShift);
                 }
                 __syncthreads();
-                const int total = ni * nS;
-                const int adv_i = kWave / nS, adv_s = kWave % nS;
-                int il = lane / nS, s = lane % nS;
-                for (int f0 = 0; f0 < total; f0 += kWave) {
-                    const bool valid = f0 + lane < total;
-                    bool hit = false, dfl = false;
-                    uint32_t e = 0;
+                for (int col = 0; col < nS; col += kWave) {
+                    const int s = col + lane;
+                    const bool valid = s < nS;
+                    double4 cj = make_double4(0.0, 0.0, 0.0, -1.0);
+                    uint32_t e = 0xffffffffu;
                     if (valid) {
-                        double4 pi = ipos[il];
-                        double4 pj = tile[s];
+                        cj = make_double4(tx[s], ty[s], tz[s], tw[s]);
                         e = tj[s];
-                        double r2 = sep2_exact(pi.x, pi.y, pi.z, pj.x, pj.y, pj.z);
-                        int64_t j = e & kIdxMask;
-                        hit = (j != ib + il) && (r2 < fmax(pi.w, pj.w));
-                        dfl = r2 < pi.w;
                     }
-                    const uint64_t m = __ballot(hit);
-                    const int below = __builtin_amdgcn_mbcnt_hi(
-                        (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-                    int first = lane - s;
-                    first = first < 0 ? 0 : first;
-                    const int below_first = __shfl(below, first);
-                    const int rank = below - below_first;
-                    const int base = valid ? icnt[il] : 0;
-                    if (hit) {
-                        int idx = base + rank;
-                        if (idx < K) nbr[(ib + il) * (int64_t)K + idx] = e | (dfl ? kDensityBit : 0u);
-                    }
-                    const bool last = valid && (s == nS - 1 || lane == kWave - 1 || f0 + lane == total - 1);
-                    if (last) icnt[il] = base + rank + (hit ? 1 : 0);
-                    s += adv_s;
-                    il += adv_i;
-                    if (s >= nS) {
-                        s -= nS;
-                        ++il;
+                    const int64_t j = valid ? (int64_t)(e & kIdxMask) : -1;
+                    // test the column against particle ib + q, append the hits
+                    auto visit = [&](int q, const double4 &pi) {
+                        const double r2 = sep2_exact(pi.x, pi.y, pi.z, cj.x, cj.y, cj.z);
+                        const bool hit = valid && (j != ib + q) && (r2 < fmax(pi.w, cj.w));
+                        const uint64_t m = __ballot(hit);
+                        if (m) {
+                            const int base = __builtin_amdgcn_readlane(cnt_reg, q);
+                            const int rank = __builtin_amdgcn_mbcnt_hi(
+                                (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+                            if (hit && base + rank < K)
+                                nbr[(ib + q) * (int64_t)K + base + rank] =
+                                    e | (r2 < pi.w ? kDensityBit : 0u);
+                            if (lane == q) cnt_reg = base + __popcll(m);
+                        }
+                    };
+                    for (int q = 0; q < ni; q += 4) {  // four broadcast reads in flight
+                        const double4 p0 = ipos[q], p1 = ipos[q + 1], p2 = ipos[q + 2],
+                                      p3 = ipos[q + 3];
+                        visit(q, p0);
+                        if (q + 1 < ni) visit(q + 1, p1);
+                        if (q + 2 < ni) visit(q + 2, p2);
+                        if (q + 3 < ni) visit(q + 3, p3);
                     }
                 }
             }
-            __syncthreads();
             if (lane < ni) {
-                int c = icnt[lane];
-                ncount[ib + lane] = c < K ? c : K;
-                if (c > K) atomicOr(&flags[FLAG_NBR_OVERFLOW], 1);
-                my_pairs += (unsigned long long)c;
+                ncount[ib + lane] = cnt_reg < K ? cnt_reg : K;
+                if (cnt_reg > K) atomicOr(&flags[FLAG_NBR_OVERFLOW], 1);
+                my_pairs += (unsigned long long)cnt_reg;
             }
             __syncthreads();
         }
@@ -479,36 +539,35 @@ __global__ __launch_bounds__(64) void k_build_pairs(
     if (lane == 0 && v) atomicAdd(pairs, v);
 }
 
-sph_status launch_build_cells(Ctx *ctx, int64_t n, const double *x, const double *y,
-                              const double *z, const double *h, int32_t nr,
-                              const int64_t *run_start, double cell_min, int32_t *perm_out,
-                              hipStream_t s) {
-    (void)run_start;
+sph_status launch_build_cells(Ctx *ctx, int64_t n, double *x, double *y, double *z,
+                              const double *h, int32_t nr, double cell_min, int32_t *perm_out,
+                              const BuildExtras *ex, hipStream_t s) {
     if (n == 0) {
         ctx->n_built = 0;
         ctx->n_runs_built = nr;
         return SPH_OK;
     }
+    BuildExtras none;
+    if (!ex) ex = &none;
     const int tb = 256;
     const int nb = (int)((n + tb - 1) / tb);
     hipLaunchKernelGGL(k_bbox, dim3(kBBoxBlocks, nr), dim3(256), 0, s, x, y, z, h, ctx->run_p,
-                       ctx->bbox_part);
-    hipLaunchKernelGGL(k_grid, dim3(1), dim3(64), 0, s, ctx->bbox_part, ctx->run_p, nr, cell_min,
+                       ctx->bbox_part, ctx->cell_count, ctx->total_keys, ex->dt, ex->vx, ex->vy,
+                       ex->vz, ex->fixed);
+    hipLaunchKernelGGL(k_grid, dim3(1), dim3(256), 0, s, ctx->bbox_part, ctx->run_p, nr, cell_min,
                        ctx->max_cells, ctx->grid, ctx->total_keys, ctx->flags);
-    hipLaunchKernelGGL(k_zero_dev_len, dim3(1024), dim3(256), 0, s, ctx->cell_count,
-                       ctx->total_keys);
     hipLaunchKernelGGL(k_keys, dim3(nb), dim3(tb), 0, s, n, x, y, z, ctx->run_p, nr, ctx->grid,
                        ctx->total_keys, ctx->key, ctx->slot, ctx->cell_count);
     sph_status st = scan<int32_t, int32_t>(ctx, ctx->cell_count, ctx->cell_start,
                                            ctx->total_keys, 0, s);
     if (st != SPH_OK) return st;
     hipLaunchKernelGGL(k_scatter, dim3(nb), dim3(tb), 0, s, n, ctx->key, ctx->slot,
-                       ctx->cell_start, ctx->total_keys, ctx->perm);
-    hipLaunchKernelGGL(k_cellsort, dim3(1024), dim3(256), 0, s, ctx->cell_start, ctx->cell_count,
-                       ctx->total_keys, ctx->perm);
+                       ctx->cell_start, ctx->total_keys, ctx->ptmp);
+    hipLaunchKernelGGL(k_cellrank, dim3(nb), dim3(tb), 0, s, n, ctx->ptmp, ctx->key,
+                       ctx->cell_start, ctx->cell_count, ctx->total_keys, ctx->perm);
     hipLaunchKernelGGL(k_gather, dim3(nb), dim3(tb), 0, s, n, ctx->perm, x, y, z, h, ctx->key,
                        ctx->run_p, nr, ctx->grid, ctx->posh64, ctx->posh32, ctx->cellc,
-                       ctx->runid, ctx->skey, perm_out);
+                       ctx->runid, ctx->skey, perm_out, ex->m, ctx->rec_d, ex->f32);
     int64_t wgs = (n + 31) / 32;
     if (wgs > 65536) wgs = 65536;
     {

@@ -4,21 +4,9 @@
 // rescaling eq.), Jaumann stress rate (Deviatoric_Stress_derivative eq.),
 // closing and opening kicks (sec. 2.4), drift, global time step from the
 // CFL condition, and conservation diagnostics.
-#include "sph_internal.h"
+#include "physics.h"
 
 namespace sph {
-
-// S -> f S, f = min(Y / sqrt(J2), 1), J2 = 1/2 S:S over the full tensor.
-__device__ __forceinline__ void plastic_return(double s[5], double Y) {
-    const double szz = -s[0] - s[1];
-    const double J2 = 0.5 * (s[0] * s[0] + s[1] * s[1] + szz * szz) + s[2] * s[2] +
-                      s[3] * s[3] + s[4] * s[4];
-    if (J2 > 0.0) {
-        const double f = Y / sqrt(J2);
-        if (f < 1.0)
-            for (int c = 0; c < 5; ++c) s[c] *= f;
-    }
-}
 
 __global__ void k_stress(int32_t phase, int64_t n, const double *__restrict__ dtp,
                          const double *__restrict__ dtnp, const double *__restrict__ G,
@@ -156,8 +144,6 @@ sph_status launch_kick_drift(Ctx *ctx, int32_t phase, int64_t n, const double *d
 // ------------------------------------------------------------ dt minimum
 // Positive doubles order like their bit patterns, so an integer atomicMin on
 // the bits is an exact, order-independent minimum.
-__global__ void k_dt_init(unsigned long long *bits) { *bits = 0x7ff0000000000000ull; }
-
 __global__ void k_dt_reduce(int64_t n, const double *__restrict__ dtc,
                             const int32_t *__restrict__ fixed, unsigned long long *bits) {
     unsigned long long best = 0x7ff0000000000000ull;
@@ -174,22 +160,28 @@ __global__ void k_dt_reduce(int64_t n, const double *__restrict__ dtc,
         const unsigned long long v = __shfl_xor(best, o);
         best = v < best ? v : best;
     }
-    if ((threadIdx.x % kWave) == 0 && best != 0x7ff0000000000000ull) atomicMin(bits, best);
+    __shared__ unsigned long long wmin[16];
+    if ((threadIdx.x % kWave) == 0) wmin[threadIdx.x / kWave] = best;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (unsigned w = 1; w < blockDim.x / kWave; ++w) best = wmin[w] < best ? wmin[w] : best;
+        if (best != 0x7ff0000000000000ull) atomicMin(bits, best);
+    }
 }
 
-__global__ void k_dt_final(const unsigned long long *bits, double cap, double *out) {
+__global__ void k_dt_final(unsigned long long *bits, double cap, double *out) {
     double d = __longlong_as_double((long long)*bits);
     if (cap > 0.0 && !(d <= cap)) d = cap;
     *out = d;
+    *bits = 0x7ff0000000000000ull;  // ready for the next reduction
 }
 
 sph_status launch_dt_min(Ctx *ctx, int64_t n, const double *dtc, const int32_t *fixed,
                          double cap, double *out, hipStream_t s) {
-    hipLaunchKernelGGL(k_dt_init, dim3(1), dim3(1), 0, s, ctx->dtbits);
     if (n > 0) {
-        int nb = (int)((n + 255) / 256);
-        nb = nb > 1024 ? 1024 : nb;
-        hipLaunchKernelGGL(k_dt_reduce, dim3(nb), dim3(256), 0, s, n, dtc, fixed, ctx->dtbits);
+        int nb = (int)((n + 1023) / 1024);
+        nb = nb > 256 ? 256 : nb;
+        hipLaunchKernelGGL(k_dt_reduce, dim3(nb), dim3(1024), 0, s, n, dtc, fixed, ctx->dtbits);
     }
     hipLaunchKernelGGL(k_dt_final, dim3(1), dim3(1), 0, s, ctx->dtbits, cap, out);
     SPH_HIP(hipGetLastError());

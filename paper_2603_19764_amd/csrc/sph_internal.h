@@ -55,6 +55,7 @@ struct Ctx {
     uint32_t *key = nullptr;        // capacity: cell key, input order
     int32_t *slot = nullptr;        // capacity: arrival rank within the cell
     int32_t *perm = nullptr;        // capacity: sorted -> input
+    int32_t *ptmp = nullptr;        // capacity: arrival order within cells
     uint32_t *skey = nullptr;       // capacity: cell key, sorted order
     int32_t *cell_count = nullptr;  // max_cells + 1
     int32_t *cell_start = nullptr;  // max_cells + 1
@@ -73,8 +74,10 @@ struct Ctx {
     unsigned long long *pairs = nullptr;  // accumulated ordered pairs
     unsigned long long *dtbits = nullptr; // scratch for dt min
     double *diag = nullptr;         // 16 doubles
-    // pair-pass records
-    void *rec = nullptr;            // capacity * 128 bytes
+    // pair-pass records (array of structures, see the pair kernels)
+    void *rec_d = nullptr;          // density: capacity * 32 bytes
+    void *rec_g = nullptr;          // gradients: capacity * 96 bytes
+    void *rec_f = nullptr;          // forces: capacity * 160 bytes
     double *gsum = nullptr;         // capacity * 15 (gradient raw sums)
     Mat *mats = nullptr;            // up to kMaxMaterials
     // kernel timing (host side): event pairs recorded around pass kernels
@@ -89,7 +92,7 @@ struct Ctx {
     char err[512] = {0};
 };
 
-constexpr int kBBoxBlocks = 64;
+constexpr int kBBoxBlocks = 256;
 constexpr int kScanBlocks = 1024;
 constexpr int kMaxMaterials = 16;
 
@@ -120,13 +123,20 @@ __device__ __forceinline__ uint32_t morton(uint32_t cx, uint32_t cy, uint32_t cz
     return key;
 }
 
-// Squared separation with no contraction: ((dx*dx + dy*dy) + dz*dz).
+// Squared separation ((dx*dx + dy*dy) + dz*dz) in IEEE double with every
+// operation rounded separately: contraction into FMA is switched off here,
+// so the neighbour criterion r^2 < H^2 is decided exactly as by any other
+// implementation that evaluates the same expression without fusion.
 __device__ __forceinline__ double sep2_exact(double xi, double yi, double zi, double xj,
                                              double yj, double zj) {
-    double dx = __dsub_rn(xi, xj);
-    double dy = __dsub_rn(yi, yj);
-    double dz = __dsub_rn(zi, zj);
-    return __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)), __dmul_rn(dz, dz));
+#pragma clang fp contract(off)
+    const double dx = xi - xj;
+    const double dy = yi - yj;
+    const double dz = zi - zj;
+    const double a = dx * dx;
+    const double b = dy * dy;
+    const double c = dz * dz;
+    return (a + b) + c;
 }
 
 // Sum over groups of L consecutive lanes (L a power of two <= 64); every
@@ -184,11 +194,20 @@ struct TimedLaunch {
     ~TimedLaunch();
 };
 
+// Optional work fused into the neighbour search by the whole-step path:
+// drift of the positions before binning, and the density-pass records.
+struct BuildExtras {
+    const double *dt = nullptr;                  // drift x += dt v (non-fixed) when set
+    const double *vx = nullptr, *vy = nullptr, *vz = nullptr;
+    const int32_t *fixed = nullptr;
+    const double *m = nullptr;                   // write density records when set
+    int32_t f32 = 0;                             // record arithmetic
+};
+
 // Launch helpers implemented in the .hip files.
-sph_status launch_build_cells(Ctx *ctx, int64_t n, const double *x, const double *y,
-                              const double *z, const double *h, int32_t n_runs,
-                              const int64_t *run_start, double cell_min, int32_t *perm_out,
-                              hipStream_t s);
+sph_status launch_build_cells(Ctx *ctx, int64_t n, double *x, double *y, double *z,
+                              const double *h, int32_t n_runs, double cell_min,
+                              int32_t *perm_out, const BuildExtras *ex, hipStream_t s);
 sph_status launch_reorder(Ctx *ctx, int64_t n, const int32_t *perm, int32_t nf,
                           const void *const *src, void *const *dst, const int32_t *eb,
                           const int32_t *rows, hipStream_t s);
@@ -226,5 +245,42 @@ sph_status launch_diag(Ctx *ctx, int64_t n, const double *x, const double *y, co
                        const double *ax, const double *ay, const double *az,
                        const double *dudt, double *out, hipStream_t s);
 sph_status launch_fill_i32(Ctx *ctx, int32_t *p, int32_t v, int64_t n, hipStream_t s);
+// pair kernels alone (records already written)
+sph_status launch_density_pairs(Ctx *ctx, int64_t n, const sph_params *prm, sph_precision prec,
+                                double *rho, double *omega, hipStream_t s);
+sph_status launch_gradient_pairs(Ctx *ctx, int64_t n, sph_precision prec, hipStream_t s);
+sph_status launch_force_pairs(Ctx *ctx, int64_t n, const sph_params *prm, sph_precision prec,
+                              double *ax, double *ay, double *az, double *dudt, double *dtc,
+                              hipStream_t s);
+sph_status launch_grad_force_pairs(Ctx *ctx, int64_t n, const sph_params *prm,
+                                   sph_precision prec, double *ax, double *ay, double *az,
+                                   double *dudt, double *dtc, hipStream_t s);
+// fused whole-step kernels: source and destination rows of the reorder
+struct StepRows {
+    const double *f_src[SPH_NF64];
+    double *f_dst[SPH_NF64];
+    const int32_t *i_src[SPH_NI32];
+    int32_t *i_dst[SPH_NI32];
+};
+sph_status launch_step_reorder(Ctx *ctx, int64_t n, const int32_t *perm, const StepRows &r,
+                               const double *dt, int32_t predict, double *vpx, double *vpy,
+                               double *vpz, double *up, hipStream_t s);
+sph_status launch_step_state(Ctx *ctx, int64_t n, sph_precision prec, const double *rho,
+                             const double *omega, const double *up, const double *vpx,
+                             const double *vpy, const double *vpz, const double *m,
+                             const int32_t *mat, int32_t nmat, const int32_t *fixed,
+                             const double *dt, int32_t predict, const double *S_half,
+                             const double *Sdot, double *P, double *cs, double *T, double *Y,
+                             double *Gmod, double *S_pred, hipStream_t s);
+sph_status launch_step_grad_rate(Ctx *ctx, int64_t n, const sph_params *prm,
+                                 const double *S_pred, const double *Gmod, const int32_t *fixed,
+                                 const double *dt, double *G, double *Sdot, double *eps2,
+                                 int64_t *n_singular, hipStream_t s);
+sph_status launch_step_kick(Ctx *ctx, int64_t n, int32_t mode, const double *dt,
+                            const double *dt_next, const int32_t *fixed, double *vx, double *vy,
+                            double *vz, double *u, const double *ax, const double *ay,
+                            const double *az, const double *dudt, double *S_half,
+                            const double *S_pred, const double *Sdot, const double *Y,
+                            hipStream_t s);
 
 }  // namespace sph

@@ -1,0 +1,224 @@
+// Fused per-particle kernels of the whole strength-SPH step (sec. 2.4
+// sequence).  The public pass entry points keep their own kernels; the step
+// path merges the per-particle work around the three pair passes so that
+// each particle's state is read from HBM once per phase:
+//   reorder + predictor          (Predict_S eq. applied to v, u)
+//   state                        (EOS, T, yield, Gamma, stress predictor and
+//                                 rescaling, gradient and force records)
+//   gradient epilogue + rate     (Corrected_Gradients eq., Jaumann rate,
+//                                 strain-rate invariant)
+//   kicks                        (closing kick with rescaling, opening kick)
+#include "physics.h"
+
+namespace sph {
+
+// --------------------------------------------------- reorder + predictor
+__global__ void k_reorder_predict(int64_t n, const int32_t *__restrict__ perm, StepRows r,
+                                  const double *__restrict__ dtp, int32_t predict,
+                                  double *__restrict__ vpx, double *__restrict__ vpy,
+                                  double *__restrict__ vpz, double *__restrict__ up) {
+    const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const int64_t o = perm[k];
+    double f[SPH_NF64];
+#pragma unroll
+    for (int c = 0; c < SPH_NF64; ++c) {
+        f[c] = r.f_src[c][o];
+        r.f_dst[c][k] = f[c];
+    }
+    int32_t fx = 0;
+#pragma unroll
+    for (int c = 0; c < SPH_NI32; ++c) {
+        const int32_t v = r.i_src[c][o];
+        r.i_dst[c][k] = v;
+        if (c == SPH_FIXED) fx = v;
+    }
+    const double hd = (predict && !fx) ? 0.5 * *dtp : 0.0;
+    vpx[k] = f[SPH_VX] + hd * f[SPH_AX];
+    vpy[k] = f[SPH_VY] + hd * f[SPH_AY];
+    vpz[k] = f[SPH_VZ] + hd * f[SPH_AZ];
+    up[k] = f[SPH_U] + hd * f[SPH_DUDT];
+}
+
+// ------------------------------------------------------------------ state
+// Record of the fused gradient + force pass (5 slots): (p, 1/H) (v, m)
+// (Kn A xx yy zz xy) (Kn A xz yz, rho, c) (Kn/(Omega rho), Kn, h, -) with
+// A = (-P I + S_pred)/(Omega rho^2), Kn = -210/(pi H^5).
+template <bool F32>
+__global__ void k_state(int64_t n, const double4 *__restrict__ posh64,
+                        const float4 *__restrict__ posh32, const double *__restrict__ rho,
+                        const double *__restrict__ omega, const double *__restrict__ up,
+                        const double *__restrict__ vpx, const double *__restrict__ vpy,
+                        const double *__restrict__ vpz, const double *__restrict__ m,
+                        const int32_t *__restrict__ mat, const int32_t *__restrict__ fixed,
+                        MatTable mt, const double *__restrict__ dtp, int32_t predict,
+                        const double *__restrict__ S_half, const double *__restrict__ Sdot,
+                        double *__restrict__ P, double *__restrict__ cs, double *__restrict__ T,
+                        double *__restrict__ Y, double *__restrict__ Gmod,
+                        double *__restrict__ S_pred, void *rec_f_v) {
+    using R = typename std::conditional<F32, float, double>::type;
+    using R4 = typename std::conditional<F32, float4, double4>::type;
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const sph_material &M = material_of(mt, mat, i);
+    const double r = rho[i], om = omega[i];
+    double p, c, t, y, gm;
+    material_state(M, r, up[i], p, c, t, y, gm);
+    P[i] = p;
+    cs[i] = c;
+    T[i] = t;
+    Y[i] = y;
+    Gmod[i] = gm;
+    const bool fx = fixed && fixed[i];
+    const double hd = (predict && !fx) ? 0.5 * *dtp : 0.0;
+    double s[5];
+    for (int k = 0; k < 5; ++k) s[k] = S_half[k * n + i] + hd * Sdot[k * n + i];
+    plastic_return(s, y);
+    for (int k = 0; k < 5; ++k) S_pred[k * n + i] = s[k];
+    // records
+    const double4 q64 = posh64[i];
+    R px, py, pz;
+    if constexpr (F32) {
+        const float4 q = posh32[i];
+        px = q.x; py = q.y; pz = q.z;
+    } else {
+        px = q64.x; py = q64.y; pz = q64.z;
+    }
+    const double H = 2.0 * q64.w;
+    const double kn = -210.0 / (kPiD * H * H * H * H * H);
+    const double sc = kn / (om * r * r);
+    R4 *rf = (R4 *)rec_f_v + 5 * i;
+    rf[0] = {px, py, pz, (R)(1.0 / H)};
+    rf[1] = {(R)vpx[i], (R)vpy[i], (R)vpz[i], (R)m[i]};
+    rf[2] = {(R)(sc * (s[0] - p)), (R)(sc * (s[1] - p)), (R)(sc * (-s[0] - s[1] - p)),
+             (R)(sc * s[2])};
+    rf[3] = {(R)(sc * s[3]), (R)(sc * s[4]), (R)r, (R)c};
+    rf[4] = {(R)(kn / (om * r)), (R)kn, (R)q64.w, (R)0};
+}
+
+// ------------------------------------------- gradient epilogue + stress rate
+__global__ void k_grad_rate(int64_t n, const double *__restrict__ gsum,
+                            const int32_t *__restrict__ ncount, int32_t use_corr,
+                            const double *__restrict__ S_pred, const double *__restrict__ Gmod,
+                            const int32_t *__restrict__ fixed, double rot,
+                            const double *__restrict__ dtp, double *__restrict__ G,
+                            double *__restrict__ Sdot, double *__restrict__ eps2,
+                            int64_t *n_singular) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    int sing = 0;
+    if (i < n) {
+        double ci[6], F[9], g[9], s[5], ds[5], e2;
+        for (int k = 0; k < 6; ++k) ci[k] = gsum[k * n + i];
+        for (int k = 0; k < 9; ++k) F[k] = gsum[(6 + k) * n + i];
+        sing = corrected_gradient(ci, F, ncount[i], use_corr, g) ? 0 : (use_corr ? 1 : 0);
+        for (int k = 0; k < 9; ++k) G[k * n + i] = g[k];
+        for (int k = 0; k < 5; ++k) s[k] = S_pred[k * n + i];
+        stress_rate(g, s, Gmod[i], rot, ds, e2);
+        for (int k = 0; k < 5; ++k) Sdot[k * n + i] = ds[k];
+        if (eps2 && !(fixed && fixed[i])) eps2[i] += *dtp * e2;
+    }
+    if (n_singular) {
+        const uint64_t mk = __ballot(sing);
+        if (mk && (threadIdx.x % kWave) == 0)
+            atomicAdd((unsigned long long *)n_singular, (unsigned long long)__popcll(mk));
+    }
+}
+
+// ------------------------------------------------------------------ kicks
+// mode 0: closing kick with rescaling then opening kick (a step);
+// mode 1: opening kick from the predicted stress (start of a run).
+__global__ void k_kick_all(int64_t n, int32_t mode, const double *__restrict__ dtp,
+                           const double *__restrict__ dtnp, const int32_t *__restrict__ fixed,
+                           double *vx, double *vy, double *vz, double *u,
+                           const double *__restrict__ ax, const double *__restrict__ ay,
+                           const double *__restrict__ az, const double *__restrict__ dudt,
+                           double *S_half, const double *__restrict__ S_pred,
+                           const double *__restrict__ Sdot, const double *__restrict__ Y) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    if (fixed && fixed[i]) return;
+    const double hn = 0.5 * *dtnp;
+    if (mode == 0) {
+        const double hd = 0.5 * *dtp;
+        vx[i] = (vx[i] + hd * ax[i]) + hn * ax[i];
+        vy[i] = (vy[i] + hd * ay[i]) + hn * ay[i];
+        vz[i] = (vz[i] + hd * az[i]) + hn * az[i];
+        u[i] = (u[i] + hd * dudt[i]) + hn * dudt[i];
+        double s[5], d[5];
+        for (int k = 0; k < 5; ++k) {
+            d[k] = Sdot[k * n + i];
+            s[k] = S_half[k * n + i] + hd * d[k];
+        }
+        plastic_return(s, Y[i]);
+        for (int k = 0; k < 5; ++k) S_half[k * n + i] = s[k] + hn * d[k];
+    } else {
+        vx[i] += hn * ax[i];
+        vy[i] += hn * ay[i];
+        vz[i] += hn * az[i];
+        u[i] += hn * dudt[i];
+        for (int k = 0; k < 5; ++k) S_half[k * n + i] = S_pred[k * n + i] + hn * Sdot[k * n + i];
+    }
+}
+
+// -------------------------------------------------------------- launches
+sph_status launch_step_reorder(Ctx *ctx, int64_t n, const int32_t *perm, const StepRows &r,
+                               const double *dt, int32_t predict, double *vpx, double *vpy,
+                               double *vpz, double *up, hipStream_t s) {
+    if (n == 0) return SPH_OK;
+    hipLaunchKernelGGL(k_reorder_predict, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n,
+                       perm, r, dt, predict, vpx, vpy, vpz, up);
+    SPH_HIP(hipGetLastError());
+    return SPH_OK;
+}
+
+sph_status launch_step_state(Ctx *ctx, int64_t n, sph_precision prec, const double *rho,
+                             const double *omega, const double *up, const double *vpx,
+                             const double *vpy, const double *vpz, const double *m,
+                             const int32_t *mat, int32_t nmat, const int32_t *fixed,
+                             const double *dt, int32_t predict, const double *S_half,
+                             const double *Sdot, double *P, double *cs, double *T, double *Y,
+                             double *Gmod, double *S_pred, hipStream_t s) {
+    if (n == 0) return SPH_OK;
+    MatTable mt;
+    mt.n = nmat;
+    for (int k = 0; k < nmat; ++k) mt.m[k] = ctx->mats[k].m;
+    const unsigned nb = (unsigned)((n + 255) / 256);
+    if (prec == SPH_FP32_CELLREL)
+        hipLaunchKernelGGL((k_state<true>), dim3(nb), dim3(256), 0, s, n, ctx->posh64,
+                           ctx->posh32, rho, omega, up, vpx, vpy, vpz, m, mat, fixed, mt, dt,
+                           predict, S_half, Sdot, P, cs, T, Y, Gmod, S_pred, ctx->rec_f);
+    else
+        hipLaunchKernelGGL((k_state<false>), dim3(nb), dim3(256), 0, s, n, ctx->posh64,
+                           ctx->posh32, rho, omega, up, vpx, vpy, vpz, m, mat, fixed, mt, dt,
+                           predict, S_half, Sdot, P, cs, T, Y, Gmod, S_pred, ctx->rec_f);
+    SPH_HIP(hipGetLastError());
+    return SPH_OK;
+}
+
+sph_status launch_step_grad_rate(Ctx *ctx, int64_t n, const sph_params *prm,
+                                 const double *S_pred, const double *Gmod, const int32_t *fixed,
+                                 const double *dt, double *G, double *Sdot, double *eps2,
+                                 int64_t *n_singular, hipStream_t s) {
+    if (n == 0) return SPH_OK;
+    hipLaunchKernelGGL(k_grad_rate, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n,
+                       ctx->gsum, ctx->ncount, prm->use_correction_tensor, S_pred, Gmod, fixed,
+                       prm->rot_sign, dt, G, Sdot, eps2, n_singular);
+    SPH_HIP(hipGetLastError());
+    return SPH_OK;
+}
+
+sph_status launch_step_kick(Ctx *ctx, int64_t n, int32_t mode, const double *dt,
+                            const double *dt_next, const int32_t *fixed, double *vx, double *vy,
+                            double *vz, double *u, const double *ax, const double *ay,
+                            const double *az, const double *dudt, double *S_half,
+                            const double *S_pred, const double *Sdot, const double *Y,
+                            hipStream_t s) {
+    if (n == 0) return SPH_OK;
+    hipLaunchKernelGGL(k_kick_all, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, mode,
+                       dt, dt_next, fixed, vx, vy, vz, u, ax, ay, az, dudt, S_half, S_pred, Sdot,
+                       Y);
+    SPH_HIP(hipGetLastError());
+    return SPH_OK;
+}
+
+}  // namespace sph

@@ -93,10 +93,17 @@ def lib():
             "sph_step": [_P, C.POINTER(sph_state), C.POINTER(sph_material), i32,
                          C.POINTER(sph_params), i32, _P],
         }
+        sig.update({
+            "sph_mlp_forward": [i32, _P, _P, _P, _P, _P, _P],
+            "sph_mlp_backward": [i32, _P, _P, _P, _P, _P, _P, _P, _P, _P],
+            "sph_mlp_adam": [_P, _P, _P, _P, i32, C.c_float, C.c_float, C.c_float, C.c_float, _P],
+        })
         for name, args in sig.items():
             f = getattr(L, name)
             f.argtypes = args
             f.restype = C.c_int
+        L.sph_mlp_num_params.argtypes = []
+        L.sph_mlp_num_params.restype = C.c_int32
         L.sph_last_error.argtypes = [_P]
         L.sph_last_error.restype = C.c_char_p
         _lib = L
@@ -302,8 +309,8 @@ class State:
         self.f64 = torch.zeros((2, SPH_NF64, self.n_cap), **dd)
         self.i32 = torch.zeros((2, SPH_NI32, self.n_cap), dtype=torch.int32, device=device)
         self.work = torch.zeros((SPH_NW, self.n_cap), **dd)
-        self.dt = torch.zeros(1, **dd)
-        self.dt_next = torch.zeros(1, **dd)
+        # the library swaps the two step scalars after every step
+        self._dt_pair = (torch.zeros(1, **dd), torch.zeros(1, **dd))
         self.n_singular = torch.zeros(1, dtype=torch.int64, device=device)
         F = self.f64[0]
         for k, row in (("x", SPH_X), ("y", SPH_Y), ("z", SPH_Z), ("vx", SPH_VX), ("vy", SPH_VY),
@@ -326,7 +333,7 @@ class State:
         c.f64[0], c.f64[1] = self.f64[0].data_ptr(), self.f64[1].data_ptr()
         c.i32[0], c.i32[1] = self.i32[0].data_ptr(), self.i32[1].data_ptr()
         c.work = self.work.data_ptr()
-        c.dt, c.dt_next = self.dt.data_ptr(), self.dt_next.data_ptr()
+        c.dt, c.dt_next = self._dt_pair[0].data_ptr(), self._dt_pair[1].data_ptr()
         c.n_singular = self.n_singular.data_ptr()
         c.cur = 0
         c.n_runs = 1 if run_start is None else len(run_start) - 1
@@ -351,6 +358,12 @@ class State:
     @property
     def cur(self):
         return self.c.cur
+
+    @property
+    def dt(self):
+        """Device scalar holding the step of the coming drift."""
+        a, b = self._dt_pair
+        return a if self.c.dt == a.data_ptr() else b
 
     def row(self, k):
         return self.f64[self.cur, k, :self.n]
@@ -382,3 +395,27 @@ class State:
                    G=W[SPH_W_G:SPH_W_G + 9][:, order], dt=W[SPH_W_DT][order],
                    id=I[SPH_ID][order])
         return out
+
+
+# ------------------------------------------------------ proposal network
+def _mlp_check(code):
+    if code != SPH_OK:
+        raise SphError(code, "network kernel launch failed")
+
+
+def sph_mlp_forward(X, params, out, h1=None, h2=None, stream=None):
+    _mlp_check(lib().sph_mlp_forward(X.shape[0], _ptr(X), _ptr(params), _ptr(out), _ptr(h1),
+                                     _ptr(h2), _stream(stream)))
+
+
+def sph_mlp_backward(X, Y, params, out, h1, h2, work, grads, stream=None):
+    _mlp_check(lib().sph_mlp_backward(X.shape[0], _ptr(X), _ptr(Y), _ptr(params), _ptr(out),
+                                      _ptr(h1), _ptr(h2), _ptr(work), _ptr(grads),
+                                      _stream(stream)))
+
+
+def sph_mlp_adam(params, grads, m, v, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8,
+                 stream=None):
+    _mlp_check(lib().sph_mlp_adam(_ptr(params), _ptr(grads), _ptr(m), _ptr(v), int(step),
+                                  float(lr), float(beta1), float(beta2), float(eps),
+                                  _stream(stream)))
