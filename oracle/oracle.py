@@ -25,6 +25,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "sph_oracle.c")
+_SRC_GRAV = os.path.join(_HERE, "gravity_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 _lock = threading.Lock()
 _lib = None
@@ -35,7 +36,7 @@ def build(force: bool = True) -> str:
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp"
         cmd = ["gcc", "-std=c99", "-O2", "-ffp-contract=off", "-fno-fast-math",
-               "-fopenmp", "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"]
+               "-fopenmp", "-fPIC", "-shared", "-o", tmp, _SRC, _SRC_GRAV, "-lm"]
         subprocess.run(cmd, check=True)
         os.replace(tmp, _LIB)
     return _LIB
@@ -390,3 +391,41 @@ class Integrator:
 
     def __getitem__(self, k):
         return self.arr[k]
+
+
+# ------------------------------------------------- self-gravity, bound mass
+def _runs(n, run_start):
+    if run_start is None:
+        return 1, None
+    rs = np.ascontiguousarray(run_start, dtype=np.int64)
+    return len(rs) - 1, rs
+
+
+def gravity(x, y, z, m, G, eps, active=None, run_start=None):
+    """Direct-sum softened gravity (gravity_oracle.c, reading G1).
+    Returns (ax, ay, az, phi)."""
+    L = lib()
+    x, y, z, m = _f64(x), _f64(y), _f64(z), _f64(m)
+    n = x.size
+    nr, rs = _runs(n, run_start)
+    act = None if active is None else np.ascontiguousarray(active, dtype=np.int32)
+    out = [np.zeros(n) for _ in range(4)]
+    L.or_gravity(C.c_int64(n), _p(x), _p(y), _p(z), _p(m), _p(act, _I32), C.c_int32(nr),
+                 _p(rs, _I64), C.c_double(G), C.c_double(eps), *[_p(o) for o in out])
+    return tuple(out)
+
+
+def bound_mass(x, y, z, vx, vy, vz, m, G, eps, run_start=None, max_iter=100):
+    """Iterative removal of unbound particles per run (reading G2).
+    Returns (bound flags int32, bound mass per run)."""
+    L = lib()
+    arrs = [_f64(a) for a in (x, y, z, vx, vy, vz, m)]
+    n = arrs[0].size
+    nr, rs = _runs(n, run_start)
+    bound = np.zeros(n, dtype=np.int32)
+    mb = np.zeros(nr)
+    L.or_bound_mass.restype = C.c_int32
+    L.or_bound_mass(C.c_int64(n), *[_p(a) for a in arrs], C.c_int32(nr), _p(rs, _I64),
+                    C.c_double(G), C.c_double(eps), C.c_int32(max_iter), _p(bound, _I32),
+                    _p(mb))
+    return bound, mb
