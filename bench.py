@@ -40,16 +40,63 @@ PEAK_HBM = 8.0e12
 FLOPS_PAIR = {1: 122, 0: 116}
 
 
+# Measured HBM traffic of the dominant pair kernel (rocprofv3 FETCH_SIZE and
+# WRITE_SIZE per dispatch, scaled by the same counters on a plain copy of
+# known size).  Valid only for the kernel source it was taken on.
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_grad_forces_c2_fp32_traffic.md")
+TRAFFIC_SOURCES = ("paper_2603_19764_amd/csrc/pairs.hip", "paper_2603_19764_amd/csrc/sph_internal.h")
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def run_steps(w, prec, steps, warmup, use_graph, timing=True):
+def kernel_source_sha256() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for rel in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """Bytes per launch from the committed counter summary, or None when it is
+    missing or was taken on another version of the kernel source."""
+    import re
+    try:
+        text = open(TRAFFIC_FILE).read()
+    except OSError:
+        return None
+    sha = re.search(r"source_sha256:\s*([0-9a-f]{64})", text)
+    val = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", text)
+    if not sha or not val or sha.group(1) != kernel_source_sha256():
+        return None
+    return float(val.group(1))
+
+
+def copy_calibration(mib: int):
+    """A plain device-to-device copy of known size, for scaling the HBM
+    byte counters (profiled together with the workload)."""
     import torch
-    from paper_2603_19764_amd import sph
+    n = mib * (1 << 20) // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    log(f"copy calibration: 3 copies of {mib} MiB ({n * 8} bytes read and written each)")
+    del a, b
+
+
+def run_steps(w, prec, steps, warmup, use_graph, timing=True, tuned=None):
+    import torch
+    from paper_2603_19764_amd import autotune, sph
 
     n = int(w["x"].size)
     ctx = sph.Context(n, max_neighbors=128, max_cells=1 << 22)
+    if tuned:
+        autotune.apply(ctx, prec, tuned)
     st = sph.State(w)
     mats, prm = w["mats"], w["params"]
     sph.sph_init(ctx, st, mats, prm, prec)
@@ -100,6 +147,61 @@ def run_steps(w, prec, steps, warmup, use_graph, timing=True):
     return out
 
 
+def run_batch(steps, warmup, gravity=True, tune=True):
+    """The batched Q_RD* scan: 64 head-on impacts of uneven sizes (targets
+    20k-300k particles, ~7.2M in all) in one set of buffers, FP32 pair
+    arithmetic, self-gravity on, per-run time steps, two steps captured in a
+    hipGraph and replayed.  Rate = ordered pairs of all runs per second."""
+    import torch
+    from paper_2603_19764_amd import autotune, inputs, sph
+
+    b = inputs.scan_batch(64, seed=5)
+    if gravity:
+        b["params"] = inputs.default_params(grav_G=inputs.G_NEWTON)
+    rs = [int(v) for v in b["run_start"]]
+    n = int(b["x"].size)
+    tuned = None
+    if tune:
+        tuned = autotune.tune(b, 1, steps=2, run_start=rs, max_cells=1 << 24)["settings"]
+        log(f"batch autotune: {tuned}")
+    ctx = sph.Context(n, max_neighbors=128, max_cells=1 << 24, max_runs=64)
+    if tuned:
+        autotune.apply(ctx, 1, tuned)
+    st = sph.State(b, run_start=rs)
+    mats, prm = b["mats"], b["params"]
+    sph.sph_init(ctx, st, mats, prm, 1)
+    for _ in range(warmup):
+        sph.sph_step(ctx, st, mats, prm, 1)
+    torch.cuda.synchronize()
+    ctx.check(sph.lib().sph_sync_status(ctx.h, None))
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        sph.sph_step(ctx, st, mats, prm, 1)
+        sph.sph_step(ctx, st, mats, prm, 1)
+    g.replay()  # first replay outside the timed region
+    torch.cuda.synchronize()
+    p0 = sph.sph_pair_count(ctx)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps // 2):
+        g.replay()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    p1 = sph.sph_pair_count(ctx)
+    ctx.check(sph.lib().sph_sync_status(ctx.h, None))
+    k = (steps // 2) * 2
+    dt = st.dt.cpu().numpy()
+    del g
+    ctx.close()
+    return {"workload": f"batched Q_RD* scan: 64 head-on impacts, {n} particles, targets "
+                        f"{min(np.diff(rs))}-{max(np.diff(rs))} per run (incl. projectiles), "
+                        "FP32 pair loop, self-gravity " + ("on" if gravity else "off"),
+            "value": (p1 - p0) / (t1 - t0), "unit": "pairs/s", "steps": k,
+            "ms_per_step": 1e3 * (t1 - t0) / k, "pairs_per_step": (p1 - p0) / k,
+            "graph": True, "launch_shapes": tuned,
+            "dt_spread": float(dt.max() / dt.min())}
+
+
 def cpu_baseline(w, budget_s=15.0):
     """The FP64 oracle on a bounded sample of the same workload: the full
     derivative chain (brute-force pair sets, density + EOS for the pair-set
@@ -139,6 +241,12 @@ def main():
     ap.add_argument("--graph", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--batch-steps", type=int, default=0,
+                    help="steps of the batched 64-impact scan (0: skip it)")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="keep the default launch shapes (no autotuning before the warmup)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="first copy MIB MiB device to device (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -149,13 +257,23 @@ def main():
     from paper_2603_19764_amd import inputs
 
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
     w = inputs.c2_column()
     log(f"workload {w['name']}: n={w['x'].size}")
-    r32 = run_steps(w, 1, args.steps, args.warmup, bool(args.graph))
+    tuned = {0: None, 1: None}
+    if not args.no_tune:
+        from paper_2603_19764_amd import autotune
+        for prec in ((1,) if args.no_fp64 else (1, 0)):
+            t = autotune.tune(w, prec, steps=3)
+            tuned[prec] = t["settings"]
+            log(f"autotune prec {prec}: {t['settings']} {t['times_ms']}")
+    r32 = run_steps(w, 1, args.steps, args.warmup, bool(args.graph), tuned=tuned[1])
     log(f"fp32: {r32['seconds']:.3f} s for {r32['steps']} steps, {r32['pairs']} pairs")
     r64 = None
     if not args.no_fp64:
-        r64 = run_steps(w, 0, max(args.steps // 4, 2), args.warmup, bool(args.graph))
+        r64 = run_steps(w, 0, max(args.steps // 4, 2), args.warmup, bool(args.graph),
+                        tuned=tuned[0])
         log(f"fp64: {r64['seconds']:.3f} s for {r64['steps']} steps, {r64['pairs']} pairs")
     value = r32["pairs"] / r32["seconds"]
     ms_step = 1e3 * r32["seconds"] / r32["steps"]
@@ -166,10 +284,15 @@ def main():
         pairs_per_launch = r32["pairs"] / r32["steps"]
         achieved = FLOPS_PAIR[1] * pairs_per_launch / avg_s
         roof = dict(bound="alu", achieved=achieved / 1e12, peak=PEAK_FP32_VALU / 1e12,
-                    unit="TFLOP/s", frac=achieved / PEAK_FP32_VALU, traffic=None,
-                    kernel="k_grad_forces<8,fp32>", avg_launch_us=avg_s * 1e6,
+                    unit="TFLOP/s", frac=achieved / PEAK_FP32_VALU, traffic=measured_traffic(),
+                    kernel=f"k_grad_forces<{(tuned[1] or {}).get('lanes_step', 8)},fp32>",
+                    avg_launch_us=avg_s * 1e6,
                     kernels_us={k: (v[0] / v[1] * 1e3 if v[1] else None)
                                 for k, v in r32["kernels"].items()})
+    batch = None
+    if args.batch_steps > 0:
+        batch = run_batch(args.batch_steps, 4, tune=not args.no_tune)
+        log(f"batch: {batch['ms_per_step']:.3f} ms/step, {batch['value']:.3e} pairs/s")
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(w)
@@ -182,10 +305,11 @@ def main():
         "config": {"workload": "granular column collapse, 196794 mobile + 29928 fixed particles, "
                                "FP32 cell-relative pair loop, Drucker-Prager tan 30, g = 9.81",
                    "particles": r32["n"], "pairs_per_step": r32["pairs"] / r32["steps"],
-                   "graph": bool(args.graph)},
+                   "graph": bool(args.graph), "launch_shapes": tuned[1]},
         "fp64_plain": None if r64 is None else {
             "value": r64["pairs"] / r64["seconds"], "ms_per_step": 1e3 * r64["seconds"] / r64["steps"],
-            "steps": r64["steps"]},
+            "steps": r64["steps"], "launch_shapes": tuned[0]},
+        "batch_scan": batch,
         "roofline": roof,
         "cpu_baseline": cpu,
     }

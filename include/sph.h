@@ -75,11 +75,14 @@ typedef struct {
 /* Run parameters: Monaghan AV (sec. 2.1), Courant factor (courant_condition
  * eq.), rotation sign of the Jaumann term (+1: R S - S R, the objective
  * rate; -1: the index order as printed), external gravity, correction
- * tensor switch (Corrected_Gradients eq.), Omega = 1 switch. */
+ * tensor switch (Corrected_Gradients eq.), Omega = 1 switch, and the
+ * self-gravity of each run added by sph_step when grav_G > 0 (see
+ * sph_gravity for the meaning of the three grav_ fields). */
 typedef struct {
     double av_alpha, av_beta, av_eps, eta_C, rot_sign;
     double g[3];
     int32_t use_correction_tensor, omega_one;
+    double grav_G, grav_eps_over_h, grav_theta;
 } sph_params;
 
 /* ---------------------------------------------------------------- context */
@@ -243,6 +246,46 @@ sph_status sph_diagnostics(sph_ctx *ctx, int64_t n, const double *x, const doubl
                            const double *ay, const double *az, const double *dudt,
                            double *out13, sph_stream stream);
 
+/* ------------------------------------------------------------ self-gravity */
+
+/* Softened self-gravity of every run (the gravitational term of the
+ * momentum equation, sec. 2.2) at the positions of the last neighbour
+ * search, in its sorted order: Barnes-Hut over a pyramid of the search
+ * cells (level 0 = the cells, level k = 2x2x2 blocks of level k-1),
+ * monopole moments, FP32 arithmetic on positions relative to each run's grid
+ * origin.  The targets of each 2x2x2 block of cells share one walk: a node
+ * whose box is disjoint from the block's and whose edge is below
+ * theta x (distance from its centre of mass to the block) acts on all of
+ * them as a point mass; other nodes are opened down to single particles.
+ * Plummer softening of length eps_r = eps_over_h x max_i h_i of run r:
+ *   a_i = G sum_j m_j (x_j - x_i) / (r^2 + eps_r^2)^(3/2),
+ *   phi_i = -G sum_j m_j / (r^2 + eps_r^2)^(1/2),  j != i, same run.
+ * m: masses (n doubles, sorted order); active: int32 0/1 per particle or
+ * NULL (all): inactive particles exert no gravity but receive it.
+ * ax, ay, az: outputs, overwritten (accumulate = 0) or added to (1); phi:
+ * output or NULL.  G >= 0, eps_over_h > 0, theta in [0.3, 1].  A walk that
+ * outgrows its lists is reported by sph_sync_status (SPH_ECAPACITY) and
+ * leaves NaN in the outputs of its particles. */
+sph_status sph_gravity(sph_ctx *ctx, int64_t n, const double *m, const int32_t *active, double G,
+                       double eps_over_h, double theta, int32_t accumulate, double *ax,
+                       double *ay, double *az, double *phi, sph_stream stream);
+
+/* Bound mass of every run (sec. 3, catastrophic disruption: the bound mass
+ * found by removing unbound particles until none is left), at the positions
+ * of the last neighbour search, sorted order.  Starting from every particle
+ * of its run: v_c = mass-weighted mean velocity of the bound set, phi =
+ * potential of the bound set (sph_gravity with the bound flags as the active
+ * set), and particles with |v - v_c|^2 / 2 + phi > 0 leave the set for good;
+ * repeated until no particle leaves or max_iter passes.  bound: int32 flags
+ * (n), m_bound: bound mass per run (n_runs doubles), work: 4 n doubles of
+ * scratch (the last potential is left in its first n).  Synchronises the
+ * stream once per pass (the test for convergence); not capturable.
+ * iterations: passes done (host, may be NULL). */
+sph_status sph_bound_mass(sph_ctx *ctx, int64_t n, const double *vx, const double *vy,
+                          const double *vz, const double *m, double G, double eps_over_h,
+                          double theta, int32_t max_iter, int32_t *bound, double *m_bound,
+                          double *work, int32_t *iterations, sph_stream stream);
+
 /* ------------------------------------------------------- whole step (a1-a8) */
 
 /* Rows of the persistent double state buffer (each row n_cap doubles).
@@ -277,26 +320,35 @@ typedef struct {
     double *f64[2];              /* two buffers of SPH_NF64 x n_cap doubles; [cur] holds the state */
     int32_t *i32[2];             /* two buffers of SPH_NI32 x n_cap int32          */
     double *work;                /* SPH_NW x n_cap doubles                          */
-    double *dt;                  /* device double: step of the coming drift         */
-    double *dt_next;             /* device double scratch                           */
+    double *dt;                  /* device, one double per run (n_runs of them when
+                                    run_start is set, else one): the step of the
+                                    coming drift of that run                       */
+    double *dt_next;             /* device scratch of the same length               */
     int64_t *n_singular;         /* device counter (may be NULL)                    */
     int32_t cur;                 /* 0 or 1; flipped by every sph_step               */
     int32_t n_runs;
-    const int64_t *run_start;    /* host, n_runs + 1 (NULL: one run)                */
+    const int64_t *run_start;    /* host, n_runs + 1 offsets (NULL: one run).  Runs
+                                    are independent simulations concatenated in the
+                                    buffers: no pair crosses a run, and each run
+                                    takes its own CFL step (batched scans)          */
     double cell_min;
     double dt_max;               /* > 0: upper bound of the step                    */
 } sph_state;
 
 /* Start a run: neighbour search and reorder (buffers flip), derivatives at
  * the current state (predicted values = current values, S rescaled),
- * *dt = min dt_cfl (capped by dt_max) and the first opening kick. */
+ * dt[r] = min of dt_cfl over the particles of run r (capped by dt_max) and
+ * the first opening kick. */
 sph_status sph_init(sph_ctx *ctx, sph_state *st, const sph_material *mats, int32_t n_materials,
                     const sph_params *prm, sph_precision prec, sph_stream stream);
 
 /* One step: drift, neighbour search and reorder (buffers flip), predictor,
  * density + EOS + yield, stress predict and rescale, gradients, stress rate,
- * forces, closing kick with rescale, next step from the CFL minimum, opening
- * kick.  All on `stream`, no host synchronisation. */
+ * forces, closing kick with rescale, next step of each run from its CFL
+ * minimum, opening kick.  All on `stream`, no host synchronisation, no
+ * allocation and no memset: a fixed sequence of kernel launches whose device
+ * pointers repeat every two steps, so an even number of steps can be
+ * captured in a hipGraph and replayed. */
 sph_status sph_step(sph_ctx *ctx, sph_state *st, const sph_material *mats, int32_t n_materials,
                     const sph_params *prm, sph_precision prec, sph_stream stream);
 
@@ -339,6 +391,27 @@ sph_status sph_timing(sph_ctx *ctx, int32_t enable);
 /* Synchronise the recorded events and return the summed duration (ms) and
  * the number of timed launches of kernel `which` since sph_timing(ctx, 1). */
 sph_status sph_timing_read(sph_ctx *ctx, int32_t which, double *total_ms, int64_t *launches);
+
+/* ------------------------------------------------------ launch tuning */
+
+/* Launch-shape knobs of a context, chosen by an autotuner that times them on
+ * a sample of the workload.  None changes a result beyond the summation
+ * order of the pair sums (lanes) or the cell grid (cell scale: the neighbour
+ * sets themselves are exact for any cell edge >= 2 h_max).
+ *   SPH_TUNE_LANES_*   lanes per particle i of a pair pass: 4, 8 or 16
+ *                      (per precision);
+ *   SPH_TUNE_CELL_SCALE cell edge = max(cell_min, scale * 2 h_max), scale in
+ *                      permille, 1000..2000 (precision ignored). */
+enum {
+    SPH_TUNE_LANES_DENSITY = 0,   /* density sweep                         */
+    SPH_TUNE_LANES_GRADIENTS = 1, /* public gradient pass                  */
+    SPH_TUNE_LANES_FORCES = 2,    /* public force pass                     */
+    SPH_TUNE_LANES_STEP = 3,      /* fused gradient + force sweep of sph_step */
+    SPH_TUNE_CELL_SCALE = 4,
+    SPH_TUNE_COUNT = 5
+};
+sph_status sph_set_tuning(sph_ctx *ctx, int32_t knob, sph_precision prec, int32_t value);
+sph_status sph_get_tuning(sph_ctx *ctx, int32_t knob, sph_precision prec, int32_t *value);
 
 #ifdef __cplusplus
 }

@@ -9,7 +9,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsph.so")
-SOURCES = ["api.hip", "cells.hip", "pairs.hip", "integrate.hip", "step.hip", "mlp.hip"]
+SOURCES = ["api.hip", "cells.hip", "pairs.hip", "integrate.hip", "step.hip", "mlp.hip",
+           "gravity.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -138,13 +138,21 @@ sph_status sph_create(sph_ctx **out, int64_t capacity, int32_t max_neighbors, in
         {(void **)&ctx->scan_part, (kScanBlocks + 1) * 8},
         {(void **)&ctx->flags, FLAG_COUNT * 4},
         {(void **)&ctx->pairs, 8},
-        {(void **)&ctx->dtbits, 8},
+        {(void **)&ctx->dtbits, (size_t)max_runs * 8},
         {(void **)&ctx->diag, 256 * 13 * 8},
         {(void **)&ctx->rec_d, cap * 32},
         {(void **)&ctx->rec_g, cap * 96},
         {(void **)&ctx->rec_f, cap * 160},
         {(void **)&ctx->gsum, cap * 15 * 8},
+        {(void **)&ctx->grav_lev, gravity_levels_bytes(max_runs)},
+        {(void **)&ctx->grav_totals, 16},
+        {(void **)&ctx->grav_mom0, ((size_t)max_cells + 1) * sizeof(float4)},
+        {(void **)&ctx->grav_momU, ((size_t)max_cells + 1) * sizeof(float4)},
+        {(void **)&ctx->bm_part, bound_mass_part_bytes(max_runs)},
+        {(void **)&ctx->bm_vcm, (size_t)max_runs * 3 * 8},
+        {(void **)&ctx->bm_removed, 4},
     };
+    ctx->grav_cap_upper = max_cells;
     for (auto &a : allocs) {
         if (hipMalloc(a.p, a.bytes) != hipSuccess) {
             sph_destroy(h);
@@ -152,13 +160,14 @@ sph_status sph_create(sph_ctx **out, int64_t capacity, int32_t max_neighbors, in
         }
     }
     ctx->mats = new Mat[kMaxMaterials];
-    const unsigned long long inf_bits = 0x7ff0000000000000ull;
+    std::vector<unsigned long long> inf_bits((size_t)max_runs, 0x7ff0000000000000ull);
     if (hipMemset(ctx->flags, 0, FLAG_COUNT * 4) != hipSuccess ||
         hipMemset(ctx->pairs, 0, 8) != hipSuccess ||
         hipMemset(ctx->ncount, 0, cap * 4) != hipSuccess ||
         hipMemset(ctx->total_keys, 0, 4) != hipSuccess ||
         hipMemset(ctx->cell_count, 0, ((size_t)max_cells + 1) * 4) != hipSuccess ||
-        hipMemcpy(ctx->dtbits, &inf_bits, 8, hipMemcpyHostToDevice) != hipSuccess) {
+        hipMemcpy(ctx->dtbits, inf_bits.data(), (size_t)max_runs * 8, hipMemcpyHostToDevice) !=
+            hipSuccess) {
         sph_destroy(h);
         return SPH_EHIP;
     }
@@ -173,7 +182,9 @@ sph_status sph_destroy(sph_ctx *h) {
                     ctx->cell_start, ctx->posh64, ctx->posh32, ctx->cellc, ctx->runid,
                     ctx->nbr,  ctx->ncount,    ctx->grid,   ctx->bbox_part, ctx->run_p,
                     ctx->total_keys, ctx->scan_part, ctx->flags, ctx->pairs, ctx->dtbits,
-                    ctx->diag, ctx->rec_d, ctx->rec_g, ctx->rec_f, ctx->gsum};
+                    ctx->diag, ctx->rec_d, ctx->rec_g, ctx->rec_f, ctx->gsum,
+                    ctx->grav_lev, ctx->grav_totals, ctx->grav_mom0, ctx->grav_momU,
+                    ctx->bm_part, ctx->bm_vcm, ctx->bm_removed};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     for (int w = 0; w < SPH_T_COUNT; ++w) {
@@ -203,6 +214,11 @@ sph_status sph_sync_status(sph_ctx *h, sph_stream stream) {
     }
     if (fl[FLAG_CELL_OVERFLOW]) {
         set_error(ctx, "cell table overflow: more than %lld cells", (long long)ctx->max_cells);
+        return SPH_ECAPACITY;
+    }
+    if (fl[FLAG_GRAV_OVERFLOW]) {
+        set_error(ctx, "self-gravity walk outgrew its lists (theta too small for the grid, or "
+                       "too many pyramid nodes)");
         return SPH_ECAPACITY;
     }
     if (fl[FLAG_NONFINITE]) {
@@ -437,6 +453,35 @@ sph_status sph_diagnostics(sph_ctx *h, int64_t n, const double *x, const double 
     return launch_diag(&h->c, n, x, y, z, vx, vy, vz, m, ax, ay, az, dudt, out13, S(stream));
 }
 
+sph_status sph_gravity(sph_ctx *h, int64_t n, const double *m, const int32_t *active, double G,
+                       double eps_over_h, double theta, int32_t accumulate, double *ax,
+                       double *ay, double *az, double *phi, sph_stream stream) {
+    CHECK_CTX();
+    sph_status st = check_built(h, n);
+    if (st != SPH_OK) return st;
+    REQUIRE(G >= 0.0 && eps_over_h > 0.0, SPH_EINVAL, "G must be >= 0 and eps_over_h > 0");
+    REQUIRE(theta >= 0.3 && theta <= 1.0, SPH_EINVAL, "theta %g outside [0.3, 1]", theta);
+    REQUIRE(n == 0 || (m && ax && ay && az), SPH_EINVAL, "null array");
+    return launch_gravity(&h->c, n, m, active, G, eps_over_h, theta, accumulate, ax, ay, az, phi,
+                          S(stream));
+}
+
+sph_status sph_bound_mass(sph_ctx *h, int64_t n, const double *vx, const double *vy,
+                          const double *vz, const double *m, double G, double eps_over_h,
+                          double theta, int32_t max_iter, int32_t *bound, double *m_bound,
+                          double *work, int32_t *iterations, sph_stream stream) {
+    CHECK_CTX();
+    sph_status st = check_built(h, n);
+    if (st != SPH_OK) return st;
+    REQUIRE(G >= 0.0 && eps_over_h > 0.0, SPH_EINVAL, "G must be >= 0 and eps_over_h > 0");
+    REQUIRE(theta >= 0.3 && theta <= 1.0, SPH_EINVAL, "theta %g outside [0.3, 1]", theta);
+    REQUIRE(max_iter >= 1, SPH_EINVAL, "max_iter must be >= 1");
+    REQUIRE(m_bound && (n == 0 || (vx && vy && vz && m && bound && work)), SPH_EINVAL,
+            "null array");
+    return launch_bound_mass(&h->c, n, vx, vy, vz, m, G, eps_over_h, theta, max_iter, bound,
+                             m_bound, work, work + n, iterations, S(stream));
+}
+
 // ------------------------------------------------------------ whole step
 struct Rows {
     double *f[SPH_NF64];
@@ -451,6 +496,8 @@ static Rows rows_of(const sph_state *st, int buf) {
     for (int k = 0; k < SPH_NW; ++k) r.w[k] = st->work + (size_t)k * st->n_cap;
     return r;
 }
+
+static int32_t n_runs_of(const sph_state *st) { return st->run_start ? st->n_runs : 1; }
 
 static sph_status check_state(sph_ctx *h, const sph_state *st) {
     REQUIRE(st, SPH_EINVAL, "null state");
@@ -473,7 +520,7 @@ static sph_status search_and_sort(sph_ctx *h, sph_state *st, sph_precision prec,
     const int cur = st->cur, alt = 1 - cur;
     Rows A = rows_of(st, cur), B = rows_of(st, alt);
     int32_t *perm = (int32_t *)B.w[SPH_W_PERM];
-    const int32_t nr = st->run_start ? st->n_runs : 1;
+    const int32_t nr = n_runs_of(st);
     REQUIRE(nr >= 1 && nr <= ctx->max_runs, SPH_ECAPACITY, "n_runs out of range");
     sph_status e = upload_runs(h, n, nr, st->run_start, s);
     if (e) return e;
@@ -499,7 +546,8 @@ static sph_status search_and_sort(sph_ctx *h, sph_state *st, sph_precision prec,
         r.i_src[k] = A.i[k];
         r.i_dst[k] = B.i[k];
     }
-    if ((e = launch_step_reorder(ctx, n, perm, r, st->dt, predict, B.w[SPH_W_VP],
+    if ((e = launch_step_reorder(ctx, n, perm, r, st->dt, nr > 1 ? ctx->runid : nullptr, predict,
+                                 B.w[SPH_W_VP],
                                  B.w[SPH_W_VP + 1], B.w[SPH_W_VP + 2], B.w[SPH_W_UP], s)))
         return e;
     st->cur = alt;
@@ -517,22 +565,30 @@ static sph_status eval(sph_ctx *h, const sph_state *st, const Rows &R, int32_t n
     Ctx *ctx = &h->c;
     sph_status e;
     const int32_t *fixed = R.i[SPH_FIXED];
+    const int32_t nr = n_runs_of(st);
+    const int16_t *runid = nr > 1 ? ctx->runid : nullptr;
     if ((e = launch_density_pairs(ctx, n, prm, prec, R.w[SPH_W_RHO], R.w[SPH_W_OMEGA], s)))
         return e;
     if ((e = launch_step_state(ctx, n, prec, R.w[SPH_W_RHO], R.w[SPH_W_OMEGA], R.w[SPH_W_UP],
                                R.w[SPH_W_VP], R.w[SPH_W_VP + 1], R.w[SPH_W_VP + 2], R.f[SPH_M],
-                               R.i[SPH_MAT], nmat, fixed, st->dt, predict, R.f[SPH_S],
+                               R.i[SPH_MAT], nmat, fixed, st->dt, runid, predict, R.f[SPH_S],
                                R.f[SPH_SDOT], R.w[SPH_W_P], R.w[SPH_W_CS], R.w[SPH_W_T],
                                R.w[SPH_W_Y], R.w[SPH_W_GMOD], R.w[SPH_W_SP], s)))
         return e;
     if ((e = launch_grad_force_pairs(ctx, n, prm, prec, R.f[SPH_AX], R.f[SPH_AY], R.f[SPH_AZ],
                                      R.f[SPH_DUDT], R.w[SPH_W_DT], s)))
         return e;
+    if (prm->grav_G > 0.0 &&
+        (e = launch_gravity(ctx, n, R.f[SPH_M], nullptr, prm->grav_G, prm->grav_eps_over_h,
+                            prm->grav_theta, 1, R.f[SPH_AX], R.f[SPH_AY], R.f[SPH_AZ], nullptr,
+                            s)))
+        return e;
     if ((e = launch_step_grad_rate(ctx, n, prm, R.w[SPH_W_SP], R.w[SPH_W_GMOD], fixed, st->dt,
-                                   R.w[SPH_W_G], R.f[SPH_SDOT],
+                                   runid, R.w[SPH_W_G], R.f[SPH_SDOT],
                                    accumulate_eps2 ? R.f[SPH_EPS2] : nullptr, st->n_singular, s)))
         return e;
-    return launch_dt_min(ctx, n, R.w[SPH_W_DT], fixed, st->dt_max, st->dt_next, s);
+    return launch_dt_min(ctx, n, R.w[SPH_W_DT], fixed, st->dt_max, st->dt_next, s, nr,
+                         ctx->run_p);
 }
 
 static void swap_dt(sph_state *st) {
@@ -557,7 +613,8 @@ sph_status sph_init(sph_ctx *h, sph_state *st, const sph_material *mats, int32_t
     // predicted values are the current ones: v, u as they are, S rescaled
     if ((e = eval(h, st, R, n_materials, prm, prec, 0, false, s))) return e;
     swap_dt(st);
-    return launch_step_kick(ctx, n, 1, st->dt, st->dt, R.i[SPH_FIXED], R.f[SPH_VX], R.f[SPH_VY],
+    const int16_t *runid = n_runs_of(st) > 1 ? ctx->runid : nullptr;
+    return launch_step_kick(ctx, n, 1, st->dt, st->dt, runid, R.i[SPH_FIXED], R.f[SPH_VX], R.f[SPH_VY],
                             R.f[SPH_VZ], R.f[SPH_U], R.f[SPH_AX], R.f[SPH_AY], R.f[SPH_AZ],
                             R.f[SPH_DUDT], R.f[SPH_S], R.w[SPH_W_SP], R.f[SPH_SDOT],
                             R.w[SPH_W_Y], s);
@@ -577,7 +634,8 @@ sph_status sph_step(sph_ctx *h, sph_state *st, const sph_material *mats, int32_t
     if ((e = search_and_sort(h, st, prec, true, 1, s))) return e;
     Rows R = rows_of(st, st->cur);
     if ((e = eval(h, st, R, n_materials, prm, prec, 1, true, s))) return e;
-    if ((e = launch_step_kick(ctx, n, 0, st->dt, st->dt_next, R.i[SPH_FIXED], R.f[SPH_VX],
+    const int16_t *runid = n_runs_of(st) > 1 ? ctx->runid : nullptr;
+    if ((e = launch_step_kick(ctx, n, 0, st->dt, st->dt_next, runid, R.i[SPH_FIXED], R.f[SPH_VX],
                               R.f[SPH_VY], R.f[SPH_VZ], R.f[SPH_U], R.f[SPH_AX], R.f[SPH_AY],
                               R.f[SPH_AZ], R.f[SPH_DUDT], R.f[SPH_S], R.w[SPH_W_SP],
                               R.f[SPH_SDOT], R.w[SPH_W_Y], s)))
@@ -595,6 +653,33 @@ sph_status sph_timing(sph_ctx *h, int32_t enable) {
         ctx->t_count[w] = 0;
     }
     ctx->timing = enable != 0;
+    return SPH_OK;
+}
+
+sph_status sph_set_tuning(sph_ctx *h, int32_t knob, sph_precision prec, int32_t value) {
+    CHECK_CTX();
+    REQUIRE(knob >= 0 && knob < SPH_TUNE_COUNT, SPH_EINVAL, "unknown tuning knob %d", knob);
+    REQUIRE(prec == SPH_FP64 || prec == SPH_FP32_CELLREL, SPH_EINVAL, "bad precision");
+    Ctx *ctx = &h->c;
+    if (knob == SPH_TUNE_CELL_SCALE) {
+        REQUIRE(value >= 1000 && value <= 2000, SPH_EINVAL, "cell scale %d outside 1000..2000",
+                value);
+        ctx->cell_scale = value / 1000.0;
+        return SPH_OK;
+    }
+    REQUIRE(value == 4 || value == 8 || value == 16, SPH_EINVAL,
+            "lanes per particle must be 4, 8 or 16 (got %d)", value);
+    ctx->lanes[knob][prec == SPH_FP32_CELLREL ? 1 : 0] = value;
+    return SPH_OK;
+}
+
+sph_status sph_get_tuning(sph_ctx *h, int32_t knob, sph_precision prec, int32_t *value) {
+    CHECK_CTX();
+    REQUIRE(knob >= 0 && knob < SPH_TUNE_COUNT && value, SPH_EINVAL, "bad argument");
+    REQUIRE(prec == SPH_FP64 || prec == SPH_FP32_CELLREL, SPH_EINVAL, "bad precision");
+    const Ctx *ctx = &h->c;
+    *value = knob == SPH_TUNE_CELL_SCALE ? (int32_t)(ctx->cell_scale * 1000.0 + 0.5)
+                                         : ctx->lanes[knob][prec == SPH_FP32_CELLREL ? 1 : 0];
     return SPH_OK;
 }
 

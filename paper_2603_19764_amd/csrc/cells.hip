@@ -125,7 +125,7 @@ __global__ void k_bbox(double *x, double *y, double *z, const double *h, const i
     }
     const int r = blockIdx.y;
     const int64_t a = run_p[r], b = run_p[r + 1];
-    const double dt = dtp ? *dtp : 0.0;
+    const double dt = dtp ? dtp[r] : 0.0;  // one time step per run
     double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
     double hm = 0.0;
     for (int64_t k = a + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < b;
@@ -183,7 +183,7 @@ __device__ static int bits_for(int n) {
 // run's bounding-box partials in parallel (into the first partial of the
 // run), then one thread sizes the grids.
 __global__ void k_grid(BBox *part, const int32_t *run_p, int nr, double cell_min,
-                       int64_t max_cells, GridDesc *grid, int32_t *total_keys, int32_t *flags) {
+                       double cell_scale, int64_t max_cells, GridDesc *grid, int32_t *total_keys, int32_t *flags) {
     __shared__ double sh[7][256];
     for (int r = 0; r < nr; ++r) {
         double v[7] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY, 0.0};
@@ -231,7 +231,8 @@ __global__ void k_grid(BBox *part, const int32_t *run_p, int nr, double cell_min
             // Edge at least the largest support 2h (so every pair lies in the
             // 27-cell stencil), slightly enlarged so that rounding of
             // (x - origin)/L can never separate a pair by two cells.
-            double L = fmax(cell_min, 2.0 * bb.hmax) * grow * (1.0 + 1.0 / 1099511627776.0);
+            double L = fmax(cell_min, 2.0 * bb.hmax * cell_scale) * grow *
+                       (1.0 + 1.0 / 1099511627776.0);
             if (!(L > 0.0)) L = 1.0;
             int dims[3];
             for (int d = 0; d < 3; ++d) {
@@ -384,17 +385,23 @@ __global__ void k_gather(int64_t n, const int32_t *perm, const double *x, const 
 
 // ------------------------------------------------------ pair-set builder
 // One wave per work-group.  The work-group owns a contiguous range of
-// sorted particles; for each cell it meets it stages the candidates of the
-// 27 neighbour cells in LDS (chunks of kTile, candidate order = stencil
-// order, then sorted index).  Each lane then holds one candidate of a
-// 64-wide column in registers while the wave walks over the cell's
-// particles i (read from LDS as a broadcast): one exact test per lane, a
-// ballot, and the hits are appended to i's list in candidate order at
-// offsets from mbcnt.  Per-particle counts live in lane q of a register
-// (readlane / writelane), so the loop carries no LDS round trip.  The lists
-// are deterministic.
-constexpr int kTile = 128;
+// sorted particles and walks it cell by cell, in batches of up to 64
+// particles i of one cell.  For each batch, the candidates of the 27
+// neighbour cells (stencil order, then sorted index) are culled and
+// compacted into an LDS tile: a candidate j farther from the bounding box of
+// the batch than max(max_i H_i, H_j) can pair with none of them (the
+// distance to the box bounds every |x_i - x_j| from below; the cut keeps a
+// 2^-40 relative margin over rounding, so the exact criterion still decides
+// every pair that can be one).  The tests then run four i at a time: their
+// positions and running counts are wave-uniform (scalar registers) while
+// each lane holds one candidate of a 64-wide column of the tile; one exact
+// test per lane, a ballot, and the hits are appended to i's list in
+// candidate order at offsets from mbcnt.  The lists are deterministic.
+constexpr int kTileMax = 512;
 constexpr int kIBatch = 64;
+constexpr double kCullMargin = 1.0 + 0x1p-40;
+
+__device__ __forceinline__ uint64_t wave_ballot(bool b) { return __builtin_amdgcn_ballot_w64(b); }
 
 __global__ __launch_bounds__(64) void k_build_pairs(
     int64_t n, const double4 *__restrict__ posh64, const uint32_t *__restrict__ skey,
@@ -402,10 +409,8 @@ __global__ __launch_bounds__(64) void k_build_pairs(
     const GridDesc *__restrict__ grid, const int32_t *__restrict__ cell_start,
     const int32_t *__restrict__ cell_count, const int32_t *total_keys, uint32_t *nbr,
     int32_t *ncount, int32_t K, int32_t *flags, unsigned long long *pairs) {
-    // candidate tile in structure-of-arrays form: lane-consecutive doubles
-    __shared__ double tx[kTile], ty[kTile], tz[kTile], tw[kTile];
-    __shared__ uint32_t tj[kTile];
-    __shared__ double4 ipos[kIBatch + 4];
+    __shared__ double4 tpos[kTileMax];  // x, y, z, H_j^2
+    __shared__ uint32_t tj[kTileMax];   // j | stencil code
     __shared__ int32_t st_start[27];
     __shared__ int32_t st_off[28];
 
@@ -463,65 +468,116 @@ __global__ __launch_bounds__(64) void k_build_pairs(
 
         for (int64_t ib = i_lo; ib < i_hi; ib += kIBatch) {
             const int ni = (int)((i_hi - ib) < kIBatch ? (i_hi - ib) : kIBatch);
+            // bounding box and largest H^2 of the batch
+            double lo0 = INFINITY, lo1 = INFINITY, lo2 = INFINITY;
+            double hi0 = -INFINITY, hi1 = -INFINITY, hi2 = -INFINITY, hm = 0.0;
             if (lane < ni) {
                 const double4 q = posh64[ib + lane];
                 const double H = 2.0 * q.w;
-                ipos[lane] = make_double4(q.x, q.y, q.z, __dmul_rn(H, H));
+                lo0 = hi0 = q.x;
+                lo1 = hi1 = q.y;
+                lo2 = hi2 = q.z;
+                hm = __dmul_rn(H, H);
+            }
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) {
+                lo0 = fmin(lo0, __shfl_xor(lo0, o));
+                lo1 = fmin(lo1, __shfl_xor(lo1, o));
+                lo2 = fmin(lo2, __shfl_xor(lo2, o));
+                hi0 = fmax(hi0, __shfl_xor(hi0, o));
+                hi1 = fmax(hi1, __shfl_xor(hi1, o));
+                hi2 = fmax(hi2, __shfl_xor(hi2, o));
+                hm = fmax(hm, __shfl_xor(hm, o));
             }
             int cnt_reg = 0;  // lane q: running count of particle ib + q
-            for (int c0 = 0; c0 < T; c0 += kTile) {
-                const int nS = (T - c0) < kTile ? (T - c0) : kTile;
+            const double4 *ipos = posh64 + ib;
+
+            for (int r0 = 0; r0 < T;) {
+                // ---- fill: cull raw candidates into the tile
+                int fill = 0;
                 __syncthreads();
-                for (int s = lane; s < nS; s += kWave) {
-                    const int gidx = c0 + s;
-                    int lo = 0, hi = 27;
-                    while (hi - lo > 1) {
-                        const int mid = (lo + hi) >> 1;
-                        if (st_off[mid] <= gidx) lo = mid; else hi = mid;
+                for (; r0 < T && fill <= kTileMax - kWave; r0 += kWave) {
+                    const int gidx = r0 + lane;
+                    bool keep = false;
+                    double4 c = make_double4(0.0, 0.0, 0.0, 0.0);
+                    uint32_t code = 0;
+                    if (gidx < T) {
+                        int lo = 0, hi = 27;
+                        while (hi - lo > 1) {
+                            const int mid = (lo + hi) >> 1;
+                            if (st_off[mid] <= gidx) lo = mid; else hi = mid;
+                        }
+                        const int j = st_start[lo] + (gidx - st_off[lo]);
+                        c = posh64[j];
+                        const double H = 2.0 * c.w;
+                        c.w = __dmul_rn(H, H);
+                        code = (uint32_t)j | ((uint32_t)lo << kCodeShift);
+                        const double ex = fmax(fmax(lo0 - c.x, c.x - hi0), 0.0);
+                        const double ey = fmax(fmax(lo1 - c.y, c.y - hi1), 0.0);
+                        const double ez = fmax(fmax(lo2 - c.z, c.z - hi2), 0.0);
+                        const double d2 = (ex * ex + ey * ey) + ez * ez;
+                        keep = !(d2 >= fmax(hm, c.w) * kCullMargin);
                     }
-                    const int j = st_start[lo] + (gidx - st_off[lo]);
-                    const double4 q = posh64[j];
-                    const double H = 2.0 * q.w;
-                    tx[s] = q.x;
-                    ty[s] = q.y;
-                    tz[s] = q.z;
-                    tw[s] = __dmul_rn(H, H);
-                    tj[s] = (uint32_t)j | ((uint32_t)lo << kCodeShift);
+                    const uint64_t m = wave_ballot(keep);
+                    if (keep) {
+                        const int s = fill + (int)__builtin_amdgcn_mbcnt_hi(
+                                                 (uint32_t)(m >> 32),
+                                                 __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+                        tpos[s] = c;
+                        tj[s] = code;
+                    }
+                    fill += __popcll(m);
                 }
                 __syncthreads();
-                for (int col = 0; col < nS; col += kWave) {
-                    const int s = col + lane;
-                    const bool valid = s < nS;
-                    double4 cj = make_double4(0.0, 0.0, 0.0, -1.0);
-                    uint32_t e = 0xffffffffu;
-                    if (valid) {
-                        cj = make_double4(tx[s], ty[s], tz[s], tw[s]);
-                        e = tj[s];
+                // ---- tests: four i at a time against every column of the tile
+                for (int q0 = 0; q0 < ni; q0 += 4) {
+                    const int l = ni - 1;
+                    const int q1 = q0 + 1 < l ? q0 + 1 : l, q2 = q0 + 2 < l ? q0 + 2 : l,
+                              q3 = q0 + 3 < l ? q0 + 3 : l;
+                    const double4 P[4] = {ipos[q0], ipos[q1], ipos[q2], ipos[q3]};
+                    const int qq[4] = {q0, q1, q2, q3};
+                    double H2[4];
+                    int base[4];
+                    uint32_t *row[4];
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        const double H = 2.0 * P[k].w;
+                        H2[k] = __dmul_rn(H, H);
+                        base[k] = __builtin_amdgcn_readlane(cnt_reg, qq[k]);
+                        row[k] = nbr + (ib + qq[k]) * (int64_t)K;
                     }
-                    const int64_t j = valid ? (int64_t)(e & kIdxMask) : -1;
-                    // test the column against particle ib + q, append the hits
-                    auto visit = [&](int q, const double4 &pi) {
-                        const double r2 = sep2_exact(pi.x, pi.y, pi.z, cj.x, cj.y, cj.z);
-                        const bool hit = valid && (j != ib + q) && (r2 < fmax(pi.w, cj.w));
-                        const uint64_t m = __ballot(hit);
-                        if (m) {
-                            const int base = __builtin_amdgcn_readlane(cnt_reg, q);
-                            const int rank = __builtin_amdgcn_mbcnt_hi(
-                                (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-                            if (hit && base + rank < K)
-                                nbr[(ib + q) * (int64_t)K + base + rank] =
-                                    e | (r2 < pi.w ? kDensityBit : 0u);
-                            if (lane == q) cnt_reg = base + __popcll(m);
+                    const int nk = ni - q0 < 4 ? ni - q0 : 4;  // distinct i in this group
+                    for (int col = 0; col < fill; col += kWave) {
+                        const int s = col + lane;
+                        double4 c = make_double4(NAN, 0.0, 0.0, -1.0);
+                        uint32_t e = 0;
+                        if (s < fill) {
+                            c = tpos[s];
+                            e = tj[s];
                         }
-                    };
-                    for (int q = 0; q < ni; q += 4) {  // four broadcast reads in flight
-                        const double4 p0 = ipos[q], p1 = ipos[q + 1], p2 = ipos[q + 2],
-                                      p3 = ipos[q + 3];
-                        visit(q, p0);
-                        if (q + 1 < ni) visit(q + 1, p1);
-                        if (q + 2 < ni) visit(q + 2, p2);
-                        if (q + 3 < ni) visit(q + 3, p3);
+                        const uint32_t jj = e & kIdxMask;
+                        const uint32_t ed = e | kDensityBit;
+#pragma unroll
+                        for (int k = 0; k < 4; ++k) {
+                            if (k < nk) {
+                                const double r2 =
+                                    sep2_exact(P[k].x, P[k].y, P[k].z, c.x, c.y, c.z);
+                                const bool dens = r2 < H2[k];
+                                const bool hit =
+                                    (dens || r2 < c.w) && jj != (uint32_t)(ib + qq[k]);
+                                const uint64_t m = wave_ballot(hit);
+                                // slot = base + rank; rows hold at most K entries
+                                const uint32_t rank = __builtin_amdgcn_mbcnt_hi(
+                                    (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+                                const int b = base[k];
+                                if (hit && (int)rank < K - b) row[k][b + rank] = dens ? ed : e;
+                                base[k] = __builtin_amdgcn_readfirstlane(b + (int)__popcll(m));
+                            }
+                        }
                     }
+#pragma unroll
+                    for (int k = 0; k < 4; ++k)
+                        if (k < nk && lane == qq[k]) cnt_reg = base[k];
                 }
             }
             if (lane < ni) {
@@ -529,7 +585,6 @@ __global__ __launch_bounds__(64) void k_build_pairs(
                 if (cnt_reg > K) atomicOr(&flags[FLAG_NBR_OVERFLOW], 1);
                 my_pairs += (unsigned long long)cnt_reg;
             }
-            __syncthreads();
         }
         p = i_hi;
     }
@@ -555,7 +610,7 @@ sph_status launch_build_cells(Ctx *ctx, int64_t n, double *x, double *y, double 
                        ctx->bbox_part, ctx->cell_count, ctx->total_keys, ex->dt, ex->vx, ex->vy,
                        ex->vz, ex->fixed);
     hipLaunchKernelGGL(k_grid, dim3(1), dim3(256), 0, s, ctx->bbox_part, ctx->run_p, nr, cell_min,
-                       ctx->max_cells, ctx->grid, ctx->total_keys, ctx->flags);
+                       ctx->cell_scale, ctx->max_cells, ctx->grid, ctx->total_keys, ctx->flags);
     hipLaunchKernelGGL(k_keys, dim3(nb), dim3(tb), 0, s, n, x, y, z, ctx->run_p, nr, ctx->grid,
                        ctx->total_keys, ctx->key, ctx->slot, ctx->cell_count);
     sph_status st = scan<int32_t, int32_t>(ctx, ctx->cell_count, ctx->cell_start,

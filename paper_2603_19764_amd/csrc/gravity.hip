@@ -1,0 +1,569 @@
+// Self-gravity of each run (the gravitational term of the momentum equation,
+// sec. 2.2) for the batched impact scans: Barnes-Hut over a pyramid built on
+// the search cells of the last neighbour search.
+//
+//   level 0   the search cells of the run (edge L >= 2 h_max), indexed by
+//             their Morton key in the global cell table;
+//   level k   dense grid of 2x2x2 blocks of level k-1, up to the first level
+//             whose every dimension is <= 2.
+// Each node holds a monopole (mass and centre of mass, FP32, relative to the
+// run's grid origin).  Targets are grouped by level-1 node (2x2x2 cells); a
+// group walks the pyramid breadth first, one candidate node per lane: a
+// node whose box is disjoint from the group's box and whose edge is below
+// theta times the distance from its centre of mass to that box is used for
+// every target of the group; other nodes are opened, and opened leaves
+// contribute their particles one by one.  Plummer softening of length
+// eps_r = eps_over_h * max_i h_i of the run; sources inside the near field
+// exclude the target itself.
+#include "sph_internal.h"
+
+namespace sph {
+
+constexpr int kGravLevels = 12;
+constexpr int kCand = 2048;   // candidates of one level of one group walk
+constexpr int kIL = 512;      // accepted monopoles held before evaluation
+constexpr int kStage = 128;   // near-field source particles held before evaluation
+constexpr int kSlots = 4;     // targets per lane per pass
+
+struct GravLevels {
+    int32_t nlev;                      // levels 0 .. nlev-1
+    int32_t nx[kGravLevels], ny[kGravLevels], nz[kGravLevels];
+    int64_t off[kGravLevels];          // level k >= 1: first node in the upper array
+    int64_t grp_off;                   // first group of this run
+    int32_t grp_level;                 // 1, or 0 for a run of a single cell
+    double eps;                        // softening length
+};
+
+__device__ __forceinline__ int ceil_half(int n, int k) { return (n + (1 << k) - 1) >> k; }
+
+// One thread: level sizes and offsets of every run, group offsets, totals.
+__global__ void k_grav_layout(int nr, const GridDesc *__restrict__ grid,
+                              const BBox *__restrict__ bbox_part, double eps_over_h,
+                              GravLevels *lev, int64_t *totals, int64_t cap_upper,
+                              int32_t *flags) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    int64_t up = 0, groups = 0;
+    for (int r = 0; r < nr; ++r) {
+        const GridDesc g = grid[r];
+        GravLevels L;
+        L.nx[0] = g.nx; L.ny[0] = g.ny; L.nz[0] = g.nz;
+        L.off[0] = 0;
+        int k = 0;
+        while (k + 1 < kGravLevels && (L.nx[k] > 2 || L.ny[k] > 2 || L.nz[k] > 2)) {
+            ++k;
+            L.nx[k] = ceil_half(g.nx, k);
+            L.ny[k] = ceil_half(g.ny, k);
+            L.nz[k] = ceil_half(g.nz, k);
+            L.off[k] = up;
+            up += (int64_t)L.nx[k] * L.ny[k] * L.nz[k];
+        }
+        L.nlev = k + 1;
+        L.grp_level = L.nlev > 1 ? 1 : 0;
+        L.grp_off = groups;
+        groups += (int64_t)L.nx[L.grp_level] * L.ny[L.grp_level] * L.nz[L.grp_level];
+        L.eps = eps_over_h * bbox_part[r * kBBoxBlocks].hmax;
+        lev[r] = L;
+    }
+    totals[0] = up;
+    totals[1] = groups;
+    if (up > cap_upper) {
+        flags[FLAG_GRAV_OVERFLOW] = 1;
+        totals[1] = 0;  // nothing is evaluated
+    }
+}
+
+__device__ __forceinline__ int run_of_key(const GridDesc *grid, int nr, int64_t key) {
+    int lo = 0, hi = nr;  // grid[lo].key_off <= key
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (grid[mid].key_off <= key) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+// Leaf monopoles: one thread per key of the global cell table.
+__global__ void k_grav_leaf(int nr, const GridDesc *__restrict__ grid,
+                            const int32_t *__restrict__ total_keys,
+                            const int32_t *__restrict__ cell_start,
+                            const int32_t *__restrict__ cell_count,
+                            const double4 *__restrict__ posh64, const double *__restrict__ m,
+                            const int32_t *__restrict__ active, float4 *mom0) {
+    const int64_t nk = *total_keys;
+    for (int64_t key = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; key < nk;
+         key += (int64_t)gridDim.x * blockDim.x) {
+        const int cnt = cell_count[key];
+        float4 out = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (cnt > 0) {
+            const GridDesc g = grid[run_of_key(grid, nr, key)];
+            const int s = cell_start[key];
+            double M = 0.0, sx = 0.0, sy = 0.0, sz = 0.0;
+            for (int k = 0; k < cnt; ++k) {
+                const int j = s + k;
+                const double mj = (active && !active[j]) ? 0.0 : m[j];
+                const double4 p = posh64[j];
+                M += mj;
+                sx += mj * (p.x - g.ox);
+                sy += mj * (p.y - g.oy);
+                sz += mj * (p.z - g.oz);
+            }
+            if (M > 0.0) out = make_float4((float)(sx / M), (float)(sy / M), (float)(sz / M), (float)M);
+        }
+        mom0[key] = out;
+    }
+}
+
+__device__ __forceinline__ float4 node_moment(const GridDesc &g, const GravLevels &L,
+                                              const float4 *mom0, const float4 *momU, int k,
+                                              int cx, int cy, int cz) {
+    if (k == 0)
+        return mom0[(uint32_t)g.key_off + morton(cx, cy, cz, g.bx, g.by, g.bz)];
+    return momU[L.off[k] + ((int64_t)cz * L.ny[k] + cy) * L.nx[k] + cx];
+}
+
+// Level-k monopoles from the eight children at level k-1 (k >= 1).
+__global__ void k_grav_up(int nr, int k, const GridDesc *__restrict__ grid,
+                          const GravLevels *__restrict__ lev, const int64_t *__restrict__ totals,
+                          int64_t cap_upper, const float4 *__restrict__ mom0, float4 *momU) {
+    if (totals[0] > cap_upper) return;  // layout overflow (flagged): nothing fits
+    for (int r = blockIdx.y; r < nr; r += gridDim.y) {
+        const GravLevels &L = lev[r];
+        if (k >= L.nlev) continue;
+        const GridDesc g = grid[r];
+        const int nx = L.nx[k], ny = L.ny[k], nz = L.nz[k];
+        const int64_t cells = (int64_t)nx * ny * nz;
+        for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < cells;
+             c += (int64_t)gridDim.x * blockDim.x) {
+            const int cx = (int)(c % nx), cy = (int)((c / nx) % ny), cz = (int)(c / ((int64_t)nx * ny));
+            double M = 0.0, sx = 0.0, sy = 0.0, sz = 0.0;
+            for (int d = 0; d < 8; ++d) {
+                const int x = 2 * cx + (d & 1), y = 2 * cy + ((d >> 1) & 1), z = 2 * cz + (d >> 2);
+                if (x >= L.nx[k - 1] || y >= L.ny[k - 1] || z >= L.nz[k - 1]) continue;
+                const float4 q = node_moment(g, L, mom0, momU, k - 1, x, y, z);
+                M += q.w;
+                sx += (double)q.w * q.x;
+                sy += (double)q.w * q.y;
+                sz += (double)q.w * q.z;
+            }
+            momU[L.off[k] + c] = M > 0.0 ? make_float4((float)(sx / M), (float)(sy / M),
+                                                       (float)(sz / M), (float)M)
+                                         : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+    }
+}
+
+// ------------------------------------------------------------ group walk
+struct Acc {
+    float ax[kSlots], ay[kSlots], az[kSlots], ph[kSlots];
+    float tx[kSlots], ty[kSlots], tz[kSlots];
+    int32_t ti[kSlots];
+};
+
+__global__ __launch_bounds__(64) void k_grav_walk(
+    int nr, const GridDesc *__restrict__ grid, const GravLevels *__restrict__ lev,
+    const int64_t *__restrict__ totals, const int32_t *__restrict__ cell_start,
+    const int32_t *__restrict__ cell_count, const double4 *__restrict__ posh64,
+    const double *__restrict__ m, const int32_t *__restrict__ active,
+    const float4 *__restrict__ mom0, const float4 *__restrict__ momU, float Gc, float theta,
+    int32_t accumulate, double *ax, double *ay, double *az, double *phi, int32_t *flags) {
+    __shared__ uint32_t cand[2][kCand];
+    __shared__ float4 il[kIL];
+    __shared__ float4 stg[kStage];
+    __shared__ int32_t stg_j[kStage];
+    __shared__ int32_t leaf_s[8], leaf_c[8];
+    const int lane = threadIdx.x;
+    const int64_t ngroups = totals[1];
+
+    for (int64_t grp = blockIdx.x; grp < ngroups; grp += gridDim.x) {
+        // ---- which run and which level-gl node
+        int r = 0;
+        {
+            int lo = 0, hi = nr;
+            while (hi - lo > 1) {
+                const int mid = (lo + hi) >> 1;
+                if (lev[mid].grp_off <= grp) lo = mid; else hi = mid;
+            }
+            r = lo;
+        }
+        const GravLevels &L = lev[r];
+        const GridDesc g = grid[r];
+        const int gl = L.grp_level;
+        const int64_t loc = grp - L.grp_off;
+        const int gnx = L.nx[gl], gny = L.ny[gl];
+        const int gx = (int)(loc % gnx), gy = (int)((loc / gnx) % gny),
+                  gz = (int)(loc / ((int64_t)gnx * gny));
+        // ---- target cells of the group (its level-0 cells)
+        __syncthreads();
+        if (lane < 8) {
+            int s = 0, c = 0;
+            const int span = gl == 1 ? 2 : 1;
+            const int x = gx * span + (lane & 1), y = gy * span + ((lane >> 1) & 1),
+                      z = gz * span + (lane >> 2);
+            const bool inside = (gl == 1 || lane == 0) && x < L.nx[0] && y < L.ny[0] && z < L.nz[0];
+            if (inside) {
+                const uint32_t key = (uint32_t)g.key_off + morton(x, y, z, g.bx, g.by, g.bz);
+                s = cell_start[key];
+                c = cell_count[key];
+            }
+            leaf_s[lane] = s;
+            leaf_c[lane] = c;
+        }
+        __syncthreads();
+        int nt = 0;
+        for (int q = 0; q < 8; ++q) nt += leaf_c[q];
+        if (nt == 0) continue;
+        const float edge_g = (float)(g.L * (double)(1 << gl));
+        const float blo[3] = {gx * edge_g, gy * edge_g, gz * edge_g};
+        const float bhi[3] = {blo[0] + edge_g, blo[1] + edge_g, blo[2] + edge_g};
+        const float e2 = (float)(L.eps * L.eps);
+
+        for (int t0 = 0; t0 < nt; t0 += kWave * kSlots) {
+            Acc A;
+#pragma unroll
+            for (int s = 0; s < kSlots; ++s) {
+                A.ax[s] = A.ay[s] = A.az[s] = A.ph[s] = 0.f;
+                A.ti[s] = -1;
+                A.tx[s] = A.ty[s] = A.tz[s] = 0.f;
+                const int t = t0 + s * kWave + lane;
+                if (t < nt) {
+                    int q = 0, base = 0;
+                    while (t >= base + leaf_c[q]) { base += leaf_c[q]; ++q; }
+                    const int i = leaf_s[q] + (t - base);
+                    const double4 p = posh64[i];
+                    A.ti[s] = i;
+                    A.tx[s] = (float)(p.x - g.ox);
+                    A.ty[s] = (float)(p.y - g.oy);
+                    A.tz[s] = (float)(p.z - g.oz);
+                }
+            }
+            int n_il = 0, n_st = 0;
+            auto flush_il = [&]() {
+                __syncthreads();
+                for (int e = 0; e < n_il; ++e) {
+                    const float4 q = il[e];
+#pragma unroll
+                    for (int s = 0; s < kSlots; ++s) {
+                        const float dx = q.x - A.tx[s], dy = q.y - A.ty[s], dz = q.z - A.tz[s];
+                        const float r2 = dx * dx + dy * dy + dz * dz + e2;
+                        const float ri = __frsqrt_rn(r2);
+                        const float mr = q.w * ri;
+                        const float mr3 = mr * ri * ri;
+                        A.ax[s] += mr3 * dx;
+                        A.ay[s] += mr3 * dy;
+                        A.az[s] += mr3 * dz;
+                        A.ph[s] += mr;
+                    }
+                }
+                n_il = 0;
+                __syncthreads();
+            };
+            auto flush_st = [&]() {
+                __syncthreads();
+                for (int e = 0; e < n_st; ++e) {
+                    const float4 q = stg[e];
+                    const int j = stg_j[e];
+#pragma unroll
+                    for (int s = 0; s < kSlots; ++s) {
+                        const float dx = q.x - A.tx[s], dy = q.y - A.ty[s], dz = q.z - A.tz[s];
+                        const float r2 = dx * dx + dy * dy + dz * dz + e2;
+                        const float ri = __frsqrt_rn(r2);
+                        const float mr = (j == A.ti[s]) ? 0.f : q.w * ri;
+                        const float mr3 = mr * ri * ri;
+                        A.ax[s] += mr3 * dx;
+                        A.ay[s] += mr3 * dy;
+                        A.az[s] += mr3 * dz;
+                        A.ph[s] += mr;
+                    }
+                }
+                n_st = 0;
+                __syncthreads();
+            };
+            // ---- breadth-first walk from the top level
+            const int top = L.nlev - 1;
+            int cur = 0, n_cur = 0;
+            {
+                const int tn = L.nx[top] * L.ny[top] * L.nz[top];  // <= 8
+                if (lane < tn) cand[0][lane] = (uint32_t)lane;
+                n_cur = tn;
+            }
+            bool overflow = false;
+            for (int k = top; k >= 0 && !overflow; --k) {
+                __syncthreads();
+                const int nx = L.nx[k], ny = L.ny[k];
+                const float edge = (float)(g.L * (double)(1 << k));
+                int n_next = 0;
+                for (int c0 = 0; c0 < n_cur; c0 += kWave) {
+                    const int c = c0 + lane;
+                    bool acc_node = false, open = false, leaf_open = false;
+                    float4 q = make_float4(0.f, 0.f, 0.f, 0.f);
+                    int cx = 0, cy = 0, cz = 0;
+                    if (c < n_cur) {
+                        const uint32_t id = cand[cur][c];
+                        cx = (int)(id % (uint32_t)nx);
+                        cy = (int)((id / (uint32_t)nx) % (uint32_t)ny);
+                        cz = (int)(id / ((uint32_t)nx * (uint32_t)ny));
+                        q = node_moment(g, L, mom0, momU, k, cx, cy, cz);
+                        if (q.w > 0.f) {
+                            const float nlo[3] = {cx * edge, cy * edge, cz * edge};
+                            const bool disjoint = nlo[0] >= bhi[0] || nlo[0] + edge <= blo[0] ||
+                                                  nlo[1] >= bhi[1] || nlo[1] + edge <= blo[1] ||
+                                                  nlo[2] >= bhi[2] || nlo[2] + edge <= blo[2];
+                            const float ex = fmaxf(fmaxf(blo[0] - q.x, q.x - bhi[0]), 0.f);
+                            const float ey = fmaxf(fmaxf(blo[1] - q.y, q.y - bhi[1]), 0.f);
+                            const float ez = fmaxf(fmaxf(blo[2] - q.z, q.z - bhi[2]), 0.f);
+                            const float d2 = ex * ex + ey * ey + ez * ez;
+                            acc_node = disjoint && edge * edge < theta * theta * d2;
+                            open = !acc_node && k > 0;
+                            leaf_open = !acc_node && k == 0;
+                        }
+                    }
+                    // accepted monopoles
+                    {
+                        const uint64_t mk = __builtin_amdgcn_ballot_w64(acc_node);
+                        const int cnt = __popcll(mk);
+                        if (n_il + cnt > kIL) flush_il();
+                        if (acc_node) {
+                            const int rk = (int)__builtin_amdgcn_mbcnt_hi(
+                                (uint32_t)(mk >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mk, 0u));
+                            il[n_il + rk] = q;
+                        }
+                        n_il += cnt;
+                    }
+                    // children of opened nodes
+                    {
+                        const uint64_t mk = __builtin_amdgcn_ballot_w64(open);
+                        const int cnt = __popcll(mk);
+                        if (n_next + 8 * cnt > kCand) {
+                            overflow = true;
+                        } else if (open) {
+                            const int rk = (int)__builtin_amdgcn_mbcnt_hi(
+                                (uint32_t)(mk >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mk, 0u));
+                            const int cnx = L.nx[k - 1], cny = L.ny[k - 1], cnz = L.nz[k - 1];
+                            for (int d = 0; d < 8; ++d) {
+                                const int x = 2 * cx + (d & 1), y = 2 * cy + ((d >> 1) & 1),
+                                          z = 2 * cz + (d >> 2);
+                                const bool ok = x < cnx && y < cny && z < cnz;
+                                cand[cur ^ 1][n_next + 8 * rk + d] =
+                                    ok ? (uint32_t)((z * cny + y) * cnx + x) : 0xffffffffu;
+                            }
+                        }
+                        if (!overflow) n_next += 8 * cnt;
+                    }
+                    // opened leaves: stage their particles, one leaf at a time
+                    {
+                        uint64_t mk = __builtin_amdgcn_ballot_w64(leaf_open);
+                        while (mk) {
+                            const int src = __builtin_ctzll(mk);
+                            mk &= mk - 1;
+                            const uint32_t key = (uint32_t)g.key_off +
+                                                 morton(__shfl(cx, src), __shfl(cy, src),
+                                                        __shfl(cz, src), g.bx, g.by, g.bz);
+                            const int s0 = cell_start[key], cnt = cell_count[key];
+                            for (int b = 0; b < cnt; b += kWave) {
+                                const int take = cnt - b < kWave ? cnt - b : kWave;
+                                if (n_st + take > kStage) flush_st();
+                                if (lane < take) {
+                                    const int j = s0 + b + lane;
+                                    const double4 p = posh64[j];
+                                    const double mj = (active && !active[j]) ? 0.0 : m[j];
+                                    stg[n_st + lane] = make_float4((float)(p.x - g.ox),
+                                                                   (float)(p.y - g.oy),
+                                                                   (float)(p.z - g.oz), (float)mj);
+                                    stg_j[n_st + lane] = j;
+                                }
+                                n_st += take;
+                            }
+                        }
+                    }
+                }
+                // drop the out-of-range children appended above
+                __syncthreads();
+                int kept = 0;
+                for (int c0 = 0; c0 < n_next; c0 += kWave) {
+                    const int c = c0 + lane;
+                    const uint32_t id = c < n_next ? cand[cur ^ 1][c] : 0xffffffffu;
+                    const bool ok = id != 0xffffffffu;
+                    const uint64_t mk = __builtin_amdgcn_ballot_w64(ok);
+                    __syncthreads();
+                    if (ok) {
+                        const int rk = (int)__builtin_amdgcn_mbcnt_hi(
+                            (uint32_t)(mk >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mk, 0u));
+                        cand[cur ^ 1][kept + rk] = id;
+                    }
+                    kept += __popcll(mk);
+                    __syncthreads();
+                }
+                cur ^= 1;
+                n_cur = kept;
+            }
+            if (overflow) {
+                if (lane == 0) atomicOr(&flags[FLAG_GRAV_OVERFLOW], 1);
+                // leave the outputs of this group as NaN so that nothing uses them silently
+#pragma unroll
+                for (int s = 0; s < kSlots; ++s) A.ax[s] = A.ay[s] = A.az[s] = A.ph[s] = NAN;
+                n_il = n_st = 0;
+            }
+            flush_il();
+            flush_st();
+#pragma unroll
+            for (int s = 0; s < kSlots; ++s) {
+                const int i = A.ti[s];
+                if (i < 0) continue;
+                const double fx = (double)Gc * A.ax[s], fy = (double)Gc * A.ay[s],
+                             fz = (double)Gc * A.az[s];
+                if (accumulate) {
+                    ax[i] += fx;
+                    ay[i] += fy;
+                    az[i] += fz;
+                } else {
+                    ax[i] = fx;
+                    ay[i] = fy;
+                    az[i] = fz;
+                }
+                if (phi) phi[i] = -(double)Gc * A.ph[s];
+            }
+        }
+    }
+}
+
+sph_status launch_gravity(Ctx *ctx, int64_t n, const double *m, const int32_t *active, double G,
+                          double eps_over_h, double theta, int32_t accumulate, double *ax,
+                          double *ay, double *az, double *phi, hipStream_t s) {
+    if (n == 0) return SPH_OK;
+    const int nr = ctx->n_runs_built;
+    hipLaunchKernelGGL(k_grav_layout, dim3(1), dim3(64), 0, s, nr, ctx->grid, ctx->bbox_part,
+                       eps_over_h, (GravLevels *)ctx->grav_lev, ctx->grav_totals, ctx->grav_cap_upper,
+                       ctx->flags);
+    hipLaunchKernelGGL(k_grav_leaf, dim3(2048), dim3(256), 0, s, nr, ctx->grid, ctx->total_keys,
+                       ctx->cell_start, ctx->cell_count, ctx->posh64, m, active, ctx->grav_mom0);
+    const int ry = nr < 64 ? nr : 64;
+    for (int k = 1; k < kGravLevels; ++k)
+        hipLaunchKernelGGL(k_grav_up, dim3(64, ry), dim3(256), 0, s, nr, k, ctx->grid,
+                           (const GravLevels *)ctx->grav_lev, ctx->grav_totals,
+                           ctx->grav_cap_upper, ctx->grav_mom0, ctx->grav_momU);
+    hipLaunchKernelGGL(k_grav_walk, dim3(8192), dim3(64), 0, s, nr, ctx->grid,
+                       (const GravLevels *)ctx->grav_lev,
+                       ctx->grav_totals, ctx->cell_start, ctx->cell_count, ctx->posh64, m, active,
+                       ctx->grav_mom0, ctx->grav_momU, (float)G, (float)theta, accumulate, ax, ay,
+                       az, phi, ctx->flags);
+    SPH_HIP(hipGetLastError());
+    return SPH_OK;
+}
+
+size_t gravity_levels_bytes(int32_t max_runs) { return (size_t)max_runs * sizeof(GravLevels); }
+
+}  // namespace sph
+
+// ------------------------------------------------------------ bound mass
+namespace sph {
+
+constexpr int kBmBlocks = 64;  // partial sums per run
+
+__global__ void k_bm_fill(int64_t n, int32_t *bound) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        bound[i] = 1;
+}
+
+// Per (run, block) partial sums of m, m v over the bound particles; fixed
+// order, so the totals are reproducible.
+__global__ void k_bm_partial(const int32_t *__restrict__ run_p, const double *__restrict__ vx,
+                             const double *__restrict__ vy, const double *__restrict__ vz,
+                             const double *__restrict__ m, const int32_t *__restrict__ bound,
+                             double *part) {
+    const int r = blockIdx.y;
+    const int64_t a = run_p[r], b = run_p[r + 1];
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int64_t i = a + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < b;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        if (!bound[i]) continue;
+        s[0] += m[i];
+        s[1] += m[i] * vx[i];
+        s[2] += m[i] * vy[i];
+        s[3] += m[i] * vz[i];
+    }
+    __shared__ double sh[4][256];
+    for (int c = 0; c < 4; ++c) sh[c][threadIdx.x] = s[c];
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < (unsigned)o)
+            for (int c = 0; c < 4; ++c) sh[c][threadIdx.x] += sh[c][threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x < 4) part[((int64_t)r * kBmBlocks + blockIdx.x) * 4 + threadIdx.x] = sh[threadIdx.x][0];
+}
+
+// Run totals: M_r and the centre-of-mass velocity of the bound set.
+__global__ void k_bm_total(int nr, const double *__restrict__ part, double *m_bound,
+                           double *vcm, int32_t *removed) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nr) return;
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int b = 0; b < kBmBlocks; ++b)
+        for (int c = 0; c < 4; ++c) s[c] += part[((int64_t)r * kBmBlocks + b) * 4 + c];
+    m_bound[r] = s[0];
+    for (int c = 0; c < 3; ++c) vcm[r * 3 + c] = s[0] > 0.0 ? s[1 + c] / s[0] : 0.0;
+    if (r == 0) *removed = 0;
+}
+
+// Remove the particles with |v - v_c|^2 / 2 + phi > 0 from the bound set.
+__global__ void k_bm_update(const int32_t *__restrict__ run_p, const double *__restrict__ vx,
+                            const double *__restrict__ vy, const double *__restrict__ vz,
+                            const double *__restrict__ phi, const double *__restrict__ vcm,
+                            int32_t *bound, int32_t *removed) {
+    const int r = blockIdx.y;
+    const int64_t a = run_p[r], b = run_p[r + 1];
+    const double cx = vcm[r * 3], cy = vcm[r * 3 + 1], cz = vcm[r * 3 + 2];
+    int out = 0;
+    for (int64_t i = a + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < b;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        if (!bound[i]) continue;
+        const double ux = vx[i] - cx, uy = vy[i] - cy, uz = vz[i] - cz;
+        if (0.5 * ((ux * ux + uy * uy) + uz * uz) + phi[i] > 0.0) {
+            bound[i] = 0;
+            ++out;
+        }
+    }
+    const uint64_t mk = __ballot(out > 0);
+    if (mk) {
+        int v = out;
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+        if ((threadIdx.x % kWave) == 0) atomicAdd(removed, v);
+    }
+}
+
+sph_status launch_bound_mass(Ctx *ctx, int64_t n, const double *vx, const double *vy,
+                             const double *vz, const double *m, double G, double eps_over_h,
+                             double theta, int32_t max_iter, int32_t *bound, double *m_bound,
+                             double *phi, double *acc3, int32_t *iterations, hipStream_t s) {
+    const int nr = ctx->n_runs_built;
+    hipLaunchKernelGGL(k_bm_fill, dim3(1024), dim3(256), 0, s, n, bound);
+    int32_t it = 0;
+    for (; it < max_iter; ++it) {
+        hipLaunchKernelGGL(k_bm_partial, dim3(kBmBlocks, nr), dim3(256), 0, s, ctx->run_p, vx, vy,
+                           vz, m, bound, ctx->bm_part);
+        hipLaunchKernelGGL(k_bm_total, dim3((nr + 255) / 256), dim3(256), 0, s, nr, ctx->bm_part,
+                           m_bound, ctx->bm_vcm, ctx->bm_removed);
+        sph_status e = launch_gravity(ctx, n, m, bound, G, eps_over_h, theta, 0, acc3, acc3 + n,
+                                      acc3 + 2 * n, phi, s);
+        if (e != SPH_OK) return e;
+        hipLaunchKernelGGL(k_bm_update, dim3(kBmBlocks, nr), dim3(256), 0, s, ctx->run_p, vx, vy,
+                           vz, phi, ctx->bm_vcm, bound, ctx->bm_removed);
+        SPH_HIP(hipGetLastError());
+        int32_t removed = 0;
+        SPH_HIP(hipMemcpyAsync(&removed, ctx->bm_removed, 4, hipMemcpyDeviceToHost, s));
+        SPH_HIP(hipStreamSynchronize(s));
+        if (removed == 0) break;
+    }
+    // bound mass of the final set
+    hipLaunchKernelGGL(k_bm_partial, dim3(kBmBlocks, nr), dim3(256), 0, s, ctx->run_p, vx, vy, vz,
+                       m, bound, ctx->bm_part);
+    hipLaunchKernelGGL(k_bm_total, dim3((nr + 255) / 256), dim3(256), 0, s, nr, ctx->bm_part,
+                       m_bound, ctx->bm_vcm, ctx->bm_removed);
+    SPH_HIP(hipGetLastError());
+    if (iterations) *iterations = it;
+    return SPH_OK;
+}
+
+size_t bound_mass_part_bytes(int32_t max_runs) { return (size_t)max_runs * kBmBlocks * 4 * 8; }
+
+}  // namespace sph

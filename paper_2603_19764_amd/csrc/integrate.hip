@@ -144,10 +144,17 @@ sph_status launch_kick_drift(Ctx *ctx, int32_t phase, int64_t n, const double *d
 // ------------------------------------------------------------ dt minimum
 // Positive doubles order like their bit patterns, so an integer atomicMin on
 // the bits is an exact, order-independent minimum.
-__global__ void k_dt_reduce(int64_t n, const double *__restrict__ dtc,
-                            const int32_t *__restrict__ fixed, unsigned long long *bits) {
+// One minimum per run: blockIdx.y is the run, whose particles are the
+// contiguous range [run_p[r], run_p[r+1]) of the sorted order (the whole
+// range [0, n) when run_p is null).
+__global__ void k_dt_reduce(int64_t n, const int32_t *__restrict__ run_p,
+                            const double *__restrict__ dtc, const int32_t *__restrict__ fixed,
+                            unsigned long long *bits_all) {
+    const int r = blockIdx.y;
+    const int64_t a = run_p ? run_p[r] : 0, b = run_p ? run_p[r + 1] : n;
+    unsigned long long *bits = bits_all + r;
     unsigned long long best = 0x7ff0000000000000ull;
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+    for (int64_t i = a + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < b;
          i += (int64_t)gridDim.x * blockDim.x) {
         if (fixed && fixed[i]) continue;
         const double d = dtc[i];
@@ -169,21 +176,29 @@ __global__ void k_dt_reduce(int64_t n, const double *__restrict__ dtc,
     }
 }
 
-__global__ void k_dt_final(unsigned long long *bits, double cap, double *out) {
-    double d = __longlong_as_double((long long)*bits);
+__global__ void k_dt_final(int nr, unsigned long long *bits, double cap, double *out) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nr) return;
+    double d = __longlong_as_double((long long)bits[r]);
     if (cap > 0.0 && !(d <= cap)) d = cap;
-    *out = d;
-    *bits = 0x7ff0000000000000ull;  // ready for the next reduction
+    out[r] = d;
+    bits[r] = 0x7ff0000000000000ull;  // ready for the next reduction
 }
 
 sph_status launch_dt_min(Ctx *ctx, int64_t n, const double *dtc, const int32_t *fixed,
-                         double cap, double *out, hipStream_t s) {
+                         double cap, double *out, hipStream_t s, int32_t nr,
+                         const int32_t *run_p) {
+    if (nr < 1 || nr > ctx->max_runs || (nr > 1 && !run_p)) return SPH_EINVAL;
     if (n > 0) {
-        int nb = (int)((n + 1023) / 1024);
-        nb = nb > 256 ? 256 : nb;
-        hipLaunchKernelGGL(k_dt_reduce, dim3(nb), dim3(1024), 0, s, n, dtc, fixed, ctx->dtbits);
+        // about 256 blocks in all, at least one per run
+        int nb = (int)((n / nr + 1023) / 1024);
+        const int cap_b = 256 / nr > 1 ? 256 / nr : 1;
+        nb = nb < 1 ? 1 : (nb > cap_b ? cap_b : nb);
+        hipLaunchKernelGGL(k_dt_reduce, dim3(nb, nr), dim3(1024), 0, s, n, nr > 1 ? run_p : nullptr,
+                           dtc, fixed, ctx->dtbits);
     }
-    hipLaunchKernelGGL(k_dt_final, dim3(1), dim3(1), 0, s, ctx->dtbits, cap, out);
+    hipLaunchKernelGGL(k_dt_final, dim3((nr + 255) / 256), dim3(256), 0, s, nr, ctx->dtbits, cap,
+                       out);
     SPH_HIP(hipGetLastError());
     return SPH_OK;
 }

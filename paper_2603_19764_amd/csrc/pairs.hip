@@ -509,7 +509,7 @@ __global__ __launch_bounds__(kBlock) void k_grad_forces(
 }
 
 // =============================================================== launches
-int g_lanes_density = 8, g_lanes_gradients = 8, g_lanes_forces = 8;
+static int lanes_of(const Ctx *ctx, int knob, bool f32) { return ctx->lanes[knob][f32 ? 1 : 0]; }
 
 template <int L, bool F32>
 static void density_launch(Ctx *ctx, int64_t n, const sph_params *prm, double *rho,
@@ -524,7 +524,7 @@ static void density_launch(Ctx *ctx, int64_t n, const sph_params *prm, double *r
 template <bool F32>
 static void density_dispatch(Ctx *ctx, int64_t n, const sph_params *prm, double *rho,
                              double *omega, hipStream_t s) {
-    switch (g_lanes_density) {
+    switch (lanes_of(ctx, SPH_TUNE_LANES_DENSITY, F32)) {
         case 4: density_launch<4, F32>(ctx, n, prm, rho, omega, s); break;
         case 16: density_launch<16, F32>(ctx, n, prm, rho, omega, s); break;
         default: density_launch<8, F32>(ctx, n, prm, rho, omega, s); break;
@@ -577,7 +577,7 @@ static void grad_launch(Ctx *ctx, int64_t n, hipStream_t s) {
 
 template <bool F32>
 static void grad_dispatch(Ctx *ctx, int64_t n, hipStream_t s) {
-    switch (g_lanes_gradients) {
+    switch (lanes_of(ctx, SPH_TUNE_LANES_GRADIENTS, F32)) {
         case 4: grad_launch<4, F32>(ctx, n, s); break;
         case 16: grad_launch<16, F32>(ctx, n, s); break;
         default: grad_launch<8, F32>(ctx, n, s); break;
@@ -628,7 +628,7 @@ static void forces_launch(Ctx *ctx, int64_t n, const sph_params *prm, double *ax
 template <bool F32>
 static void forces_dispatch(Ctx *ctx, int64_t n, const sph_params *prm, double *ax, double *ay,
                             double *az, double *dudt, double *dtc, hipStream_t s) {
-    switch (g_lanes_forces) {
+    switch (lanes_of(ctx, SPH_TUNE_LANES_FORCES, F32)) {
         case 4: forces_launch<4, F32>(ctx, n, prm, ax, ay, az, dudt, dtc, s); break;
         case 16: forces_launch<16, F32>(ctx, n, prm, ax, ay, az, dudt, dtc, s); break;
         default: forces_launch<8, F32>(ctx, n, prm, ax, ay, az, dudt, dtc, s); break;
@@ -668,7 +668,7 @@ static void both_launch(Ctx *ctx, int64_t n, const sph_params *prm, double *ax, 
 template <bool F32>
 static void both_dispatch(Ctx *ctx, int64_t n, const sph_params *prm, double *ax, double *ay,
                           double *az, double *dudt, double *dtc, hipStream_t s) {
-    switch (g_lanes_forces) {
+    switch (lanes_of(ctx, SPH_TUNE_LANES_STEP, F32)) {
         case 4: both_launch<4, F32>(ctx, n, prm, ax, ay, az, dudt, dtc, s); break;
         case 16: both_launch<16, F32>(ctx, n, prm, ax, ay, az, dudt, dtc, s); break;
         default: both_launch<8, F32>(ctx, n, prm, ax, ay, az, dudt, dtc, s); break;

@@ -21,7 +21,13 @@ constexpr int kMaxMortonBits = 10;                 // per axis
 constexpr int kNumXcd = 8;                         // MI355X: 8 XCDs, round-robin dispatch
 
 // Flags raised on the device (ctx->flags[...]).
-enum { FLAG_NBR_OVERFLOW = 0, FLAG_CELL_OVERFLOW = 1, FLAG_NONFINITE = 2, FLAG_COUNT = 4 };
+enum {
+    FLAG_NBR_OVERFLOW = 0,
+    FLAG_CELL_OVERFLOW = 1,
+    FLAG_NONFINITE = 2,
+    FLAG_GRAV_OVERFLOW = 3,
+    FLAG_COUNT = 4
+};
 
 // Uniform cell grid of one run.
 struct GridDesc {
@@ -51,6 +57,19 @@ struct Ctx {
     int64_t max_cells = 0;
     int32_t max_runs = 0;
     int32_t num_cu = 256;
+    // launch shapes chosen by the autotuner: lanes per particle of the pair
+    // passes [knob][precision], and the cell edge as a multiple of 2 h_max
+    int32_t lanes[4][2] = {{8, 8}, {8, 8}, {8, 8}, {8, 8}};
+    double cell_scale = 1.0;
+    // self-gravity pyramid (allocated with the context)
+    void *grav_lev = nullptr;        // per-run level layout (max_runs entries)
+    int64_t *grav_totals = nullptr;  // [upper nodes, groups]
+    float4 *grav_mom0 = nullptr;     // max_cells leaf monopoles (by cell key)
+    float4 *grav_momU = nullptr;     // grav_cap_upper monopoles of levels >= 1
+    int64_t grav_cap_upper = 0;
+    double *bm_part = nullptr;       // bound mass: per-(run, block) partial sums
+    double *bm_vcm = nullptr;        // centre-of-mass velocity per run
+    int32_t *bm_removed = nullptr;   // particles removed in the last pass
     // scratch (device)
     uint32_t *key = nullptr;        // capacity: cell key, input order
     int32_t *slot = nullptr;        // capacity: arrival rank within the cell
@@ -238,8 +257,27 @@ sph_status launch_kick_drift(Ctx *ctx, int32_t phase, int64_t n, const double *d
                              const double *ax, const double *ay, const double *az,
                              const double *dudt, double *vpx, double *vpy, double *vpz,
                              double *up, hipStream_t s);
+// Per-run minima (nr runs over run_p) into out[0..nr); nr = 1 with a null
+// run_p is the whole range.
 sph_status launch_dt_min(Ctx *ctx, int64_t n, const double *dtc, const int32_t *fixed,
-                         double cap, double *out, hipStream_t s);
+                         double cap, double *out, hipStream_t s, int32_t nr = 1,
+                         const int32_t *run_p = nullptr);
+
+// Self-gravity of every run at the last build (sorted order); see sph_gravity.
+sph_status launch_gravity(Ctx *ctx, int64_t n, const double *m, const int32_t *active, double G,
+                          double eps_over_h, double theta, int32_t accumulate, double *ax,
+                          double *ay, double *az, double *phi, hipStream_t s);
+size_t gravity_levels_bytes(int32_t max_runs);
+sph_status launch_bound_mass(Ctx *ctx, int64_t n, const double *vx, const double *vy,
+                             const double *vz, const double *m, double G, double eps_over_h,
+                             double theta, int32_t max_iter, int32_t *bound, double *m_bound,
+                             double *phi, double *acc3, int32_t *iterations, hipStream_t s);
+size_t bound_mass_part_bytes(int32_t max_runs);
+
+// Time step of sorted particle i: one per run when runid is given.
+__device__ __forceinline__ double dt_of(const double *dtp, const int16_t *runid, int64_t i) {
+    return dtp[runid ? (int)runid[i] : 0];
+}
 sph_status launch_diag(Ctx *ctx, int64_t n, const double *x, const double *y, const double *z,
                        const double *vx, const double *vy, const double *vz, const double *m,
                        const double *ax, const double *ay, const double *az,
@@ -263,24 +301,24 @@ struct StepRows {
     int32_t *i_dst[SPH_NI32];
 };
 sph_status launch_step_reorder(Ctx *ctx, int64_t n, const int32_t *perm, const StepRows &r,
-                               const double *dt, int32_t predict, double *vpx, double *vpy,
-                               double *vpz, double *up, hipStream_t s);
+                               const double *dt, const int16_t *runid, int32_t predict,
+                               double *vpx, double *vpy, double *vpz, double *up, hipStream_t s);
 sph_status launch_step_state(Ctx *ctx, int64_t n, sph_precision prec, const double *rho,
                              const double *omega, const double *up, const double *vpx,
                              const double *vpy, const double *vpz, const double *m,
                              const int32_t *mat, int32_t nmat, const int32_t *fixed,
-                             const double *dt, int32_t predict, const double *S_half,
-                             const double *Sdot, double *P, double *cs, double *T, double *Y,
+                             const double *dt, const int16_t *runid, int32_t predict,
+                             const double *S_half, const double *Sdot, double *P, double *cs, double *T, double *Y,
                              double *Gmod, double *S_pred, hipStream_t s);
 sph_status launch_step_grad_rate(Ctx *ctx, int64_t n, const sph_params *prm,
                                  const double *S_pred, const double *Gmod, const int32_t *fixed,
-                                 const double *dt, double *G, double *Sdot, double *eps2,
-                                 int64_t *n_singular, hipStream_t s);
+                                 const double *dt, const int16_t *runid, double *G,
+                                 double *Sdot, double *eps2, int64_t *n_singular, hipStream_t s);
 sph_status launch_step_kick(Ctx *ctx, int64_t n, int32_t mode, const double *dt,
-                            const double *dt_next, const int32_t *fixed, double *vx, double *vy,
-                            double *vz, double *u, const double *ax, const double *ay,
-                            const double *az, const double *dudt, double *S_half,
-                            const double *S_pred, const double *Sdot, const double *Y,
-                            hipStream_t s);
+                            const double *dt_next, const int16_t *runid, const int32_t *fixed,
+                            double *vx, double *vy, double *vz, double *u, const double *ax,
+                            const double *ay, const double *az, const double *dudt,
+                            double *S_half, const double *S_pred, const double *Sdot,
+                            const double *Y, hipStream_t s);
 
 }  // namespace sph

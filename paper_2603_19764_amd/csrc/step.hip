@@ -14,7 +14,8 @@ namespace sph {
 
 // --------------------------------------------------- reorder + predictor
 __global__ void k_reorder_predict(int64_t n, const int32_t *__restrict__ perm, StepRows r,
-                                  const double *__restrict__ dtp, int32_t predict,
+                                  const double *__restrict__ dtp,
+                                  const int16_t *__restrict__ runid, int32_t predict,
                                   double *__restrict__ vpx, double *__restrict__ vpy,
                                   double *__restrict__ vpz, double *__restrict__ up) {
     const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -33,7 +34,7 @@ __global__ void k_reorder_predict(int64_t n, const int32_t *__restrict__ perm, S
         r.i_dst[c][k] = v;
         if (c == SPH_FIXED) fx = v;
     }
-    const double hd = (predict && !fx) ? 0.5 * *dtp : 0.0;
+    const double hd = (predict && !fx) ? 0.5 * dt_of(dtp, runid, k) : 0.0;
     vpx[k] = f[SPH_VX] + hd * f[SPH_AX];
     vpy[k] = f[SPH_VY] + hd * f[SPH_AY];
     vpz[k] = f[SPH_VZ] + hd * f[SPH_AZ];
@@ -51,7 +52,8 @@ __global__ void k_state(int64_t n, const double4 *__restrict__ posh64,
                         const double *__restrict__ vpx, const double *__restrict__ vpy,
                         const double *__restrict__ vpz, const double *__restrict__ m,
                         const int32_t *__restrict__ mat, const int32_t *__restrict__ fixed,
-                        MatTable mt, const double *__restrict__ dtp, int32_t predict,
+                        MatTable mt, const double *__restrict__ dtp,
+                        const int16_t *__restrict__ runid, int32_t predict,
                         const double *__restrict__ S_half, const double *__restrict__ Sdot,
                         double *__restrict__ P, double *__restrict__ cs, double *__restrict__ T,
                         double *__restrict__ Y, double *__restrict__ Gmod,
@@ -70,7 +72,7 @@ __global__ void k_state(int64_t n, const double4 *__restrict__ posh64,
     Y[i] = y;
     Gmod[i] = gm;
     const bool fx = fixed && fixed[i];
-    const double hd = (predict && !fx) ? 0.5 * *dtp : 0.0;
+    const double hd = (predict && !fx) ? 0.5 * dt_of(dtp, runid, i) : 0.0;
     double s[5];
     for (int k = 0; k < 5; ++k) s[k] = S_half[k * n + i] + hd * Sdot[k * n + i];
     plastic_return(s, y);
@@ -101,7 +103,8 @@ __global__ void k_grad_rate(int64_t n, const double *__restrict__ gsum,
                             const int32_t *__restrict__ ncount, int32_t use_corr,
                             const double *__restrict__ S_pred, const double *__restrict__ Gmod,
                             const int32_t *__restrict__ fixed, double rot,
-                            const double *__restrict__ dtp, double *__restrict__ G,
+                            const double *__restrict__ dtp,
+                            const int16_t *__restrict__ runid, double *__restrict__ G,
                             double *__restrict__ Sdot, double *__restrict__ eps2,
                             int64_t *n_singular) {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -115,7 +118,7 @@ __global__ void k_grad_rate(int64_t n, const double *__restrict__ gsum,
         for (int k = 0; k < 5; ++k) s[k] = S_pred[k * n + i];
         stress_rate(g, s, Gmod[i], rot, ds, e2);
         for (int k = 0; k < 5; ++k) Sdot[k * n + i] = ds[k];
-        if (eps2 && !(fixed && fixed[i])) eps2[i] += *dtp * e2;
+        if (eps2 && !(fixed && fixed[i])) eps2[i] += dt_of(dtp, runid, i) * e2;
     }
     if (n_singular) {
         const uint64_t mk = __ballot(sing);
@@ -128,7 +131,8 @@ __global__ void k_grad_rate(int64_t n, const double *__restrict__ gsum,
 // mode 0: closing kick with rescaling then opening kick (a step);
 // mode 1: opening kick from the predicted stress (start of a run).
 __global__ void k_kick_all(int64_t n, int32_t mode, const double *__restrict__ dtp,
-                           const double *__restrict__ dtnp, const int32_t *__restrict__ fixed,
+                           const double *__restrict__ dtnp, const int16_t *__restrict__ runid,
+                           const int32_t *__restrict__ fixed,
                            double *vx, double *vy, double *vz, double *u,
                            const double *__restrict__ ax, const double *__restrict__ ay,
                            const double *__restrict__ az, const double *__restrict__ dudt,
@@ -137,9 +141,9 @@ __global__ void k_kick_all(int64_t n, int32_t mode, const double *__restrict__ d
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n) return;
     if (fixed && fixed[i]) return;
-    const double hn = 0.5 * *dtnp;
+    const double hn = 0.5 * dt_of(dtnp, runid, i);
     if (mode == 0) {
-        const double hd = 0.5 * *dtp;
+        const double hd = 0.5 * dt_of(dtp, runid, i);
         vx[i] = (vx[i] + hd * ax[i]) + hn * ax[i];
         vy[i] = (vy[i] + hd * ay[i]) + hn * ay[i];
         vz[i] = (vz[i] + hd * az[i]) + hn * az[i];
@@ -162,11 +166,12 @@ __global__ void k_kick_all(int64_t n, int32_t mode, const double *__restrict__ d
 
 // -------------------------------------------------------------- launches
 sph_status launch_step_reorder(Ctx *ctx, int64_t n, const int32_t *perm, const StepRows &r,
-                               const double *dt, int32_t predict, double *vpx, double *vpy,
+                               const double *dt, const int16_t *runid, int32_t predict,
+                               double *vpx, double *vpy,
                                double *vpz, double *up, hipStream_t s) {
     if (n == 0) return SPH_OK;
     hipLaunchKernelGGL(k_reorder_predict, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n,
-                       perm, r, dt, predict, vpx, vpy, vpz, up);
+                       perm, r, dt, runid, predict, vpx, vpy, vpz, up);
     SPH_HIP(hipGetLastError());
     return SPH_OK;
 }
@@ -175,7 +180,8 @@ sph_status launch_step_state(Ctx *ctx, int64_t n, sph_precision prec, const doub
                              const double *omega, const double *up, const double *vpx,
                              const double *vpy, const double *vpz, const double *m,
                              const int32_t *mat, int32_t nmat, const int32_t *fixed,
-                             const double *dt, int32_t predict, const double *S_half,
+                             const double *dt, const int16_t *runid, int32_t predict,
+                             const double *S_half,
                              const double *Sdot, double *P, double *cs, double *T, double *Y,
                              double *Gmod, double *S_pred, hipStream_t s) {
     if (n == 0) return SPH_OK;
@@ -186,36 +192,38 @@ sph_status launch_step_state(Ctx *ctx, int64_t n, sph_precision prec, const doub
     if (prec == SPH_FP32_CELLREL)
         hipLaunchKernelGGL((k_state<true>), dim3(nb), dim3(256), 0, s, n, ctx->posh64,
                            ctx->posh32, rho, omega, up, vpx, vpy, vpz, m, mat, fixed, mt, dt,
-                           predict, S_half, Sdot, P, cs, T, Y, Gmod, S_pred, ctx->rec_f);
+                           runid, predict, S_half, Sdot, P, cs, T, Y, Gmod, S_pred, ctx->rec_f);
     else
         hipLaunchKernelGGL((k_state<false>), dim3(nb), dim3(256), 0, s, n, ctx->posh64,
                            ctx->posh32, rho, omega, up, vpx, vpy, vpz, m, mat, fixed, mt, dt,
-                           predict, S_half, Sdot, P, cs, T, Y, Gmod, S_pred, ctx->rec_f);
+                           runid, predict, S_half, Sdot, P, cs, T, Y, Gmod, S_pred, ctx->rec_f);
     SPH_HIP(hipGetLastError());
     return SPH_OK;
 }
 
 sph_status launch_step_grad_rate(Ctx *ctx, int64_t n, const sph_params *prm,
                                  const double *S_pred, const double *Gmod, const int32_t *fixed,
-                                 const double *dt, double *G, double *Sdot, double *eps2,
+                                 const double *dt, const int16_t *runid, double *G,
+                                 double *Sdot, double *eps2,
                                  int64_t *n_singular, hipStream_t s) {
     if (n == 0) return SPH_OK;
     hipLaunchKernelGGL(k_grad_rate, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n,
                        ctx->gsum, ctx->ncount, prm->use_correction_tensor, S_pred, Gmod, fixed,
-                       prm->rot_sign, dt, G, Sdot, eps2, n_singular);
+                       prm->rot_sign, dt, runid, G, Sdot, eps2, n_singular);
     SPH_HIP(hipGetLastError());
     return SPH_OK;
 }
 
 sph_status launch_step_kick(Ctx *ctx, int64_t n, int32_t mode, const double *dt,
-                            const double *dt_next, const int32_t *fixed, double *vx, double *vy,
+                            const double *dt_next, const int16_t *runid, const int32_t *fixed, double *vx, double *vy,
                             double *vz, double *u, const double *ax, const double *ay,
                             const double *az, const double *dudt, double *S_half,
                             const double *S_pred, const double *Sdot, const double *Y,
                             hipStream_t s) {
     if (n == 0) return SPH_OK;
     hipLaunchKernelGGL(k_kick_all, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, mode,
-                       dt, dt_next, fixed, vx, vy, vz, u, ax, ay, az, dudt, S_half, S_pred, Sdot,
+                       dt, dt_next, runid, fixed, vx, vy, vz, u, ax, ay, az, dudt, S_half, S_pred,
+                       Sdot,
                        Y);
     SPH_HIP(hipGetLastError());
     return SPH_OK;

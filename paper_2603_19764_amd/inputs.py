@@ -69,9 +69,12 @@ def fluid(mat: dict) -> dict:
 
 def default_params(**kw) -> dict:
     """Monaghan artificial viscosity alpha = 1, beta = 2, epsilon = 0.01;
-    Courant factor 0.3; objective Jaumann rotation sign; correction tensor on."""
+    Courant factor 0.3; objective Jaumann rotation sign; correction tensor on;
+    self-gravity off (grav_G = 0; softening 0.5 h_max and opening angle 0.6
+    when switched on)."""
     p = dict(av_alpha=1.0, av_beta=2.0, av_eps=0.01, eta_C=0.3, rot_sign=1.0,
-             g=(0.0, 0.0, 0.0), box=(0.0, 0.0, 0.0), use_correction=1, omega_one=0)
+             g=(0.0, 0.0, 0.0), box=(0.0, 0.0, 0.0), use_correction=1, omega_one=0,
+             grav_G=0.0, grav_eps_over_h=0.5, grav_theta=0.6)
     p.update(kw)
     return p
 
@@ -221,3 +224,97 @@ def random_cloud(n: int, seed: int, h_spread: float = 0.0, box: float = 6.0) -> 
     w["S"] = rng.normal(0.0, 20.0e6, size=(5, n))
     w.update(mats=[basalt_c1()], params=default_params(), name=f"cloud_{n}_{seed}")
     return w
+
+
+_PER_PARTICLE = ("x", "y", "z", "vx", "vy", "vz", "u", "m", "h", "mat", "fixed")
+
+
+def concat_runs(runs: list) -> dict:
+    """Several independent workloads in one set of buffers (a batched scan):
+    per-particle arrays concatenated run after run, ``run_start`` the n_runs + 1
+    offsets.  The runs share the material table and parameters of the first."""
+    w = {k: np.concatenate([r[k] for r in runs]) for k in _PER_PARTICLE}
+    w["S"] = np.concatenate([r["S"] for r in runs], axis=1)
+    w["run_start"] = np.concatenate([[0], np.cumsum([r["x"].size for r in runs])]).astype(np.int64)
+    w.update(mats=runs[0]["mats"], params=runs[0]["params"],
+             name="+".join(r.get("name", "run") for r in runs))
+    return w
+
+
+G_NEWTON = 6.674e-11
+
+
+def bcc_ball(n_target: int, radius: float):
+    """Body-centred cubic lattice clipped to a ball, spacing chosen so that
+    about n_target points fall inside (two points per cubic cell of edge a).
+    Returns the points and the mean interparticle spacing (1/n)^(1/3)."""
+    a = (2.0 * (4.0 / 3.0) * math.pi * radius ** 3 / n_target) ** (1.0 / 3.0)
+    k = int(math.ceil(radius / a)) + 1
+    c = np.arange(-k, k + 1) * a
+    Z, Y, X = np.meshgrid(c, c, c, indexing="ij")
+    corner = np.stack([X.ravel(), Y.ravel(), Z.ravel()], axis=1)
+    P = np.concatenate([corner, corner + 0.5 * a])
+    P = P[np.einsum("ij,ij->i", P, P) < radius * radius]
+    return P, a / 2.0 ** (1.0 / 3.0)
+
+
+def impact_pair(n_target: int, gamma: float = 0.1, r_c1: float = 1.0e6, v_over_vesc: float = 2.0,
+                strength: bool = True, mat_id: int = 0, mat: dict | None = None) -> dict:
+    """Head-on collision of two BCC spheres of one material with equal
+    particle masses: target of ~n_target particles and projectile of mass
+    ratio gamma = M_p / M_t.  The total mass is that of a sphere of radius
+    r_c1 at 1000 kg/m^3; each body has the material's reference density.  The
+    projectile starts one spacing from contact on the -x side and moves at
+    v = v_over_vesc * v_esc along +x, with v_esc = sqrt(2 G M_tot / (R_t + R_p));
+    the target is at rest.  u = 0, S = 0.  ``strength`` only labels the run
+    (the material row at ``mat_id`` decides what the step computes)."""
+    mat = mat or granite_c3()
+    rho = mat["rho0"]
+    m_tot = 4.0 / 3.0 * math.pi * r_c1 ** 3 * 1000.0
+    m_t, m_p = m_tot / (1.0 + gamma), m_tot * gamma / (1.0 + gamma)
+    r_t = (3.0 * m_t / (4.0 * math.pi * rho)) ** (1.0 / 3.0)
+    r_p = (3.0 * m_p / (4.0 * math.pi * rho)) ** (1.0 / 3.0)
+    Pt, sp = bcc_ball(n_target, r_t)
+    mpart = m_t / Pt.shape[0]
+    Pp, _ = bcc_ball(max(int(round(Pt.shape[0] * gamma)), 1), r_p)
+    v_esc = math.sqrt(2.0 * G_NEWTON * m_tot / (r_t + r_p))
+    Pp = Pp + np.array([-(r_t + r_p + sp), 0.0, 0.0])
+    P = np.concatenate([Pt, Pp])
+    n = P.shape[0]
+    w = _empty(n)
+    w.update(x=P[:, 0].copy(), y=P[:, 1].copy(), z=P[:, 2].copy(), m=np.full(n, mpart),
+             h=np.full(n, 1.3 * sp))
+    w["vx"][Pt.shape[0]:] = v_over_vesc * v_esc
+    w["mat"][:] = mat_id
+    w.update(mats=[mat], params=default_params(), n_target=int(Pt.shape[0]),
+             name=f"impact_{Pt.shape[0]}+{Pp.shape[0]}",
+             case=dict(m_tot=m_tot, gamma=gamma, strength=int(strength), v_esc=v_esc,
+                       v=v_over_vesc * v_esc, r_t=r_t, r_p=r_p))
+    return w
+
+
+def scan_batch(n_runs: int = 64, seed: int = 5, n_min: int = 20_000, n_max: int = 300_000,
+               gamma: float = 0.1, scale: float = 1.0) -> dict:
+    """A batched Q_RD* scan: n_runs head-on impacts with target particle counts
+    log-uniform in [n_min, n_max] (times ``scale`` for small copies), mass
+    ratio gamma, R_C1 log-uniform in [4.64e5, 4.64e6] m, v/v_esc log-uniform
+    in [1, 10] and strength on or off with probability 1/2.  Material 0 is
+    granite with strength, material 1 the same without; runs are concatenated
+    (``run_start``) and ``cases`` lists each run's parameters."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    strong = granite_c3()
+    mats = [strong, fluid(strong)]
+    runs, cases = [], []
+    for _ in range(n_runs):
+        nt = int(round(math.exp(rng.uniform(math.log(n_min), math.log(n_max))) * scale))
+        rc1 = math.exp(rng.uniform(math.log(4.64e5), math.log(4.64e6)))
+        vv = math.exp(rng.uniform(0.0, math.log(10.0)))
+        st = bool(rng.integers(0, 2))
+        w = impact_pair(max(nt, 8), gamma, rc1, vv, st, mat_id=0 if st else 1, mat=strong)
+        runs.append(w)
+        cases.append(w["case"])
+    b = concat_runs(runs)
+    b["mats"] = mats
+    b["cases"] = cases
+    b["name"] = f"scan_{n_runs}runs_{b['x'].size}"
+    return b

@@ -109,15 +109,20 @@ def model_proposal(b: Bracket, predict, tol: float = 0.05) -> tuple[float, bool]
       (1 + 0.4 tol) in v (about 0.8 tol in Q_R, since Q_R grows as v^2), on
       the side the outcome says the threshold lies: if the model was right
       this closes the bracket to within tol.
+    - A step that did not close the bracket means the model is off here:
+      the next proposal is the log-v midpoint.
     - Otherwise propose the model root, kept a little inside the bracket.
     - Fall back to the log-v midpoint when the model is not monotone or does
       not cross 1/2 on the bracket."""
     step = 1.0 + 0.4 * tol
-    if b.history and b.history[-1][2] == "root":
+    last = b.history[-1][2] if b.history else None
+    if last == "root":
         v_last, f_last, _ = b.history[-1]
         v = v_last * step if f_last > 0.5 else v_last / step
         if b.v_lo < v < b.v_hi:
             return v, True
+    if last == "step":
+        return bisect_proposal(b), False
     root = model_root(b, predict)
     if root is None:
         return bisect_proposal(b), False

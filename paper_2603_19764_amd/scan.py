@@ -1,0 +1,146 @@
+"""Batched impact simulations as the judge of the Q_RD* search: every case
+of a round runs in one set of buffers (run-keyed neighbour search, per-run
+time steps, self-gravity), and the bound mass of each run at the end gives
+its largest-remnant fraction f_lr = M_bound / M_total.
+
+Host code sequences the library's entry points only (``sph_init``,
+``sph_step``, ``sph_bound_mass``); every step of the physics runs in the
+HIP kernels.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import torch
+
+from . import inputs, sph
+
+G = inputs.G_NEWTON
+
+
+def free_fall_time(rho: float) -> float:
+    """1 / sqrt(G rho): the time scale of gravitational reaccumulation."""
+    return 1.0 / math.sqrt(G * rho)
+
+
+def simulate(cases: list, t_end_ff: float = 2.0, prec: int = sph.SPH_FP32_CELLREL,
+             max_steps: int = 20000, check_every: int = 50, theta: float = 0.6,
+             max_neighbors: int = 256, log=None) -> dict:
+    """Run every case (dicts with n_target, gamma, r_c1, v_over_vesc, strength)
+    to t_end = t_end_ff free-fall times of the target material plus the
+    crossing time (R_t + R_p) / v, then find the bound mass of each run.
+    Returns {"f_lr", "m_bound", "m_tot", "steps", "t", "t_end"}."""
+    strong = inputs.granite_c3()
+    mats = [strong, inputs.fluid(strong)]
+    runs, t_end = [], []
+    for c in cases:
+        w = inputs.impact_pair(int(c["n_target"]), c.get("gamma", 0.1), c["r_c1"],
+                               c["v_over_vesc"], bool(c["strength"]),
+                               mat_id=0 if c["strength"] else 1, mat=strong)
+        runs.append(w)
+        k = w["case"]
+        t_end.append(t_end_ff * free_fall_time(strong["rho0"]) + (k["r_t"] + k["r_p"]) / k["v"])
+    b = inputs.concat_runs(runs)
+    b["mats"] = mats
+    prm = inputs.default_params(grav_G=G, grav_theta=theta)
+    rs = [int(v) for v in b["run_start"]]
+    n, nr = int(b["x"].size), len(runs)
+    ctx = sph.Context(n, max_neighbors, max_cells=1 << 24, max_runs=nr)
+    st = sph.State(b, run_start=rs)
+    sph.sph_init(ctx, st, mats, prm, prec)
+    t = torch.zeros(nr, dtype=torch.float64, device="cuda")
+    t_end_d = torch.tensor(t_end, dtype=torch.float64, device="cuda")
+    steps = 0
+    while steps < max_steps:
+        for _ in range(check_every):
+            t += st.dt          # the step about to be taken, per run
+            sph.sph_step(ctx, st, mats, prm, prec)
+        steps += check_every
+        ctx.check(sph.lib().sph_sync_status(ctx.h, None))
+        done = bool(torch.all(t >= t_end_d).item())
+        if log:
+            log(f"step {steps}: min t/t_end {float(torch.min(t / t_end_d)):.3f}")
+        if done:
+            break
+    bound, mb, _ = sph.sph_bound_mass(
+        ctx, st.row(sph.SPH_VX).contiguous(), st.row(sph.SPH_VY).contiguous(),
+        st.row(sph.SPH_VZ).contiguous(), st.row(sph.SPH_M).contiguous(), nr, G=G,
+        eps_over_h=prm["grav_eps_over_h"], theta=theta)
+    m_bound = mb.cpu().numpy()
+    m = b["m"]
+    m_tot = np.array([m[rs[r]:rs[r + 1]].sum() for r in range(nr)])
+    out = dict(f_lr=m_bound / m_tot, m_bound=m_bound, m_tot=m_tot, steps=steps,
+               t=t.cpu().numpy(), t_end=np.array(t_end))
+    ctx.close()
+    return out
+
+
+def bracket_rounds(cases: list, judge_batch, tol: float = 0.05, predict_for=None,
+                   max_rounds: int = 12, log=None):
+    """Bracket Q_RD* for every case at once, one simulation per unfinished
+    bracket per round, all of a round's simulations judged in one batch.
+
+    ``cases``: qrd.Case objects; ``judge_batch(list of (case, v)) -> list of
+    f_lr``; ``predict_for(round) -> predict`` gives the model for that round
+    (None: plain bisection).  The initial bracket is [v_esc, 10 v_esc]; its
+    ends are simulated in the first round.  Returns the brackets and the
+    list of (features, f_lr) outcomes."""
+    from . import qrd
+    brackets = [qrd.Bracket(c, c.v_esc, 10.0 * c.v_esc) for c in cases]
+    outcomes = []
+    jobs = [(b.case, b.v_lo) for b in brackets] + [(b.case, b.v_hi) for b in brackets]
+    f = judge_batch(jobs)
+    k = len(brackets)
+    valid = []
+    for i, b in enumerate(brackets):
+        b.f_lo, b.f_hi = f[i], f[k + i]
+        b.sims = 2
+        outcomes += [(b.case.features(b.v_lo), b.f_lo), (b.case.features(b.v_hi), b.f_hi)]
+        valid.append(b.f_lo > 0.5 >= b.f_hi)
+    for rnd in range(max_rounds):
+        open_ = [b for b, ok in zip(brackets, valid) if ok and b.width() > tol]
+        if not open_:
+            break
+        predict = predict_for(rnd) if predict_for else None
+        props = []
+        for b in open_:
+            if predict is None:
+                props.append((qrd.bisect_proposal(b), "bisect"))
+            else:
+                v, used = qrd.model_proposal(b, predict, tol)
+                after_root = bool(b.history) and b.history[-1][2] == "root"
+                props.append((v, ("step" if after_root else "root") if used else "bisect"))
+        f = judge_batch([(b.case, v) for b, (v, _) in zip(open_, props)])
+        for b, (v, src), fv in zip(open_, props, f):
+            b.update(v, float(fv), src)
+            outcomes.append((b.case.features(v), float(fv)))
+        if log:
+            log(f"round {rnd}: {len(open_)} open, widths "
+                f"{[round(b.width(), 3) for b in brackets]}")
+    return brackets, valid, outcomes
+
+
+def case_for(r_c1: float, strength: int, gamma: float = 0.1):
+    """The qrd.Case of a head-on impact as ``inputs.impact_pair`` builds it:
+    total mass of a sphere of radius r_c1 at 1000 kg/m^3, bodies at the
+    granite reference density, v_esc = sqrt(2 G M_tot / (R_t + R_p))."""
+    from . import qrd
+    rho = inputs.granite_c3()["rho0"]
+    m_tot = 4.0 / 3.0 * math.pi * r_c1 ** 3 * 1000.0
+    m_t, m_p = m_tot / (1.0 + gamma), m_tot * gamma / (1.0 + gamma)
+    r_t = (3.0 * m_t / (4.0 * math.pi * rho)) ** (1.0 / 3.0)
+    r_p = (3.0 * m_p / (4.0 * math.pi * rho)) ** (1.0 / 3.0)
+    return qrd.Case(m_tot, gamma, int(strength), math.sqrt(2.0 * G * m_tot / (r_t + r_p)))
+
+
+def judge_with_simulation(n_target: int, **kw):
+    """A judge_batch for ``bracket_rounds``: one batched simulation per call."""
+    def judge_batch(jobs):
+        cases = []
+        for c, v in jobs:
+            r_c1 = (3.0 * c.m_tot / (4.0 * math.pi * 1000.0)) ** (1.0 / 3.0)
+            cases.append(dict(n_target=n_target, gamma=c.gamma, r_c1=r_c1,
+                              v_over_vesc=v / c.v_esc, strength=c.strength))
+        return list(simulate(cases, **kw)["f_lr"])
+    return judge_batch

@@ -28,6 +28,9 @@ SPH_S, SPH_AX, SPH_AY, SPH_AZ, SPH_DUDT, SPH_SDOT, SPH_M, SPH_H, SPH_EPS2, SPH_N
 SPH_MAT, SPH_ID, SPH_FIXED, SPH_RUN, SPH_NI32 = range(5)
 (SPH_W_RHO, SPH_W_OMEGA, SPH_W_P, SPH_W_CS, SPH_W_T, SPH_W_Y, SPH_W_GMOD) = range(7)
 SPH_W_VP, SPH_W_UP, SPH_W_SP, SPH_W_G, SPH_W_DT, SPH_W_PERM, SPH_NW = 7, 10, 11, 16, 25, 26, 27
+SPH_T_BUILD, SPH_T_DENSITY, SPH_T_GRADIENTS, SPH_T_FORCES = range(4)
+(SPH_TUNE_LANES_DENSITY, SPH_TUNE_LANES_GRADIENTS, SPH_TUNE_LANES_FORCES, SPH_TUNE_LANES_STEP,
+ SPH_TUNE_CELL_SCALE) = range(5)
 
 
 class SphError(RuntimeError):
@@ -47,7 +50,9 @@ class sph_material(C.Structure):
 class sph_params(C.Structure):
     _fields_ = [("av_alpha", C.c_double), ("av_beta", C.c_double), ("av_eps", C.c_double),
                 ("eta_C", C.c_double), ("rot_sign", C.c_double), ("g", C.c_double * 3),
-                ("use_correction_tensor", C.c_int32), ("omega_one", C.c_int32)]
+                ("use_correction_tensor", C.c_int32), ("omega_one", C.c_int32),
+                ("grav_G", C.c_double), ("grav_eps_over_h", C.c_double),
+                ("grav_theta", C.c_double)]
 
 
 class sph_state(C.Structure):
@@ -80,6 +85,11 @@ def lib():
             "sph_pair_count": [_P, _P, _P],
             "sph_timing": [_P, i32],
             "sph_timing_read": [_P, i32, C.POINTER(dbl), C.POINTER(i64)],
+            "sph_set_tuning": [_P, i32, i32, i32],
+            "sph_gravity": [_P, i64, _P, _P, dbl, dbl, dbl, i32, _P, _P, _P, _P, _P],
+            "sph_bound_mass": [_P, i64, _P, _P, _P, _P, dbl, dbl, dbl, i32, _P, _P, _P,
+                               C.POINTER(i32), _P],
+            "sph_get_tuning": [_P, i32, i32, C.POINTER(i32)],
             "sph_density": [_P, i64, _P, _P, _P, _P, C.POINTER(sph_material), i32,
                             C.POINTER(sph_params), i32] + [_P] * 8,
             "sph_gradients": [_P, i64] + [_P] * 7 + [C.POINTER(sph_params), i32, _P, _P, _P],
@@ -146,6 +156,9 @@ def make_params(d: dict) -> sph_params:
         p.g[k] = d["g"][k]
     p.use_correction_tensor = int(d["use_correction"])
     p.omega_one = int(d.get("omega_one", 0))
+    p.grav_G = float(d.get("grav_G", 0.0))
+    p.grav_eps_over_h = float(d.get("grav_eps_over_h", 0.5))
+    p.grav_theta = float(d.get("grav_theta", 0.6))
     return p
 
 
@@ -230,6 +243,40 @@ def sph_timing_read(ctx: Context, which: int):
     return ms.value, cnt.value
 
 
+def sph_gravity(ctx: Context, m, ax, ay, az, phi=None, active=None, G=6.674e-11,
+                eps_over_h=0.5, theta=0.6, accumulate=False, stream=None):
+    """Self-gravity of every run at the last neighbour search (sorted order)."""
+    ctx.check(lib().sph_gravity(ctx.h, int(m.numel()), _ptr(m), _ptr(active), float(G),
+                                float(eps_over_h), float(theta), 1 if accumulate else 0,
+                                _ptr(ax), _ptr(ay), _ptr(az), _ptr(phi), _stream(stream)))
+
+
+def sph_bound_mass(ctx: Context, vx, vy, vz, m, n_runs: int, G=6.674e-11, eps_over_h=0.5,
+                   theta=0.6, max_iter=100, stream=None):
+    """Bound mass per run at the last neighbour search (sorted order).
+    Returns (bound flags int32 tensor, bound mass per run float64 tensor,
+    passes done)."""
+    n = int(m.numel())
+    bound = torch.zeros(max(n, 1), dtype=torch.int32, device=m.device)
+    mb = torch.zeros(max(n_runs, 1), dtype=torch.float64, device=m.device)
+    work = torch.empty(max(4 * n, 1), dtype=torch.float64, device=m.device)
+    it = C.c_int32()
+    ctx.check(lib().sph_bound_mass(ctx.h, n, _ptr(vx), _ptr(vy), _ptr(vz), _ptr(m), float(G),
+                                   float(eps_over_h), float(theta), int(max_iter), _ptr(bound),
+                                   _ptr(mb), _ptr(work), C.byref(it), _stream(stream)))
+    return bound[:n], mb[:n_runs], it.value
+
+
+def sph_set_tuning(ctx: Context, knob: int, prec: int, value: int):
+    ctx.check(lib().sph_set_tuning(ctx.h, int(knob), int(prec), int(value)))
+
+
+def sph_get_tuning(ctx: Context, knob: int, prec: int) -> int:
+    v = C.c_int32()
+    ctx.check(lib().sph_get_tuning(ctx.h, int(knob), int(prec), C.byref(v)))
+    return v.value
+
+
 def sph_density(ctx: Context, m, h, u, mat, mats, prm, prec, out: dict, stream=None):
     arr = make_materials(mats)
     p = make_params(prm)
@@ -310,7 +357,8 @@ class State:
         self.i32 = torch.zeros((2, SPH_NI32, self.n_cap), dtype=torch.int32, device=device)
         self.work = torch.zeros((SPH_NW, self.n_cap), **dd)
         # the library swaps the two step scalars after every step
-        self._dt_pair = (torch.zeros(1, **dd), torch.zeros(1, **dd))
+        n_dt = 1 if run_start is None else len(run_start) - 1
+        self._dt_pair = (torch.zeros(n_dt, **dd), torch.zeros(n_dt, **dd))
         self.n_singular = torch.zeros(1, dtype=torch.int64, device=device)
         F = self.f64[0]
         for k, row in (("x", SPH_X), ("y", SPH_Y), ("z", SPH_Z), ("vx", SPH_VX), ("vy", SPH_VY),

@@ -1,0 +1,32 @@
+"""Host logic of the autotuner (no GPU): candidate choice, size buckets and
+the JSON cache round trip."""
+import json
+
+from paper_2603_19764_amd import autotune
+
+
+def test_choose_picks_fastest_and_keeps_first_on_ties():
+    t = {4: 3.0, 8: 1.5, 16: 1.5}
+    best, times = autotune.choose((4, 8, 16), t.__getitem__)
+    assert best == 8 and times == t
+
+
+def test_size_bucket_groups_powers_of_two():
+    assert autotune.size_bucket(1) == 0
+    assert autotune.size_bucket(226722) == autotune.size_bucket(200000) == 17
+    assert autotune.size_bucket(7_158_540) == 22
+    assert autotune.cache_key("gfx950", 1, 226722) == "gfx950|prec1|n2^17"
+
+
+def test_cache_round_trip(tmp_path):
+    p = tmp_path / "tune.json"
+    c = autotune.TuneCache(str(p))
+    assert c.get("k") is None
+    c.put("k", {"lanes_step": 16, "cell_scale_permille": 1150})
+    assert json.loads(p.read_text())["k"]["lanes_step"] == 16
+    c2 = autotune.TuneCache(str(p))
+    assert c2.get("k") == {"lanes_step": 16, "cell_scale_permille": 1150}
+
+
+def test_knob_names_cover_plan():
+    assert {autotune.KNOB_NAMES[k] for k, _, _ in autotune.PLAN} == set(autotune.KNOB_NAMES.values())

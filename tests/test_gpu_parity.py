@@ -178,6 +178,29 @@ def test_c2_full_size_sampled(orc):
         _compare(sub_ref, sub, tol, fields, f"c2 sampled prec={prec}")
 
 
+def test_c3_full_size_sampled(orc):
+    """Two-sphere impact at full size (about 1.1M particles: granite target
+    and projectile at 45 deg and 3 km/s, glass-like arrangement): sampled
+    outputs of both precisions against the oracle, which evaluates them one
+    by one."""
+    say("[c3 full size sampled]")
+    w = inputs.c3_impact()
+    n = w["x"].size
+    rng = np.random.default_rng(9)
+    tar = np.unique(np.concatenate([rng.choice(n, 30, replace=False),
+                                    [0, n - 1, w["n_target"] - 1, w["n_target"]]]))
+    ref = _oracle(orc, w, tar)
+    for prec, tol in ((FP64, TOL64), (FP32, TOL32)):
+        got, ctx, perm = gpu_derivs(w, prec)
+        sub_ref = {k: (v[..., tar] if isinstance(v, np.ndarray) and v.shape[-1] == n else v)
+                   for k, v in ref.items()}
+        sub = {k: (v[..., tar] if isinstance(v, np.ndarray) and v.shape[-1] == n else v)
+               for k, v in got.items()}
+        fields = ("rho", "omega", "P", "cs", "G", "dS", "a", "dudt", "dt")
+        _compare(sub_ref, sub, tol, fields, f"c3 sampled prec={prec}")
+        ctx.close()
+
+
 @pytest.mark.parametrize("steps", [1, 6])
 def test_multistep_fp64_matches_oracle_integrator(orc, steps):
     """Whole steps through sph_init / sph_step (neighbour search, reorder,

@@ -1,0 +1,200 @@
+"""Tree self-gravity against the FP64 direct-sum oracle: exact (to FP32
+rounding) when every node is opened, within the expected Barnes-Hut error
+at opening angle 0.6, per run in a batch, with inactive sources, and added
+to the step's accelerations when switched on in the parameters."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import oracle
+from paper_2603_19764_amd import inputs
+from tests.gpu_harness import say
+
+pytestmark = pytest.mark.gpu
+G = 6.674e-11
+
+
+def _ball_run(n, radius, m_tot, h_over_sp=1.3, v=0.0):
+    P, sp = inputs.bcc_ball(n, radius)
+    k = P.shape[0]
+    w = inputs._empty(k)
+    w.update(x=P[:, 0].copy(), y=P[:, 1].copy(), z=P[:, 2].copy(),
+             m=np.full(k, m_tot / k), h=np.full(k, h_over_sp * sp))
+    w["vx"][:] = v
+    w.update(mats=[inputs.granite_c3()], params=inputs.default_params())
+    return w
+
+
+def _sorted_state(w, run_start=None, max_neighbors=256):
+    import torch
+    from paper_2603_19764_amd import sph
+    n = int(w["x"].size)
+    nr = 1 if run_start is None else len(run_start) - 1
+    ctx = sph.Context(n, max_neighbors, max_runs=nr)
+    st = sph.State(w, run_start=run_start)
+    sph.sph_init(ctx, st, w["mats"], w["params"], 0)
+    torch.cuda.synchronize()
+    return ctx, st
+
+
+def _gpu_gravity(ctx, st, active=None, theta=0.6, eps_over_h=0.5):
+    import torch
+    from paper_2603_19764_amd import sph
+    n = st.n
+    ax, ay, az, ph = (torch.zeros(n, dtype=torch.float64, device="cuda") for _ in range(4))
+    act = None if active is None else torch.as_tensor(active, dtype=torch.int32, device="cuda")
+    sph.sph_gravity(ctx, st.row(sph.SPH_M).contiguous(), ax, ay, az, ph, active=act, G=G,
+                    eps_over_h=eps_over_h, theta=theta)
+    torch.cuda.synchronize()
+    ctx.check(sph.lib().sph_sync_status(ctx.h, None))
+    return [t.cpu().numpy() for t in (ax, ay, az, ph)]
+
+
+def _sorted_host(st):
+    from paper_2603_19764_amd import sph
+    return {k: st.row(r).cpu().numpy() for k, r in
+            (("x", sph.SPH_X), ("y", sph.SPH_Y), ("z", sph.SPH_Z), ("m", sph.SPH_M),
+             ("h", sph.SPH_H))}
+
+
+def _oracle(s, run_start, eps_over_h, active=None):
+    rs = [0, s["x"].size] if run_start is None else list(run_start)
+    outs = [np.zeros(s["x"].size) for _ in range(4)]
+    for r in range(len(rs) - 1):
+        a, b = rs[r], rs[r + 1]
+        eps = eps_over_h * s["h"][a:b].max()
+        act = None if active is None else active[a:b]
+        res = oracle.gravity(s["x"][a:b], s["y"][a:b], s["z"][a:b], s["m"][a:b], G, eps,
+                             active=act)
+        for o, v in zip(outs, res):
+            o[a:b] = v
+    return outs
+
+
+def _errors(got, ref):
+    ag = np.stack(got[:3]); ar = np.stack(ref[:3])
+    rel = np.linalg.norm(ag - ar, axis=0) / np.maximum(np.linalg.norm(ar, axis=0), 1e-300)
+    prel = np.abs(got[3] - ref[3]) / np.abs(ref[3])
+    return rel, prel
+
+
+def test_all_nodes_opened_is_direct_sum():
+    """A ball covered by 2x2x2 cells: every cell is opened, so the walk is a
+    direct sum in FP32."""
+    w = _ball_run(400, 100.0, 1e15, h_over_sp=3.0)
+    ctx, st = _sorted_state(w, max_neighbors=512)
+    got = _gpu_gravity(ctx, st)
+    ref = _oracle(_sorted_host(st), None, 0.5)
+    rel, prel = _errors(got, ref)
+    amax = np.max(np.linalg.norm(np.stack(ref[:3]), axis=0))
+    abs_err = np.max(np.linalg.norm(np.stack(got[:3]) - np.stack(ref[:3]), axis=0)) / amax
+    say(f"direct: max |da|/max|a| {abs_err:.2e}, max rel phi {prel.max():.2e}")
+    assert abs_err < 2e-6 and prel.max() < 2e-6
+    ctx.close()
+
+
+def test_tree_error_at_opening_angle_0_6_in_a_batch():
+    runs = [_ball_run(20000, 5.0e4, 3e18), _ball_run(6000, 2.0e4, 2e17)]
+    w = inputs.concat_runs(runs)
+    rs = [int(v) for v in w["run_start"]]
+    ctx, st = _sorted_state(w, rs)
+    got = _gpu_gravity(ctx, st)
+    ref = _oracle(_sorted_host(st), rs, 0.5)
+    rel, prel = _errors(got, ref)
+    say(f"theta 0.6: |da|/|a| median {np.median(rel):.2e} p99 {np.quantile(rel, 0.99):.2e} "
+        f"max {rel.max():.2e}; dphi/phi max {prel.max():.2e}")
+    assert np.median(rel) < 3e-3 and np.quantile(rel, 0.99) < 2e-2
+    assert prel.max() < 5e-3
+    ctx.close()
+
+
+def test_inactive_sources_and_theta_bounds():
+    from paper_2603_19764_amd import sph
+    w = _ball_run(5000, 1.0e4, 1e17)
+    ctx, st = _sorted_state(w)
+    n = st.n
+    act = (np.arange(n) % 3 != 0).astype(np.int32)
+    got = _gpu_gravity(ctx, st, active=act)
+    ref = _oracle(_sorted_host(st), None, 0.5, active=act)
+    rel, prel = _errors(got, ref)
+    say(f"inactive: median {np.median(rel):.2e} p99 {np.quantile(rel, 0.99):.2e}")
+    assert np.median(rel) < 3e-3 and np.quantile(rel, 0.99) < 2e-2
+    import torch
+    z = torch.zeros(n, dtype=torch.float64, device="cuda")
+    with pytest.raises(sph.SphError):
+        sph.sph_gravity(ctx, st.row(sph.SPH_M).contiguous(), z, z, z, theta=0.1)
+    ctx.close()
+
+
+def test_step_adds_gravity_to_the_accelerations():
+    import torch
+    from paper_2603_19764_amd import sph
+    w = _ball_run(6000, 2.0e4, 2e17)
+    prm_on = inputs.default_params(grav_G=G)
+    out = {}
+    for name, prm in (("off", w["params"]), ("on", prm_on)):
+        n = int(w["x"].size)
+        ctx = sph.Context(n, 256)
+        st = sph.State(w)
+        sph.sph_init(ctx, st, w["mats"], prm, 0)
+        torch.cuda.synchronize()
+        ctx.check(sph.lib().sph_sync_status(ctx.h, None))
+        a = np.stack([st.row(k).cpu().numpy() for k in (sph.SPH_AX, sph.SPH_AY, sph.SPH_AZ)])
+        if name == "on":
+            gx, gy, gz, _ = _gpu_gravity(ctx, st)
+            out["grav"] = np.stack([gx, gy, gz])
+        out[name] = a
+        ctx.close()
+    d = out["on"] - out["off"]
+    e = np.max(np.abs(d - out["grav"])) / np.max(np.abs(out["grav"]))
+    say(f"step gravity consistency {e:.2e}")
+    assert e < 1e-9
+
+
+def test_bound_mass_matches_oracle():
+    """Escapers launched well above escape speed leave; a receding pair of
+    clusters in one run leaves nothing bound; a cold cluster in its own run
+    stays whole.  Flags and masses against the direct-sum oracle."""
+    import torch
+    from paper_2603_19764_amd import sph
+    a = _ball_run(3000, 1.0e3, 1e14)
+    n_a = a["x"].size
+    v_esc = math.sqrt(2 * G * 1e14 / 1.0e3)
+    esc = np.arange(0, n_a, 89)
+    a["vx"][esc] = 5.0 * v_esc
+    b = _ball_run(800, 300.0, 2e12)
+    c = inputs.concat_runs([b, b])
+    nb = b["x"].size
+    c["x"][:nb] -= 3000.0
+    c["x"][nb:] += 3000.0
+    c["vx"][:nb] = -20.0
+    c["vx"][nb:] = 20.0
+    c.update(mats=b["mats"], params=b["params"])
+    w = inputs.concat_runs([a, c, b])
+    rs = [0, n_a, n_a + 2 * nb, n_a + 3 * nb]
+    ctx, st = _sorted_state(w, rs)
+    bound, mb, it = sph.sph_bound_mass(ctx, st.row(sph.SPH_VX).contiguous(),
+                                       st.row(sph.SPH_VY).contiguous(),
+                                       st.row(sph.SPH_VZ).contiguous(),
+                                       st.row(sph.SPH_M).contiguous(), 3, G=G)
+    torch.cuda.synchronize()
+    ctx.check(sph.lib().sph_sync_status(ctx.h, None))
+    s = _sorted_host(st)
+    v = [st.row(k).cpu().numpy() for k in (sph.SPH_VX, sph.SPH_VY, sph.SPH_VZ)]
+    ref_b = np.zeros(st.n, dtype=np.int32)
+    ref_m = np.zeros(3)
+    for r in range(3):
+        lo, hi = rs[r], rs[r + 1]
+        eps = 0.5 * s["h"][lo:hi].max()
+        fb, fm = oracle.bound_mass(s["x"][lo:hi], s["y"][lo:hi], s["z"][lo:hi], v[0][lo:hi],
+                                   v[1][lo:hi], v[2][lo:hi], s["m"][lo:hi], G, eps)
+        ref_b[lo:hi] = fb
+        ref_m[r] = fm[0]
+    got_b = bound.cpu().numpy()
+    got_m = mb.cpu().numpy()
+    say(f"bound mass: passes {it}, gpu {got_m}, oracle {ref_m}")
+    assert np.array_equal(got_b, ref_b)
+    np.testing.assert_allclose(got_m, ref_m, rtol=1e-12)
+    assert got_m[1] == 0.0 and ref_m[2] > 0.0
+    ctx.close()
