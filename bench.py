@@ -60,16 +60,18 @@ def kernel_source_sha256() -> str:
     return h.hexdigest()
 
 
-def measured_traffic():
-    """Bytes per launch from the committed counter summary, or None when it is
-    missing or was taken on another version of the kernel source."""
+def measured_traffic(kernel: str):
+    """Bytes per launch of ``kernel`` (e.g. "k_grad_forces<4,fp32>") from the
+    committed counter summary, or None when it is missing, does not list that
+    instantiation, or was taken on another version of the kernel source."""
     import re
     try:
         text = open(TRAFFIC_FILE).read()
     except OSError:
         return None
     sha = re.search(r"source_sha256:\s*([0-9a-f]{64})", text)
-    val = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", text)
+    val = re.search(r"traffic_bytes_per_launch\[" + re.escape(kernel) + r"\]:\s*([0-9.eE+]+)",
+                    text)
     if not sha or not val or sha.group(1) != kernel_source_sha256():
         return None
     return float(val.group(1))
@@ -283,9 +285,10 @@ def main():
         avg_s = ms / cnt * 1e-3
         pairs_per_launch = r32["pairs"] / r32["steps"]
         achieved = FLOPS_PAIR[1] * pairs_per_launch / avg_s
+        kname = f"k_grad_forces<{(tuned[1] or {}).get('lanes_step', 8)},fp32>"
         roof = dict(bound="alu", achieved=achieved / 1e12, peak=PEAK_FP32_VALU / 1e12,
-                    unit="TFLOP/s", frac=achieved / PEAK_FP32_VALU, traffic=measured_traffic(),
-                    kernel=f"k_grad_forces<{(tuned[1] or {}).get('lanes_step', 8)},fp32>",
+                    unit="TFLOP/s", frac=achieved / PEAK_FP32_VALU,
+                    traffic=measured_traffic(kname), kernel=kname,
                     avg_launch_us=avg_s * 1e6,
                     kernels_us={k: (v[0] / v[1] * 1e3 if v[1] else None)
                                 for k, v in r32["kernels"].items()})

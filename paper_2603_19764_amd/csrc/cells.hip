@@ -397,7 +397,7 @@ __global__ void k_gather(int64_t n, const int32_t *perm, const double *x, const 
 // each lane holds one candidate of a 64-wide column of the tile; one exact
 // test per lane, a ballot, and the hits are appended to i's list in
 // candidate order at offsets from mbcnt.  The lists are deterministic.
-constexpr int kTileMax = 512;
+constexpr int kTileMax = 256;
 constexpr int kIBatch = 64;
 constexpr double kCullMargin = 1.0 + 0x1p-40;
 
@@ -492,9 +492,9 @@ __global__ __launch_bounds__(64) void k_build_pairs(
             int cnt_reg = 0;  // lane q: running count of particle ib + q
             const double4 *ipos = posh64 + ib;
 
-            for (int r0 = 0; r0 < T;) {
+            int fill = 0;  // kept candidates in the tile (carried over between chunks)
+            for (int r0 = 0; r0 < T || fill > 0;) {
                 // ---- fill: cull raw candidates into the tile
-                int fill = 0;
                 __syncthreads();
                 for (; r0 < T && fill <= kTileMax - kWave; r0 += kWave) {
                     const int gidx = r0 + lane;
@@ -529,6 +529,9 @@ __global__ __launch_bounds__(64) void k_build_pairs(
                     fill += __popcll(m);
                 }
                 __syncthreads();
+                // full columns only while raw candidates remain; the ragged
+                // rest is carried to the front of the tile for the next chunk
+                const int cols = r0 < T ? (fill / kWave) * kWave : fill;
                 // ---- tests: four i at a time against every column of the tile
                 for (int q0 = 0; q0 < ni; q0 += 4) {
                     const int l = ni - 1;
@@ -547,11 +550,11 @@ __global__ __launch_bounds__(64) void k_build_pairs(
                         row[k] = nbr + (ib + qq[k]) * (int64_t)K;
                     }
                     const int nk = ni - q0 < 4 ? ni - q0 : 4;  // distinct i in this group
-                    for (int col = 0; col < fill; col += kWave) {
+                    for (int col = 0; col < cols; col += kWave) {
                         const int s = col + lane;
                         double4 c = make_double4(NAN, 0.0, 0.0, -1.0);
                         uint32_t e = 0;
-                        if (s < fill) {
+                        if (s < cols) {
                             c = tpos[s];
                             e = tj[s];
                         }
@@ -579,6 +582,20 @@ __global__ __launch_bounds__(64) void k_build_pairs(
                     for (int k = 0; k < 4; ++k)
                         if (k < nk && lane == qq[k]) cnt_reg = base[k];
                 }
+                // carry the kept candidates not tested yet (fewer than 64)
+                const int rest = fill - cols;
+                double4 cr = make_double4(0.0, 0.0, 0.0, 0.0);
+                uint32_t er = 0;
+                if (lane < rest) {
+                    cr = tpos[cols + lane];
+                    er = tj[cols + lane];
+                }
+                __syncthreads();
+                if (lane < rest) {
+                    tpos[lane] = cr;
+                    tj[lane] = er;
+                }
+                fill = rest;
             }
             if (lane < ni) {
                 ncount[ib + lane] = cnt_reg < K ? cnt_reg : K;

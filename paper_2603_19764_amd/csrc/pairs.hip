@@ -127,22 +127,32 @@ __global__ __launch_bounds__(kBlock) void k_density(
         if constexpr (F32) L32 = grid[runid[i]].L32;
         const int c = ncount[i];
         const uint32_t *row = nbr + i * (int64_t)K;
-        uint32_t en = lg < c ? row[lg] : 0u;
+        // Software pipeline: the entry two ahead and the record one ahead are
+        // in flight while a pair is evaluated.  Loads are unconditional (the
+        // entry index is clamped into the row, a record index past the list
+        // is replaced by i), so no branch hides them from the wait counters.
+        uint32_t e = row[lg < K ? lg : K - 1];
+        e = lg < c ? e : (uint32_t)i;
+        uint32_t en = row[lg + L < K ? lg + L : K - 1];
+        R4 pj = rec[e & kIdxMask];
         for (int k = lg; k < c; k += L) {
-            const uint32_t e = en;
-            en = k + L < c ? row[k + L] : 0u;  // next entry in flight
-            if (!(e & kDensityBit)) continue;
-            const R4 pj = rec[e & kIdxMask];
+            const uint32_t enn = row[k + 2 * L < K ? k + 2 * L : K - 1];
+            const uint32_t e_next = k + L < c ? en : (uint32_t)i;
+            const R4 pn = rec[e_next & kIdxMask];
             R dx, dy, dz;
             separation<F32>(pi, pj, e, shs, L32, dx, dy, dz);
             const R q = root(dx * dx + dy * dy + dz * dz) * Hinv;
             R t = (R)1 - q;
             t = t > (R)0 ? t : (R)0;
             const R t3 = t * t * t;
-            const R w = pj.w * (t3 * t * ((R)1 + (R)4 * q));
-            const R dh = pj.w * (t3 * ((R)3 + q * ((R)9 - (R)32 * q)));
+            const R mj = (e & kDensityBit) ? pj.w : (R)0;
+            const R w = mj * (t3 * t * ((R)1 + (R)4 * q));
+            const R dh = mj * (t3 * ((R)3 + q * ((R)9 - (R)32 * q)));
             sw += (double)w;
             sd += (double)dh;
+            e = e_next;
+            en = enn;
+            pj = pn;
         }
     }
     sw = group_sum<L>(sw);
@@ -431,12 +441,21 @@ __global__ __launch_bounds__(kBlock) void k_grad_forces(
         if constexpr (F32) L32 = grid[runid[i]].L32;
         const int c = ncount[i];
         const uint32_t *row = nbr + i * (int64_t)K;
-        uint32_t en = lg < c ? row[lg] : 0u;
-        for (int k = lg; k < c; k += L) {
-            const uint32_t e = en;
-            en = k + L < c ? row[k + L] : 0u;  // next entry in flight
+        // Software pipeline (see k_density): entry two ahead, record one
+        // ahead, unconditional loads.
+        uint32_t e = row[lg < K ? lg : K - 1];
+        e = lg < c ? e : (uint32_t)i;
+        uint32_t en = row[lg + L < K ? lg + L : K - 1];
+        R4 pj, vj, Aj, Bj, Hj;
+        {
             const R4 *rj = rec + kRecBoth * (int64_t)(e & kIdxMask);
-            const R4 pj = rj[0], vj = rj[1], Aj = rj[2], Bj = rj[3], Hj = rj[4];
+            pj = rj[0]; vj = rj[1]; Aj = rj[2]; Bj = rj[3]; Hj = rj[4];
+        }
+        for (int k = lg; k < c; k += L) {
+            const uint32_t enn = row[k + 2 * L < K ? k + 2 * L : K - 1];
+            const uint32_t e_next = k + L < c ? en : (uint32_t)i;
+            const R4 *rn = rec + kRecBoth * (int64_t)(e_next & kIdxMask);
+            const R4 pn = rn[0], vn = rn[1], An = rn[2], Bn = rn[3], Hn = rn[4];
             R dx, dy, dz;
             separation<F32>(pi, pj, e, shs, L32, dx, dy, dz);
             const R r2 = dx * dx + dy * dy + dz * dz;
@@ -481,6 +500,9 @@ __global__ __launch_bounds__(kBlock) void k_grad_forces(
                 du += (R)0.5 * sv * vr;
                 mumax = mumax > -mu ? mumax : -mu;
             }
+            e = e_next;
+            en = enn;
+            pj = pn; vj = vn; Aj = An; Bj = Bn; Hj = Hn;
         }
     }
     c_xx = group_sum<L>(c_xx); c_yy = group_sum<L>(c_yy); c_zz = group_sum<L>(c_zz);
