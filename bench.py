@@ -164,9 +164,11 @@ def run_batch(steps, warmup, gravity=True, tune=True):
     n = int(b["x"].size)
     tuned = None
     if tune:
-        tuned = autotune.tune(b, 1, steps=2, run_start=rs, max_cells=1 << 24)["settings"]
+        tuned = autotune.tune(b, 1, steps=2, run_start=rs, max_neighbors=256,
+                              max_cells=1 << 24)["settings"]
         log(f"batch autotune: {tuned}")
-    ctx = sph.Context(n, max_neighbors=128, max_cells=1 << 24, max_runs=64)
+    # colliding bodies compress: room for twice the neighbours of the lattice
+    ctx = sph.Context(n, max_neighbors=256, max_cells=1 << 24, max_runs=64)
     if tuned:
         autotune.apply(ctx, 1, tuned)
     st = sph.State(b, run_start=rs)
@@ -204,6 +206,39 @@ def run_batch(steps, warmup, gravity=True, tune=True):
             "dt_spread": float(dt.max() / dt.min())}
 
 
+def run_curve(sizes=(32, 64, 128, 160), steps=40, warmup=3):
+    """Throughput against size: the single-step block workload (16^3 lattice,
+    spacing 1 m, jitter, shear flow) scaled to n_side^3 particles, FP32 and
+    FP64 whole steps."""
+    from paper_2603_19764_amd import inputs
+    out = []
+    for k in sizes:
+        w = inputs.c1_block(k)
+        row = {"n_side": k, "particles": int(w["x"].size)}
+        for prec, name in ((1, "fp32"), (0, "fp64")):
+            r = run_steps(w, prec, steps, warmup, False, timing=False)
+            row[name] = {"pairs_per_s": r["pairs"] / r["seconds"],
+                         "ms_per_step": 1e3 * r["seconds"] / r["steps"]}
+        log(f"curve {k}^3: {row}")
+        out.append(row)
+    return out
+
+
+def run_impact_step(steps=4, warmup=2):
+    """The two-sphere impact (about 1.1M particles, glass-like bodies, 45 deg,
+    3 km/s, gravity excluded): whole steps in FP32 and in FP64."""
+    from paper_2603_19764_amd import inputs
+    w = inputs.c3_impact()
+    row = {"particles": int(w["x"].size)}
+    for prec, name in ((1, "fp32"), (0, "fp64")):
+        r = run_steps(w, prec, steps, warmup, False, timing=False)
+        row[name] = {"pairs_per_s": r["pairs"] / r["seconds"],
+                     "ms_per_step": 1e3 * r["seconds"] / r["steps"],
+                     "pairs_per_step": r["pairs"] / r["steps"]}
+    log(f"impact: {row}")
+    return row
+
+
 def cpu_baseline(w, budget_s=15.0):
     """The FP64 oracle on a bounded sample of the same workload: the full
     derivative chain (brute-force pair sets, density + EOS for the pair-set
@@ -229,8 +264,17 @@ def cpu_baseline(w, budget_s=15.0):
     off, _, _ = oracle.pair_lists(w["x"], w["y"], w["z"], w["h"], w["params"], tar)
     pairs = int(off[-1])
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    model = "unknown CPU"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
     return dict(value=pairs / dt, unit="pairs/s", cores=threads, kind="oracle",
-                sample=f"{ntar} random targets of the {n}-particle column, full FP64 derivative "
+                sample=f"{model}, {threads} threads: "
+                       f"{ntar} random targets of the {n}-particle column, full FP64 derivative "
                        f"chain with brute-force O(N^2) neighbour search, {pairs} target pairs in "
                        f"{dt:.2f} s")
 
@@ -243,6 +287,10 @@ def main():
     ap.add_argument("--graph", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-curve", action="store_true",
+                    help="skip the size curve (block workload, 32^3 to 160^3)")
+    ap.add_argument("--no-impact", action="store_true",
+                    help="skip the 1.1M-particle two-sphere impact steps")
     ap.add_argument("--batch-steps", type=int, default=0,
                     help="steps of the batched 64-impact scan (0: skip it)")
     ap.add_argument("--no-tune", action="store_true",
@@ -292,6 +340,8 @@ def main():
                     avg_launch_us=avg_s * 1e6,
                     kernels_us={k: (v[0] / v[1] * 1e3 if v[1] else None)
                                 for k, v in r32["kernels"].items()})
+    curve = None if args.no_curve else run_curve()
+    impact = None if args.no_impact else run_impact_step()
     batch = None
     if args.batch_steps > 0:
         batch = run_batch(args.batch_steps, 4, tune=not args.no_tune)
@@ -312,6 +362,8 @@ def main():
         "fp64_plain": None if r64 is None else {
             "value": r64["pairs"] / r64["seconds"], "ms_per_step": 1e3 * r64["seconds"] / r64["steps"],
             "steps": r64["steps"], "launch_shapes": tuned[0]},
+        "size_curve": curve,
+        "impact_1p1M": impact,
         "batch_scan": batch,
         "roofline": roof,
         "cpu_baseline": cpu,

@@ -20,7 +20,10 @@
  *   - Every call is asynchronous on `stream` (a hipStream_t; NULL is the
  *     null stream) and allocates nothing; a call sequence can be captured
  *     into a hipGraph.  Scalars that change from step to step (the time
- *     step) are read from device memory for that reason.
+ *     step) are read from device memory for that reason.  Exceptions, which
+ *     synchronise and are not capturable: sph_sync_status, sph_timing_read,
+ *     sph_bound_mass, and the first call with a new run layout
+ *     (sph_state.run_start), which uploads it.
  *   - Argument errors are returned synchronously (SPH_EINVAL, SPH_ESTATE,
  *     SPH_ECAPACITY).  Conditions found on the device (neighbour list
  *     overflow, cell table overflow) raise a device flag that
