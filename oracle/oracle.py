@@ -429,3 +429,17 @@ def bound_mass(x, y, z, vx, vy, vz, m, G, eps, run_start=None, max_iter=100):
                     C.c_double(G), C.c_double(eps), C.c_int32(max_iter), _p(bound, _I32),
                     _p(mb))
     return bound, mb
+
+
+# ------------------------------------------------ adaptive smoothing length
+def adapt_h(x, y, z, m, h, prm: dict, n_ngb: float, tol=1e-12, max_iter=50):
+    """Newton-Raphson smoothing lengths at constant kernel mass (reading H1).
+    Returns (h, largest number of Newton steps)."""
+    L = lib()
+    x, y, z, m, h = (_f64(a) for a in (x, y, z, m, h))
+    out = np.zeros_like(h)
+    p = params(prm)
+    L.or_adapt_h.restype = C.c_int32
+    it = L.or_adapt_h(C.c_int64(x.size), _p(x), _p(y), _p(z), _p(m), _p(h), C.byref(p),
+                      C.c_double(n_ngb), C.c_double(tol), C.c_int32(max_iter), _p(out))
+    return out, int(it)

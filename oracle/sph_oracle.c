@@ -43,6 +43,9 @@
  *       c_min [sec. 2.3 uses EOSlib / M-ANEOS, which are not available].
  *   K8  the thermal-softening factor is clamped at zero for T >= T_melt,
  *       and strength switched off for a material means Gamma = 0, Y = 0.
+ *   H1  adaptive smoothing length: the constant kernel mass of the
+ *       kernel-mass equation (sec. 2.1) is written N_ngb m_i with N_ngb a
+ *       run parameter; Newton-Raphson steps limited to a factor 2.
  *   K9  time integration: single global step, kick-drift-kick with the
  *       predictor of Predict_S eq. applied to v, u and S; the closing kick
  *       is followed by the plastic rescaling, the opening kick is not
@@ -216,6 +219,61 @@ void or_density(int64_t n, const double *x, const double *y, const double *z,
         rho[i] = sum_w;
         omega[i] = p->omega_one ? 1.0 : 1.0 + h[i] / (3.0 * sum_w) * sum_dh;
     }
+}
+
+/* ----------------------------------------------------------------------- */
+/* Adaptive smoothing length (sec. 2.1, the kernel-mass equation): h_i is   */
+/* chosen so that the mass inside the kernel support stays constant,       */
+/*    (4/3) pi (2 h_i)^3 rho_i(h_i) = N_ngb m_i,                           */
+/* solved by Newton-Raphson with the density and its h-derivative:          */
+/*    f(h)  = (32 pi / 3) h^3 rho(h) - N_ngb m_i,                           */
+/*    f'(h) = 32 pi h^2 rho(h) + (32 pi / 3) h^3 drho/dh                    */
+/*          = 32 pi h^2 rho Omega.                                          */
+/* Each Newton step is limited to a factor of 2 either way; the iteration   */
+/* stops when |dh| <= tol h or after max_iter steps (reading H1: the target  */
+/* mass is written N_ngb m_i, N_ngb a run parameter).  Returns the largest   */
+/* number of steps any particle took.                                       */
+/* ----------------------------------------------------------------------- */
+int32_t or_adapt_h(int64_t n, const double *x, const double *y, const double *z,
+                   const double *m, const double *h_in, const or_params *p, double n_ngb,
+                   double tol, int32_t max_iter, double *h_out)
+{
+    int32_t worst = 0;
+    #pragma omp parallel for schedule(dynamic, 16) reduction(max:worst)
+    for (int64_t i = 0; i < n; ++i) {
+        double h = h_in[i];
+        int32_t it = 0;
+        for (; it < max_iter; ++it) {
+            const double H2 = supp2(h);
+            double rho = 0.0, drho = 0.0, d[3];
+            for (int64_t j = 0; j < n; ++j) {
+                double r;
+                if (j == i) {
+                    r = 0.0;
+                } else {
+                    double r2 = sep2(x, y, z, i, j, p->box, d);
+                    if (!(r2 < H2)) continue;
+                    r = sqrt(r2);
+                }
+                rho += m[j] * or_W(r, h);
+                drho += m[j] * or_dWdh(r, h);
+            }
+            const double f = (32.0 * OR_PI / 3.0) * h * h * h * rho - n_ngb * m[i];
+            const double fp = 32.0 * OR_PI * h * h * rho + (32.0 * OR_PI / 3.0) * h * h * h * drho;
+            double hn = fp > 0.0 ? h - f / fp : 2.0 * h;
+            if (hn > 2.0 * h) hn = 2.0 * h;
+            if (hn < 0.5 * h) hn = 0.5 * h;
+            const double dh = hn - h;
+            h = hn;
+            if (fabs(dh) <= tol * h) {
+                ++it;
+                break;
+            }
+        }
+        h_out[i] = h;
+        if (it > worst) worst = it;
+    }
+    return worst;
 }
 
 /* ----------------------------------------------------------------------- */
