@@ -54,7 +54,8 @@ class Params(C.Structure):
     _fields_ = [("av_alpha", C.c_double), ("av_beta", C.c_double), ("av_eps", C.c_double),
                 ("eta_C", C.c_double), ("rot_sign", C.c_double),
                 ("g", C.c_double * 3), ("box", C.c_double * 3),
-                ("use_correction", C.c_int32), ("omega_one", C.c_int32)]
+                ("use_correction", C.c_int32), ("omega_one", C.c_int32),
+                ("adapt_ngb", C.c_double), ("adapt_skin", C.c_double)]
 
 
 class _State(C.Structure):
@@ -130,6 +131,8 @@ def params(d: dict) -> Params:
         p.box[k] = d.get("box", (0.0, 0.0, 0.0))[k]
     p.use_correction = int(d["use_correction"])
     p.omega_one = int(d.get("omega_one", 0))
+    p.adapt_ngb = float(d.get("adapt_ngb", 0.0))
+    p.adapt_skin = float(d.get("adapt_skin", 1.25))
     return p
 
 
@@ -432,14 +435,18 @@ def bound_mass(x, y, z, vx, vy, vz, m, G, eps, run_start=None, max_iter=100):
 
 
 # ------------------------------------------------ adaptive smoothing length
-def adapt_h(x, y, z, m, h, prm: dict, n_ngb: float, tol=1e-12, max_iter=50):
-    """Newton-Raphson smoothing lengths at constant kernel mass (reading H1).
-    Returns (h, largest number of Newton steps)."""
+def adapt_h(x, y, z, m, h, prm: dict, n_ngb: float, tol=1e-12, max_iter=50, h_cap=None,
+            fixed=None):
+    """Newton-Raphson smoothing lengths at constant kernel mass (reading H1),
+    optionally capped per particle.  Returns (h, largest number of steps)."""
     L = lib()
     x, y, z, m, h = (_f64(a) for a in (x, y, z, m, h))
+    cap = None if h_cap is None else _f64(h_cap)
+    fx = None if fixed is None else np.ascontiguousarray(fixed, dtype=np.uint8)
     out = np.zeros_like(h)
     p = params(prm)
     L.or_adapt_h.restype = C.c_int32
-    it = L.or_adapt_h(C.c_int64(x.size), _p(x), _p(y), _p(z), _p(m), _p(h), C.byref(p),
-                      C.c_double(n_ngb), C.c_double(tol), C.c_int32(max_iter), _p(out))
+    it = L.or_adapt_h(C.c_int64(x.size), _p(x), _p(y), _p(z), _p(m), _p(h), _p(cap),
+                      _p(fx, _U8), C.byref(p), C.c_double(n_ngb), C.c_double(tol),
+                      C.c_int32(max_iter), _p(out))
     return out, int(it)

@@ -79,6 +79,8 @@ typedef struct {
     double box[3];          /* periodic box lengths; 0 = open along that axis */
     int32_t use_correction; /* 1: G = F C, 0: G = F                            */
     int32_t omega_one;      /* 1: Omega = 1; 0: Omega as defined               */
+    double adapt_ngb;       /* > 0: adapt h to this kernel mass / m each step   */
+    double adapt_skin;      /* cap of one adaptation: h <= adapt_skin * h_old   */
 } or_params;
 
 /* ----------------------------------------------------------------------- */
@@ -231,18 +233,26 @@ void or_density(int64_t n, const double *x, const double *y, const double *z,
 /*          = 32 pi h^2 rho Omega.                                          */
 /* Each Newton step is limited to a factor of 2 either way; the iteration   */
 /* stops when |dh| <= tol h or after max_iter steps (reading H1: the target  */
-/* mass is written N_ngb m_i, N_ngb a run parameter).  Returns the largest   */
-/* number of steps any particle took.                                       */
+/* mass is written N_ngb m_i, N_ngb a run parameter).  With a cap h_cap_i    */
+/* (the length a neighbour search covered), a step past the cap is held at   */
+/* it, and a particle whose next step would leave it again stops there.     */
+/* Fixed particles (fixed[i] != 0) keep h_in.  Returns the largest number   */
+/* of steps any particle took.                                              */
 /* ----------------------------------------------------------------------- */
 int32_t or_adapt_h(int64_t n, const double *x, const double *y, const double *z,
-                   const double *m, const double *h_in, const or_params *p, double n_ngb,
-                   double tol, int32_t max_iter, double *h_out)
+                   const double *m, const double *h_in, const double *h_cap,
+                   const uint8_t *fixed, const or_params *p, double n_ngb, double tol,
+                   int32_t max_iter, double *h_out)
 {
     int32_t worst = 0;
     #pragma omp parallel for schedule(dynamic, 16) reduction(max:worst)
     for (int64_t i = 0; i < n; ++i) {
-        double h = h_in[i];
+        double h = h_cap ? fmin(h_in[i], h_cap[i]) : h_in[i];
         int32_t it = 0;
+        if (fixed && fixed[i]) {
+            h_out[i] = h_in[i];
+            continue;
+        }
         for (; it < max_iter; ++it) {
             const double H2 = supp2(h);
             double rho = 0.0, drho = 0.0, d[3];
@@ -263,6 +273,13 @@ int32_t or_adapt_h(int64_t n, const double *x, const double *y, const double *z,
             double hn = fp > 0.0 ? h - f / fp : 2.0 * h;
             if (hn > 2.0 * h) hn = 2.0 * h;
             if (hn < 0.5 * h) hn = 0.5 * h;
+            if (h_cap && hn > h_cap[i]) {
+                if (h == h_cap[i]) {
+                    ++it;
+                    break;
+                }
+                hn = h_cap[i];
+            }
             const double dh = hn - h;
             h = hn;
             if (fabs(dh) <= tol * h) {
@@ -730,7 +747,8 @@ typedef struct {
     double *ax, *ay, *az;       /* derivatives of the last evaluation       */
     double *dudt, *dS;          /* dS is 5n                                  */
     double *eps2;               /* accumulated strain-rate invariant        */
-    const double *m, *h;
+    const double *m;
+    double *h;                  /* smoothing lengths (changed only when adapted) */
     const int32_t *mat;
     const uint8_t *fixed;
     /* outputs of the last evaluation */
@@ -773,6 +791,21 @@ static double min_dt(const or_state_t *s)
 /* Initial evaluation at t = 0 (predicted values = current values), choice
  * of the first step from the CFL condition (or dt_fixed > 0), and the
  * first opening kick. */
+/* Adaptive smoothing lengths before an evaluation (reading H1), capped at
+ * adapt_skin times the lengths on entry, fixed particles unchanged. */
+#define OR_ADAPT_TOL 1e-10
+#define OR_ADAPT_ITER 30
+static void adapt_lengths(or_state_t *s, const or_params *p)
+{
+    if (!(p->adapt_ngb > 0.0)) return;
+    int64_t n = s->n;
+    double *cap = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    for (int64_t i = 0; i < n; ++i) cap[i] = p->adapt_skin * s->h[i];
+    or_adapt_h(n, s->x, s->y, s->z, s->m, s->h, cap, s->fixed, p, p->adapt_ngb, OR_ADAPT_TOL,
+               OR_ADAPT_ITER, s->h);
+    free(cap);
+}
+
 void or_init(or_state_t *s, const or_material *mats, const or_params *p, double dt_fixed)
 {
     int64_t n = s->n;
@@ -781,6 +814,7 @@ void or_init(or_state_t *s, const or_material *mats, const or_params *p, double 
     double *Sp = (double *)malloc(sizeof(double) * 5 * (size_t)n);
     double *e2 = (double *)malloc(sizeof(double) * (size_t)n);
     memcpy(Sp, s->S, sizeof(double) * 5 * (size_t)n);
+    adapt_lengths(s, p);
     eval_derivs(s, mats, p, s->vx, s->vy, s->vz, s->u, Sp, tar, e2);
     s->dt = dt_fixed > 0.0 ? dt_fixed : min_dt(s);
     double hd = 0.5 * s->dt;
@@ -830,6 +864,7 @@ void or_step(or_state_t *s, const or_material *mats, const or_params *p, double 
         up[i] = s->u[i] + hd * s->dudt[i];
         for (int c = 0; c < 5; ++c) Sp[c * n + i] = s->S[c * n + i] + hd * s->dS[c * n + i];
     }
+    adapt_lengths(s, p);
     eval_derivs(s, mats, p, vpx, vpy, vpz, up, Sp, tar, e2);
     /* closing kick to the full step, rescaling of S */
     for (int64_t i = 0; i < n; ++i) {

@@ -71,3 +71,37 @@ def test_isolated_particle_grows_by_the_step_limit():
     h, it = oracle.adapt_h(x, y, z, m, np.array([1.0, 1.0]), prm, 50.0, max_iter=5)
     np.testing.assert_allclose(h, [32.0, 32.0])
     assert it == 5
+
+
+def test_cap_and_fixed_particles():
+    """With a cap, particles whose length would pass it stop exactly there;
+    the others reach the uncapped answer; fixed particles keep theirs."""
+    x, y, z, m, prm = _lattice(10)
+    N = _n_ngb_for(1.3, x, y, z, m, prm)
+    n = x.size
+    h0 = np.full(n, 1.0)
+    cap = np.full(n, 1.2)
+    cap[::7] = 1.5
+    fixed = np.zeros(n, dtype=np.uint8)
+    fixed[5] = 1
+    h, _ = oracle.adapt_h(x, y, z, m, h0, prm, N, tol=1e-13, h_cap=cap, fixed=fixed)
+    open_ = cap > 1.3
+    open_[5] = False
+    assert np.all(h[~open_ & (fixed == 0)] == 1.2)
+    assert np.max(np.abs(h[open_] - 1.3)) < 1e-10
+    assert h[5] == 1.0
+
+
+def test_integrator_adapts_lengths():
+    """The oracle integrator adapts h before each evaluation when asked."""
+    from oracle.oracle import Integrator
+    w = inputs.c1_block(6)
+    prm = dict(w["params"], adapt_ngb=70.0, adapt_skin=1.25)
+    st = {k: w[k] for k in ("x", "y", "z", "m", "h", "mat", "vx", "vy", "vz", "u", "S", "fixed")}
+    it = Integrator(st, w["mats"], prm)
+    h1 = np.array(it["h"])
+    assert not np.allclose(h1, w["h"])
+    assert np.all(h1 <= 1.25 * w["h"] * (1 + 1e-15))
+    it.step(1)
+    h2 = np.array(it["h"])
+    assert np.all(h2 <= 1.25 * h1 * (1 + 1e-15))
