@@ -80,12 +80,16 @@ typedef struct {
  * rate; -1: the index order as printed), external gravity, correction
  * tensor switch (Corrected_Gradients eq.), Omega = 1 switch, and the
  * self-gravity of each run added by sph_step when grav_G > 0 (see
- * sph_gravity for the meaning of the three grav_ fields). */
+ * sph_gravity for the meaning of the three grav_ fields), and adaptive
+ * smoothing lengths (kernel-mass equation of sec. 2.1) when adapt_ngb > 0. */
 typedef struct {
     double av_alpha, av_beta, av_eps, eta_C, rot_sign;
     double g[3];
     int32_t use_correction_tensor, omega_one;
     double grav_G, grav_eps_over_h, grav_theta;
+    double adapt_ngb;   /* > 0: sph_init / sph_step adapt h to constant kernel
+                           mass (sph_adapt_h) before each evaluation          */
+    double adapt_skin;  /* cap of one adaptation: h <= adapt_skin h_old (>= 1) */
 } sph_params;
 
 /* ---------------------------------------------------------------- context */
@@ -248,6 +252,25 @@ sph_status sph_diagnostics(sph_ctx *ctx, int64_t n, const double *x, const doubl
                            const double *vz, const double *m, const double *ax,
                            const double *ay, const double *az, const double *dudt,
                            double *out13, sph_stream stream);
+
+/* ------------------------------------------------- adaptive smoothing length */
+
+/* Smoothing lengths at constant kernel mass (the kernel-mass equation of
+ * sec. 2.1): for every particle, Newton-Raphson on
+ *     (4/3) pi (2 h_i)^3 rho_i(h_i) = n_ngb m_i
+ * with rho and drho/dh summed over the pair list of the last neighbour
+ * search (self term included), each step limited to a factor 2, until
+ * |dh| <= tol h or max_iter steps.  The search must have been done with
+ * lengths h_search at least as large as the answer: a step past a
+ * particle's h_search is held at h_search, and a particle whose next step
+ * would leave it again stops there and is counted in *n_clamped (device
+ * int64, may be NULL; not reset by the call).  Sorted order.  m, h_start:
+ * masses and starting lengths (n doubles); h_out: result (n doubles, may
+ * equal h_start); *iterations: device int32 raised to the largest number of
+ * steps taken (may be NULL; not reset).  FP64. */
+sph_status sph_adapt_h(sph_ctx *ctx, int64_t n, const double *m, const double *h_start,
+                       double n_ngb, double tol, int32_t max_iter, double *h_out,
+                       int64_t *n_clamped, int32_t *iterations, sph_stream stream);
 
 /* ------------------------------------------------------------ self-gravity */
 

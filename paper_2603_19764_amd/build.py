@@ -10,7 +10,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsph.so")
 SOURCES = ["api.hip", "cells.hip", "pairs.hip", "integrate.hip", "step.hip", "mlp.hip",
-           "gravity.hip"]
+           "gravity.hip", "hadapt.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -138,7 +138,7 @@ sph_status sph_create(sph_ctx **out, int64_t capacity, int32_t max_neighbors, in
         {(void **)&ctx->scan_part, (kScanBlocks + 1) * 8},
         {(void **)&ctx->flags, FLAG_COUNT * 4},
         {(void **)&ctx->pairs, 8},
-        {(void **)&ctx->dtbits, (size_t)max_runs * 8},
+        {(void **)&ctx->dtbits, (size_t)max_runs * 3 * 8},
         {(void **)&ctx->diag, 256 * 13 * 8},
         {(void **)&ctx->rec_d, cap * 32},
         {(void **)&ctx->rec_g, cap * 96},
@@ -160,13 +160,13 @@ sph_status sph_create(sph_ctx **out, int64_t capacity, int32_t max_neighbors, in
         }
     }
     ctx->mats = new Mat[kMaxMaterials];
-    std::vector<unsigned long long> inf_bits((size_t)max_runs, 0x7ff0000000000000ull);
+    std::vector<unsigned long long> inf_bits((size_t)max_runs * 3, 0x7ff0000000000000ull);
     if (hipMemset(ctx->flags, 0, FLAG_COUNT * 4) != hipSuccess ||
         hipMemset(ctx->pairs, 0, 8) != hipSuccess ||
         hipMemset(ctx->ncount, 0, cap * 4) != hipSuccess ||
         hipMemset(ctx->total_keys, 0, 4) != hipSuccess ||
         hipMemset(ctx->cell_count, 0, ((size_t)max_cells + 1) * 4) != hipSuccess ||
-        hipMemcpy(ctx->dtbits, inf_bits.data(), (size_t)max_runs * 8, hipMemcpyHostToDevice) !=
+        hipMemcpy(ctx->dtbits, inf_bits.data(), (size_t)max_runs * 3 * 8, hipMemcpyHostToDevice) !=
             hipSuccess) {
         sph_destroy(h);
         return SPH_EHIP;
@@ -482,6 +482,19 @@ sph_status sph_bound_mass(sph_ctx *h, int64_t n, const double *vx, const double 
                              m_bound, work, work + n, iterations, S(stream));
 }
 
+sph_status sph_adapt_h(sph_ctx *h, int64_t n, const double *m, const double *h_start,
+                       double n_ngb, double tol, int32_t max_iter, double *h_out,
+                       int64_t *n_clamped, int32_t *iterations, sph_stream stream) {
+    CHECK_CTX();
+    sph_status st = check_built(h, n);
+    if (st != SPH_OK) return st;
+    REQUIRE(n_ngb > 0.0 && tol > 0.0 && max_iter >= 1, SPH_EINVAL,
+            "n_ngb and tol must be > 0 and max_iter >= 1");
+    REQUIRE(n == 0 || (m && h_start && h_out), SPH_EINVAL, "null array");
+    return launch_adapt_h(&h->c, n, m, h_start, nullptr, n_ngb, tol, max_iter, h_out, n_clamped,
+                          iterations, S(stream));
+}
+
 // ------------------------------------------------------------ whole step
 struct Rows {
     double *f[SPH_NF64];
@@ -498,6 +511,7 @@ static Rows rows_of(const sph_state *st, int buf) {
 }
 
 static int32_t n_runs_of(const sph_state *st) { return st->run_start ? st->n_runs : 1; }
+static unsigned long long *step_bits(Ctx *ctx, int other);
 
 static sph_status check_state(sph_ctx *h, const sph_state *st) {
     REQUIRE(st, SPH_EINVAL, "null state");
@@ -514,7 +528,8 @@ static sph_status check_state(sph_ctx *h, const sph_state *st) {
 // reorder of every state row into the other buffer with the predictor of v
 // and u fused in (predict = 0 at the start of a run: predicted = current).
 static sph_status search_and_sort(sph_ctx *h, sph_state *st, sph_precision prec, bool drift,
-                                  int32_t predict, hipStream_t s) {
+                                  int32_t predict, hipStream_t s,
+                                  const double *h_build = nullptr) {
     Ctx *ctx = &h->c;
     const int64_t n = st->n;
     const int cur = st->cur, alt = 1 - cur;
@@ -534,8 +549,8 @@ static sph_status search_and_sort(sph_ctx *h, sph_state *st, sph_precision prec,
     }
     ex.m = A.f[SPH_M];  // the gather reads the unsorted state: records in sorted order
     ex.f32 = prec == SPH_FP32_CELLREL;
-    if ((e = launch_build_cells(ctx, n, A.f[SPH_X], A.f[SPH_Y], A.f[SPH_Z], A.f[SPH_H], nr,
-                                st->cell_min, perm, &ex, s)))
+    if ((e = launch_build_cells(ctx, n, A.f[SPH_X], A.f[SPH_Y], A.f[SPH_Z],
+                                h_build ? h_build : A.f[SPH_H], nr, st->cell_min, perm, &ex, s)))
         return e;
     StepRows r;
     for (int k = 0; k < SPH_NF64; ++k) {
@@ -552,6 +567,32 @@ static sph_status search_and_sort(sph_ctx *h, sph_state *st, sph_precision prec,
         return e;
     st->cur = alt;
     return SPH_OK;
+}
+
+// Neighbour search of a step.  With adaptive smoothing lengths
+// (prm->adapt_ngb > 0): search with the lengths enlarged by adapt_skin,
+// Newton-Raphson to constant kernel mass over those lists (capped at the
+// enlarged lengths, fixed particles unchanged), then the exact search with
+// the new lengths.  The second search neither drifts nor changes the
+// predictor inputs, so the state is the same as after one plain search.
+constexpr double kAdaptTol = 1e-10;
+constexpr int32_t kAdaptIter = 30;
+
+static sph_status step_search(sph_ctx *h, sph_state *st, const sph_params *prm,
+                              sph_precision prec, bool drift, int32_t predict, hipStream_t s) {
+    if (!(prm->adapt_ngb > 0.0)) return search_and_sort(h, st, prec, drift, predict, s);
+    Ctx *ctx = &h->c;
+    const int64_t n = st->n;
+    Rows A = rows_of(st, st->cur);
+    double *hs = A.w[SPH_W_T];  // free until the state kernel of this step
+    sph_status e;
+    if ((e = launch_scale(ctx, n, A.f[SPH_H], prm->adapt_skin, hs, s))) return e;
+    if ((e = search_and_sort(h, st, prec, drift, predict, s, hs))) return e;
+    Rows R = rows_of(st, st->cur);
+    if ((e = launch_adapt_h(ctx, n, R.f[SPH_M], R.f[SPH_H], R.i[SPH_FIXED], prm->adapt_ngb,
+                            kAdaptTol, kAdaptIter, R.f[SPH_H], nullptr, nullptr, s)))
+        return e;
+    return search_and_sort(h, st, prec, false, predict, s);
 }
 
 // Derivatives at the sorted state: density pass, per-particle state (EOS,
@@ -587,8 +628,28 @@ static sph_status eval(sph_ctx *h, const sph_state *st, const Rows &R, int32_t n
                                    runid, R.w[SPH_W_G], R.f[SPH_SDOT],
                                    accumulate_eps2 ? R.f[SPH_EPS2] : nullptr, st->n_singular, s)))
         return e;
-    return launch_dt_min(ctx, n, R.w[SPH_W_DT], fixed, st->dt_max, st->dt_next, s, nr,
-                         ctx->run_p);
+    return launch_dt_reduce(ctx, n, R.w[SPH_W_DT], fixed, step_bits(ctx, 0), s, nr, ctx->run_p);
+}
+
+// The kick that follows an evaluation turns the minima into the next step
+// and clears the other buffer; then the parity flips.
+static sph_status kick(sph_ctx *h, sph_state *st, const Rows &R, int32_t mode, hipStream_t s) {
+    Ctx *ctx = &h->c;
+    const int32_t nr = n_runs_of(st);
+    const int16_t *runid = nr > 1 ? ctx->runid : nullptr;
+    sph_status e = launch_step_kick(
+        ctx, st->n, mode, st->dt, step_bits(ctx, 0), st->dt_max, st->dt_next, step_bits(ctx, 1),
+        nr, runid, R.i[SPH_FIXED], R.f[SPH_VX], R.f[SPH_VY], R.f[SPH_VZ], R.f[SPH_U],
+        R.f[SPH_AX], R.f[SPH_AY], R.f[SPH_AZ], R.f[SPH_DUDT], R.f[SPH_S], R.w[SPH_W_SP],
+        R.f[SPH_SDOT], R.w[SPH_W_Y], s);
+    ctx->dt_parity ^= 1;
+    return e;
+}
+
+// Minima buffers of the whole step: the current one (other = 0) and the one
+// to clear (other = 1); see Ctx::dtbits.
+static unsigned long long *step_bits(Ctx *ctx, int other) {
+    return ctx->dtbits + (size_t)ctx->max_runs * (1 + (ctx->dt_parity ^ other));
 }
 
 static void swap_dt(sph_state *st) {
@@ -606,18 +667,17 @@ sph_status sph_init(sph_ctx *h, sph_state *st, const sph_material *mats, int32_t
     REQUIRE(prec == SPH_FP64 || prec == SPH_FP32_CELLREL, SPH_EINVAL, "bad precision");
     if ((e = set_mats(h, mats, n_materials))) return e;
     hipStream_t s = S(stream);
-    Ctx *ctx = &h->c;
-    const int64_t n = st->n;
-    if ((e = search_and_sort(h, st, prec, false, 0, s))) return e;
+    REQUIRE(!(prm->adapt_ngb > 0.0) || prm->adapt_skin >= 1.0, SPH_EINVAL,
+            "adapt_skin must be >= 1");
+    if ((e = step_search(h, st, prm, prec, false, 0, s))) return e;
     Rows R = rows_of(st, st->cur);
     // predicted values are the current ones: v, u as they are, S rescaled
     if ((e = eval(h, st, R, n_materials, prm, prec, 0, false, s))) return e;
+    // the opening kick uses the new step only: it writes it to dt_next, and
+    // the swap makes it the step of the first drift
+    if ((e = kick(h, st, R, 1, s))) return e;
     swap_dt(st);
-    const int16_t *runid = n_runs_of(st) > 1 ? ctx->runid : nullptr;
-    return launch_step_kick(ctx, n, 1, st->dt, st->dt, runid, R.i[SPH_FIXED], R.f[SPH_VX], R.f[SPH_VY],
-                            R.f[SPH_VZ], R.f[SPH_U], R.f[SPH_AX], R.f[SPH_AY], R.f[SPH_AZ],
-                            R.f[SPH_DUDT], R.f[SPH_S], R.w[SPH_W_SP], R.f[SPH_SDOT],
-                            R.w[SPH_W_Y], s);
+    return SPH_OK;
 }
 
 sph_status sph_step(sph_ctx *h, sph_state *st, const sph_material *mats, int32_t n_materials,
@@ -629,17 +689,12 @@ sph_status sph_step(sph_ctx *h, sph_state *st, const sph_material *mats, int32_t
     REQUIRE(prec == SPH_FP64 || prec == SPH_FP32_CELLREL, SPH_EINVAL, "bad precision");
     if ((e = set_mats(h, mats, n_materials))) return e;
     hipStream_t s = S(stream);
-    Ctx *ctx = &h->c;
-    const int64_t n = st->n;
-    if ((e = search_and_sort(h, st, prec, true, 1, s))) return e;
+    REQUIRE(!(prm->adapt_ngb > 0.0) || prm->adapt_skin >= 1.0, SPH_EINVAL,
+            "adapt_skin must be >= 1");
+    if ((e = step_search(h, st, prm, prec, true, 1, s))) return e;
     Rows R = rows_of(st, st->cur);
     if ((e = eval(h, st, R, n_materials, prm, prec, 1, true, s))) return e;
-    const int16_t *runid = n_runs_of(st) > 1 ? ctx->runid : nullptr;
-    if ((e = launch_step_kick(ctx, n, 0, st->dt, st->dt_next, runid, R.i[SPH_FIXED], R.f[SPH_VX],
-                              R.f[SPH_VY], R.f[SPH_VZ], R.f[SPH_U], R.f[SPH_AX], R.f[SPH_AY],
-                              R.f[SPH_AZ], R.f[SPH_DUDT], R.f[SPH_S], R.w[SPH_W_SP],
-                              R.f[SPH_SDOT], R.w[SPH_W_Y], s)))
-        return e;
+    if ((e = kick(h, st, R, 0, s))) return e;
     swap_dt(st);
     return SPH_OK;
 }

@@ -185,9 +185,9 @@ __global__ void k_dt_final(int nr, unsigned long long *bits, double cap, double 
     bits[r] = 0x7ff0000000000000ull;  // ready for the next reduction
 }
 
-sph_status launch_dt_min(Ctx *ctx, int64_t n, const double *dtc, const int32_t *fixed,
-                         double cap, double *out, hipStream_t s, int32_t nr,
-                         const int32_t *run_p) {
+sph_status launch_dt_reduce(Ctx *ctx, int64_t n, const double *dtc, const int32_t *fixed,
+                            unsigned long long *bits, hipStream_t s, int32_t nr,
+                            const int32_t *run_p) {
     if (nr < 1 || nr > ctx->max_runs || (nr > 1 && !run_p)) return SPH_EINVAL;
     if (n > 0) {
         // about 256 blocks in all, at least one per run
@@ -195,8 +195,17 @@ sph_status launch_dt_min(Ctx *ctx, int64_t n, const double *dtc, const int32_t *
         const int cap_b = 256 / nr > 1 ? 256 / nr : 1;
         nb = nb < 1 ? 1 : (nb > cap_b ? cap_b : nb);
         hipLaunchKernelGGL(k_dt_reduce, dim3(nb, nr), dim3(1024), 0, s, n, nr > 1 ? run_p : nullptr,
-                           dtc, fixed, ctx->dtbits);
+                           dtc, fixed, bits);
     }
+    SPH_HIP(hipGetLastError());
+    return SPH_OK;
+}
+
+sph_status launch_dt_min(Ctx *ctx, int64_t n, const double *dtc, const int32_t *fixed,
+                         double cap, double *out, hipStream_t s, int32_t nr,
+                         const int32_t *run_p) {
+    sph_status e = launch_dt_reduce(ctx, n, dtc, fixed, ctx->dtbits, s, nr, run_p);
+    if (e != SPH_OK) return e;
     hipLaunchKernelGGL(k_dt_final, dim3((nr + 255) / 256), dim3(256), 0, s, nr, ctx->dtbits, cap,
                        out);
     SPH_HIP(hipGetLastError());

@@ -8,17 +8,9 @@
 #include <vector>
 
 #include "../../include/sph.h"
+#include "device_util.h"
 
 namespace sph {
-
-// ------------------------------------------------------------------ limits
-constexpr int kWave = 64;
-constexpr int kIdxBits = 26;                       // neighbour entry: j index bits
-constexpr uint32_t kIdxMask = (1u << kIdxBits) - 1;
-constexpr int kCodeShift = kIdxBits;               // 5 bits: stencil cell 0..26
-constexpr uint32_t kDensityBit = 1u << 31;         // j is in the density set of i
-constexpr int kMaxMortonBits = 10;                 // per axis
-constexpr int kNumXcd = 8;                         // MI355X: 8 XCDs, round-robin dispatch
 
 // Flags raised on the device (ctx->flags[...]).
 enum {
@@ -91,7 +83,11 @@ struct Ctx {
     int64_t *scan_part = nullptr;   // scan partials (kScanBlocks + 1)
     int32_t *flags = nullptr;       // FLAG_COUNT
     unsigned long long *pairs = nullptr;  // accumulated ordered pairs
-    unsigned long long *dtbits = nullptr; // scratch for dt min
+    // per-run step minima as ordered bit patterns: [0] for sph_dt_min,
+    // [1 + parity] for the whole step, which alternates between the two so
+    // that a step's kick can read one while clearing the other
+    unsigned long long *dtbits = nullptr;  // 3 * max_runs
+    int32_t dt_parity = 0;
     double *diag = nullptr;         // 16 doubles
     // pair-pass records (array of structures, see the pair kernels)
     void *rec_d = nullptr;          // density: capacity * 32 bytes
@@ -114,82 +110,6 @@ struct Ctx {
 constexpr int kBBoxBlocks = 256;
 constexpr int kScanBlocks = 1024;
 constexpr int kMaxMaterials = 16;
-
-// --------------------------------------------------------- device helpers
-__device__ __forceinline__ int lane_id() { return __lane_id(); }
-
-// Block index remapped so that consecutive logical blocks run on the same
-// XCD (hardware dispatches block b to XCD b % 8): XCD x gets a contiguous
-// range of logical blocks.  Bijective for any grid size.
-__device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t nb) {
-    uint32_t q = nb / kNumXcd, r = nb % kNumXcd;
-    uint32_t x = b % kNumXcd, k = b / kNumXcd;
-    return x * q + (x < r ? x : r) + k;
-}
-
-// Interleave cell coordinates into a Morton key with per-axis bit counts.
-__device__ __forceinline__ uint32_t morton(uint32_t cx, uint32_t cy, uint32_t cz,
-                                           int bx, int by, int bz) {
-    uint32_t key = 0;
-    int pos = 0;
-    int mb = bx > by ? bx : by;
-    mb = mb > bz ? mb : bz;
-    for (int l = 0; l < mb; ++l) {
-        if (l < bx) key |= ((cx >> l) & 1u) << pos++;
-        if (l < by) key |= ((cy >> l) & 1u) << pos++;
-        if (l < bz) key |= ((cz >> l) & 1u) << pos++;
-    }
-    return key;
-}
-
-// Squared separation ((dx*dx + dy*dy) + dz*dz) in IEEE double with every
-// operation rounded separately: contraction into FMA is switched off here,
-// so the neighbour criterion r^2 < H^2 is decided exactly as by any other
-// implementation that evaluates the same expression without fusion.
-__device__ __forceinline__ double sep2_exact(double xi, double yi, double zi, double xj,
-                                             double yj, double zj) {
-#pragma clang fp contract(off)
-    const double dx = xi - xj;
-    const double dy = yi - yj;
-    const double dz = zi - zj;
-    const double a = dx * dx;
-    const double b = dy * dy;
-    const double c = dz * dz;
-    return (a + b) + c;
-}
-
-// Sum over groups of L consecutive lanes (L a power of two <= 64); every
-// lane of the group receives the group sum.
-template <int L>
-__device__ __forceinline__ float group_sum(float v) {
-#pragma unroll
-    for (int o = L / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, L);
-    return v;
-}
-template <int L>
-__device__ __forceinline__ double group_sum(double v) {
-#pragma unroll
-    for (int o = L / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, L);
-    return v;
-}
-template <int L>
-__device__ __forceinline__ float group_min(float v) {
-#pragma unroll
-    for (int o = L / 2; o > 0; o >>= 1) v = fminf(v, __shfl_xor(v, o, L));
-    return v;
-}
-template <int L>
-__device__ __forceinline__ double group_max(double v) {
-#pragma unroll
-    for (int o = L / 2; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, L));
-    return v;
-}
-template <int L>
-__device__ __forceinline__ float group_max(float v) {
-#pragma unroll
-    for (int o = L / 2; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, L));
-    return v;
-}
 
 // ------------------------------------------------------------ host helpers
 #define SPH_HIP(expr)                                                          \
@@ -262,6 +182,10 @@ sph_status launch_kick_drift(Ctx *ctx, int32_t phase, int64_t n, const double *d
 sph_status launch_dt_min(Ctx *ctx, int64_t n, const double *dtc, const int32_t *fixed,
                          double cap, double *out, hipStream_t s, int32_t nr = 1,
                          const int32_t *run_p = nullptr);
+// Reduction only, into bits (the step's kick finishes it); see launch_step_kick.
+sph_status launch_dt_reduce(Ctx *ctx, int64_t n, const double *dtc, const int32_t *fixed,
+                            unsigned long long *bits, hipStream_t s, int32_t nr,
+                            const int32_t *run_p);
 
 // Self-gravity of every run at the last build (sorted order); see sph_gravity.
 sph_status launch_gravity(Ctx *ctx, int64_t n, const double *m, const int32_t *active, double G,
@@ -273,6 +197,14 @@ sph_status launch_bound_mass(Ctx *ctx, int64_t n, const double *vx, const double
                              double theta, int32_t max_iter, int32_t *bound, double *m_bound,
                              double *phi, double *acc3, int32_t *iterations, hipStream_t s);
 size_t bound_mass_part_bytes(int32_t max_runs);
+// Adaptive smoothing lengths over the last build's lists; see sph_adapt_h.
+sph_status launch_adapt_h(Ctx *ctx, int64_t n, const double *m, const double *h_start,
+                          const int32_t *fixed, double n_ngb, double tol, int32_t max_iter,
+                          double *h_out, int64_t *n_clamped, int32_t *iterations,
+                          hipStream_t s);
+// b = f a (n doubles)
+sph_status launch_scale(Ctx *ctx, int64_t n, const double *a, double f, double *b,
+                        hipStream_t s);
 
 // Time step of sorted particle i: one per run when runid is given.
 __device__ __forceinline__ double dt_of(const double *dtp, const int16_t *runid, int64_t i) {
@@ -314,11 +246,16 @@ sph_status launch_step_grad_rate(Ctx *ctx, int64_t n, const sph_params *prm,
                                  const double *S_pred, const double *Gmod, const int32_t *fixed,
                                  const double *dt, const int16_t *runid, double *G,
                                  double *Sdot, double *eps2, int64_t *n_singular, hipStream_t s);
+// Kicks; the next step of each run is taken from the minima in bits_cur
+// (capped at dt_cap when > 0) and written to dt_next[0..nr); bits_clear is
+// set to +inf for the following reduction.
 sph_status launch_step_kick(Ctx *ctx, int64_t n, int32_t mode, const double *dt,
-                            const double *dt_next, const int16_t *runid, const int32_t *fixed,
-                            double *vx, double *vy, double *vz, double *u, const double *ax,
-                            const double *ay, const double *az, const double *dudt,
-                            double *S_half, const double *S_pred, const double *Sdot,
-                            const double *Y, hipStream_t s);
+                            const unsigned long long *bits_cur, double dt_cap,
+                            double *dt_next, unsigned long long *bits_clear, int32_t nr,
+                            const int16_t *runid, const int32_t *fixed, double *vx, double *vy,
+                            double *vz, double *u, const double *ax, const double *ay,
+                            const double *az, const double *dudt, double *S_half,
+                            const double *S_pred, const double *Sdot, const double *Y,
+                            hipStream_t s);
 
 }  // namespace sph

@@ -130,8 +130,18 @@ __global__ void k_grad_rate(int64_t n, const double *__restrict__ gsum,
 // ------------------------------------------------------------------ kicks
 // mode 0: closing kick with rescaling then opening kick (a step);
 // mode 1: opening kick from the predicted stress (start of a run).
+// The next step of a run is its CFL minimum (bit pattern, capped) read
+// here directly; threads r < nr also store it to dt_next[r] for the next
+// step's drift and clear bits_clear[r] for the next reduction.
+__device__ __forceinline__ double dt_from_bits(unsigned long long b, double cap) {
+    double d = __longlong_as_double((long long)b);
+    return (cap > 0.0 && !(d <= cap)) ? cap : d;
+}
+
 __global__ void k_kick_all(int64_t n, int32_t mode, const double *__restrict__ dtp,
-                           const double *__restrict__ dtnp, const int16_t *__restrict__ runid,
+                           const unsigned long long *__restrict__ bits_cur, double dt_cap,
+                           double *__restrict__ dt_next, unsigned long long *__restrict__ bits_clear,
+                           int32_t nr, const int16_t *__restrict__ runid,
                            const int32_t *__restrict__ fixed,
                            double *vx, double *vy, double *vz, double *u,
                            const double *__restrict__ ax, const double *__restrict__ ay,
@@ -139,9 +149,13 @@ __global__ void k_kick_all(int64_t n, int32_t mode, const double *__restrict__ d
                            double *S_half, const double *__restrict__ S_pred,
                            const double *__restrict__ Sdot, const double *__restrict__ Y) {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < nr) {
+        dt_next[i] = dt_from_bits(bits_cur[i], dt_cap);
+        bits_clear[i] = 0x7ff0000000000000ull;
+    }
     if (i >= n) return;
     if (fixed && fixed[i]) return;
-    const double hn = 0.5 * dt_of(dtnp, runid, i);
+    const double hn = 0.5 * dt_from_bits(bits_cur[runid ? (int)runid[i] : 0], dt_cap);
     if (mode == 0) {
         const double hd = 0.5 * dt_of(dtp, runid, i);
         vx[i] = (vx[i] + hd * ax[i]) + hn * ax[i];
@@ -215,16 +229,18 @@ sph_status launch_step_grad_rate(Ctx *ctx, int64_t n, const sph_params *prm,
 }
 
 sph_status launch_step_kick(Ctx *ctx, int64_t n, int32_t mode, const double *dt,
-                            const double *dt_next, const int16_t *runid, const int32_t *fixed, double *vx, double *vy,
+                            const unsigned long long *bits_cur, double dt_cap,
+                            double *dt_next, unsigned long long *bits_clear, int32_t nr,
+                            const int16_t *runid, const int32_t *fixed, double *vx, double *vy,
                             double *vz, double *u, const double *ax, const double *ay,
                             const double *az, const double *dudt, double *S_half,
                             const double *S_pred, const double *Sdot, const double *Y,
                             hipStream_t s) {
-    if (n == 0) return SPH_OK;
-    hipLaunchKernelGGL(k_kick_all, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, mode,
-                       dt, dt_next, runid, fixed, vx, vy, vz, u, ax, ay, az, dudt, S_half, S_pred,
-                       Sdot,
-                       Y);
+    const int64_t m = n > nr ? n : nr;
+    if (m == 0) return SPH_OK;
+    hipLaunchKernelGGL(k_kick_all, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, n, mode,
+                       dt, bits_cur, dt_cap, dt_next, bits_clear, nr, runid, fixed, vx, vy, vz, u,
+                       ax, ay, az, dudt, S_half, S_pred, Sdot, Y);
     SPH_HIP(hipGetLastError());
     return SPH_OK;
 }

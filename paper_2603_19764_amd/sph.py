@@ -52,7 +52,8 @@ class sph_params(C.Structure):
                 ("eta_C", C.c_double), ("rot_sign", C.c_double), ("g", C.c_double * 3),
                 ("use_correction_tensor", C.c_int32), ("omega_one", C.c_int32),
                 ("grav_G", C.c_double), ("grav_eps_over_h", C.c_double),
-                ("grav_theta", C.c_double)]
+                ("grav_theta", C.c_double), ("adapt_ngb", C.c_double),
+                ("adapt_skin", C.c_double)]
 
 
 class sph_state(C.Structure):
@@ -87,6 +88,7 @@ def lib():
             "sph_timing_read": [_P, i32, C.POINTER(dbl), C.POINTER(i64)],
             "sph_set_tuning": [_P, i32, i32, i32],
             "sph_gravity": [_P, i64, _P, _P, dbl, dbl, dbl, i32, _P, _P, _P, _P, _P],
+            "sph_adapt_h": [_P, i64, _P, _P, dbl, dbl, i32, _P, _P, _P, _P],
             "sph_bound_mass": [_P, i64, _P, _P, _P, _P, dbl, dbl, dbl, i32, _P, _P, _P,
                                C.POINTER(i32), _P],
             "sph_get_tuning": [_P, i32, i32, C.POINTER(i32)],
@@ -159,6 +161,8 @@ def make_params(d: dict) -> sph_params:
     p.grav_G = float(d.get("grav_G", 0.0))
     p.grav_eps_over_h = float(d.get("grav_eps_over_h", 0.5))
     p.grav_theta = float(d.get("grav_theta", 0.6))
+    p.adapt_ngb = float(d.get("adapt_ngb", 0.0))
+    p.adapt_skin = float(d.get("adapt_skin", 1.25))
     return p
 
 
@@ -265,6 +269,14 @@ def sph_bound_mass(ctx: Context, vx, vy, vz, m, n_runs: int, G=6.674e-11, eps_ov
                                    float(eps_over_h), float(theta), int(max_iter), _ptr(bound),
                                    _ptr(mb), _ptr(work), C.byref(it), _stream(stream)))
     return bound[:n], mb[:n_runs], it.value
+
+
+def sph_adapt_h(ctx: Context, m, h_start, h_out, n_ngb: float, tol=1e-12, max_iter=50,
+                n_clamped=None, iterations=None, stream=None):
+    """Smoothing lengths at constant kernel mass over the last build's lists."""
+    ctx.check(lib().sph_adapt_h(ctx.h, int(m.numel()), _ptr(m), _ptr(h_start), float(n_ngb),
+                                float(tol), int(max_iter), _ptr(h_out), _ptr(n_clamped),
+                                _ptr(iterations), _stream(stream)))
 
 
 def sph_set_tuning(ctx: Context, knob: int, prec: int, value: int):
