@@ -73,6 +73,12 @@ typedef struct {
     double shear_modulus, nu;     /* > 0: constant; otherwise 3(1-2nu)/(2(1+nu)) rho c^2 */
     double Y0, Ym, mu_i, mu_d, xi, T_melt; /* Collins yield, thermal softening    */
     int32_t strength_on, thermal_softening_on;
+    /* Melting temperature as a table of density (sec. 2.3 gives T_melt as a
+     * tabulated function of rho): with tmelt_n >= 2 nodes (ascending rho),
+     * T_melt(rho) is interpolated linearly and held at the end values
+     * outside the table; otherwise the constant T_melt above is used. */
+    int32_t tmelt_n, tmelt_pad;
+    double tmelt_rho[8], tmelt_T[8];
 } sph_material;
 
 /* Run parameters: Monaghan AV (sec. 2.1), Courant factor (courant_condition

@@ -47,7 +47,9 @@ class Material(C.Structure):
         "rho0", "A", "B", "E0", "Eiv", "Ecv", "a", "b", "alpha", "beta",
         "cv", "T_ref", "c_min", "shear_modulus", "nu",
         "Y0", "Ym", "mu_i", "mu_d", "xi", "T_melt")] + [
-        ("strength_on", C.c_int32), ("thermal_softening_on", C.c_int32)]
+        ("strength_on", C.c_int32), ("thermal_softening_on", C.c_int32),
+        ("tmelt_n", C.c_int32), ("tmelt_pad", C.c_int32),
+        ("tmelt_rho", C.c_double * 8), ("tmelt_T", C.c_double * 8)]
 
 
 class Params(C.Structure):
@@ -111,7 +113,15 @@ def _f64(a):
 def material(d: dict) -> Material:
     m = Material()
     for k, _ in Material._fields_:
+        if k.startswith("tmelt_"):
+            continue
         setattr(m, k, d[k])
+    tab_r, tab_t = d.get("tmelt_rho"), d.get("tmelt_T")
+    if tab_r is not None:
+        assert len(tab_r) == len(tab_t) <= 8
+        m.tmelt_n = len(tab_r)
+        for k, (r, t) in enumerate(zip(tab_r, tab_t)):
+            m.tmelt_rho[k], m.tmelt_T[k] = r, t
     return m
 
 
@@ -158,12 +168,15 @@ def tillotson(mat: dict, rho, u):
     return P, c, dr, du
 
 
-def yield_strength(mat: dict, P, T):
+def yield_strength(mat: dict, P, T, rho=None):
+    """Yield strength at pressure P, temperature T and density rho (rho only
+    matters for a tabulated melting temperature; default rho0)."""
     P, T = np.broadcast_arrays(_f64(P), _f64(T))
     P, T = _f64(P), _f64(T)
+    R = None if rho is None else _f64(np.broadcast_to(_f64(rho), P.shape))
     Y = np.empty(P.size)
     m = material(mat)
-    lib().or_yield_arr(C.byref(m), C.c_int64(P.size), _p(P), _p(T), _p(Y))
+    lib().or_yield_arr(C.byref(m), C.c_int64(P.size), _p(R), _p(P), _p(T), _p(Y))
     return Y
 
 

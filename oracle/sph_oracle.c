@@ -43,6 +43,8 @@
  *       c_min [sec. 2.3 uses EOSlib / M-ANEOS, which are not available].
  *   K8  the thermal-softening factor is clamped at zero for T >= T_melt,
  *       and strength switched off for a material means Gamma = 0, Y = 0.
+ *   K8b a melting temperature given as a table of density (sec. 2.3) is
+ *       interpolated piecewise-linearly and held at its end values.
  *   H1  adaptive smoothing length: the constant kernel mass of the
  *       kernel-mass equation (sec. 2.1) is written N_ngb m_i with N_ngb a
  *       run parameter; Newton-Raphson steps limited to a factor 2.
@@ -71,6 +73,10 @@ typedef struct {
     /* Collins yield and thermal softening */
     double Y0, Ym, mu_i, mu_d, xi, T_melt;
     int32_t strength_on, thermal_softening_on;
+    /* melting temperature as a table of density (reading K8b): used when
+     * tmelt_n >= 2, nodes in ascending density */
+    int32_t tmelt_n, tmelt_pad;
+    double tmelt_rho[8], tmelt_T[8];
 } or_material;
 
 typedef struct {
@@ -370,8 +376,23 @@ void or_tillotson(const or_material *M, double rho, double u,
 /*   Y_d = mu_d P                                    damaged                */
 /*   Y   = min(Y_i, Y_d)                                                    */
 /*   Y  <- Y tanh(xi (T_melt/T - 1))                 thermal softening      */
+/* T_melt is the material constant, or, with a table (sec. 2.3: T_melt as a */
+/* tabulated function of density), the piecewise-linear interpolation of   */
+/* the table at rho, held at the end values outside it (reading K8b).       */
 /* ----------------------------------------------------------------------- */
-double or_yield(const or_material *M, double P, double T)
+double or_tmelt(const or_material *M, double rho)
+{
+    if (M->tmelt_n < 2) return M->T_melt;
+    const int n = M->tmelt_n;
+    if (rho <= M->tmelt_rho[0]) return M->tmelt_T[0];
+    if (rho >= M->tmelt_rho[n - 1]) return M->tmelt_T[n - 1];
+    int k = 0;
+    while (rho >= M->tmelt_rho[k + 1]) ++k;
+    const double w = (rho - M->tmelt_rho[k]) / (M->tmelt_rho[k + 1] - M->tmelt_rho[k]);
+    return M->tmelt_T[k] + w * (M->tmelt_T[k + 1] - M->tmelt_T[k]);
+}
+
+double or_yield(const or_material *M, double rho, double P, double T)
 {
     if (!M->strength_on) return 0.0;
     double Pp = P > 0.0 ? P : 0.0;
@@ -379,7 +400,7 @@ double or_yield(const or_material *M, double P, double T)
     double Yd = M->mu_d * Pp;
     double Y = Yi < Yd ? Yi : Yd;
     if (M->thermal_softening_on) {
-        double s = tanh(M->xi * (M->T_melt / T - 1.0));
+        double s = tanh(M->xi * (or_tmelt(M, rho) / T - 1.0));
         Y *= (s > 0.0 ? s : 0.0);            /* reading K8 */
     }
     return Y;
@@ -410,7 +431,7 @@ void or_state(int64_t nt, const int64_t *tar, const double *rho, const double *u
         P[i] = Pi;
         c[i] = ci;
         T[i] = Ti;
-        Y[i] = or_yield(M, Pi, Ti);
+        Y[i] = or_yield(M, rho[i], Pi, Ti);
         Gam[i] = or_shear_modulus(M, rho[i], ci);
     }
 }
@@ -915,9 +936,10 @@ void or_tillotson_arr(const or_material *M, int64_t n, const double *rho, const 
                      dPdu ? &dPdu[i] : NULL);
 }
 
-void or_yield_arr(const or_material *M, int64_t n, const double *P, const double *T, double *Y)
+void or_yield_arr(const or_material *M, int64_t n, const double *rho, const double *P,
+                  const double *T, double *Y)
 {
-    for (int64_t i = 0; i < n; ++i) Y[i] = or_yield(M, P[i], T[i]);
+    for (int64_t i = 0; i < n; ++i) Y[i] = or_yield(M, rho ? rho[i] : M->rho0, P[i], T[i]);
 }
 
 /* Rows of 9 (G) and 5 (S) per entry, entry-major. */

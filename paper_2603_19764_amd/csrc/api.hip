@@ -321,6 +321,11 @@ static sph_status set_mats(sph_ctx *h, const sph_material *mats, int32_t nmat) {
         REQUIRE(m.rho0 > 0 && m.E0 > 0 && m.cv > 0 && m.Ecv > m.Eiv, SPH_EINVAL,
                 "material %d: invalid Tillotson or temperature constants", k);
         REQUIRE(!m.strength_on || m.Ym > m.Y0, SPH_EINVAL, "material %d: Ym must exceed Y0", k);
+        REQUIRE(m.tmelt_n >= 0 && m.tmelt_n <= 8, SPH_EINVAL,
+                "material %d: melting table with %d nodes (0..8)", k, m.tmelt_n);
+        for (int q = 1; q < m.tmelt_n; ++q)
+            REQUIRE(m.tmelt_rho[q] > m.tmelt_rho[q - 1], SPH_EINVAL,
+                    "material %d: melting table densities must ascend", k);
         h->c.mats[k].m = m;
     }
     return SPH_OK;

@@ -72,6 +72,19 @@ __device__ inline void tillotson(const sph_material &M, double rho, double u, do
     c = c < M.c_min ? M.c_min : c;
 }
 
+// Melting temperature: the constant, or the linear interpolation of the
+// material's density table, held at its end values outside it.
+__device__ inline double melt_temperature(const sph_material &M, double rho) {
+    const int n = M.tmelt_n;
+    if (n < 2) return M.T_melt;
+    if (rho <= M.tmelt_rho[0]) return M.tmelt_T[0];
+    if (rho >= M.tmelt_rho[n - 1]) return M.tmelt_T[n - 1];
+    int k = 0;
+    while (k + 2 < n && rho >= M.tmelt_rho[k + 1]) ++k;
+    const double w = (rho - M.tmelt_rho[k]) / (M.tmelt_rho[k + 1] - M.tmelt_rho[k]);
+    return M.tmelt_T[k] + w * (M.tmelt_T[k + 1] - M.tmelt_T[k]);
+}
+
 // EOS, temperature, Collins yield (intact fit, Coulomb friction, minimum,
 // pressure clipped at 0) with thermal softening, and shear modulus.
 __device__ inline void material_state(const sph_material &M, double rho, double u, double &P,
@@ -86,7 +99,7 @@ __device__ inline void material_state(const sph_material &M, double rho, double 
         const double yd = M.mu_d * pp;
         Y = yi < yd ? yi : yd;
         if (M.thermal_softening_on) {
-            const double s = tanh(M.xi * (M.T_melt / T - 1.0));
+            const double s = tanh(M.xi * (melt_temperature(M, rho) / T - 1.0));
             Y *= s > 0.0 ? s : 0.0;
         }
         Gm = M.shear_modulus > 0.0 ? M.shear_modulus

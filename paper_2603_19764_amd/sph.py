@@ -44,7 +44,9 @@ class sph_material(C.Structure):
         "rho0", "A", "B", "E0", "Eiv", "Ecv", "a", "b", "alpha", "beta",
         "cv", "T_ref", "c_min", "shear_modulus", "nu",
         "Y0", "Ym", "mu_i", "mu_d", "xi", "T_melt")] + [
-        ("strength_on", C.c_int32), ("thermal_softening_on", C.c_int32)]
+        ("strength_on", C.c_int32), ("thermal_softening_on", C.c_int32),
+        ("tmelt_n", C.c_int32), ("tmelt_pad", C.c_int32),
+        ("tmelt_rho", C.c_double * 8), ("tmelt_T", C.c_double * 8)]
 
 
 class sph_params(C.Structure):
@@ -137,9 +139,20 @@ def _stream(stream=None):
 
 
 def make_material(d: dict) -> sph_material:
+    """Material block from a dict; optional ``tmelt_rho`` / ``tmelt_T`` (up to
+    8 nodes, ascending density) give a tabulated melting temperature."""
     m = sph_material()
     for k, _ in sph_material._fields_:
+        if k.startswith("tmelt_"):
+            continue
         setattr(m, k, d[k])
+    tab_r, tab_t = d.get("tmelt_rho"), d.get("tmelt_T")
+    if tab_r is not None:
+        if len(tab_r) != len(tab_t) or len(tab_r) > 8:
+            raise ValueError("tmelt_rho and tmelt_T must have the same length, at most 8")
+        m.tmelt_n = len(tab_r)
+        for k, (r, t) in enumerate(zip(tab_r, tab_t)):
+            m.tmelt_rho[k], m.tmelt_T[k] = r, t
     return m
 
 

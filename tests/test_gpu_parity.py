@@ -237,3 +237,20 @@ def test_multistep_fp64_matches_oracle_integrator(orc, steps):
     say("multistep", {k: f"{v:.2e}" for k, v in e.items()})
     for k, v in e.items():
         assert v < 1e-9, (k, v)
+
+
+def test_tabulated_melting_temperature_parity(orc):
+    """A hot block whose melting temperature is a table of density: thermal
+    softening then varies with each particle's density."""
+    say("[melting table]")
+    w = inputs.c1_block(10, variant="y")
+    w["u"] = np.full(w["x"].size, 5.0e5)          # T = 925 K
+    mat = dict(w["mats"][0], tmelt_rho=[2500.0, 2650.0, 2800.0],
+               tmelt_T=[900.0, 1000.0, 1150.0])
+    w["mats"] = [mat]
+    ref = _oracle(orc, w)
+    got, ctx, perm = gpu_derivs(w, FP64)
+    errs = _compare(ref, got, TOL64, ("rho", "T", "Y", "S_pred", "dS", "a", "dudt"),
+                    "melting table fp64")
+    # the table is exercised: yield varies beyond what density alone does
+    assert np.ptp(ref["Y"]) > 0.0

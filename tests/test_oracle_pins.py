@@ -480,3 +480,26 @@ def test_integrator_conserves_momentum_and_is_deterministic(orc):
     p1 = np.array([np.sum(w["m"] * a[k]) for k in ("vx", "vy", "vz")])
     scale = np.sum(w["m"] * np.abs(a["ax"])) * a.dt
     assert np.abs(p1 - p0).max() < 1e-10 * max(scale, 1e-30) + 1e-12 * np.abs(p0).max()
+
+
+def test_tabulated_melting_temperature(orc):
+    """Melting temperature as a table of density (sec. 2.3): a flat table is
+    the constant, node densities give the node values, outside the table the
+    end values hold, and between two nodes it is linear (the softening factor
+    inverted for T_melt)."""
+    base = dict(inputs.basalt_c1(), xi=1.2)
+    P, T = 5e7, 900.0
+    flat = dict(base, tmelt_rho=[2500.0, 2900.0], tmelt_T=[base["T_melt"]] * 2)
+    for rho in (2400.0, 2700.0, 3000.0):
+        assert orc.yield_strength(flat, P, T, rho)[0] == orc.yield_strength(base, P, T, rho)[0]
+    tab = dict(base, tmelt_rho=[2500.0, 2700.0, 2900.0], tmelt_T=[1000.0, 1200.0, 1500.0])
+    for rho, tm in ((2500.0, 1000.0), (2700.0, 1200.0), (2900.0, 1500.0), (2000.0, 1000.0),
+                    (3500.0, 1500.0)):
+        ref = orc.yield_strength(dict(base, T_melt=tm), P, T, rho)[0]
+        assert math.isclose(orc.yield_strength(tab, P, T, rho)[0], ref, rel_tol=1e-14)
+    # between nodes: recover T_melt from the softening factor
+    y0 = orc.yield_strength(dict(base, thermal_softening_on=0), P, T)[0]
+    for rho, tm in ((2600.0, 1100.0), (2750.0, 1275.0)):
+        f = orc.yield_strength(tab, P, T, rho)[0] / y0
+        tm_back = T * (1.0 + math.atanh(f) / base["xi"])
+        assert math.isclose(tm_back, tm, rel_tol=1e-10)
