@@ -217,6 +217,10 @@ __global__ __launch_bounds__(64) void k_grav_walk(
         const float e2 = (float)(L.eps * L.eps);
 
         for (int t0 = 0; t0 < nt; t0 += kWave * kSlots) {
+            // slots holding targets in this pass (wave-uniform): empty slots
+            // are skipped by the evaluation loops
+            const int ns = (nt - t0 + kWave - 1) / kWave < kSlots ? (nt - t0 + kWave - 1) / kWave
+                                                                   : kSlots;
             Acc A;
 #pragma unroll
             for (int s = 0; s < kSlots; ++s) {
@@ -242,6 +246,7 @@ __global__ __launch_bounds__(64) void k_grav_walk(
                     const float4 q = il[e];
 #pragma unroll
                     for (int s = 0; s < kSlots; ++s) {
+                        if (s >= ns) break;
                         const float dx = q.x - A.tx[s], dy = q.y - A.ty[s], dz = q.z - A.tz[s];
                         const float r2 = dx * dx + dy * dy + dz * dz + e2;
                         const float ri = __frsqrt_rn(r2);
@@ -263,6 +268,7 @@ __global__ __launch_bounds__(64) void k_grav_walk(
                     const int j = stg_j[e];
 #pragma unroll
                     for (int s = 0; s < kSlots; ++s) {
+                        if (s >= ns) break;
                         const float dx = q.x - A.tx[s], dy = q.y - A.ty[s], dz = q.z - A.tz[s];
                         const float r2 = dx * dx + dy * dy + dz * dz + e2;
                         const float ri = __frsqrt_rn(r2);

@@ -52,6 +52,8 @@ def simulate(cases: list, t_end_ff: float = 2.0, prec: int = sph.SPH_FP32_CELLRE
     t = torch.zeros(nr, dtype=torch.float64, device="cuda")
     t_end_d = torch.tensor(t_end, dtype=torch.float64, device="cuda")
     steps = 0
+    import time
+    t0 = time.perf_counter()
     while steps < max_steps:
         for _ in range(check_every):
             t += st.dt          # the step about to be taken, per run
@@ -60,7 +62,8 @@ def simulate(cases: list, t_end_ff: float = 2.0, prec: int = sph.SPH_FP32_CELLRE
         ctx.check(sph.lib().sph_sync_status(ctx.h, None))
         done = bool(torch.all(t >= t_end_d).item())
         if log:
-            log(f"step {steps}: min t/t_end {float(torch.min(t / t_end_d)):.3f}")
+            log(f"  {nr} runs, {n} particles: step {steps}, min t/t_end "
+                f"{float(torch.min(t / t_end_d)):.3f}, {time.perf_counter() - t0:.1f} s")
         if done:
             break
     bound, mb, _ = sph.sph_bound_mass(

@@ -14,7 +14,7 @@ pytestmark = pytest.mark.gpu
 def test_qrd_scan_with_simulation_judge():
     from paper_2603_19764_amd import scan
     from paper_2603_19764_amd.proposal import MlpProposer
-    judge = scan.judge_with_simulation(n_target=3000, t_end_ff=1.5)
+    judge = scan.judge_with_simulation(n_target=3000, t_end_ff=1.5, log=say)
     train = [scan.case_for(r, s) for r in (5e5, 1.2e6, 3e6) for s in (0, 1)]
     held = [scan.case_for(r, s) for r in (7.5e5, 2e6) for s in (0, 1)]
     br_t, ok_t, outs = scan.bracket_rounds(train, judge, log=say)
