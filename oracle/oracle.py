@@ -49,7 +49,9 @@ class Material(C.Structure):
         "Y0", "Ym", "mu_i", "mu_d", "xi", "T_melt")] + [
         ("strength_on", C.c_int32), ("thermal_softening_on", C.c_int32),
         ("tmelt_n", C.c_int32), ("tmelt_pad", C.c_int32),
-        ("tmelt_rho", C.c_double * 8), ("tmelt_T", C.c_double * 8)]
+        ("tmelt_rho", C.c_double * 8), ("tmelt_T", C.c_double * 8),
+        ("eos_nrho", C.c_int32), ("eos_nu", C.c_int32)] + [
+        (k, C.POINTER(C.c_double)) for k in ("eos_rho", "eos_u", "eos_P", "eos_c", "eos_T")]
 
 
 class Params(C.Structure):
@@ -96,7 +98,7 @@ def _declare(L):
     L.or_J2.restype = C.c_double
     L.or_J2.argtypes = [_D]
     L.or_yield.restype = C.c_double
-    L.or_yield.argtypes = [C.POINTER(Material), C.c_double, C.c_double]
+    L.or_yield.argtypes = [C.POINTER(Material), C.c_double, C.c_double, C.c_double]
     L.or_shear_modulus.restype = C.c_double
     L.or_shear_modulus.argtypes = [C.POINTER(Material), C.c_double, C.c_double]
 
@@ -110,12 +112,34 @@ def _f64(a):
 
 
 # ---------------------------------------------------------------- structures
+def _eos_arrays(tab):
+    """Contiguous float64 copies of a tabulated EOS: dict with node vectors
+    ``rho`` (n_rho), ``u`` (n_u) and value grids ``P``, ``c``, ``T``
+    (n_rho x n_u)."""
+    r, u = _f64(tab["rho"]).ravel(), _f64(tab["u"]).ravel()
+    vals = [_f64(tab[k]).reshape(r.size, u.size) for k in ("P", "c", "T")]
+    return [r, u] + vals
+
+
 def material(d: dict) -> Material:
+    """Material block.  With an ``eos_table`` entry (a dict, treated as
+    immutable) the block points into float64 copies of the table that this
+    module keeps for the life of the process."""
     m = Material()
     for k, _ in Material._fields_:
-        if k.startswith("tmelt_"):
+        if k.startswith("tmelt_") or k.startswith("eos_"):
             continue
         setattr(m, k, d[k])
+    tab = d.get("eos_table")
+    if tab is not None:
+        hit = _EOS_KEEP.get(id(tab))
+        if hit is None or hit[0] is not tab:
+            hit = (tab, _eos_arrays(tab))
+            _EOS_KEEP[id(tab)] = hit
+        arrs = hit[1]
+        m.eos_nrho, m.eos_nu = arrs[0].size, arrs[1].size
+        for k, a in zip(("eos_rho", "eos_u", "eos_P", "eos_c", "eos_T"), arrs):
+            setattr(m, k, _p(a))
     tab_r, tab_t = d.get("tmelt_rho"), d.get("tmelt_T")
     if tab_r is not None:
         assert len(tab_r) == len(tab_t) <= 8
@@ -123,6 +147,10 @@ def material(d: dict) -> Material:
         for k, (r, t) in enumerate(zip(tab_r, tab_t)):
             m.tmelt_rho[k], m.tmelt_T[k] = r, t
     return m
+
+
+# tables referenced by Material blocks (keyed by the table dict; small)
+_EOS_KEEP = {}
 
 
 def materials(lst) -> C.Array:
@@ -166,6 +194,18 @@ def tillotson(mat: dict, rho, u):
     m = material(mat)
     lib().or_tillotson_arr(C.byref(m), C.c_int64(n), _p(rho), _p(u), _p(P), _p(c), _p(dr), _p(du))
     return P, c, dr, du
+
+
+def eos(mat: dict, rho, u):
+    """Return (P, c, T) of the material's EOS: its table when it has one,
+    otherwise Tillotson with T = T_ref + u / cv."""
+    rho, u = np.broadcast_arrays(_f64(rho), _f64(u))
+    rho, u = _f64(rho), _f64(u)
+    n = rho.size
+    P, c, T = (np.empty(n) for _ in range(3))
+    m = material(mat)
+    lib().or_eos_arr(C.byref(m), C.c_int64(n), _p(rho), _p(u), _p(P), _p(c), _p(T))
+    return P.reshape(rho.shape), c.reshape(rho.shape), T.reshape(rho.shape)
 
 
 def yield_strength(mat: dict, P, T, rho=None):

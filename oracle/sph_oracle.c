@@ -41,6 +41,11 @@
  *   K7  the EOS is Tillotson; temperature is T = T_ref + u / c_v; the sound
  *       speed follows c^2 = (dP/drho)_u + P/rho^2 (dP/du)_rho, floored at
  *       c_min [sec. 2.3 uses EOSlib / M-ANEOS, which are not available].
+ *   K7b an EOS given as a table (sec. 2.3 takes P, c and T from M-ANEOS
+ *       tables) holds P, c and T at the nodes of a rectangular grid in
+ *       (rho, u); between nodes the values are bilinear in (rho, u), rho
+ *       and u outside the grid are moved to its edge, and c is floored at
+ *       c_min as for Tillotson.
  *   K8  the thermal-softening factor is clamped at zero for T >= T_melt,
  *       and strength switched off for a material means Gamma = 0, Y = 0.
  *   K8b a melting temperature given as a table of density (sec. 2.3) is
@@ -77,6 +82,10 @@ typedef struct {
      * tmelt_n >= 2, nodes in ascending density */
     int32_t tmelt_n, tmelt_pad;
     double tmelt_rho[8], tmelt_T[8];
+    /* tabulated EOS (reading K7b): used when eos_nrho >= 2 and eos_nu >= 2;
+     * grid eos_rho x eos_u (ascending), values [i_rho * eos_nu + i_u] */
+    int32_t eos_nrho, eos_nu;
+    const double *eos_rho, *eos_u, *eos_P, *eos_c, *eos_T;
 } or_material;
 
 typedef struct {
@@ -416,6 +425,59 @@ double or_shear_modulus(const or_material *M, double rho, double c)
     return 3.0 * (1.0 - 2.0 * M->nu) / (2.0 * (1.0 + M->nu)) * K;
 }
 
+/* ----------------------------------------------------------------------- */
+/* Tabulated EOS (reading K7b).  The cell is the one whose lower node is   */
+/* the last node not above the (clamped) coordinate, so a coordinate on an */
+/* interior node takes the cell above it; the top node belongs to the last */
+/* cell.  Within the cell, with weights w_r, w_u in [0, 1]:                 */
+/*   f = f0 + w_r (f1 - f0),  f0 = f00 + w_u (f01 - f00),                   */
+/*                            f1 = f10 + w_u (f11 - f10),                   */
+/* the bilinear interpolant of the four corner values.                      */
+/* ----------------------------------------------------------------------- */
+static int table_cell(const double *node, int n, double *x)
+{
+    if (*x < node[0]) *x = node[0];
+    if (*x > node[n - 1]) *x = node[n - 1];
+    int k = 0;
+    while (k + 2 < n && *x >= node[k + 1]) ++k;
+    return k;
+}
+
+static double bilinear(const double *f, int nu, int kr, int ku, double wr, double wu)
+{
+    const double f00 = f[kr * nu + ku], f01 = f[kr * nu + ku + 1];
+    const double f10 = f[(kr + 1) * nu + ku], f11 = f[(kr + 1) * nu + ku + 1];
+    const double f0 = f00 + wu * (f01 - f00);
+    const double f1 = f10 + wu * (f11 - f10);
+    return f0 + wr * (f1 - f0);
+}
+
+void or_eos_table(const or_material *M, double rho, double u, double *P, double *c, double *T)
+{
+    const int nr = M->eos_nrho, nu = M->eos_nu;
+    double r = rho, e = u;
+    const int kr = table_cell(M->eos_rho, nr, &r);
+    const int ku = table_cell(M->eos_u, nu, &e);
+    const double wr = (r - M->eos_rho[kr]) / (M->eos_rho[kr + 1] - M->eos_rho[kr]);
+    const double wu = (e - M->eos_u[ku]) / (M->eos_u[ku + 1] - M->eos_u[ku]);
+    *P = bilinear(M->eos_P, nu, kr, ku, wr, wu);
+    double cc = bilinear(M->eos_c, nu, kr, ku, wr, wu);
+    *c = cc < M->c_min ? M->c_min : cc;
+    *T = bilinear(M->eos_T, nu, kr, ku, wr, wu);
+}
+
+/* P, c and T of one particle: the table when the material has one, else
+ * Tillotson with T = T_ref + u / c_v (reading K7). */
+void or_eos(const or_material *M, double rho, double u, double *P, double *c, double *T)
+{
+    if (M->eos_nrho >= 2 && M->eos_nu >= 2) {
+        or_eos_table(M, rho, u, P, c, T);
+        return;
+    }
+    or_tillotson(M, rho, u, P, c, NULL, NULL);
+    *T = M->T_ref + u / M->cv;
+}
+
 /* Per-particle state after the density: P, c, T, Y, Gamma. */
 void or_state(int64_t nt, const int64_t *tar, const double *rho, const double *u,
               const int32_t *mat, const or_material *mats,
@@ -425,9 +487,8 @@ void or_state(int64_t nt, const int64_t *tar, const double *rho, const double *u
     for (int64_t k = 0; k < nt; ++k) {
         int64_t i = tar[k];
         const or_material *M = &mats[mat[i]];
-        double Pi, ci;
-        or_tillotson(M, rho[i], u[i], &Pi, &ci, NULL, NULL);
-        double Ti = M->T_ref + u[i] / M->cv;
+        double Pi, ci, Ti;
+        or_eos(M, rho[i], u[i], &Pi, &ci, &Ti);
         P[i] = Pi;
         c[i] = ci;
         T[i] = Ti;
@@ -934,6 +995,12 @@ void or_tillotson_arr(const or_material *M, int64_t n, const double *rho, const 
     for (int64_t i = 0; i < n; ++i)
         or_tillotson(M, rho[i], u[i], &P[i], &c[i], dPdrho ? &dPdrho[i] : NULL,
                      dPdu ? &dPdu[i] : NULL);
+}
+
+void or_eos_arr(const or_material *M, int64_t n, const double *rho, const double *u,
+                double *P, double *c, double *T)
+{
+    for (int64_t i = 0; i < n; ++i) or_eos(M, rho[i], u[i], &P[i], &c[i], &T[i]);
 }
 
 void or_yield_arr(const or_material *M, int64_t n, const double *rho, const double *P,

@@ -1,8 +1,11 @@
 """Seeded synthetic inputs for the strength-SPH hot path.
 
-This module only lays out particles and draws random numbers; it holds none
-of the method's arithmetic (no kernel, EOS, yield or force formula).  Both the
-GPU path and the CPU oracle take their inputs from here.
+This module only lays out particles, draws random numbers and fills input
+tables; it holds none of the method's arithmetic (no kernel, Tillotson, yield
+or force formula, no table interpolation).  Both the GPU path and the CPU
+oracle take their inputs from here.  The one closed form evaluated here is the
+stiffened-gas law that fills the synthetic EOS table (``eos_table_stiffened``),
+a stand-in for an M-ANEOS table, which is data for the method.
 
 A workload is a dict of numpy arrays in SI units:
   x, y, z, vx, vy, vz, m, h, u   float64 (n,)
@@ -65,6 +68,32 @@ def granite_c3() -> dict:
 def fluid(mat: dict) -> dict:
     """The same material with strength switched off."""
     return dict(mat, strength_on=0)
+
+
+def eos_table_stiffened(rho0: float, c0: float, gamma0: float, cv: float = 800.0,
+                        T_ref: float = 300.0, rho_range=(0.25, 4.0), u_max: float = 1.0e8,
+                        n_rho: int = 96, n_u: int = 96, u_first: float = 1.0e3) -> dict:
+    """Synthetic tabulated EOS standing in for an M-ANEOS table.
+
+    Node values follow the stiffened-gas (linear Mie-Grueneisen) law
+        P = c0^2 (rho - rho0) + gamma0 rho u,
+        c^2 = c0^2 + gamma0 u + gamma0 P / rho   (clipped at 0),
+        T = T_ref + u / cv,
+    on density nodes geometric over rho_range * rho0 and energy nodes 0 plus
+    a geometric series from u_first to u_max.  Returns the dict that
+    materials take as ``eos_table``: rho (n_rho), u (n_u), P, c, T
+    (n_rho x n_u)."""
+    rho = rho0 * np.geomspace(rho_range[0], rho_range[1], n_rho)
+    u = np.concatenate([[0.0], np.geomspace(u_first, u_max, n_u - 1)])
+    R, U = np.meshgrid(rho, u, indexing="ij")
+    P = c0 * c0 * (R - rho0) + gamma0 * R * U
+    c2 = c0 * c0 + gamma0 * U + gamma0 * P / R
+    return dict(rho=rho, u=u, P=P, c=np.sqrt(np.maximum(c2, 0.0)), T=T_ref + U / cv)
+
+
+def tabulated(mat: dict, table: dict) -> dict:
+    """The same material with its EOS taken from ``table``."""
+    return dict(mat, eos_table=table)
 
 
 def default_params(**kw) -> dict:
