@@ -79,6 +79,26 @@ typedef struct {
      * outside the table; otherwise the constant T_melt above is used. */
     int32_t tmelt_n, tmelt_pad;
     double tmelt_rho[8], tmelt_T[8];
+    /* Tabulated EOS (sec. 2.3 takes P, c and T from M-ANEOS tables): with
+     * eos_nrho >= 2 and eos_nu >= 2 the state comes from a table instead of
+     * Tillotson.  eos_rho[eos_nrho] and eos_u[eos_nu] are the node
+     * coordinates, strictly ascending; eos_P, eos_c, eos_T hold the values
+     * at the nodes, row-major [i_rho * eos_nu + i_u].  All five are DEVICE
+     * pointers owned by the caller and must stay valid while calls that use
+     * the material run.  Between nodes each value is the bilinear
+     * interpolant in (rho, u); rho and u outside the grid are moved to its
+     * edge; c is floored at c_min.  The Tillotson constants, cv and T_ref
+     * are then unused.  Both counts at most 2^20, their product at most
+     * 2^26; nodes that are not ascending give wrong values, never an
+     * out-of-bounds read. */
+    int32_t eos_nrho, eos_nu;
+    const double *eos_rho, *eos_u, *eos_P, *eos_c, *eos_T;
+    /* Tillotson only: the cold (compressed-branch) formula gives zero
+     * pressure, with zero derivatives, for rho < rho_limit * rho0, so that
+     * strongly expanded cold material (a free surface, a crack) carries no
+     * tension; the blend with the hot branch keeps its form.  0 <= rho_limit
+     * <= 1; 0 keeps the formula's tension everywhere. */
+    double rho_limit;
 } sph_material;
 
 /* Run parameters: Monaghan AV (sec. 2.1), Courant factor (courant_condition

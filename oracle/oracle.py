@@ -51,7 +51,8 @@ class Material(C.Structure):
         ("tmelt_n", C.c_int32), ("tmelt_pad", C.c_int32),
         ("tmelt_rho", C.c_double * 8), ("tmelt_T", C.c_double * 8),
         ("eos_nrho", C.c_int32), ("eos_nu", C.c_int32)] + [
-        (k, C.POINTER(C.c_double)) for k in ("eos_rho", "eos_u", "eos_P", "eos_c", "eos_T")]
+        (k, C.POINTER(C.c_double)) for k in ("eos_rho", "eos_u", "eos_P", "eos_c", "eos_T")] + [
+        ("rho_limit", C.c_double)]
 
 
 class Params(C.Structure):
@@ -127,9 +128,10 @@ def material(d: dict) -> Material:
     module keeps for the life of the process."""
     m = Material()
     for k, _ in Material._fields_:
-        if k.startswith("tmelt_") or k.startswith("eos_"):
+        if k.startswith("tmelt_") or k.startswith("eos_") or k == "rho_limit":
             continue
         setattr(m, k, d[k])
+    m.rho_limit = float(d.get("rho_limit", 0.0))
     tab = d.get("eos_table")
     if tab is not None:
         hit = _EOS_KEEP.get(id(tab))

@@ -46,6 +46,10 @@
  *       (rho, u); between nodes the values are bilinear in (rho, u), rho
  *       and u outside the grid are moved to its edge, and c is floored at
  *       c_min as for Tillotson.
+ *   K7c optionally (rho_limit > 0) the cold Tillotson formula is cut to
+ *       zero pressure for rho < rho_limit rho0: material expanded that far
+ *       carries no tension, the usual treatment of cold expanded states in
+ *       Tillotson codes; the blend with the hot branch keeps its form.
  *   K8  the thermal-softening factor is clamped at zero for T >= T_melt,
  *       and strength switched off for a material means Gamma = 0, Y = 0.
  *   K8b a melting temperature given as a table of density (sec. 2.3) is
@@ -86,6 +90,9 @@ typedef struct {
      * grid eos_rho x eos_u (ascending), values [i_rho * eos_nu + i_u] */
     int32_t eos_nrho, eos_nu;
     const double *eos_rho, *eos_u, *eos_P, *eos_c, *eos_T;
+    /* Tillotson: the cold formula gives no pressure below rho_limit rho0
+     * (reading K7c; 0 keeps the tension of the formula) */
+    double rho_limit;
 } or_material;
 
 typedef struct {
@@ -316,12 +323,19 @@ int32_t or_adapt_h(int64_t n, const double *x, const double *y, const double *z,
 /*   hot expanded (eta < 1 and u >= Ecv):                                   */
 /*      Pe = a rho u + (b rho u / w + A mu exp(-beta z)) exp(-alpha z^2)    */
 /*   otherwise the linear blend in u of Pe and Pc.                          */
+/*   Pc = 0 (with zero derivatives) for eta < rho_limit (reading K7c).      */
 /* Sound speed from the partial derivatives of the active branch.           */
 /* ----------------------------------------------------------------------- */
 static void till_compressed(const or_material *M, double rho, double u,
                             double *P, double *dPdrho, double *dPdu)
 {
     double eta = rho / M->rho0;
+    if (eta < M->rho_limit) {
+        *P = 0.0;
+        *dPdrho = 0.0;
+        *dPdu = 0.0;
+        return;
+    }
     double mu = eta - 1.0;
     double w = u / (M->E0 * eta * eta) + 1.0;
     *P = (M->a + M->b / w) * rho * u + M->A * mu + M->B * mu * mu;

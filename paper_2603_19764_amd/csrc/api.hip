@@ -122,6 +122,7 @@ sph_status sph_create(sph_ctx **out, int64_t capacity, int32_t max_neighbors, in
         {(void **)&ctx->slot, cap * 4},
         {(void **)&ctx->perm, cap * 4},
         {(void **)&ctx->ptmp, cap * 4},
+        {(void **)&ctx->octant, cap},
         {(void **)&ctx->skey, cap * 4},
         {(void **)&ctx->cell_count, ((size_t)max_cells + 1) * 4},
         {(void **)&ctx->cell_start, ((size_t)max_cells + 1) * 4},
@@ -147,6 +148,7 @@ sph_status sph_create(sph_ctx **out, int64_t capacity, int32_t max_neighbors, in
         {(void **)&ctx->grav_lev, gravity_levels_bytes(max_runs)},
         {(void **)&ctx->grav_totals, 16},
         {(void **)&ctx->grav_mom0, ((size_t)max_cells + 1) * sizeof(float4)},
+        {(void **)&ctx->grav_mom8, ((size_t)max_cells + 1) * 8 * sizeof(float4)},
         {(void **)&ctx->grav_momU, ((size_t)max_cells + 1) * sizeof(float4)},
         {(void **)&ctx->bm_part, bound_mass_part_bytes(max_runs)},
         {(void **)&ctx->bm_vcm, (size_t)max_runs * 3 * 8},
@@ -184,7 +186,7 @@ sph_status sph_destroy(sph_ctx *h) {
                     ctx->total_keys, ctx->scan_part, ctx->flags, ctx->pairs, ctx->dtbits,
                     ctx->diag, ctx->rec_d, ctx->rec_g, ctx->rec_f, ctx->gsum,
                     ctx->grav_lev, ctx->grav_totals, ctx->grav_mom0, ctx->grav_momU,
-                    ctx->bm_part, ctx->bm_vcm, ctx->bm_removed};
+                    ctx->bm_part, ctx->bm_vcm, ctx->bm_removed, ctx->octant, ctx->grav_mom8};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     for (int w = 0; w < SPH_T_COUNT; ++w) {
@@ -318,8 +320,20 @@ static sph_status set_mats(sph_ctx *h, const sph_material *mats, int32_t nmat) {
     REQUIRE(mats && nmat >= 1 && nmat <= 8, SPH_EINVAL, "need 1..8 materials");
     for (int k = 0; k < nmat; ++k) {
         const sph_material &m = mats[k];
-        REQUIRE(m.rho0 > 0 && m.E0 > 0 && m.cv > 0 && m.Ecv > m.Eiv, SPH_EINVAL,
-                "material %d: invalid Tillotson or temperature constants", k);
+        const bool table = m.eos_nrho >= 2 || m.eos_nu >= 2;
+        if (table) {
+            REQUIRE(m.eos_nrho >= 2 && m.eos_nu >= 2 && m.eos_nrho <= (1 << 20) &&
+                        m.eos_nu <= (1 << 20) && (int64_t)m.eos_nrho * m.eos_nu <= (1ll << 26),
+                    SPH_EINVAL, "material %d: EOS table of %d x %d nodes", k, m.eos_nrho,
+                    m.eos_nu);
+            REQUIRE(m.eos_rho && m.eos_u && m.eos_P && m.eos_c && m.eos_T, SPH_EINVAL,
+                    "material %d: null EOS table pointer", k);
+        } else {
+            REQUIRE(m.rho0 > 0 && m.E0 > 0 && m.cv > 0 && m.Ecv > m.Eiv, SPH_EINVAL,
+                    "material %d: invalid Tillotson or temperature constants", k);
+            REQUIRE(m.rho_limit >= 0.0 && m.rho_limit <= 1.0, SPH_EINVAL,
+                    "material %d: rho_limit %g outside [0, 1]", k, m.rho_limit);
+        }
         REQUIRE(!m.strength_on || m.Ym > m.Y0, SPH_EINVAL, "material %d: Ym must exceed Y0", k);
         REQUIRE(m.tmelt_n >= 0 && m.tmelt_n <= 8, SPH_EINVAL,
                 "material %d: melting table with %d nodes (0..8)", k, m.tmelt_n);

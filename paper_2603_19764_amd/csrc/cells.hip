@@ -289,13 +289,21 @@ __global__ void k_keys(int64_t n, const double *x, const double *y, const double
         return;
     }
     uint32_t kk = 0xffffffffu;
+    int oct = 0;
     if (valid) {
         const int r = nr > 1 ? run_of(run_p, nr, k) : 0;
         const GridDesc g = grid[r];
-        int cx, cy, cz;
-        cell_of(g, x[k], y[k], z[k], cx, cy, cz);
+        const double tx = (x[k] - g.ox) * g.invL, ty = (y[k] - g.oy) * g.invL,
+                     tz = (z[k] - g.oz) * g.invL;
+        int cx = (int)floor(tx), cy = (int)floor(ty), cz = (int)floor(tz);
+        cx = cx < 0 ? 0 : (cx >= g.nx ? g.nx - 1 : cx);
+        cy = cy < 0 ? 0 : (cy >= g.ny ? g.ny - 1 : cy);
+        cz = cz < 0 ? 0 : (cz >= g.nz ? g.nz - 1 : cz);
         kk = (uint32_t)g.key_off + morton(cx, cy, cz, g.bx, g.by, g.bz);
         key[k] = kk;
+        // octant of the particle in its cell (the half-cells of the gravity
+        // tree below the search cells)
+        oct = (tx - cx >= 0.5 ? 1 : 0) | (ty - cy >= 0.5 ? 2 : 0) | (tz - cz >= 0.5 ? 4 : 0);
     }
     // One atomic per distinct key of the wave: lanes with equal keys take
     // consecutive slots in lane order.
@@ -314,7 +322,7 @@ __global__ void k_keys(int64_t n, const double *x, const double *y, const double
                                                        __builtin_amdgcn_mbcnt_lo((uint32_t)peers, 0u));
         todo &= ~peers;
     }
-    if (valid) slot[k] = my_slot;
+    if (valid) slot[k] = my_slot | (oct << kIdxBits);
 }
 
 __global__ void k_scatter(int64_t n, const uint32_t *key, const int32_t *slot,
@@ -325,29 +333,35 @@ __global__ void k_scatter(int64_t n, const uint32_t *key, const int32_t *slot,
         out[k] = (int32_t)k;
         return;
     }
-    out[cell_start[key[k]] + slot[k]] = (int32_t)k;
+    const int32_t sl = slot[k];
+    out[cell_start[key[k]] + (sl & (int32_t)kIdxMask)] = (int32_t)k | (sl & ~(int32_t)kIdxMask);
 }
 
 // Arrival order inside a cell depends on atomics; placing each member at its
-// rank by input index makes the permutation deterministic.  One thread per
-// particle counts the members of its cell with a smaller input index.
+// rank by (octant, input index) makes the permutation deterministic and
+// leaves the members of each octant contiguous.  One thread per particle
+// counts the members of its cell that precede it; arrival entries hold the
+// input index in the low kIdxBits bits and the octant above them.
 __global__ void k_cellrank(int64_t n, const int32_t *__restrict__ arrived,
                            const uint32_t *__restrict__ key,
                            const int32_t *__restrict__ cell_start,
                            const int32_t *__restrict__ cell_count, const int32_t *total_keys,
-                           int32_t *__restrict__ perm) {
+                           int32_t *__restrict__ perm, uint8_t *__restrict__ octant) {
     const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (p >= n) return;
-    const int32_t o = arrived[p];
+    const int32_t e = arrived[p];
+    const int32_t o = e & (int32_t)kIdxMask;
     if (*total_keys == 0) {
         perm[p] = o;
+        octant[p] = 0;
         return;
     }
     const uint32_t kk = key[o];
     const int32_t cs = cell_start[kk], c = cell_count[kk];
     int rank = 0;
-    for (int l = 0; l < c; ++l) rank += arrived[cs + l] < o;
+    for (int l = 0; l < c; ++l) rank += arrived[cs + l] < e;
     perm[cs + rank] = o;
+    octant[cs + rank] = (uint8_t)(e >> kIdxBits);
 }
 
 // Sorted copies of positions and h, cell-relative float offsets, packed
@@ -636,7 +650,7 @@ sph_status launch_build_cells(Ctx *ctx, int64_t n, double *x, double *y, double 
     hipLaunchKernelGGL(k_scatter, dim3(nb), dim3(tb), 0, s, n, ctx->key, ctx->slot,
                        ctx->cell_start, ctx->total_keys, ctx->ptmp);
     hipLaunchKernelGGL(k_cellrank, dim3(nb), dim3(tb), 0, s, n, ctx->ptmp, ctx->key,
-                       ctx->cell_start, ctx->cell_count, ctx->total_keys, ctx->perm);
+                       ctx->cell_start, ctx->cell_count, ctx->total_keys, ctx->perm, ctx->octant);
     hipLaunchKernelGGL(k_gather, dim3(nb), dim3(tb), 0, s, n, ctx->perm, x, y, z, h, ctx->key,
                        ctx->run_p, nr, ctx->grid, ctx->posh64, ctx->posh32, ctx->cellc,
                        ctx->runid, ctx->skey, perm_out, ex->m, ctx->rec_d, ex->f32);

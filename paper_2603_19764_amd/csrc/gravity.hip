@@ -6,13 +6,16 @@
 //             their Morton key in the global cell table;
 //   level k   dense grid of 2x2x2 blocks of level k-1, up to the first level
 //             whose every dimension is <= 2.
+//   level -1  the eight octants of each search cell (the cell build orders
+//             the members of a cell by octant).
 // Each node holds a monopole (mass and centre of mass, FP32, relative to the
 // run's grid origin).  Targets are grouped by level-1 node (2x2x2 cells); a
 // group walks the pyramid breadth first, one candidate node per lane: a
 // node whose box is disjoint from the group's box and whose edge is below
 // theta times the distance from its centre of mass to that box is used for
-// every target of the group; other nodes are opened, and opened leaves
-// contribute their particles one by one.  Plummer softening of length
+// every target of the group; other nodes are opened.  An opened cell tests
+// its octants the same way, and the particles of the octants it cannot
+// accept are used one by one.  Plummer softening of length
 // eps_r = eps_over_h * max_i h_i of the run; sources inside the near field
 // exclude the target itself.
 #include "sph_internal.h"
@@ -23,7 +26,7 @@ constexpr int kGravLevels = 12;
 constexpr int kCand = 2048;   // candidates of one level of one group walk
 constexpr int kIL = 512;      // accepted monopoles held before evaluation
 constexpr int kStage = 128;   // near-field source particles held before evaluation
-constexpr int kSlots = 4;     // targets per lane per pass
+constexpr int kSlots = 8;     // targets per lane per pass
 
 struct GravLevels {
     int32_t nlev;                      // levels 0 .. nlev-1
@@ -81,34 +84,55 @@ __device__ __forceinline__ int run_of_key(const GridDesc *grid, int nr, int64_t 
     return lo;
 }
 
-// Leaf monopoles: one thread per key of the global cell table.
+__device__ __forceinline__ float4 monopole(double M, double sx, double sy, double sz) {
+    return M > 0.0 ? make_float4((float)(sx / M), (float)(sy / M), (float)(sz / M), (float)M)
+                   : make_float4(0.f, 0.f, 0.f, 0.f);
+}
+
+// Cell and octant monopoles: one thread per key of the global cell table.
+// The members of a cell are ordered by octant, so each octant is one run of
+// consecutive members.
 __global__ void k_grav_leaf(int nr, const GridDesc *__restrict__ grid,
                             const int32_t *__restrict__ total_keys,
                             const int32_t *__restrict__ cell_start,
                             const int32_t *__restrict__ cell_count,
+                            const uint8_t *__restrict__ octant,
                             const double4 *__restrict__ posh64, const double *__restrict__ m,
-                            const int32_t *__restrict__ active, float4 *mom0) {
+                            const int32_t *__restrict__ active, float4 *mom0, float4 *mom8) {
     const int64_t nk = *total_keys;
     for (int64_t key = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; key < nk;
          key += (int64_t)gridDim.x * blockDim.x) {
         const int cnt = cell_count[key];
-        float4 out = make_float4(0.f, 0.f, 0.f, 0.f);
+        for (int o = 0; o < 8; ++o) mom8[key * 8 + o] = make_float4(0.f, 0.f, 0.f, 0.f);
+        double M = 0.0, sx = 0.0, sy = 0.0, sz = 0.0;
         if (cnt > 0) {
             const GridDesc g = grid[run_of_key(grid, nr, key)];
             const int s = cell_start[key];
-            double M = 0.0, sx = 0.0, sy = 0.0, sz = 0.0;
+            double Mo = 0.0, ox = 0.0, oy = 0.0, oz = 0.0;
+            int cur = octant[s];
             for (int k = 0; k < cnt; ++k) {
                 const int j = s + k;
+                const int o = octant[j];
+                if (o != cur) {
+                    mom8[key * 8 + cur] = monopole(Mo, ox, oy, oz);
+                    Mo = ox = oy = oz = 0.0;
+                    cur = o;
+                }
                 const double mj = (active && !active[j]) ? 0.0 : m[j];
                 const double4 p = posh64[j];
+                const double px = mj * (p.x - g.ox), py = mj * (p.y - g.oy), pz = mj * (p.z - g.oz);
+                Mo += mj;
+                ox += px;
+                oy += py;
+                oz += pz;
                 M += mj;
-                sx += mj * (p.x - g.ox);
-                sy += mj * (p.y - g.oy);
-                sz += mj * (p.z - g.oz);
+                sx += px;
+                sy += py;
+                sz += pz;
             }
-            if (M > 0.0) out = make_float4((float)(sx / M), (float)(sy / M), (float)(sz / M), (float)M);
+            mom8[key * 8 + cur] = monopole(Mo, ox, oy, oz);
         }
-        mom0[key] = out;
+        mom0[key] = monopole(M, sx, sy, sz);
     }
 }
 
@@ -162,8 +186,9 @@ __global__ __launch_bounds__(64) void k_grav_walk(
     int nr, const GridDesc *__restrict__ grid, const GravLevels *__restrict__ lev,
     const int64_t *__restrict__ totals, const int32_t *__restrict__ cell_start,
     const int32_t *__restrict__ cell_count, const double4 *__restrict__ posh64,
-    const double *__restrict__ m, const int32_t *__restrict__ active,
-    const float4 *__restrict__ mom0, const float4 *__restrict__ momU, float Gc, float theta,
+    const uint8_t *__restrict__ octant, const double *__restrict__ m,
+    const int32_t *__restrict__ active, const float4 *__restrict__ mom0,
+    const float4 *__restrict__ mom8, const float4 *__restrict__ momU, float Gc, float theta,
     int32_t accumulate, double *ax, double *ay, double *az, double *phi, int32_t *flags) {
     __shared__ uint32_t cand[2][kCand];
     __shared__ float4 il[kIL];
@@ -354,27 +379,68 @@ __global__ __launch_bounds__(64) void k_grav_walk(
                         }
                         if (!overflow) n_next += 8 * cnt;
                     }
-                    // opened leaves: stage their particles, one leaf at a time
-                    {
-                        uint64_t mk = __builtin_amdgcn_ballot_w64(leaf_open);
+                    // opened cells: their octants are accepted as monopoles
+                    // like other nodes, or their particles are staged
+                    if (k == 0) {
+                        const uint32_t key0 =
+                            leaf_open ? (uint32_t)g.key_off + morton(cx, cy, cz, g.bx, g.by, g.bz)
+                                      : 0u;
+                        const float half = 0.5f * edge;
+                        uint32_t lmask = 0;
+                        for (int d = 0; d < 8; ++d) {
+                            bool acc8 = false;
+                            float4 q8 = make_float4(0.f, 0.f, 0.f, 0.f);
+                            if (leaf_open) {
+                                q8 = mom8[(size_t)key0 * 8 + d];
+                                if (q8.w > 0.f) {
+                                    const float olo[3] = {(float)(2 * cx + (d & 1)) * half,
+                                                          (float)(2 * cy + ((d >> 1) & 1)) * half,
+                                                          (float)(2 * cz + (d >> 2)) * half};
+                                    const bool dis = olo[0] >= bhi[0] || olo[0] + half <= blo[0] ||
+                                                     olo[1] >= bhi[1] || olo[1] + half <= blo[1] ||
+                                                     olo[2] >= bhi[2] || olo[2] + half <= blo[2];
+                                    const float ex = fmaxf(fmaxf(blo[0] - q8.x, q8.x - bhi[0]), 0.f);
+                                    const float ey = fmaxf(fmaxf(blo[1] - q8.y, q8.y - bhi[1]), 0.f);
+                                    const float ez = fmaxf(fmaxf(blo[2] - q8.z, q8.z - bhi[2]), 0.f);
+                                    acc8 = dis && half * half < theta * theta * (ex * ex + ey * ey + ez * ez);
+                                    if (!acc8) lmask |= 1u << d;
+                                }
+                            }
+                            const uint64_t mk = __builtin_amdgcn_ballot_w64(acc8);
+                            const int cnt = __popcll(mk);
+                            if (cnt == 0) continue;
+                            if (n_il + cnt > kIL) flush_il();
+                            if (acc8) {
+                                const int rk = (int)__builtin_amdgcn_mbcnt_hi(
+                                    (uint32_t)(mk >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mk, 0u));
+                                il[n_il + rk] = q8;
+                            }
+                            n_il += cnt;
+                        }
+                        uint64_t mk = __builtin_amdgcn_ballot_w64(lmask != 0);
                         while (mk) {
                             const int src = __builtin_ctzll(mk);
                             mk &= mk - 1;
-                            const uint32_t key = (uint32_t)g.key_off +
-                                                 morton(__shfl(cx, src), __shfl(cy, src),
-                                                        __shfl(cz, src), g.bx, g.by, g.bz);
-                            const int s0 = cell_start[key], cnt = cell_count[key];
+                            const uint32_t kk = (uint32_t)__shfl((int)key0, src);
+                            const uint32_t lm = (uint32_t)__shfl((int)lmask, src);
+                            const int s0 = cell_start[kk], cnt = cell_count[kk];
                             for (int b = 0; b < cnt; b += kWave) {
-                                const int take = cnt - b < kWave ? cnt - b : kWave;
+                                const int j = s0 + b + lane;
+                                const bool in = b + lane < cnt && ((lm >> octant[j]) & 1u);
+                                const uint64_t mj = __builtin_amdgcn_ballot_w64(in);
+                                const int take = __popcll(mj);
+                                if (take == 0) continue;
                                 if (n_st + take > kStage) flush_st();
-                                if (lane < take) {
-                                    const int j = s0 + b + lane;
+                                if (in) {
+                                    const int rk = (int)__builtin_amdgcn_mbcnt_hi(
+                                        (uint32_t)(mj >> 32),
+                                        __builtin_amdgcn_mbcnt_lo((uint32_t)mj, 0u));
                                     const double4 p = posh64[j];
-                                    const double mj = (active && !active[j]) ? 0.0 : m[j];
-                                    stg[n_st + lane] = make_float4((float)(p.x - g.ox),
-                                                                   (float)(p.y - g.oy),
-                                                                   (float)(p.z - g.oz), (float)mj);
-                                    stg_j[n_st + lane] = j;
+                                    const double mass = (active && !active[j]) ? 0.0 : m[j];
+                                    stg[n_st + rk] = make_float4((float)(p.x - g.ox),
+                                                                 (float)(p.y - g.oy),
+                                                                 (float)(p.z - g.oz), (float)mass);
+                                    stg_j[n_st + rk] = j;
                                 }
                                 n_st += take;
                             }
@@ -440,7 +506,8 @@ sph_status launch_gravity(Ctx *ctx, int64_t n, const double *m, const int32_t *a
                        eps_over_h, (GravLevels *)ctx->grav_lev, ctx->grav_totals, ctx->grav_cap_upper,
                        ctx->flags);
     hipLaunchKernelGGL(k_grav_leaf, dim3(2048), dim3(256), 0, s, nr, ctx->grid, ctx->total_keys,
-                       ctx->cell_start, ctx->cell_count, ctx->posh64, m, active, ctx->grav_mom0);
+                       ctx->cell_start, ctx->cell_count, ctx->octant, ctx->posh64, m, active,
+                       ctx->grav_mom0, ctx->grav_mom8);
     const int ry = nr < 64 ? nr : 64;
     for (int k = 1; k < kGravLevels; ++k)
         hipLaunchKernelGGL(k_grav_up, dim3(64, ry), dim3(256), 0, s, nr, k, ctx->grid,
@@ -448,8 +515,9 @@ sph_status launch_gravity(Ctx *ctx, int64_t n, const double *m, const int32_t *a
                            ctx->grav_cap_upper, ctx->grav_mom0, ctx->grav_momU);
     hipLaunchKernelGGL(k_grav_walk, dim3(8192), dim3(64), 0, s, nr, ctx->grid,
                        (const GravLevels *)ctx->grav_lev,
-                       ctx->grav_totals, ctx->cell_start, ctx->cell_count, ctx->posh64, m, active,
-                       ctx->grav_mom0, ctx->grav_momU, (float)G, (float)theta, accumulate, ax, ay,
+                       ctx->grav_totals, ctx->cell_start, ctx->cell_count, ctx->posh64,
+                       ctx->octant, m, active, ctx->grav_mom0, ctx->grav_mom8, ctx->grav_momU,
+                       (float)G, (float)theta, accumulate, ax, ay,
                        az, phi, ctx->flags);
     SPH_HIP(hipGetLastError());
     return SPH_OK;

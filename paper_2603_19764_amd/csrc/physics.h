@@ -23,10 +23,15 @@ __device__ __forceinline__ const sph_material &material_of(const MatTable &mt, c
     return mt.m[id];
 }
 
-// Tillotson, compressed or cold branch: P and its partial derivatives.
+// Tillotson, compressed or cold branch: P and its partial derivatives (zero
+// below rho_limit rho0).
 __device__ inline void till_cold(const sph_material &M, double rho, double u, double &P,
                                  double &dr, double &du) {
     const double eta = rho / M.rho0, mu = eta - 1.0;
+    if (eta < M.rho_limit) {  // expanded below the limit: no tension
+        P = dr = du = 0.0;
+        return;
+    }
     const double w = u / (M.E0 * eta * eta) + 1.0;
     P = (M.a + M.b / w) * rho * u + M.A * mu + M.B * mu * mu;
     dr = M.a * u + M.b * u / w + 2.0 * M.b * u * (w - 1.0) / (w * w) +
@@ -85,12 +90,56 @@ __device__ inline double melt_temperature(const sph_material &M, double rho) {
     return M.tmelt_T[k] + w * (M.tmelt_T[k + 1] - M.tmelt_T[k]);
 }
 
+// Cell of a coordinate on ascending table nodes: x is clamped to the node
+// range and the result is the largest k in [0, n-2] with node[k] <= x, by
+// bisection (every probe is inside node[0..n-2]).
+__device__ inline int table_cell(const double *node, int n, double &x) {
+    const double lo = node[0], hi = node[n - 1];
+    x = x < lo ? lo : (x > hi ? hi : x);
+    int a = 0, b = n - 2;
+    while (a < b) {
+        const int mid = (a + b + 1) >> 1;
+        if (node[mid] <= x)
+            a = mid;
+        else
+            b = mid - 1;
+    }
+    return a;
+}
+
+// Bilinear interpolant of one value grid in cell (kr, ku) at weights wr, wu.
+__device__ inline double table_bilinear(const double *f, int nu, int kr, int ku, double wr,
+                                        double wu) {
+    const double *r0 = f + (int64_t)kr * nu + ku, *r1 = r0 + nu;
+    const double f0 = r0[0] + wu * (r0[1] - r0[0]);
+    const double f1 = r1[0] + wu * (r1[1] - r1[0]);
+    return f0 + wr * (f1 - f0);
+}
+
+// Tabulated EOS: P, c (floored at c_min) and T from the material's table.
+__device__ inline void table_eos(const sph_material &M, double rho, double u, double &P,
+                                 double &c, double &T) {
+    const int nu = M.eos_nu;
+    const int kr = table_cell(M.eos_rho, M.eos_nrho, rho);
+    const int ku = table_cell(M.eos_u, nu, u);
+    const double wr = (rho - M.eos_rho[kr]) / (M.eos_rho[kr + 1] - M.eos_rho[kr]);
+    const double wu = (u - M.eos_u[ku]) / (M.eos_u[ku + 1] - M.eos_u[ku]);
+    P = table_bilinear(M.eos_P, nu, kr, ku, wr, wu);
+    c = table_bilinear(M.eos_c, nu, kr, ku, wr, wu);
+    c = c < M.c_min ? M.c_min : c;
+    T = table_bilinear(M.eos_T, nu, kr, ku, wr, wu);
+}
+
 // EOS, temperature, Collins yield (intact fit, Coulomb friction, minimum,
 // pressure clipped at 0) with thermal softening, and shear modulus.
 __device__ inline void material_state(const sph_material &M, double rho, double u, double &P,
                                       double &c, double &T, double &Y, double &Gm) {
-    tillotson(M, rho, u, P, c);
-    T = M.T_ref + u / M.cv;
+    if (M.eos_nrho >= 2 && M.eos_nu >= 2) {
+        table_eos(M, rho, u, P, c, T);
+    } else {
+        tillotson(M, rho, u, P, c);
+        T = M.T_ref + u / M.cv;
+    }
     Y = 0.0;
     Gm = 0.0;
     if (M.strength_on) {

@@ -56,7 +56,8 @@ struct Ctx {
     // self-gravity pyramid (allocated with the context)
     void *grav_lev = nullptr;        // per-run level layout (max_runs entries)
     int64_t *grav_totals = nullptr;  // [upper nodes, groups]
-    float4 *grav_mom0 = nullptr;     // max_cells leaf monopoles (by cell key)
+    float4 *grav_mom0 = nullptr;     // max_cells cell monopoles (by cell key)
+    float4 *grav_mom8 = nullptr;     // 8 max_cells octant monopoles (by cell key, octant)
     float4 *grav_momU = nullptr;     // grav_cap_upper monopoles of levels >= 1
     int64_t grav_cap_upper = 0;
     double *bm_part = nullptr;       // bound mass: per-(run, block) partial sums
@@ -67,6 +68,7 @@ struct Ctx {
     int32_t *slot = nullptr;        // capacity: arrival rank within the cell
     int32_t *perm = nullptr;        // capacity: sorted -> input
     int32_t *ptmp = nullptr;        // capacity: arrival order within cells
+    uint8_t *octant = nullptr;      // capacity: octant of each sorted particle in its cell
     uint32_t *skey = nullptr;       // capacity: cell key, sorted order
     int32_t *cell_count = nullptr;  // max_cells + 1
     int32_t *cell_start = nullptr;  // max_cells + 1

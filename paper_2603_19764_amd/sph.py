@@ -11,6 +11,7 @@ from __future__ import annotations
 import ctypes as C
 import os
 
+import numpy as np
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -46,7 +47,10 @@ class sph_material(C.Structure):
         "Y0", "Ym", "mu_i", "mu_d", "xi", "T_melt")] + [
         ("strength_on", C.c_int32), ("thermal_softening_on", C.c_int32),
         ("tmelt_n", C.c_int32), ("tmelt_pad", C.c_int32),
-        ("tmelt_rho", C.c_double * 8), ("tmelt_T", C.c_double * 8)]
+        ("tmelt_rho", C.c_double * 8), ("tmelt_T", C.c_double * 8),
+        ("eos_nrho", C.c_int32), ("eos_nu", C.c_int32)] + [
+        (k, C.c_void_p) for k in ("eos_rho", "eos_u", "eos_P", "eos_c", "eos_T")] + [
+        ("rho_limit", C.c_double)]
 
 
 class sph_params(C.Structure):
@@ -138,14 +142,44 @@ def _stream(stream=None):
     return s.cuda_stream
 
 
+# device copies of tabulated EOS, keyed by the table dict (kept for the life
+# of the process: tables are small and their pointers go into kernels)
+_EOS_DEVICE = {}
+
+
+def device_eos_table(tab: dict):
+    """Device float64 copies (rho, u, P, c, T) of a tabulated EOS given as a
+    dict of node vectors ``rho`` (n_rho), ``u`` (n_u) and value grids ``P``,
+    ``c``, ``T`` (n_rho x n_u).  The dict is treated as immutable: the copy
+    is made once per dict and kept."""
+    hit = _EOS_DEVICE.get(id(tab))
+    if hit is None or hit[0] is not tab:
+        r = np.ascontiguousarray(tab["rho"], dtype=np.float64).ravel()
+        u = np.ascontiguousarray(tab["u"], dtype=np.float64).ravel()
+        grids = [np.ascontiguousarray(tab[k], dtype=np.float64).reshape(r.size, u.size)
+                 for k in ("P", "c", "T")]
+        dev = tuple(torch.from_numpy(a.copy()).to("cuda") for a in [r, u] + grids)
+        hit = (tab, dev)
+        _EOS_DEVICE[id(tab)] = hit
+    return hit[1]
+
+
 def make_material(d: dict) -> sph_material:
     """Material block from a dict; optional ``tmelt_rho`` / ``tmelt_T`` (up to
-    8 nodes, ascending density) give a tabulated melting temperature."""
+    8 nodes, ascending density) give a tabulated melting temperature, and an
+    optional ``eos_table`` (see ``device_eos_table``) a tabulated EOS."""
     m = sph_material()
     for k, _ in sph_material._fields_:
-        if k.startswith("tmelt_"):
+        if k.startswith("tmelt_") or k.startswith("eos_") or k == "rho_limit":
             continue
         setattr(m, k, d[k])
+    m.rho_limit = float(d.get("rho_limit", 0.0))
+    tab = d.get("eos_table")
+    if tab is not None:
+        dev = device_eos_table(tab)
+        m.eos_nrho, m.eos_nu = dev[0].numel(), dev[1].numel()
+        for k, t in zip(("eos_rho", "eos_u", "eos_P", "eos_c", "eos_T"), dev):
+            setattr(m, k, t.data_ptr())
     tab_r, tab_t = d.get("tmelt_rho"), d.get("tmelt_T")
     if tab_r is not None:
         if len(tab_r) != len(tab_t) or len(tab_r) > 8:

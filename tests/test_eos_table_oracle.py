@@ -149,3 +149,33 @@ def test_fine_table_of_tillotson_converges(rho_over_rho0):
     scale = mat["A"] * 0.05
     assert np.max(np.abs(Pt - Pw)) < 1e-4 * scale + 1e-5 * np.max(np.abs(Pw))
     np.testing.assert_allclose(ct, cw, rtol=2e-4)
+
+
+def test_tillotson_tension_cut():
+    """Reading K7c: with rho_limit the cold formula gives no pressure below
+    rho_limit rho0; above it, and in the hot branch, nothing changes; in the
+    blend the cold part vanishes, so P runs from 0 at E_iv to the hot value at
+    E_cv."""
+    base = inputs.granite_c3()
+    cut = dict(base, rho_limit=0.9)
+    r0, eiv, ecv = base["rho0"], base["Eiv"], base["Ecv"]
+    rho = np.array([0.5, 0.85, 0.899]) * r0
+    u = np.full(3, 1.0e3)                          # cold: the thermal term is small
+    P, c, _, _ = orc.tillotson(cut, rho, u)
+    assert np.all(P == 0.0) and np.all(c == base["c_min"])
+    P0, _, _, _ = orc.tillotson(base, rho, u)
+    assert np.all(P0 < -1e8)                       # the formula's tension that is cut
+    rho = np.array([0.9, 0.95, 1.0, 1.3]) * r0
+    u = np.array([0.0, 0.5 * eiv, 2.0 * ecv, 0.9 * eiv])
+    for a, b in zip(orc.tillotson(cut, rho, u), orc.tillotson(base, rho, u)):
+        assert np.array_equal(a, b)
+    hot_rho = np.array([0.3, 0.6, 0.85]) * r0
+    for a, b in zip(orc.tillotson(cut, hot_rho, np.full(3, 1.5 * ecv)),
+                    orc.tillotson(base, hot_rho, np.full(3, 1.5 * ecv))):
+        assert np.array_equal(a, b)
+    # blend: zero at E_iv, the uncut hot value at E_cv
+    Pl, _, _, _ = orc.tillotson(cut, hot_rho, np.full(3, eiv * (1 + 1e-12)))
+    assert np.all(np.abs(Pl) < 1e-6 * base["A"])
+    Ph, _, _, _ = orc.tillotson(cut, hot_rho, np.full(3, ecv * (1 - 1e-12)))
+    Pb, _, _, _ = orc.tillotson(base, hot_rho, np.full(3, ecv))
+    np.testing.assert_allclose(Ph, Pb, rtol=1e-9, atol=1e-3)
