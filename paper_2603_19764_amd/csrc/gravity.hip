@@ -11,9 +11,10 @@
 // Each node holds a monopole (mass and centre of mass, FP32, relative to the
 // run's grid origin).  Targets are grouped by level-1 node (2x2x2 cells); a
 // group walks the pyramid breadth first, one candidate node per lane: a
-// node whose box is disjoint from the group's box and whose edge is below
-// theta times the distance from its centre of mass to that box is used for
-// every target of the group; other nodes are opened.  An opened cell tests
+// node whose box is disjoint from the group's box and for which b < theta d
+// is used for every target of the group (b: distance from the node's centre
+// of mass to its farthest corner, d: from the centre of mass to the group's
+// box); other nodes are opened.  An opened cell tests
 // its octants the same way, and the particles of the octants it cannot
 // accept are used one by one.  Plummer softening of length
 // eps_r = eps_over_h * max_i h_i of the run; sources inside the near field
@@ -342,7 +343,12 @@ __global__ __launch_bounds__(64) void k_grav_walk(
                             const float ey = fmaxf(fmaxf(blo[1] - q.y, q.y - bhi[1]), 0.f);
                             const float ez = fmaxf(fmaxf(blo[2] - q.z, q.z - bhi[2]), 0.f);
                             const float d2 = ex * ex + ey * ey + ez * ez;
-                            acc_node = disjoint && edge * edge < theta * theta * d2;
+                            // b: distance from the centre of mass to the
+                            // node's farthest corner
+                            const float bx = fmaxf(q.x - nlo[0], nlo[0] + edge - q.x);
+                            const float by = fmaxf(q.y - nlo[1], nlo[1] + edge - q.y);
+                            const float bz = fmaxf(q.z - nlo[2], nlo[2] + edge - q.z);
+                            acc_node = disjoint && bx * bx + by * by + bz * bz < theta * theta * d2;
                             open = !acc_node && k > 0;
                             leaf_open = !acc_node && k == 0;
                         }
@@ -402,7 +408,11 @@ __global__ __launch_bounds__(64) void k_grav_walk(
                                     const float ex = fmaxf(fmaxf(blo[0] - q8.x, q8.x - bhi[0]), 0.f);
                                     const float ey = fmaxf(fmaxf(blo[1] - q8.y, q8.y - bhi[1]), 0.f);
                                     const float ez = fmaxf(fmaxf(blo[2] - q8.z, q8.z - bhi[2]), 0.f);
-                                    acc8 = dis && half * half < theta * theta * (ex * ex + ey * ey + ez * ez);
+                                    const float bx = fmaxf(q8.x - olo[0], olo[0] + half - q8.x);
+                                    const float by = fmaxf(q8.y - olo[1], olo[1] + half - q8.y);
+                                    const float bz = fmaxf(q8.z - olo[2], olo[2] + half - q8.z);
+                                    acc8 = dis && bx * bx + by * by + bz * bz <
+                                                      theta * theta * (ex * ex + ey * ey + ez * ez);
                                     if (!acc8) lmask |= 1u << d;
                                 }
                             }

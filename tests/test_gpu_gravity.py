@@ -84,11 +84,14 @@ def _errors(got, ref):
 
 
 def test_all_nodes_opened_is_direct_sum():
-    """A ball covered by 2x2x2 cells: every cell is opened, so the walk is a
-    direct sum in FP32."""
+    """A ball covered by 2x2x2 cells at opening angle 0.3: no cell or octant
+    is accepted (for the farthest octant, per axis, its centre of mass lies
+    0.75 + e cell edges from the target cell and 0.25 + |e| from the
+    octant's farthest corner, |e| <= 0.25, and 0.25 + |e| > 0.3 (0.75 + e)),
+    so the walk is a direct sum in FP32."""
     w = _ball_run(400, 100.0, 1e15, h_over_sp=3.0)
     ctx, st = _sorted_state(w, max_neighbors=512)
-    got = _gpu_gravity(ctx, st)
+    got = _gpu_gravity(ctx, st, theta=0.3)
     ref = _oracle(_sorted_host(st), None, 0.5)
     rel, prel = _errors(got, ref)
     amax = np.max(np.linalg.norm(np.stack(ref[:3]), axis=0))

@@ -24,7 +24,9 @@ TOL64 = 1e-10
 # summed in double: 2.4e-7 measured on the 16^3 block.  The EOS amplifies the
 # density error where c^2 nearly vanishes (expanded cold states at the block's
 # corners), which shows in c and the CFL step: 1.4e-6 and 1.5e-5 measured.
-TOL32 = dict(rho=1e-6, omega=1e-6, P=1e-5, cs=1e-5, G=1e-5, dS=1e-5, a=1e-5, dudt=2e-5, dt=1e-4)
+# P is bounded through the density: max |dP| <= c^2 max |drho|, so its error
+# is taken relative to max(rho) max(c)^2 with the density bound.
+TOL32 = dict(rho=1e-6, omega=1e-6, P=1e-6, cs=1e-5, G=1e-5, dS=1e-5, a=1e-5, dudt=2e-5, dt=1e-4)
 
 
 def _oracle(orc, w, targets=None):
@@ -48,7 +50,14 @@ def _compare(ref, got, tol, fields, label):
     errs = {}
     for k in fields:
         r = ref["c" if k == "cs" else ("Gam" if k == "Gmod" else k)]
-        errs[k] = norm_err(got[k], r)
+        if k == "P" and isinstance(tol, dict):
+            # FP32 form: the pair arithmetic reaches P only through rho, so
+            # |dP| <= (dP/drho) |drho| <= c^2 |drho|; the error is measured
+            # against that bulk-modulus scale, since max |P| can be close to
+            # zero in an unstressed body
+            errs[k] = float(np.max(np.abs(got[k] - r)) / (np.max(ref["rho"]) * np.max(ref["c"]) ** 2))
+        else:
+            errs[k] = norm_err(got[k], r)
     say(label, {k: f"{v:.2e}" for k, v in errs.items()})
     for k, e in errs.items():
         bound = tol[k] if isinstance(tol, dict) else tol
