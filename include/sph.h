@@ -303,12 +303,14 @@ sph_status sph_adapt_h(sph_ctx *ctx, int64_t n, const double *m, const double *h
 /* Softened self-gravity of every run (the gravitational term of the
  * momentum equation, sec. 2.2) at the positions of the last neighbour
  * search, in its sorted order: Barnes-Hut over a pyramid of the search
- * cells (level 0 = the cells, level k = 2x2x2 blocks of level k-1),
- * monopole moments, FP32 arithmetic on positions relative to each run's grid
- * origin.  The targets of each 2x2x2 block of cells share one walk: a node
- * whose box is disjoint from the block's and whose edge is below
- * theta x (distance from its centre of mass to the block) acts on all of
- * them as a point mass; other nodes are opened down to single particles.
+ * cells (level 0 = the cells, level k = 2x2x2 blocks of level k-1, level -1
+ * = the octants of each cell), monopole moments, FP32 arithmetic on
+ * positions relative to each run's grid origin.  The targets of each 2x2x2
+ * block of cells share one walk: a node whose box is disjoint from the
+ * block's and for which b < theta d (b: distance from the node's centre of
+ * mass to its farthest corner; d: from the centre of mass to the block)
+ * acts on all of them as a point mass; other nodes are opened down to
+ * single particles.
  * Plummer softening of length eps_r = eps_over_h x max_i h_i of run r:
  *   a_i = G sum_j m_j (x_j - x_i) / (r^2 + eps_r^2)^(3/2),
  *   phi_i = -G sum_j m_j / (r^2 + eps_r^2)^(1/2),  j != i, same run.
@@ -400,7 +402,9 @@ sph_status sph_init(sph_ctx *ctx, sph_state *st, const sph_material *mats, int32
  * minimum, opening kick.  All on `stream`, no host synchronisation, no
  * allocation and no memset: a fixed sequence of kernel launches whose device
  * pointers repeat every two steps, so an even number of steps can be
- * captured in a hipGraph and replayed. */
+ * captured in a hipGraph and replayed.  Particle masses must be positive
+ * (the fused sweep stores each particle's mass-weighted terms and divides
+ * its own by its mass). */
 sph_status sph_step(sph_ctx *ctx, sph_state *st, const sph_material *mats, int32_t n_materials,
                     const sph_params *prm, sph_precision prec, sph_stream stream);
 

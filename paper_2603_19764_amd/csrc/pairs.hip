@@ -405,8 +405,18 @@ __global__ __launch_bounds__(kBlock) void k_forces(
 // ==================================================== gradients + forces
 // The force pass needs only density-pass quantities and the rescaled
 // predicted stress, not the velocity gradient, so the whole-step path
-// evaluates both sums in one sweep over the pair lists.  Record (5 slots):
-// (p, 1/H) (v, m) (Kn A xx yy zz xy) (Kn A xz yz, rho, c) (Kn/(Omega rho), Kn, h, -).
+// evaluates both sums in one sweep over the pair lists.  Record (5 slots,
+// written by the whole-step state kernel; A = sigma/(Omega rho^2)):
+//   (p, 1/H) (v, m) (m Kn A: xx yy zz xy) (m Kn A: xz yz, rho/2, c/2)
+//   (-m Kn/(2 Omega rho), m Kn/2, h/2, 1/m).
+// Neighbour j's factors are used as stored; particle i's are divided by m_i
+// once, so every pair term carries m_j without a product of its own:
+//   -w_ij    = (m_j t_i^3) G_i + t_j^3 G'_j          (G = -Kn/(2 Omega rho))
+//   dv_i    += (m_j t_i^3) (Kn A)_i x_ij + t_j^3 (m Kn A)_j x_ij
+//   du_i    -= (m_j t_i^3) v_ij . (Kn A)_i x_ij
+// and the viscosity term takes one reciprocal, of D rho_bar with
+// D = r^2 + eps h_bar^2:  mu = h_bar v.x rho_bar / (D rho_bar),
+// Pi = mu (beta mu - alpha c_bar) D / (D rho_bar).
 constexpr int kRecBoth = 5;
 
 template <int L, bool F32>
@@ -430,12 +440,17 @@ __global__ __launch_bounds__(kBlock) void k_grad_forces(
     R c_xx = 0, c_yy = 0, c_zz = 0, c_xy = 0, c_xz = 0, c_yz = 0;
     R f[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     R acx = 0, acy = 0, acz = 0, du = 0, mumax = 0;
-    R4 Bi = {0, 0, 0, 0}, Hi = {0, 0, 0, 0};
+    R hi2 = 0, ci2 = 0;
     if (active) {
         const R4 *ri = rec + kRecBoth * i;
-        const R4 pi = ri[0], vi = ri[1], Ai = ri[2];
-        Bi = ri[3];
-        Hi = ri[4];
+        const R4 pi = ri[0], vi = ri[1], A2 = ri[2], B2 = ri[3], H2 = ri[4];
+        const R im = H2.w;
+        const R4 Ai = {A2.x * im, A2.y * im, A2.z * im, A2.w * im};
+        const R bix = B2.x * im, biy = B2.y * im;
+        const R Gi = H2.x * im, Xi = H2.y * im;
+        hi2 = H2.z;
+        ci2 = B2.w;
+        const R ri2 = B2.z;
         const R ral = (R)al, rbe = (R)be, reps = (R)eps;
         float L32 = 0.f;
         if constexpr (F32) L32 = grid[runid[i]].L32;
@@ -464,36 +479,36 @@ __global__ __launch_bounds__(kBlock) void k_grad_forces(
             ti = ti > (R)0 ? ti : (R)0;
             tj = tj > (R)0 ? tj : (R)0;
             const R ti3 = ti * ti * ti, tj3 = tj * tj * tj;
-            const R mj = vj.w;
+            const R mti = vj.w * ti3;
             const R ux = vi.x - vj.x, uy = vi.y - vj.y, uz = vi.z - vj.z;
-            // gradient sums: -w = -1/2 m_j (K_i/(Om rho)_i + K_j/(Om rho)_j)
-            const R nw = (R)(-0.5) * mj * (Hi.x * ti3 + Hj.x * tj3);
+            // gradient sums
+            const R nw = mti * Gi + tj3 * Hj.x;
             const R wx = nw * dx, wy = nw * dy, wz = nw * dz;
             c_xx += wx * dx; c_yy += wy * dy; c_zz += wz * dz;
             c_xy += wx * dy; c_xz += wx * dz; c_yz += wy * dz;
             f[0] += ux * wx; f[1] += ux * wy; f[2] += ux * wz;
             f[3] += uy * wx; f[4] += uy * wy; f[5] += uy * wz;
             f[6] += uz * wx; f[7] += uz * wy; f[8] += uz * wz;
-            // forces: y_k = (Kn A)_k x_ij
-            const R yix = Ai.x * dx + Ai.w * dy + Bi.x * dz;
-            const R yiy = Ai.w * dx + Ai.y * dy + Bi.y * dz;
-            const R yiz = Bi.x * dx + Bi.y * dy + Ai.z * dz;
+            // forces
+            const R yix = Ai.x * dx + Ai.w * dy + bix * dz;
+            const R yiy = Ai.w * dx + Ai.y * dy + biy * dz;
+            const R yiz = bix * dx + biy * dy + Ai.z * dz;
             const R yjx = Aj.x * dx + Aj.w * dy + Bj.x * dz;
             const R yjy = Aj.w * dx + Aj.y * dy + Bj.y * dz;
             const R yjz = Bj.x * dx + Bj.y * dy + Aj.z * dz;
-            acx += mj * (ti3 * yix + tj3 * yjx);
-            acy += mj * (ti3 * yiy + tj3 * yjy);
-            acz += mj * (ti3 * yiz + tj3 * yjz);
-            du -= mj * ti3 * (ux * yix + uy * yiy + uz * yiz);
+            acx += mti * yix; acx += tj3 * yjx;
+            acy += mti * yiy; acy += tj3 * yjy;
+            acz += mti * yiz; acz += tj3 * yjz;
+            du -= mti * (ux * yix + uy * yiy + uz * yiz);
             const R vr = ux * dx + uy * dy + uz * dz;
             if (vr < (R)0) {
-                const R hb = (R)0.5 * (Hi.z + Hj.z);
-                const R mu = quot(hb * vr, r2 + reps * hb * hb);
-                const R cb = (R)0.5 * (Bi.w + Bj.w);
-                const R rb = (R)0.5 * (Bi.z + Bj.z);
-                const R Pi = quot(-ral * cb * mu + rbe * mu * mu, rb);
-                const R gw = (R)0.5 * (Hi.y * ti3 + Hj.y * tj3);  // mean K
-                const R sv = mj * Pi * gw;
+                const R hb = hi2 + Hj.z;
+                const R D = r2 + reps * hb * hb;
+                const R rb = ri2 + Bj.z;
+                const R inv = quot((R)1, D * rb);
+                const R mu = hb * vr * rb * inv;
+                const R Pi = mu * (rbe * mu - ral * (ci2 + Bj.w)) * (D * inv);
+                const R sv = (mti * Xi + tj3 * Hj.y) * Pi;  // m_j Pi mean K
                 acx -= sv * dx;
                 acy -= sv * dy;
                 acz -= sv * dz;
@@ -520,8 +535,8 @@ __global__ __launch_bounds__(kBlock) void k_grad_forces(
         o[3 * n] = c_xy; o[4 * n] = c_xz; o[5 * n] = c_yz;
 #pragma unroll
         for (int a = 0; a < 9; ++a) o[(6 + a) * n] = f[a];
-        const double hi = (double)Hi.z;
-        const double ci = (double)Bi.w;
+        const double hi = 2.0 * (double)hi2;
+        const double ci = 2.0 * (double)ci2;
         ax[i] = (double)acx + gx;
         ay[i] = (double)acy + gy;
         az[i] = (double)acz + gz;

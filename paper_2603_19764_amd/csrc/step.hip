@@ -86,16 +86,21 @@ __global__ void k_state(int64_t n, const double4 *__restrict__ posh64,
     } else {
         px = q64.x; py = q64.y; pz = q64.z;
     }
+    // (p, 1/H) (v, m) (m Kn A: xx yy zz xy) (m Kn A: xz yz, rho/2, c/2)
+    // (-m Kn/(2 Omega rho), m Kn/2, h/2, 1/m), A = sigma/(Omega rho^2): the
+    // sweep uses j's terms as stored and i's divided by m_i once
     const double H = 2.0 * q64.w;
+    const double mi = m[i];
     const double kn = -210.0 / (kPiD * H * H * H * H * H);
-    const double sc = kn / (om * r * r);
+    const double sc = mi * kn / (om * r * r);
     R4 *rf = (R4 *)rec_f_v + 5 * i;
     rf[0] = {px, py, pz, (R)(1.0 / H)};
-    rf[1] = {(R)vpx[i], (R)vpy[i], (R)vpz[i], (R)m[i]};
+    rf[1] = {(R)vpx[i], (R)vpy[i], (R)vpz[i], (R)mi};
     rf[2] = {(R)(sc * (s[0] - p)), (R)(sc * (s[1] - p)), (R)(sc * (-s[0] - s[1] - p)),
              (R)(sc * s[2])};
-    rf[3] = {(R)(sc * s[3]), (R)(sc * s[4]), (R)r, (R)c};
-    rf[4] = {(R)(kn / (om * r)), (R)kn, (R)q64.w, (R)0};
+    rf[3] = {(R)(sc * s[3]), (R)(sc * s[4]), (R)(0.5 * r), (R)(0.5 * c)};
+    rf[4] = {(R)(-0.5 * mi * kn / (om * r)), (R)(0.5 * mi * kn), (R)(0.5 * q64.w),
+             (R)(mi > 0.0 ? 1.0 / mi : 0.0)};
 }
 
 // ------------------------------------------- gradient epilogue + stress rate

@@ -49,12 +49,11 @@ def basalt_c1() -> dict:
 
 def granular_c2() -> dict:
     """Granular basalt (rho0 = 2600): zero cohesion, friction tan(30 deg), shear
-    modulus from the bulk modulus with nu = 0.25, no thermal softening, and no
-    tension (cold states below rho0 carry no pressure: rho_limit = 1)."""
+    modulus from the bulk modulus with nu = 0.25, no thermal softening."""
     e = dict(_BASALT_EOS, rho0=2600.0)
     return dict(e, cv=800.0, T_ref=300.0, c_min=_cmin(e), shear_modulus=0.0, nu=0.25,
                 Y0=0.0, Ym=3.5e9, mu_i=2.0, mu_d=math.tan(math.radians(30.0)), xi=1.2,
-                T_melt=1373.0, strength_on=1, thermal_softening_on=0, rho_limit=1.0)
+                T_melt=1373.0, strength_on=1, thermal_softening_on=0)
 
 
 def granite_c3() -> dict:
