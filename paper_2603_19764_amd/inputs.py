@@ -65,6 +65,14 @@ def granite_c3() -> dict:
                 strength_on=1, thermal_softening_on=1)
 
 
+def granite_impact() -> dict:
+    """The granite of the two-sphere impact with cold expanded states cut to
+    zero pressure below 0.9 rho0 (``rho_limit``): the material of the
+    batched impact scans, whose bodies run for thousands of steps with free
+    surfaces."""
+    return dict(granite_c3(), rho_limit=0.9)
+
+
 def fluid(mat: dict) -> dict:
     """The same material with strength switched off."""
     return dict(mat, strength_on=0)
@@ -331,7 +339,7 @@ def scan_batch(n_runs: int = 64, seed: int = 5, n_min: int = 20_000, n_max: int 
     granite with strength, material 1 the same without; runs are concatenated
     (``run_start``) and ``cases`` lists each run's parameters."""
     rng = np.random.Generator(np.random.PCG64(seed))
-    strong = granite_c3()
+    strong = granite_impact()
     mats = [strong, fluid(strong)]
     runs, cases = [], []
     for _ in range(n_runs):

@@ -3,6 +3,8 @@ gravity, strength on or off) run in batches, one simulation per open
 bracket per round; the bound-mass fraction of each run decides.  The
 network is trained on the outcomes of training cases and then guides the
 search on held-out cases next to plain bisection."""
+import time
+
 import numpy as np
 import pytest
 
@@ -14,12 +16,14 @@ pytestmark = pytest.mark.gpu
 def test_qrd_scan_with_simulation_judge():
     from paper_2603_19764_amd import scan
     from paper_2603_19764_amd.proposal import MlpProposer
-    judge = scan.judge_with_simulation(n_target=3000, t_end_ff=1.5, log=say)
-    train = [scan.case_for(r, s) for r in (5e5, 1.2e6, 3e6) for s in (0, 1)]
-    held = [scan.case_for(r, s) for r in (7.5e5, 2e6) for s in (0, 1)]
+    t0 = time.perf_counter()
+    judge = scan.judge_with_simulation(n_target=2000, t_end_ff=1.5, check_every=100, log=say)
+    train = [scan.case_for(r, s) for r in (6e5, 2.5e6) for s in (0, 1)]
+    held = [scan.case_for(1.2e6, s) for s in (0, 1)]
     br_t, ok_t, outs = scan.bracket_rounds(train, judge, log=say)
-    say(f"training brackets valid {ok_t}, sims {[b.sims for b in br_t]}")
-    assert sum(ok_t) >= 4
+    say(f"training brackets valid {ok_t}, sims {[b.sims for b in br_t]}, "
+        f"{time.perf_counter() - t0:.0f} s")
+    assert sum(ok_t) >= 3
     X = np.array([o[0] for o in outs])
     Y = np.array([o[1] for o in outs])
     net = MlpProposer(seed=1, lr=3e-3)
@@ -32,8 +36,8 @@ def test_qrd_scan_with_simulation_judge():
     q_b = [b.q_rd() for b, ok in zip(br_b, ok_b) if ok]
     q_n = [b.q_rd() for b, ok in zip(br_n, ok_n) if ok]
     say(f"held-out: bisection sims {sims_b} (Q_RD* {np.round(q_b, 0)}), "
-        f"network sims {sims_n} (Q_RD* {np.round(q_n, 0)})")
-    assert ok_b == ok_n and sum(ok_b) >= 2
+        f"network sims {sims_n} (Q_RD* {np.round(q_n, 0)}), {time.perf_counter() - t0:.0f} s")
+    assert ok_b == ok_n and sum(ok_b) >= 1
     for b, ok in zip(br_b + br_n, ok_b + ok_n):
         if ok:
             assert b.width() <= 0.05
