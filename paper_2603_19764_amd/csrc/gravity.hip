@@ -24,9 +24,9 @@
 namespace sph {
 
 constexpr int kGravLevels = 12;
-constexpr int kCand = 2048;   // candidates of one level of one group walk
-constexpr int kIL = 512;      // accepted monopoles held before evaluation
-constexpr int kStage = 128;   // near-field source particles held before evaluation
+constexpr int kCand = 1024;   // candidates of one level (>= 1) of one group walk
+constexpr int kIL = 128;      // accepted monopoles held before evaluation
+constexpr int kStage = 64;    // near-field source particles held before evaluation
 constexpr int kSlots = 8;     // targets per lane per pass
 
 struct GravLevels {
@@ -318,6 +318,98 @@ __global__ __launch_bounds__(64) void k_grav_walk(
                 n_cur = tn;
             }
             bool overflow = false;
+            // b < theta d with b from the centre of mass to the node's
+            // farthest corner and d from it to the group's box; the node's
+            // box must be disjoint from the group's
+            auto accepts = [&](const float4 &q, float lx, float ly, float lz, float e) -> bool {
+                const bool disjoint = lx >= bhi[0] || lx + e <= blo[0] || ly >= bhi[1] ||
+                                      ly + e <= blo[1] || lz >= bhi[2] || lz + e <= blo[2];
+                const float ex = fmaxf(fmaxf(blo[0] - q.x, q.x - bhi[0]), 0.f);
+                const float ey = fmaxf(fmaxf(blo[1] - q.y, q.y - bhi[1]), 0.f);
+                const float ez = fmaxf(fmaxf(blo[2] - q.z, q.z - bhi[2]), 0.f);
+                const float bx = fmaxf(q.x - lx, lx + e - q.x);
+                const float by = fmaxf(q.y - ly, ly + e - q.y);
+                const float bz = fmaxf(q.z - lz, lz + e - q.z);
+                return disjoint &&
+                       bx * bx + by * by + bz * bz < theta * theta * (ex * ex + ey * ey + ez * ez);
+            };
+            // wave-wide: append the lanes' accepted monopoles to the list
+            auto push_il = [&](bool acc, const float4 &q) {
+                const uint64_t mk = __builtin_amdgcn_ballot_w64(acc);
+                const int cnt = __popcll(mk);
+                if (cnt == 0) return;
+                if (n_il + cnt > kIL) flush_il();
+                if (acc) {
+                    const int rk = (int)__builtin_amdgcn_mbcnt_hi(
+                        (uint32_t)(mk >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mk, 0u));
+                    il[n_il + rk] = q;
+                }
+                n_il += cnt;
+            };
+            // wave-wide: one search cell per lane (valid lanes): the cell
+            // as a monopole, else its octants, else the particles of the
+            // octants it cannot accept
+            auto handle_cell = [&](bool valid, int cx, int cy, int cz) {
+                const float Lc = (float)g.L, half = 0.5f * Lc;
+                uint32_t key0 = 0u;
+                float4 q = make_float4(0.f, 0.f, 0.f, 0.f);
+                bool acc = false, open = false;
+                if (valid) {
+                    key0 = (uint32_t)g.key_off + morton(cx, cy, cz, g.bx, g.by, g.bz);
+                    q = mom0[key0];
+                    if (q.w > 0.f) {
+                        acc = accepts(q, cx * Lc, cy * Lc, cz * Lc, Lc);
+                        open = !acc;
+                    }
+                }
+                push_il(acc, q);
+                if (!__builtin_amdgcn_ballot_w64(open)) return;
+                uint32_t lmask = 0;
+                for (int d = 0; d < 8; ++d) {
+                    bool acc8 = false;
+                    float4 q8 = make_float4(0.f, 0.f, 0.f, 0.f);
+                    if (open) {
+                        q8 = mom8[(size_t)key0 * 8 + d];
+                        if (q8.w > 0.f) {
+                            acc8 = accepts(q8, (float)(2 * cx + (d & 1)) * half,
+                                           (float)(2 * cy + ((d >> 1) & 1)) * half,
+                                           (float)(2 * cz + (d >> 2)) * half, half);
+                            if (!acc8) lmask |= 1u << d;
+                        }
+                    }
+                    push_il(acc8, q8);
+                }
+                uint64_t mk = __builtin_amdgcn_ballot_w64(lmask != 0);
+                while (mk) {
+                    const int src = __builtin_ctzll(mk);
+                    mk &= mk - 1;
+                    const uint32_t kk = (uint32_t)__shfl((int)key0, src);
+                    const uint32_t lm = (uint32_t)__shfl((int)lmask, src);
+                    const int s0 = cell_start[kk], cnt = cell_count[kk];
+                    for (int b = 0; b < cnt; b += kWave) {
+                        const int j = s0 + b + lane;
+                        const bool in = b + lane < cnt && ((lm >> octant[j]) & 1u);
+                        const uint64_t mj = __builtin_amdgcn_ballot_w64(in);
+                        const int take = __popcll(mj);
+                        if (take == 0) continue;
+                        if (n_st + take > kStage) flush_st();
+                        if (in) {
+                            const int rk = (int)__builtin_amdgcn_mbcnt_hi(
+                                (uint32_t)(mj >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mj, 0u));
+                            const double4 p = posh64[j];
+                            const double mass = (active && !active[j]) ? 0.0 : m[j];
+                            stg[n_st + rk] = make_float4((float)(p.x - g.ox), (float)(p.y - g.oy),
+                                                         (float)(p.z - g.oz), (float)mass);
+                            stg_j[n_st + rk] = j;
+                        }
+                        n_st += take;
+                    }
+                }
+            };
+            // levels top .. 1 breadth first through the candidate lists; the
+            // children of opened level-1 nodes (search cells) are handled by
+            // the lane that opened them; a run of a single level starts at
+            // its cells
             for (int k = top; k >= 0 && !overflow; --k) {
                 __syncthreads();
                 const int nx = L.nx[k], ny = L.ny[k];
@@ -325,47 +417,40 @@ __global__ __launch_bounds__(64) void k_grav_walk(
                 int n_next = 0;
                 for (int c0 = 0; c0 < n_cur; c0 += kWave) {
                     const int c = c0 + lane;
-                    bool acc_node = false, open = false, leaf_open = false;
-                    float4 q = make_float4(0.f, 0.f, 0.f, 0.f);
                     int cx = 0, cy = 0, cz = 0;
                     if (c < n_cur) {
                         const uint32_t id = cand[cur][c];
                         cx = (int)(id % (uint32_t)nx);
                         cy = (int)((id / (uint32_t)nx) % (uint32_t)ny);
                         cz = (int)(id / ((uint32_t)nx * (uint32_t)ny));
-                        q = node_moment(g, L, mom0, momU, k, cx, cy, cz);
-                        if (q.w > 0.f) {
-                            const float nlo[3] = {cx * edge, cy * edge, cz * edge};
-                            const bool disjoint = nlo[0] >= bhi[0] || nlo[0] + edge <= blo[0] ||
-                                                  nlo[1] >= bhi[1] || nlo[1] + edge <= blo[1] ||
-                                                  nlo[2] >= bhi[2] || nlo[2] + edge <= blo[2];
-                            const float ex = fmaxf(fmaxf(blo[0] - q.x, q.x - bhi[0]), 0.f);
-                            const float ey = fmaxf(fmaxf(blo[1] - q.y, q.y - bhi[1]), 0.f);
-                            const float ez = fmaxf(fmaxf(blo[2] - q.z, q.z - bhi[2]), 0.f);
-                            const float d2 = ex * ex + ey * ey + ez * ez;
-                            // b: distance from the centre of mass to the
-                            // node's farthest corner
-                            const float bx = fmaxf(q.x - nlo[0], nlo[0] + edge - q.x);
-                            const float by = fmaxf(q.y - nlo[1], nlo[1] + edge - q.y);
-                            const float bz = fmaxf(q.z - nlo[2], nlo[2] + edge - q.z);
-                            acc_node = disjoint && bx * bx + by * by + bz * bz < theta * theta * d2;
-                            open = !acc_node && k > 0;
-                            leaf_open = !acc_node && k == 0;
-                        }
                     }
-                    // accepted monopoles
-                    {
-                        const uint64_t mk = __builtin_amdgcn_ballot_w64(acc_node);
-                        const int cnt = __popcll(mk);
-                        if (n_il + cnt > kIL) flush_il();
-                        if (acc_node) {
-                            const int rk = (int)__builtin_amdgcn_mbcnt_hi(
-                                (uint32_t)(mk >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mk, 0u));
-                            il[n_il + rk] = q;
+                    bool acc_node = false, open = false;
+                    float4 q = make_float4(0.f, 0.f, 0.f, 0.f);
+                    if (k > 0) {
+                        if (c < n_cur) {
+                            q = node_moment(g, L, mom0, momU, k, cx, cy, cz);
+                            if (q.w > 0.f) {
+                                acc_node = accepts(q, cx * edge, cy * edge, cz * edge, edge);
+                                open = !acc_node;
+                            }
                         }
-                        n_il += cnt;
+                        push_il(acc_node, q);
                     }
-                    // children of opened nodes
+                    if (k <= 1) {
+                        // cells: the eight children of opened level-1 nodes,
+                        // or the candidates themselves at level 0
+                        const int cnx = L.nx[0], cny = L.ny[0], cnz = L.nz[0];
+                        for (int d = 0; d < (k == 1 ? 8 : 1); ++d) {
+                            const int x = k == 1 ? 2 * cx + (d & 1) : cx;
+                            const int y = k == 1 ? 2 * cy + ((d >> 1) & 1) : cy;
+                            const int z = k == 1 ? 2 * cz + (d >> 2) : cz;
+                            const bool v = k == 1 ? open && x < cnx && y < cny && z < cnz
+                                                  : c < n_cur;
+                            handle_cell(v, x, y, z);
+                        }
+                        continue;
+                    }
+                    // children of opened nodes into the next level's list
                     {
                         const uint64_t mk = __builtin_amdgcn_ballot_w64(open);
                         const int cnt = __popcll(mk);
@@ -384,77 +469,6 @@ __global__ __launch_bounds__(64) void k_grav_walk(
                             }
                         }
                         if (!overflow) n_next += 8 * cnt;
-                    }
-                    // opened cells: their octants are accepted as monopoles
-                    // like other nodes, or their particles are staged
-                    if (k == 0) {
-                        const uint32_t key0 =
-                            leaf_open ? (uint32_t)g.key_off + morton(cx, cy, cz, g.bx, g.by, g.bz)
-                                      : 0u;
-                        const float half = 0.5f * edge;
-                        uint32_t lmask = 0;
-                        for (int d = 0; d < 8; ++d) {
-                            bool acc8 = false;
-                            float4 q8 = make_float4(0.f, 0.f, 0.f, 0.f);
-                            if (leaf_open) {
-                                q8 = mom8[(size_t)key0 * 8 + d];
-                                if (q8.w > 0.f) {
-                                    const float olo[3] = {(float)(2 * cx + (d & 1)) * half,
-                                                          (float)(2 * cy + ((d >> 1) & 1)) * half,
-                                                          (float)(2 * cz + (d >> 2)) * half};
-                                    const bool dis = olo[0] >= bhi[0] || olo[0] + half <= blo[0] ||
-                                                     olo[1] >= bhi[1] || olo[1] + half <= blo[1] ||
-                                                     olo[2] >= bhi[2] || olo[2] + half <= blo[2];
-                                    const float ex = fmaxf(fmaxf(blo[0] - q8.x, q8.x - bhi[0]), 0.f);
-                                    const float ey = fmaxf(fmaxf(blo[1] - q8.y, q8.y - bhi[1]), 0.f);
-                                    const float ez = fmaxf(fmaxf(blo[2] - q8.z, q8.z - bhi[2]), 0.f);
-                                    const float bx = fmaxf(q8.x - olo[0], olo[0] + half - q8.x);
-                                    const float by = fmaxf(q8.y - olo[1], olo[1] + half - q8.y);
-                                    const float bz = fmaxf(q8.z - olo[2], olo[2] + half - q8.z);
-                                    acc8 = dis && bx * bx + by * by + bz * bz <
-                                                      theta * theta * (ex * ex + ey * ey + ez * ez);
-                                    if (!acc8) lmask |= 1u << d;
-                                }
-                            }
-                            const uint64_t mk = __builtin_amdgcn_ballot_w64(acc8);
-                            const int cnt = __popcll(mk);
-                            if (cnt == 0) continue;
-                            if (n_il + cnt > kIL) flush_il();
-                            if (acc8) {
-                                const int rk = (int)__builtin_amdgcn_mbcnt_hi(
-                                    (uint32_t)(mk >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mk, 0u));
-                                il[n_il + rk] = q8;
-                            }
-                            n_il += cnt;
-                        }
-                        uint64_t mk = __builtin_amdgcn_ballot_w64(lmask != 0);
-                        while (mk) {
-                            const int src = __builtin_ctzll(mk);
-                            mk &= mk - 1;
-                            const uint32_t kk = (uint32_t)__shfl((int)key0, src);
-                            const uint32_t lm = (uint32_t)__shfl((int)lmask, src);
-                            const int s0 = cell_start[kk], cnt = cell_count[kk];
-                            for (int b = 0; b < cnt; b += kWave) {
-                                const int j = s0 + b + lane;
-                                const bool in = b + lane < cnt && ((lm >> octant[j]) & 1u);
-                                const uint64_t mj = __builtin_amdgcn_ballot_w64(in);
-                                const int take = __popcll(mj);
-                                if (take == 0) continue;
-                                if (n_st + take > kStage) flush_st();
-                                if (in) {
-                                    const int rk = (int)__builtin_amdgcn_mbcnt_hi(
-                                        (uint32_t)(mj >> 32),
-                                        __builtin_amdgcn_mbcnt_lo((uint32_t)mj, 0u));
-                                    const double4 p = posh64[j];
-                                    const double mass = (active && !active[j]) ? 0.0 : m[j];
-                                    stg[n_st + rk] = make_float4((float)(p.x - g.ox),
-                                                                 (float)(p.y - g.oy),
-                                                                 (float)(p.z - g.oz), (float)mass);
-                                    stg_j[n_st + rk] = j;
-                                }
-                                n_st += take;
-                            }
-                        }
                     }
                 }
                 // drop the out-of-range children appended above

@@ -43,7 +43,8 @@ __global__ void k_reorder_predict(int64_t n, const int32_t *__restrict__ perm, S
 
 // ------------------------------------------------------------------ state
 // Record of the fused gradient + force pass (5 slots): (p, 1/H) (v, m)
-// (Kn A xx yy zz xy) (Kn A xz yz, rho, c) (Kn/(Omega rho), Kn, h, -) with
+// (m Kn A xx yy zz xy) (m Kn A xz yz, rho/2, c/2)
+// (-m Kn/(2 Omega rho), m Kn/2, h/2, 1/m) with
 // A = (-P I + S_pred)/(Omega rho^2), Kn = -210/(pi H^5).
 template <bool F32>
 __global__ void k_state(int64_t n, const double4 *__restrict__ posh64,
