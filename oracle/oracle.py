@@ -60,7 +60,8 @@ class Params(C.Structure):
                 ("eta_C", C.c_double), ("rot_sign", C.c_double),
                 ("g", C.c_double * 3), ("box", C.c_double * 3),
                 ("use_correction", C.c_int32), ("omega_one", C.c_int32),
-                ("adapt_ngb", C.c_double), ("adapt_skin", C.c_double)]
+                ("adapt_ngb", C.c_double), ("adapt_skin", C.c_double),
+                ("eta_a", C.c_double), ("rungs", C.c_int32), ("rungs_pad", C.c_int32)]
 
 
 class _State(C.Structure):
@@ -70,7 +71,10 @@ class _State(C.Structure):
         ("mat", C.POINTER(C.c_int32)), ("fixed", C.POINTER(C.c_uint8))] + [
         (k, C.POINTER(C.c_double)) for k in (
             "rho", "omega", "P", "cs", "T", "Y", "Gam", "G", "dt_i")] + [
-        ("dt", C.c_double), ("n_singular", C.c_int64), ("pairs", C.c_int64)]
+        ("dt", C.c_double), ("n_singular", C.c_int64), ("pairs", C.c_int64),
+        ("dtp", C.POINTER(C.c_int64)), ("el", C.POINTER(C.c_int64)),
+        ("ticks", C.c_int64), ("tick", C.c_double), ("n_clamped", C.c_int64),
+        ("time", C.c_double)]
 
 
 def lib():
@@ -100,6 +104,9 @@ def _declare(L):
     L.or_J2.argtypes = [_D]
     L.or_yield.restype = C.c_double
     L.or_yield.argtypes = [C.POINTER(Material), C.c_double, C.c_double, C.c_double]
+    L.or_rung_step.restype = C.c_int64
+    L.or_rung_step.argtypes = [C.c_int32, C.c_double, C.c_double, C.c_int64, C.c_int64,
+                               C.POINTER(C.c_int64)]
     L.or_shear_modulus.restype = C.c_double
     L.or_shear_modulus.argtypes = [C.POINTER(Material), C.c_double, C.c_double]
 
@@ -173,6 +180,8 @@ def params(d: dict) -> Params:
     p.omega_one = int(d.get("omega_one", 0))
     p.adapt_ngb = float(d.get("adapt_ngb", 0.0))
     p.adapt_skin = float(d.get("adapt_skin", 1.25))
+    p.eta_a = float(d.get("eta_a", 0.0))
+    p.rungs = int(d.get("rungs", 0))
     return p
 
 
@@ -220,6 +229,14 @@ def yield_strength(mat: dict, P, T, rho=None):
     m = material(mat)
     lib().or_yield_arr(C.byref(m), C.c_int64(P.size), _p(R), _p(P), _p(T), _p(Y))
     return Y
+
+
+def rung_step(rungs: int, tick: float, d: float, t: int, cur: int):
+    """Individual step of a particle in ticks (reading T1): returns
+    (step, clamped)."""
+    k = C.c_int64(0)
+    v = lib().or_rung_step(rungs, tick, d, t, cur, C.byref(k))
+    return int(v), int(k.value)
 
 
 def shear_modulus(mat: dict, rho: float, c: float) -> float:
@@ -400,7 +417,10 @@ def derivs(st: dict, mats: list, prm: dict, targets=None):
 
 class Integrator:
     """Multi-step FP64 integration of a particle set (kick-drift-kick with the
-    predictor of the paper's sec. 2.4), for tests that follow a state in time."""
+    predictor of the paper's sec. 2.4), for tests that follow a state in time.
+    With ``prm["rungs"] > 0`` each ``step`` is one substep of the individual
+    steps to the next end of a particle's step, and ``dt_fixed`` is the base
+    step."""
 
     _FIELDS = ("rho", "omega", "P", "cs", "T", "Y", "Gam", "dt_i")
 
@@ -431,6 +451,10 @@ class Integrator:
             setattr(s, k, _p(self.arr[k]))
         s.mat = _p(self.mat, _I32)
         s.fixed = _p(self.fixed, _U8)
+        self.arr["dtp"] = np.zeros(n, dtype=np.int64)   # ticks (individual steps)
+        self.arr["el"] = np.zeros(n, dtype=np.int64)
+        s.dtp = _p(self.arr["dtp"], _I64)
+        s.el = _p(self.arr["el"], _I64)
         self._s = s
         lib().or_init(C.byref(s), self._mats, C.byref(self._prm), C.c_double(self.dt_fixed))
 
@@ -441,6 +465,22 @@ class Integrator:
     @property
     def pairs(self):
         return self._s.pairs
+
+    @property
+    def time(self):
+        return self._s.time
+
+    @property
+    def ticks(self):
+        return self._s.ticks
+
+    @property
+    def tick(self):
+        return self._s.tick
+
+    @property
+    def n_clamped(self):
+        return self._s.n_clamped
 
     def step(self, k: int = 1):
         for _ in range(k):

@@ -57,10 +57,26 @@
  *   H1  adaptive smoothing length: the constant kernel mass of the
  *       kernel-mass equation (sec. 2.1) is written N_ngb m_i with N_ngb a
  *       run parameter; Newton-Raphson steps limited to a factor 2.
- *   K9  time integration: single global step, kick-drift-kick with the
- *       predictor of Predict_S eq. applied to v, u and S; the closing kick
- *       is followed by the plastic rescaling, the opening kick is not
- *       [sec. 2.4].
+ *   K9  time integration: kick-drift-kick with the predictor of Predict_S
+ *       eq. applied to v, u and S; the closing kick is followed by the
+ *       plastic rescaling, the opening kick is not [sec. 2.4].  A particle's
+ *       step is the smaller of the CFL step (courant_condition eq.) and,
+ *       with eta_a > 0, the acceleration criterion eta_a sqrt(h_i/|a_i|)
+ *       (reading T2: the length in that criterion is h_i).  Without rungs
+ *       the particles share one step, the minimum over them.
+ *   T1  hierarchical individual steps [sec. 2.4 defers the scheme to Paper
+ *       I]: particle steps are dt0 2^-r, r = 0 .. rungs-1, dt0 the base
+ *       step; a particle takes the longest of these not above its own step,
+ *       and may lengthen it only at a time that is a multiple of the new
+ *       step.  The simulation advances to the next end of any particle's
+ *       step; every particle drifts, and is predicted to that time from the
+ *       start of its own step with its last derivatives (v, u and S as in
+ *       the predictor above, with the time elapsed in its step in place of
+ *       half a step).  Density, EOS, yield and the rescaled predicted stress
+ *       are evaluated for all particles (they are the neighbour values);
+ *       gradients, stress rates and forces, the closing kick and the new
+ *       step for the particles whose step ends there, followed by their
+ *       opening kick.
  */
 #include <math.h>
 #include <stdint.h>
@@ -103,6 +119,9 @@ typedef struct {
     int32_t omega_one;      /* 1: Omega = 1; 0: Omega as defined               */
     double adapt_ngb;       /* > 0: adapt h to this kernel mass / m each step   */
     double adapt_skin;      /* cap of one adaptation: h <= adapt_skin * h_old   */
+    double eta_a;           /* > 0: acceleration criterion eta_a sqrt(h/|a|)    */
+    int32_t rungs;          /* > 0: individual steps dt0 2^-r, r < rungs (T1)  */
+    int32_t rungs_pad;
 } or_params;
 
 /* ----------------------------------------------------------------------- */
@@ -849,25 +868,38 @@ typedef struct {
     const uint8_t *fixed;
     /* outputs of the last evaluation */
     double *rho, *omega, *P, *cs, *T, *Y, *Gam, *G, *dt_i;
-    double dt;                  /* current global step                       */
+    double dt;                  /* current global step (the next substep with
+                                   rungs)                                    */
     int64_t n_singular, pairs;
+    /* individual steps (reading T1), in ticks of the shortest rung
+     * (tick = dt0 2^-(rungs-1)): each particle's step and the time elapsed
+     * in it, the simulation time; the number of particles whose step was
+     * cut to the shortest rung; the simulation time in seconds */
+    int64_t *dtp, *el;
+    int64_t ticks;
+    double tick;
+    int64_t n_clamped;
+    double time;
 } or_state_t;
 
 /* One derivative evaluation at the current positions with the predicted
  * velocity vp, energy up and stress Sp (Sp is rescaled in place). */
 static void eval_derivs(or_state_t *s, const or_material *mats, const or_params *p,
                         const double *vpx, const double *vpy, const double *vpz,
-                        const double *up, double *Sp, int64_t *tar, double *e2rate)
+                        const double *up, double *Sp, int64_t *tar, int64_t nt,
+                        int64_t *act, int64_t na, double *e2rate)
 {
+    /* density, state and rescaled predicted stress for the targets tar,
+     * gradients, stress rates and forces for the targets act */
     int64_t n = s->n;
-    or_density(n, s->x, s->y, s->z, s->m, s->h, p, n, tar, s->rho, s->omega);
-    or_state(n, tar, s->rho, up, s->mat, mats, s->P, s->cs, s->T, s->Y, s->Gam);
-    or_plastic_return_all(n, n, tar, Sp, s->Y);
+    or_density(n, s->x, s->y, s->z, s->m, s->h, p, nt, tar, s->rho, s->omega);
+    or_state(nt, tar, s->rho, up, s->mat, mats, s->P, s->cs, s->T, s->Y, s->Gam);
+    or_plastic_return_all(n, nt, tar, Sp, s->Y);
     or_gradients(n, s->x, s->y, s->z, vpx, vpy, vpz, s->m, s->h, s->rho, s->omega, p,
-                 n, tar, s->G, NULL, NULL, &s->n_singular);
-    or_stress_rate(n, n, tar, s->G, Sp, s->Gam, p->rot_sign, s->dS, e2rate);
+                 na, act, s->G, NULL, NULL, &s->n_singular);
+    or_stress_rate(n, na, act, s->G, Sp, s->Gam, p->rot_sign, s->dS, e2rate);
     or_forces(n, s->x, s->y, s->z, vpx, vpy, vpz, s->m, s->h, s->rho, s->omega,
-              s->P, s->cs, Sp, p, n, tar, s->ax, s->ay, s->az, s->dudt, s->dt_i);
+              s->P, s->cs, Sp, p, na, act, s->ax, s->ay, s->az, s->dudt, s->dt_i);
     int64_t *cnt = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
     or_pair_counts(n, s->x, s->y, s->z, s->h, p, n, tar, cnt);
     int64_t tot = 0;
@@ -876,12 +908,43 @@ static void eval_derivs(or_state_t *s, const or_material *mats, const or_params 
     s->pairs = tot;
 }
 
-static double min_dt(const or_state_t *s)
+/* Own step of particle i: the CFL step and, with eta_a > 0, the
+ * acceleration criterion (reading T2). */
+static double own_step(const or_state_t *s, const or_params *p, int64_t i)
+{
+    double d = s->dt_i[i];
+    if (p->eta_a > 0.0) {
+        double a = sqrt((s->ax[i] * s->ax[i] + s->ay[i] * s->ay[i]) + s->az[i] * s->az[i]);
+        if (a > 0.0) {
+            double da = p->eta_a * sqrt(s->h[i] / a);
+            if (da < d) d = da;
+        }
+    }
+    return d;
+}
+
+static double min_dt(const or_state_t *s, const or_params *p)
 {
     double d = INFINITY;
-    for (int64_t i = 0; i < s->n; ++i)
-        if (!s->fixed[i] && s->dt_i[i] < d) d = s->dt_i[i];
+    for (int64_t i = 0; i < s->n; ++i) {
+        if (s->fixed[i]) continue;
+        double di = own_step(s, p, i);
+        if (di < d) d = di;
+    }
     return d;
+}
+
+/* Rung step in ticks (reading T1): the longest 2^(rungs-1-r) ticks whose
+ * duration is not above d, the shortest rung if none is (counted); longer
+ * than the current step cur only where the time t is a multiple of it. */
+static int64_t rung_step(int rungs, double tick, double d, int64_t t, int64_t cur,
+                         int64_t *clamped)
+{
+    int64_t st = (int64_t)1 << (rungs - 1);
+    while (st > 1 && (double)st * tick > d) st >>= 1;
+    if ((double)st * tick > d) ++*clamped;
+    while (st > cur && t % st != 0) st >>= 1;
+    return st;
 }
 
 /* Initial evaluation at t = 0 (predicted values = current values), choice
@@ -911,11 +974,29 @@ void or_init(or_state_t *s, const or_material *mats, const or_params *p, double 
     double *e2 = (double *)malloc(sizeof(double) * (size_t)n);
     memcpy(Sp, s->S, sizeof(double) * 5 * (size_t)n);
     adapt_lengths(s, p);
-    eval_derivs(s, mats, p, s->vx, s->vy, s->vz, s->u, Sp, tar, e2);
-    s->dt = dt_fixed > 0.0 ? dt_fixed : min_dt(s);
-    double hd = 0.5 * s->dt;
+    eval_derivs(s, mats, p, s->vx, s->vy, s->vz, s->u, Sp, tar, n, tar, n, e2);
+    s->time = 0.0;
+    s->ticks = 0;
+    s->n_clamped = 0;
+    if (p->rungs > 0) {
+        /* individual steps: dt_fixed is the base step dt0 */
+        const int64_t top = (int64_t)1 << (p->rungs - 1);
+        s->tick = ldexp(dt_fixed, -(p->rungs - 1));
+        int64_t next = top;
+        for (int64_t i = 0; i < n; ++i) {
+            s->el[i] = 0;
+            s->dtp[i] = top;
+            if (s->fixed[i]) continue;
+            s->dtp[i] = rung_step(p->rungs, s->tick, own_step(s, p, i), 0, top, &s->n_clamped);
+            if (s->dtp[i] < next) next = s->dtp[i];
+        }
+        s->dt = (double)next * s->tick;
+    } else {
+        s->dt = dt_fixed > 0.0 ? dt_fixed : min_dt(s, p);
+    }
     for (int64_t i = 0; i < n; ++i) {
         if (s->fixed[i]) continue;
+        double hd = 0.5 * (p->rungs > 0 ? (double)s->dtp[i] * s->tick : s->dt);
         s->vx[i] += hd * s->ax[i];
         s->vy[i] += hd * s->ay[i];
         s->vz[i] += hd * s->az[i];
@@ -926,13 +1007,18 @@ void or_init(or_state_t *s, const or_material *mats, const or_params *p, double 
 }
 
 /* One step of the kick-drift-kick scheme with the predictor of
- * Predict_S eq. (reading K9).  On entry v, u, S hold the half-step values
- * and a, dudt, dS the derivatives of the previous evaluation. */
+ * Predict_S eq. (reading K9), or, with rungs, one substep of the individual
+ * steps (reading T1) to the next end of a particle's step.  On entry v, u,
+ * S hold the values kicked at the start of each particle's step and a,
+ * dudt, dS the derivatives of its last evaluation. */
 void or_step(or_state_t *s, const or_material *mats, const or_params *p, double dt_fixed)
 {
     int64_t n = s->n;
-    double dt = s->dt, hd = 0.5 * dt;
+    const int hier = p->rungs > 0;
+    double dt = s->dt;
+    int64_t sub = hier ? (int64_t)llround(dt / s->tick) : 0;   /* substep in ticks */
     int64_t *tar = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
+    int64_t *act = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
     for (int64_t i = 0; i < n; ++i) tar[i] = i;
     double *vpx = (double *)malloc(sizeof(double) * (size_t)n);
     double *vpy = (double *)malloc(sizeof(double) * (size_t)n);
@@ -947,24 +1033,45 @@ void or_step(or_state_t *s, const or_material *mats, const or_params *p, double 
         s->y[i] += dt * s->vy[i];
         s->z[i] += dt * s->vz[i];
     }
-    /* predictor: half step with the previous derivatives */
+    if (hier) {
+        s->ticks += sub;
+        s->time = (double)s->ticks * s->tick;
+    } else {
+        s->time += dt;
+    }
+    /* predictor: from the kicked values with the last derivatives, over the
+     * time elapsed in each particle's step less half of it (half a step
+     * for a particle whose step ends now) */
+    int64_t na = 0;
     for (int64_t i = 0; i < n; ++i) {
         if (s->fixed[i]) {
             vpx[i] = s->vx[i]; vpy[i] = s->vy[i]; vpz[i] = s->vz[i]; up[i] = s->u[i];
             for (int c = 0; c < 5; ++c) Sp[c * n + i] = s->S[c * n + i];
+            if (!hier) act[na++] = i;   /* shared step: derivatives of every particle */
             continue;
         }
-        vpx[i] = s->vx[i] + hd * s->ax[i];
-        vpy[i] = s->vy[i] + hd * s->ay[i];
-        vpz[i] = s->vz[i] + hd * s->az[i];
-        up[i] = s->u[i] + hd * s->dudt[i];
-        for (int c = 0; c < 5; ++c) Sp[c * n + i] = s->S[c * n + i] + hd * s->dS[c * n + i];
+        double tau = 0.5 * dt;
+        if (hier) {
+            s->el[i] += sub;
+            tau = ((double)s->el[i] - 0.5 * (double)s->dtp[i]) * s->tick;
+            if (s->el[i] == s->dtp[i]) act[na++] = i;
+        } else {
+            act[na++] = i;
+        }
+        vpx[i] = s->vx[i] + tau * s->ax[i];
+        vpy[i] = s->vy[i] + tau * s->ay[i];
+        vpz[i] = s->vz[i] + tau * s->az[i];
+        up[i] = s->u[i] + tau * s->dudt[i];
+        for (int c = 0; c < 5; ++c) Sp[c * n + i] = s->S[c * n + i] + tau * s->dS[c * n + i];
     }
     adapt_lengths(s, p);
-    eval_derivs(s, mats, p, vpx, vpy, vpz, up, Sp, tar, e2);
-    /* closing kick to the full step, rescaling of S */
-    for (int64_t i = 0; i < n; ++i) {
+    eval_derivs(s, mats, p, vpx, vpy, vpz, up, Sp, tar, n, act, na, e2);
+    /* closing kick of the particles whose step ends, rescaling of S */
+    for (int64_t k = 0; k < na; ++k) {
+        int64_t i = act[k];
         if (s->fixed[i]) continue;
+        double own = hier ? (double)s->dtp[i] * s->tick : dt;
+        double hd = 0.5 * own;
         s->vx[i] += hd * s->ax[i];
         s->vy[i] += hd * s->ay[i];
         s->vz[i] += hd * s->az[i];
@@ -973,21 +1080,50 @@ void or_step(or_state_t *s, const or_material *mats, const or_params *p, double 
         for (int c = 0; c < 5; ++c) s5[c] = s->S[c * n + i] + hd * s->dS[c * n + i];
         or_plastic_return(s5, s->Y[i]);
         for (int c = 0; c < 5; ++c) s->S[c * n + i] = s5[c];
-        s->eps2[i] += dt * e2[i];
+        s->eps2[i] += own * e2[i];
     }
-    /* next step, opening kick (no rescaling) */
-    double dtn = dt_fixed > 0.0 ? dt_fixed : min_dt(s);
-    double hn = 0.5 * dtn;
-    for (int64_t i = 0; i < n; ++i) {
+    /* their next steps, opening kick (no rescaling) */
+    double dtn = 0.0;
+    if (hier) {
+        for (int64_t k = 0; k < na; ++k) {
+            int64_t i = act[k];
+            s->dtp[i] = rung_step(p->rungs, s->tick, own_step(s, p, i), s->ticks, s->dtp[i],
+                                  &s->n_clamped);
+            s->el[i] = 0;
+        }
+    } else {
+        dtn = dt_fixed > 0.0 ? dt_fixed : min_dt(s, p);
+    }
+    for (int64_t k = 0; k < na; ++k) {
+        int64_t i = act[k];
         if (s->fixed[i]) continue;
+        double hn = 0.5 * (hier ? (double)s->dtp[i] * s->tick : dtn);
         s->vx[i] += hn * s->ax[i];
         s->vy[i] += hn * s->ay[i];
         s->vz[i] += hn * s->az[i];
         s->u[i] += hn * s->dudt[i];
         for (int c = 0; c < 5; ++c) s->S[c * n + i] += hn * s->dS[c * n + i];
     }
-    s->dt = dtn;
-    free(vpx); free(vpy); free(vpz); free(up); free(Sp); free(e2); free(tar);
+    /* the next substep: to the next end of any particle's step */
+    if (hier) {
+        int64_t next = (int64_t)1 << (p->rungs - 1);
+        for (int64_t i = 0; i < n; ++i) {
+            if (s->fixed[i]) continue;
+            int64_t rem = s->dtp[i] - s->el[i];
+            if (rem < next) next = rem;
+        }
+        s->dt = (double)next * s->tick;
+    } else {
+        s->dt = dtn;
+    }
+    free(vpx); free(vpy); free(vpz); free(up); free(Sp); free(e2); free(tar); free(act);
+}
+
+/* The rung rule on its own, for the tests. */
+int64_t or_rung_step(int32_t rungs, double tick, double d, int64_t t, int64_t cur,
+                     int64_t *clamped)
+{
+    return rung_step(rungs, tick, d, t, cur, clamped);
 }
 
 /* ----------------------------------------------------------------------- */
