@@ -116,6 +116,13 @@ typedef struct {
     double adapt_ngb;   /* > 0: sph_init / sph_step adapt h to constant kernel
                            mass (sph_adapt_h) before each evaluation          */
     double adapt_skin;  /* cap of one adaptation: h <= adapt_skin h_old (>= 1) */
+    double eta_a;       /* > 0: a particle's step is also capped by the
+                           acceleration criterion eta_a sqrt(h_i / |a_i|)
+                           (time-integration section)                        */
+    int32_t rungs;      /* > 0: hierarchical individual steps dt0 2^-r,
+                           r = 0 .. rungs-1 (<= 40), dt0 = sph_state.dt_max;
+                           0: one step per run                              */
+    int32_t rungs_pad;
 } sph_params;
 
 /* ---------------------------------------------------------------- context */
@@ -351,13 +358,17 @@ enum {
     SPH_AX = 12, SPH_AY, SPH_AZ, SPH_DUDT,
     SPH_SDOT = 16,                  /* 5 rows */
     SPH_M = 21, SPH_H, SPH_EPS2,
-    SPH_NF64 = 24
+    SPH_DTP = 24,                   /* individual steps: the particle's step and   */
+    SPH_EL = 25,                    /* the time elapsed in it, in ticks (exact)    */
+    SPH_NF64 = 26
 };
 /* Rows of the persistent int32 state buffer: material id, particle id (any
  * caller label, carried through the sorts), fixed flag (0/1), run id. */
 enum { SPH_MAT = 0, SPH_ID, SPH_FIXED, SPH_RUN, SPH_NI32 = 4 };
 
-/* Rows of the work buffer (each n_cap doubles) written by sph_step. */
+/* Rows of the work buffer (each n_cap doubles) written by sph_step.  With
+ * individual steps, rows that hold derivatives or their sums (G, DT) are
+ * valid only where SPH_W_ACT is 1 (the particles whose step ended). */
 enum {
     SPH_W_RHO = 0, SPH_W_OMEGA, SPH_W_P, SPH_W_CS, SPH_W_T, SPH_W_Y, SPH_W_GMOD,
     SPH_W_VP = 7,                   /* 3 rows */
@@ -366,7 +377,10 @@ enum {
     SPH_W_G = 16,                   /* 9 rows */
     SPH_W_DT = 25,
     SPH_W_PERM = 26,                /* int32 view of one row */
-    SPH_NW = 27
+    SPH_W_TAU = 27,                 /* predictor interval of the step, then (with
+                                       rungs) the time to the end of the step      */
+    SPH_W_ACT = 28,                 /* int32 view: 1 where the step ends now        */
+    SPH_NW = 29
 };
 
 typedef struct {
@@ -386,20 +400,35 @@ typedef struct {
                                     buffers: no pair crosses a run, and each run
                                     takes its own CFL step (batched scans)          */
     double cell_min;
-    double dt_max;               /* > 0: upper bound of the step                    */
+    double dt_max;               /* > 0: upper bound of the step; with individual
+                                    steps (sph_params.rungs > 0) the base step dt0  */
+    double *clock;               /* device, one double per run (individual steps
+                                    only, else may be NULL): the run's time in ticks
+                                    of the shortest rung, dt0 2^-(rungs-1)           */
 } sph_state;
 
 /* Start a run: neighbour search and reorder (buffers flip), derivatives at
  * the current state (predicted values = current values, S rescaled),
  * dt[r] = min of dt_cfl over the particles of run r (capped by dt_max) and
- * the first opening kick. */
+ * the first opening kick.  With individual steps (prm->rungs > 0, dt_max =
+ * the base step dt0, clock set): each particle takes the longest step
+ * dt0 2^-r not above its own (CFL, and acceleration criterion when
+ * eta_a > 0), its opening kick uses it, clock[r] = 0 and dt[r] is the
+ * shortest step of run r. */
 sph_status sph_init(sph_ctx *ctx, sph_state *st, const sph_material *mats, int32_t n_materials,
                     const sph_params *prm, sph_precision prec, sph_stream stream);
 
 /* One step: drift, neighbour search and reorder (buffers flip), predictor,
  * density + EOS + yield, stress predict and rescale, gradients, stress rate,
  * forces, closing kick with rescale, next step of each run from its CFL
- * minimum, opening kick.  All on `stream`, no host synchronisation, no
+ * minimum, opening kick.  With individual steps it is one substep of each
+ * run, to the nearest end of a particle's step: every particle drifts and
+ * is predicted from the start of its own step (time elapsed less half its
+ * step); density, EOS, yield and the rescaled predicted stress for all;
+ * gradients, stress rate, forces, closing kick, new step (lengthened only
+ * at a multiple of the new step; below the shortest rung is reported by
+ * sph_sync_status) and opening kick for the particles whose step ends
+ * (SPH_W_ACT); clock[r] advances by the substep in ticks.  All on `stream`, no host synchronisation, no
  * allocation and no memset: a fixed sequence of kernel launches whose device
  * pointers repeat every two steps, so an even number of steps can be
  * captured in a hipGraph and replayed.  Particle masses must be positive

@@ -223,6 +223,11 @@ sph_status sph_sync_status(sph_ctx *h, sph_stream stream) {
                        "too many pyramid nodes)");
         return SPH_ECAPACITY;
     }
+    if (fl[FLAG_RUNG_CLAMP]) {
+        set_error(ctx, "a particle's step is below the shortest rung (raise rungs or lower "
+                       "the base step)");
+        return SPH_ECAPACITY;
+    }
     if (fl[FLAG_NONFINITE]) {
         set_error(ctx, "non-finite value");
         return SPH_ENONFINITE;
@@ -546,8 +551,12 @@ static sph_status check_state(sph_ctx *h, const sph_state *st) {
 // Neighbour search (with the drift fused in when `drift`), then the
 // reorder of every state row into the other buffer with the predictor of v
 // and u fused in (predict = 0 at the start of a run: predicted = current).
-static sph_status search_and_sort(sph_ctx *h, sph_state *st, sph_precision prec, bool drift,
-                                  int32_t predict, hipStream_t s,
+static double tick_of(const sph_state *st, const sph_params *prm) {
+    return prm->rungs > 0 ? ldexp(st->dt_max, -(prm->rungs - 1)) : 0.0;
+}
+
+static sph_status search_and_sort(sph_ctx *h, sph_state *st, const sph_params *prm,
+                                  sph_precision prec, bool drift, int32_t predict, hipStream_t s,
                                   const double *h_build = nullptr) {
     Ctx *ctx = &h->c;
     const int64_t n = st->n;
@@ -581,8 +590,9 @@ static sph_status search_and_sort(sph_ctx *h, sph_state *st, sph_precision prec,
         r.i_dst[k] = B.i[k];
     }
     if ((e = launch_step_reorder(ctx, n, perm, r, st->dt, nr > 1 ? ctx->runid : nullptr, predict,
-                                 B.w[SPH_W_VP],
-                                 B.w[SPH_W_VP + 1], B.w[SPH_W_VP + 2], B.w[SPH_W_UP], s)))
+                                 prm->rungs > 0 ? 1 : 0, tick_of(st, prm), B.w[SPH_W_VP],
+                                 B.w[SPH_W_VP + 1], B.w[SPH_W_VP + 2], B.w[SPH_W_UP],
+                                 B.w[SPH_W_TAU], (int32_t *)B.w[SPH_W_ACT], s)))
         return e;
     st->cur = alt;
     return SPH_OK;
@@ -599,19 +609,22 @@ constexpr int32_t kAdaptIter = 30;
 
 static sph_status step_search(sph_ctx *h, sph_state *st, const sph_params *prm,
                               sph_precision prec, bool drift, int32_t predict, hipStream_t s) {
-    if (!(prm->adapt_ngb > 0.0)) return search_and_sort(h, st, prec, drift, predict, s);
+    if (!(prm->adapt_ngb > 0.0)) return search_and_sort(h, st, prm, prec, drift, predict, s);
     Ctx *ctx = &h->c;
     const int64_t n = st->n;
     Rows A = rows_of(st, st->cur);
     double *hs = A.w[SPH_W_T];  // free until the state kernel of this step
     sph_status e;
     if ((e = launch_scale(ctx, n, A.f[SPH_H], prm->adapt_skin, hs, s))) return e;
-    if ((e = search_and_sort(h, st, prec, drift, predict, s, hs))) return e;
+    if ((e = search_and_sort(h, st, prm, prec, drift, predict, s, hs))) return e;
     Rows R = rows_of(st, st->cur);
     if ((e = launch_adapt_h(ctx, n, R.f[SPH_M], R.f[SPH_H], R.i[SPH_FIXED], prm->adapt_ngb,
                             kAdaptTol, kAdaptIter, R.f[SPH_H], nullptr, nullptr, s)))
         return e;
-    return search_and_sort(h, st, prec, false, predict, s);
+    // the second search repeats the first one's predictor; with individual
+    // steps (predict = 2) without advancing the elapsed times again
+    return search_and_sort(h, st, prm, prec, false, (predict && prm->rungs > 0) ? 2 : predict,
+                           s);
 }
 
 // Derivatives at the sorted state: density pass, per-particle state (EOS,
@@ -626,28 +639,67 @@ static sph_status eval(sph_ctx *h, const sph_state *st, const Rows &R, int32_t n
     sph_status e;
     const int32_t *fixed = R.i[SPH_FIXED];
     const int32_t nr = n_runs_of(st);
-    const int16_t *runid = nr > 1 ? ctx->runid : nullptr;
+    const bool hier = prm->rungs > 0;
+    // with individual steps only the particles whose step ends are evaluated
+    // past the per-particle state (every particle at the start of a run)
+    const int32_t *act = (hier && predict) ? (const int32_t *)R.w[SPH_W_ACT] : nullptr;
     if ((e = launch_density_pairs(ctx, n, prm, prec, R.w[SPH_W_RHO], R.w[SPH_W_OMEGA], s)))
         return e;
     if ((e = launch_step_state(ctx, n, prec, R.w[SPH_W_RHO], R.w[SPH_W_OMEGA], R.w[SPH_W_UP],
                                R.w[SPH_W_VP], R.w[SPH_W_VP + 1], R.w[SPH_W_VP + 2], R.f[SPH_M],
-                               R.i[SPH_MAT], nmat, fixed, st->dt, runid, predict, R.f[SPH_S],
+                               R.i[SPH_MAT], nmat, fixed, R.w[SPH_W_TAU], R.f[SPH_S],
                                R.f[SPH_SDOT], R.w[SPH_W_P], R.w[SPH_W_CS], R.w[SPH_W_T],
                                R.w[SPH_W_Y], R.w[SPH_W_GMOD], R.w[SPH_W_SP], s)))
         return e;
     if ((e = launch_grad_force_pairs(ctx, n, prm, prec, R.f[SPH_AX], R.f[SPH_AY], R.f[SPH_AZ],
-                                     R.f[SPH_DUDT], R.w[SPH_W_DT], s)))
+                                     R.f[SPH_DUDT], R.w[SPH_W_DT], s, act)))
         return e;
     if (prm->grav_G > 0.0 &&
         (e = launch_gravity(ctx, n, R.f[SPH_M], nullptr, prm->grav_G, prm->grav_eps_over_h,
                             prm->grav_theta, 1, R.f[SPH_AX], R.f[SPH_AY], R.f[SPH_AZ], nullptr,
-                            s)))
+                            s, act)))
         return e;
-    if ((e = launch_step_grad_rate(ctx, n, prm, R.w[SPH_W_SP], R.w[SPH_W_GMOD], fixed, st->dt,
-                                   runid, R.w[SPH_W_G], R.f[SPH_SDOT],
+    if ((e = launch_step_grad_rate(ctx, n, prm, R.w[SPH_W_SP], R.w[SPH_W_GMOD], fixed,
+                                   R.w[SPH_W_TAU], act, R.w[SPH_W_G], R.f[SPH_SDOT],
                                    accumulate_eps2 ? R.f[SPH_EPS2] : nullptr, st->n_singular, s)))
         return e;
+    if (prm->eta_a > 0.0 &&
+        (e = launch_accel_limit(ctx, n, prm->eta_a, R.f[SPH_AX], R.f[SPH_AY], R.f[SPH_AZ],
+                                R.f[SPH_H], act, R.w[SPH_W_DT], s)))
+        return e;
+    if (hier) return SPH_OK;  // the kick takes the new steps
     return launch_dt_reduce(ctx, n, R.w[SPH_W_DT], fixed, step_bits(ctx, 0), s, nr, ctx->run_p);
+}
+
+// Individual steps: kicks and new steps of the particles whose step ended,
+// then each run's next substep (the nearest end of a step) and its clock.
+static sph_status kick_hier(sph_ctx *h, sph_state *st, const Rows &R, const sph_params *prm,
+                            int32_t init, hipStream_t s) {
+    Ctx *ctx = &h->c;
+    const int32_t nr = n_runs_of(st);
+    const int16_t *runid = nr > 1 ? ctx->runid : nullptr;
+    const double tick = tick_of(st, prm);
+    sph_status e = launch_kick_hier(
+        ctx, st->n, init, prm->rungs, tick, st->dt, st->clock, runid, R.i[SPH_FIXED],
+        (const int32_t *)R.w[SPH_W_ACT], R.f[SPH_VX], R.f[SPH_VY], R.f[SPH_VZ], R.f[SPH_U],
+        R.f[SPH_AX], R.f[SPH_AY], R.f[SPH_AZ], R.f[SPH_DUDT], R.f[SPH_S], R.w[SPH_W_SP],
+        R.f[SPH_SDOT], R.w[SPH_W_Y], R.w[SPH_W_DT], R.f[SPH_DTP], R.f[SPH_EL], R.w[SPH_W_TAU], s);
+    if (e) return e;
+    if ((e = launch_dt_reduce(ctx, st->n, R.w[SPH_W_TAU], R.i[SPH_FIXED], step_bits(ctx, 0), s,
+                              nr, ctx->run_p)))
+        return e;
+    e = launch_hier_next(ctx, nr, init, tick, step_bits(ctx, 0), step_bits(ctx, 1), st->dt,
+                         st->dt_next, st->clock, s);
+    ctx->dt_parity ^= 1;
+    return e;
+}
+
+static sph_status check_rungs(sph_ctx *h, const sph_state *st, const sph_params *prm) {
+    if (prm->rungs == 0) return SPH_OK;
+    REQUIRE(prm->rungs > 0 && prm->rungs <= 40, SPH_EINVAL, "rungs must be in 0..40");
+    REQUIRE(st->dt_max > 0.0, SPH_EINVAL, "individual steps need the base step in dt_max");
+    REQUIRE(st->clock, SPH_EINVAL, "individual steps need the per-run clock");
+    return SPH_OK;
 }
 
 // The kick that follows an evaluation turns the minima into the next step
@@ -688,13 +740,14 @@ sph_status sph_init(sph_ctx *h, sph_state *st, const sph_material *mats, int32_t
     hipStream_t s = S(stream);
     REQUIRE(!(prm->adapt_ngb > 0.0) || prm->adapt_skin >= 1.0, SPH_EINVAL,
             "adapt_skin must be >= 1");
+    if ((e = check_rungs(h, st, prm))) return e;
     if ((e = step_search(h, st, prm, prec, false, 0, s))) return e;
     Rows R = rows_of(st, st->cur);
     // predicted values are the current ones: v, u as they are, S rescaled
     if ((e = eval(h, st, R, n_materials, prm, prec, 0, false, s))) return e;
     // the opening kick uses the new step only: it writes it to dt_next, and
     // the swap makes it the step of the first drift
-    if ((e = kick(h, st, R, 1, s))) return e;
+    if ((e = prm->rungs > 0 ? kick_hier(h, st, R, prm, 1, s) : kick(h, st, R, 1, s))) return e;
     swap_dt(st);
     return SPH_OK;
 }
@@ -710,10 +763,11 @@ sph_status sph_step(sph_ctx *h, sph_state *st, const sph_material *mats, int32_t
     hipStream_t s = S(stream);
     REQUIRE(!(prm->adapt_ngb > 0.0) || prm->adapt_skin >= 1.0, SPH_EINVAL,
             "adapt_skin must be >= 1");
+    if ((e = check_rungs(h, st, prm))) return e;
     if ((e = step_search(h, st, prm, prec, true, 1, s))) return e;
     Rows R = rows_of(st, st->cur);
     if ((e = eval(h, st, R, n_materials, prm, prec, 1, true, s))) return e;
-    if ((e = kick(h, st, R, 0, s))) return e;
+    if ((e = prm->rungs > 0 ? kick_hier(h, st, R, prm, 0, s) : kick(h, st, R, 0, s))) return e;
     swap_dt(st);
     return SPH_OK;
 }

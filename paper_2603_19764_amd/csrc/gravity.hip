@@ -190,7 +190,8 @@ __global__ __launch_bounds__(64) void k_grav_walk(
     const uint8_t *__restrict__ octant, const double *__restrict__ m,
     const int32_t *__restrict__ active, const float4 *__restrict__ mom0,
     const float4 *__restrict__ mom8, const float4 *__restrict__ momU, float Gc, float theta,
-    int32_t accumulate, double *ax, double *ay, double *az, double *phi, int32_t *flags) {
+    int32_t accumulate, double *ax, double *ay, double *az, double *phi, int32_t *flags,
+    const int32_t *__restrict__ tmask) {
     __shared__ uint32_t cand[2][kCand];
     __shared__ float4 il[kIL];
     __shared__ float4 stg[kStage];
@@ -503,7 +504,7 @@ __global__ __launch_bounds__(64) void k_grav_walk(
 #pragma unroll
             for (int s = 0; s < kSlots; ++s) {
                 const int i = A.ti[s];
-                if (i < 0) continue;
+                if (i < 0 || (tmask && !tmask[i])) continue;
                 const double fx = (double)Gc * A.ax[s], fy = (double)Gc * A.ay[s],
                              fz = (double)Gc * A.az[s];
                 if (accumulate) {
@@ -523,7 +524,8 @@ __global__ __launch_bounds__(64) void k_grav_walk(
 
 sph_status launch_gravity(Ctx *ctx, int64_t n, const double *m, const int32_t *active, double G,
                           double eps_over_h, double theta, int32_t accumulate, double *ax,
-                          double *ay, double *az, double *phi, hipStream_t s) {
+                          double *ay, double *az, double *phi, hipStream_t s,
+                          const int32_t *tmask) {
     if (n == 0) return SPH_OK;
     const int nr = ctx->n_runs_built;
     hipLaunchKernelGGL(k_grav_layout, dim3(1), dim3(64), 0, s, nr, ctx->grid, ctx->bbox_part,
@@ -542,7 +544,7 @@ sph_status launch_gravity(Ctx *ctx, int64_t n, const double *m, const int32_t *a
                        ctx->grav_totals, ctx->cell_start, ctx->cell_count, ctx->posh64,
                        ctx->octant, m, active, ctx->grav_mom0, ctx->grav_mom8, ctx->grav_momU,
                        (float)G, (float)theta, accumulate, ax, ay,
-                       az, phi, ctx->flags);
+                       az, phi, ctx->flags, tmask);
     SPH_HIP(hipGetLastError());
     return SPH_OK;
 }

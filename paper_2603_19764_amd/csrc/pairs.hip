@@ -426,7 +426,7 @@ __global__ __launch_bounds__(kBlock) void k_grad_forces(
     const typename Real<F32>::T4 *__restrict__ rec, double al, double be, double eps,
     double etaC, double gx, double gy, double gz, double *__restrict__ gsum,
     double *__restrict__ ax, double *__restrict__ ay, double *__restrict__ az,
-    double *__restrict__ dudt, double *__restrict__ dtc) {
+    double *__restrict__ dudt, double *__restrict__ dtc, const int32_t *__restrict__ act) {
     using R = typename Real<F32>::T;
     using R4 = typename Real<F32>::T4;
     __shared__ float shs[81];
@@ -436,7 +436,7 @@ __global__ __launch_bounds__(kBlock) void k_grad_forces(
     }
     const int64_t i = (int64_t)xcd_block(blockIdx.x, gridDim.x) * (kBlock / L) + threadIdx.x / L;
     const int lg = threadIdx.x % L;
-    const bool active = i < n;
+    const bool active = i < n && (!act || act[i]);
     R c_xx = 0, c_yy = 0, c_zz = 0, c_xy = 0, c_xz = 0, c_yz = 0;
     R f[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     R acx = 0, acy = 0, acz = 0, du = 0, mumax = 0;
@@ -693,22 +693,24 @@ sph_status launch_forces(Ctx *ctx, int64_t n, const double *vx, const double *vy
 
 template <int L, bool F32>
 static void both_launch(Ctx *ctx, int64_t n, const sph_params *prm, double *ax, double *ay,
-                        double *az, double *dudt, double *dtc, hipStream_t s) {
+                        double *az, double *dudt, double *dtc, const int32_t *act,
+                        hipStream_t s) {
     using R4 = typename Real<F32>::T4;
     const int nb = (int)((n * L + kBlock - 1) / kBlock);
     hipLaunchKernelGGL((k_grad_forces<L, F32>), dim3(nb), dim3(kBlock), 0, s, n, ctx->runid,
                        ctx->grid, ctx->nbr, ctx->ncount, ctx->max_nbr, (const R4 *)ctx->rec_f,
                        prm->av_alpha, prm->av_beta, prm->av_eps, prm->eta_C, prm->g[0], prm->g[1],
-                       prm->g[2], ctx->gsum, ax, ay, az, dudt, dtc);
+                       prm->g[2], ctx->gsum, ax, ay, az, dudt, dtc, act);
 }
 
 template <bool F32>
 static void both_dispatch(Ctx *ctx, int64_t n, const sph_params *prm, double *ax, double *ay,
-                          double *az, double *dudt, double *dtc, hipStream_t s) {
+                          double *az, double *dudt, double *dtc, const int32_t *act,
+                          hipStream_t s) {
     switch (lanes_of(ctx, SPH_TUNE_LANES_STEP, F32)) {
-        case 4: both_launch<4, F32>(ctx, n, prm, ax, ay, az, dudt, dtc, s); break;
-        case 16: both_launch<16, F32>(ctx, n, prm, ax, ay, az, dudt, dtc, s); break;
-        default: both_launch<8, F32>(ctx, n, prm, ax, ay, az, dudt, dtc, s); break;
+        case 4: both_launch<4, F32>(ctx, n, prm, ax, ay, az, dudt, dtc, act, s); break;
+        case 16: both_launch<16, F32>(ctx, n, prm, ax, ay, az, dudt, dtc, act, s); break;
+        default: both_launch<8, F32>(ctx, n, prm, ax, ay, az, dudt, dtc, act, s); break;
     }
 }
 
@@ -716,11 +718,12 @@ static void both_dispatch(Ctx *ctx, int64_t n, const sph_params *prm, double *ax
 // whole-step state kernel into rec_f).
 sph_status launch_grad_force_pairs(Ctx *ctx, int64_t n, const sph_params *prm,
                                    sph_precision prec, double *ax, double *ay, double *az,
-                                   double *dudt, double *dtc, hipStream_t s) {
+                                   double *dudt, double *dtc, hipStream_t s,
+                                   const int32_t *act) {
     if (n == 0) return SPH_OK;
     TimedLaunch tl(ctx, SPH_T_FORCES, s);
-    prec == SPH_FP32_CELLREL ? both_dispatch<true>(ctx, n, prm, ax, ay, az, dudt, dtc, s)
-                             : both_dispatch<false>(ctx, n, prm, ax, ay, az, dudt, dtc, s);
+    prec == SPH_FP32_CELLREL ? both_dispatch<true>(ctx, n, prm, ax, ay, az, dudt, dtc, act, s)
+                             : both_dispatch<false>(ctx, n, prm, ax, ay, az, dudt, dtc, act, s);
     SPH_HIP(hipGetLastError());
     return SPH_OK;
 }

@@ -18,7 +18,8 @@ enum {
     FLAG_CELL_OVERFLOW = 1,
     FLAG_NONFINITE = 2,
     FLAG_GRAV_OVERFLOW = 3,
-    FLAG_COUNT = 4
+    FLAG_RUNG_CLAMP = 4,
+    FLAG_COUNT = 5
 };
 
 // Uniform cell grid of one run.
@@ -190,9 +191,11 @@ sph_status launch_dt_reduce(Ctx *ctx, int64_t n, const double *dtc, const int32_
                             const int32_t *run_p);
 
 // Self-gravity of every run at the last build (sorted order); see sph_gravity.
+// tmask (may be NULL): only the targets with tmask[i] != 0 receive outputs.
 sph_status launch_gravity(Ctx *ctx, int64_t n, const double *m, const int32_t *active, double G,
                           double eps_over_h, double theta, int32_t accumulate, double *ax,
-                          double *ay, double *az, double *phi, hipStream_t s);
+                          double *ay, double *az, double *phi, hipStream_t s,
+                          const int32_t *tmask = nullptr);
 size_t gravity_levels_bytes(int32_t max_runs);
 sph_status launch_bound_mass(Ctx *ctx, int64_t n, const double *vx, const double *vy,
                              const double *vz, const double *m, double G, double eps_over_h,
@@ -224,9 +227,11 @@ sph_status launch_gradient_pairs(Ctx *ctx, int64_t n, sph_precision prec, hipStr
 sph_status launch_force_pairs(Ctx *ctx, int64_t n, const sph_params *prm, sph_precision prec,
                               double *ax, double *ay, double *az, double *dudt, double *dtc,
                               hipStream_t s);
+// act (may be NULL): only the particles with act[i] != 0 are evaluated.
 sph_status launch_grad_force_pairs(Ctx *ctx, int64_t n, const sph_params *prm,
                                    sph_precision prec, double *ax, double *ay, double *az,
-                                   double *dudt, double *dtc, hipStream_t s);
+                                   double *dudt, double *dtc, hipStream_t s,
+                                   const int32_t *act = nullptr);
 // fused whole-step kernels: source and destination rows of the reorder
 struct StepRows {
     const double *f_src[SPH_NF64];
@@ -236,18 +241,33 @@ struct StepRows {
 };
 sph_status launch_step_reorder(Ctx *ctx, int64_t n, const int32_t *perm, const StepRows &r,
                                const double *dt, const int16_t *runid, int32_t predict,
-                               double *vpx, double *vpy, double *vpz, double *up, hipStream_t s);
+                               int32_t hier, double tick, double *vpx, double *vpy, double *vpz,
+                               double *up, double *tau, int32_t *act, hipStream_t s);
 sph_status launch_step_state(Ctx *ctx, int64_t n, sph_precision prec, const double *rho,
                              const double *omega, const double *up, const double *vpx,
                              const double *vpy, const double *vpz, const double *m,
                              const int32_t *mat, int32_t nmat, const int32_t *fixed,
-                             const double *dt, const int16_t *runid, int32_t predict,
-                             const double *S_half, const double *Sdot, double *P, double *cs, double *T, double *Y,
-                             double *Gmod, double *S_pred, hipStream_t s);
+                             const double *tau, const double *S_half, const double *Sdot,
+                             double *P, double *cs, double *T, double *Y, double *Gmod,
+                             double *S_pred, hipStream_t s);
 sph_status launch_step_grad_rate(Ctx *ctx, int64_t n, const sph_params *prm,
                                  const double *S_pred, const double *Gmod, const int32_t *fixed,
-                                 const double *dt, const int16_t *runid, double *G,
+                                 const double *tau, const int32_t *act, double *G,
                                  double *Sdot, double *eps2, int64_t *n_singular, hipStream_t s);
+sph_status launch_accel_limit(Ctx *ctx, int64_t n, double eta_a, const double *ax,
+                              const double *ay, const double *az, const double *h,
+                              const int32_t *act, double *dtc, hipStream_t s);
+sph_status launch_kick_hier(Ctx *ctx, int64_t n, int32_t init, int32_t rungs, double tick,
+                            const double *dt, const double *clock, const int16_t *runid,
+                            const int32_t *fixed, const int32_t *act, double *vx, double *vy,
+                            double *vz, double *u, const double *ax, const double *ay,
+                            const double *az, const double *dudt, double *S_half,
+                            const double *S_pred, const double *Sdot, const double *Y,
+                            const double *dtc, double *step, double *elapsed, double *rem,
+                            hipStream_t s);
+sph_status launch_hier_next(Ctx *ctx, int32_t nr, int32_t init, double tick,
+                            const unsigned long long *bits_cur, unsigned long long *bits_clear,
+                            const double *dt, double *dt_next, double *clock, hipStream_t s);
 // Kicks; the next step of each run is taken from the minima in bits_cur
 // (capped at dt_cap when > 0) and written to dt_next[0..nr); bits_clear is
 // set to +inf for the following reduction.

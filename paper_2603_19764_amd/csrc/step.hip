@@ -13,11 +13,19 @@
 namespace sph {
 
 // --------------------------------------------------- reorder + predictor
+// The predictor interval tau of each particle: half the run's step with one
+// step per run; with individual steps (hier) the time elapsed in the
+// particle's own step (advanced here by the run's substep; predict = 2: not
+// advanced, a repeated reorder of the same step) less half of that step,
+// and act = 1 where the step ends now.  predict = 0 (start of a run):
+// tau = 0, every particle evaluated.
 __global__ void k_reorder_predict(int64_t n, const int32_t *__restrict__ perm, StepRows r,
                                   const double *__restrict__ dtp,
                                   const int16_t *__restrict__ runid, int32_t predict,
-                                  double *__restrict__ vpx, double *__restrict__ vpy,
-                                  double *__restrict__ vpz, double *__restrict__ up) {
+                                  int32_t hier, double tick, double *__restrict__ vpx,
+                                  double *__restrict__ vpy, double *__restrict__ vpz,
+                                  double *__restrict__ up, double *__restrict__ tau,
+                                  int32_t *__restrict__ act) {
     const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (k >= n) return;
     const int64_t o = perm[k];
@@ -34,7 +42,21 @@ __global__ void k_reorder_predict(int64_t n, const int32_t *__restrict__ perm, S
         r.i_dst[c][k] = v;
         if (c == SPH_FIXED) fx = v;
     }
-    const double hd = (predict && !fx) ? 0.5 * dt_of(dtp, runid, k) : 0.0;
+    double hd = 0.0;
+    int32_t a = 1;
+    if (predict && hier) {
+        a = 0;
+        if (!fx) {
+            const double el = f[SPH_EL] + (predict == 1 ? rint(dt_of(dtp, runid, k) / tick) : 0.0);
+            r.f_dst[SPH_EL][k] = el;
+            hd = (el - 0.5 * f[SPH_DTP]) * tick;
+            a = el == f[SPH_DTP] ? 1 : 0;
+        }
+    } else if (predict && !fx) {
+        hd = 0.5 * dt_of(dtp, runid, k);
+    }
+    tau[k] = hd;
+    act[k] = a;
     vpx[k] = f[SPH_VX] + hd * f[SPH_AX];
     vpy[k] = f[SPH_VY] + hd * f[SPH_AY];
     vpz[k] = f[SPH_VZ] + hd * f[SPH_AZ];
@@ -53,8 +75,7 @@ __global__ void k_state(int64_t n, const double4 *__restrict__ posh64,
                         const double *__restrict__ vpx, const double *__restrict__ vpy,
                         const double *__restrict__ vpz, const double *__restrict__ m,
                         const int32_t *__restrict__ mat, const int32_t *__restrict__ fixed,
-                        MatTable mt, const double *__restrict__ dtp,
-                        const int16_t *__restrict__ runid, int32_t predict,
+                        MatTable mt, const double *__restrict__ tau,
                         const double *__restrict__ S_half, const double *__restrict__ Sdot,
                         double *__restrict__ P, double *__restrict__ cs, double *__restrict__ T,
                         double *__restrict__ Y, double *__restrict__ Gmod,
@@ -72,8 +93,7 @@ __global__ void k_state(int64_t n, const double4 *__restrict__ posh64,
     T[i] = t;
     Y[i] = y;
     Gmod[i] = gm;
-    const bool fx = fixed && fixed[i];
-    const double hd = (predict && !fx) ? 0.5 * dt_of(dtp, runid, i) : 0.0;
+    const double hd = tau[i];
     double s[5];
     for (int k = 0; k < 5; ++k) s[k] = S_half[k * n + i] + hd * Sdot[k * n + i];
     plastic_return(s, y);
@@ -109,13 +129,12 @@ __global__ void k_grad_rate(int64_t n, const double *__restrict__ gsum,
                             const int32_t *__restrict__ ncount, int32_t use_corr,
                             const double *__restrict__ S_pred, const double *__restrict__ Gmod,
                             const int32_t *__restrict__ fixed, double rot,
-                            const double *__restrict__ dtp,
-                            const int16_t *__restrict__ runid, double *__restrict__ G,
-                            double *__restrict__ Sdot, double *__restrict__ eps2,
-                            int64_t *n_singular) {
+                            const double *__restrict__ tau, const int32_t *__restrict__ act,
+                            double *__restrict__ G, double *__restrict__ Sdot,
+                            double *__restrict__ eps2, int64_t *n_singular) {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     int sing = 0;
-    if (i < n) {
+    if (i < n && (!act || act[i])) {
         double ci[6], F[9], g[9], s[5], ds[5], e2;
         for (int k = 0; k < 6; ++k) ci[k] = gsum[k * n + i];
         for (int k = 0; k < 9; ++k) F[k] = gsum[(6 + k) * n + i];
@@ -124,7 +143,8 @@ __global__ void k_grad_rate(int64_t n, const double *__restrict__ gsum,
         for (int k = 0; k < 5; ++k) s[k] = S_pred[k * n + i];
         stress_rate(g, s, Gmod[i], rot, ds, e2);
         for (int k = 0; k < 5; ++k) Sdot[k * n + i] = ds[k];
-        if (eps2 && !(fixed && fixed[i])) eps2[i] += dt_of(dtp, runid, i) * e2;
+        // the step that ends here is twice the predictor interval
+        if (eps2 && !(fixed && fixed[i])) eps2[i] += 2.0 * tau[i] * e2;
     }
     if (n_singular) {
         const uint64_t mk = __ballot(sing);
@@ -184,14 +204,112 @@ __global__ void k_kick_all(int64_t n, int32_t mode, const double *__restrict__ d
     }
 }
 
+// ------------------------------------------------ acceleration criterion
+// dt_i <- min(dt_i, eta_a sqrt(h_i / |a_i|)) once a is complete (after
+// gravity), for the particles evaluated.
+__global__ void k_accel_limit(int64_t n, double eta_a, const double *__restrict__ ax,
+                              const double *__restrict__ ay, const double *__restrict__ az,
+                              const double *__restrict__ h, const int32_t *__restrict__ act,
+                              double *__restrict__ dtc) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n || (act && !act[i])) return;
+    const double a = sqrt((ax[i] * ax[i] + ay[i] * ay[i]) + az[i] * az[i]);
+    if (a > 0.0) {
+        const double d = eta_a * sqrt(h[i] / a);
+        if (d < dtc[i]) dtc[i] = d;
+    }
+}
+
+// --------------------------------------------------- individual steps
+// Step of a particle in ticks: the longest 2^(rungs-1-r) ticks whose
+// duration does not exceed its own step d (the shortest rung if none,
+// flagged), longer than its current step cur only where the run's time t
+// (ticks) is a multiple of it.
+__device__ __forceinline__ double rung_ticks(int rungs, double tick, double d, double t,
+                                             double cur, int32_t *flags) {
+    double st = ldexp(1.0, rungs - 1);
+    while (st > 1.0 && st * tick > d) st *= 0.5;
+    if (st * tick > d) flags[FLAG_RUNG_CLAMP] = 1;
+    while (st > cur && fmod(t, st) != 0.0) st *= 0.5;
+    return st;
+}
+
+// Particles whose step ends (act): closing kick with rescaling (not at the
+// start of a run), the next step, opening kick, elapsed time reset.  Every
+// particle that is not fixed then leaves the duration to the end of its
+// step in rem (the next substep of its run is the minimum).
+__global__ void k_kick_hier(int64_t n, int32_t init, int32_t rungs, double tick,
+                            const double *__restrict__ dtp, const double *__restrict__ clock,
+                            const int16_t *__restrict__ runid, const int32_t *__restrict__ fixed,
+                            const int32_t *__restrict__ act, double *vx, double *vy, double *vz,
+                            double *u, const double *__restrict__ ax, const double *__restrict__ ay,
+                            const double *__restrict__ az, const double *__restrict__ dudt,
+                            double *S_half, const double *__restrict__ S_pred,
+                            const double *__restrict__ Sdot, const double *__restrict__ Y,
+                            const double *__restrict__ dtc, double *step, double *elapsed,
+                            double *rem, int32_t *flags) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    if (fixed && fixed[i]) {
+        rem[i] = 0.0;
+        return;
+    }
+    if (!act[i]) {
+        rem[i] = (step[i] - elapsed[i]) * tick;
+        return;
+    }
+    const int r = runid ? (int)runid[i] : 0;
+    const double top = ldexp(1.0, rungs - 1);
+    double s[5], d[5];
+    for (int k = 0; k < 5; ++k) d[k] = Sdot[k * n + i];
+    double cur = top, t = 0.0;
+    if (init) {
+        for (int k = 0; k < 5; ++k) s[k] = S_pred[k * n + i];
+    } else {
+        const double hd = 0.5 * step[i] * tick;
+        vx[i] += hd * ax[i];
+        vy[i] += hd * ay[i];
+        vz[i] += hd * az[i];
+        u[i] += hd * dudt[i];
+        for (int k = 0; k < 5; ++k) s[k] = S_half[k * n + i] + hd * d[k];
+        plastic_return(s, Y[i]);
+        cur = step[i];
+        t = clock[r] + rint(dtp[r] / tick);
+    }
+    const double st = rung_ticks(rungs, tick, dtc[i], t, cur, flags);
+    const double hn = 0.5 * st * tick;
+    vx[i] += hn * ax[i];
+    vy[i] += hn * ay[i];
+    vz[i] += hn * az[i];
+    u[i] += hn * dudt[i];
+    for (int k = 0; k < 5; ++k) S_half[k * n + i] = s[k] + hn * d[k];
+    step[i] = st;
+    elapsed[i] = 0.0;
+    rem[i] = st * tick;
+}
+
+// Per run: the next substep from the reduced minimum, the run's clock
+// advanced by the substep just taken (set to 0 at the start of a run), the
+// other minima buffer cleared.
+__global__ void k_hier_next(int32_t nr, int32_t init, double tick,
+                            const unsigned long long *__restrict__ bits_cur,
+                            unsigned long long *bits_clear, const double *__restrict__ dt,
+                            double *dt_next, double *clock) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nr) return;
+    dt_next[r] = __longlong_as_double((long long)bits_cur[r]);
+    clock[r] = init ? 0.0 : clock[r] + rint(dt[r] / tick);
+    bits_clear[r] = 0x7ff0000000000000ull;
+}
+
 // -------------------------------------------------------------- launches
 sph_status launch_step_reorder(Ctx *ctx, int64_t n, const int32_t *perm, const StepRows &r,
                                const double *dt, const int16_t *runid, int32_t predict,
-                               double *vpx, double *vpy,
-                               double *vpz, double *up, hipStream_t s) {
+                               int32_t hier, double tick, double *vpx, double *vpy, double *vpz,
+                               double *up, double *tau, int32_t *act, hipStream_t s) {
     if (n == 0) return SPH_OK;
     hipLaunchKernelGGL(k_reorder_predict, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n,
-                       perm, r, dt, runid, predict, vpx, vpy, vpz, up);
+                       perm, r, dt, runid, predict, hier, tick, vpx, vpy, vpz, up, tau, act);
     SPH_HIP(hipGetLastError());
     return SPH_OK;
 }
@@ -200,8 +318,7 @@ sph_status launch_step_state(Ctx *ctx, int64_t n, sph_precision prec, const doub
                              const double *omega, const double *up, const double *vpx,
                              const double *vpy, const double *vpz, const double *m,
                              const int32_t *mat, int32_t nmat, const int32_t *fixed,
-                             const double *dt, const int16_t *runid, int32_t predict,
-                             const double *S_half,
+                             const double *tau, const double *S_half,
                              const double *Sdot, double *P, double *cs, double *T, double *Y,
                              double *Gmod, double *S_pred, hipStream_t s) {
     if (n == 0) return SPH_OK;
@@ -211,25 +328,25 @@ sph_status launch_step_state(Ctx *ctx, int64_t n, sph_precision prec, const doub
     const unsigned nb = (unsigned)((n + 255) / 256);
     if (prec == SPH_FP32_CELLREL)
         hipLaunchKernelGGL((k_state<true>), dim3(nb), dim3(256), 0, s, n, ctx->posh64,
-                           ctx->posh32, rho, omega, up, vpx, vpy, vpz, m, mat, fixed, mt, dt,
-                           runid, predict, S_half, Sdot, P, cs, T, Y, Gmod, S_pred, ctx->rec_f);
+                           ctx->posh32, rho, omega, up, vpx, vpy, vpz, m, mat, fixed, mt, tau,
+                           S_half, Sdot, P, cs, T, Y, Gmod, S_pred, ctx->rec_f);
     else
         hipLaunchKernelGGL((k_state<false>), dim3(nb), dim3(256), 0, s, n, ctx->posh64,
-                           ctx->posh32, rho, omega, up, vpx, vpy, vpz, m, mat, fixed, mt, dt,
-                           runid, predict, S_half, Sdot, P, cs, T, Y, Gmod, S_pred, ctx->rec_f);
+                           ctx->posh32, rho, omega, up, vpx, vpy, vpz, m, mat, fixed, mt, tau,
+                           S_half, Sdot, P, cs, T, Y, Gmod, S_pred, ctx->rec_f);
     SPH_HIP(hipGetLastError());
     return SPH_OK;
 }
 
 sph_status launch_step_grad_rate(Ctx *ctx, int64_t n, const sph_params *prm,
                                  const double *S_pred, const double *Gmod, const int32_t *fixed,
-                                 const double *dt, const int16_t *runid, double *G,
+                                 const double *tau, const int32_t *act, double *G,
                                  double *Sdot, double *eps2,
                                  int64_t *n_singular, hipStream_t s) {
     if (n == 0) return SPH_OK;
     hipLaunchKernelGGL(k_grad_rate, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n,
                        ctx->gsum, ctx->ncount, prm->use_correction_tensor, S_pred, Gmod, fixed,
-                       prm->rot_sign, dt, runid, G, Sdot, eps2, n_singular);
+                       prm->rot_sign, tau, act, G, Sdot, eps2, n_singular);
     SPH_HIP(hipGetLastError());
     return SPH_OK;
 }
@@ -247,6 +364,43 @@ sph_status launch_step_kick(Ctx *ctx, int64_t n, int32_t mode, const double *dt,
     hipLaunchKernelGGL(k_kick_all, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, n, mode,
                        dt, bits_cur, dt_cap, dt_next, bits_clear, nr, runid, fixed, vx, vy, vz, u,
                        ax, ay, az, dudt, S_half, S_pred, Sdot, Y);
+    SPH_HIP(hipGetLastError());
+    return SPH_OK;
+}
+
+sph_status launch_accel_limit(Ctx *ctx, int64_t n, double eta_a, const double *ax,
+                              const double *ay, const double *az, const double *h,
+                              const int32_t *act, double *dtc, hipStream_t s) {
+    (void)ctx;
+    if (n == 0) return SPH_OK;
+    hipLaunchKernelGGL(k_accel_limit, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n,
+                       eta_a, ax, ay, az, h, act, dtc);
+    SPH_HIP(hipGetLastError());
+    return SPH_OK;
+}
+
+sph_status launch_kick_hier(Ctx *ctx, int64_t n, int32_t init, int32_t rungs, double tick,
+                            const double *dt, const double *clock, const int16_t *runid,
+                            const int32_t *fixed, const int32_t *act, double *vx, double *vy,
+                            double *vz, double *u, const double *ax, const double *ay,
+                            const double *az, const double *dudt, double *S_half,
+                            const double *S_pred, const double *Sdot, const double *Y,
+                            const double *dtc, double *step, double *elapsed, double *rem,
+                            hipStream_t s) {
+    if (n == 0) return SPH_OK;
+    hipLaunchKernelGGL(k_kick_hier, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, init,
+                       rungs, tick, dt, clock, runid, fixed, act, vx, vy, vz, u, ax, ay, az, dudt,
+                       S_half, S_pred, Sdot, Y, dtc, step, elapsed, rem, ctx->flags);
+    SPH_HIP(hipGetLastError());
+    return SPH_OK;
+}
+
+sph_status launch_hier_next(Ctx *ctx, int32_t nr, int32_t init, double tick,
+                            const unsigned long long *bits_cur, unsigned long long *bits_clear,
+                            const double *dt, double *dt_next, double *clock, hipStream_t s) {
+    (void)ctx;
+    hipLaunchKernelGGL(k_hier_next, dim3((unsigned)((nr + 255) / 256)), dim3(256), 0, s, nr,
+                       init, tick, bits_cur, bits_clear, dt, dt_next, clock);
     SPH_HIP(hipGetLastError());
     return SPH_OK;
 }

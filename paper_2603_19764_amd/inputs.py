@@ -111,7 +111,8 @@ def default_params(**kw) -> dict:
     when switched on)."""
     p = dict(av_alpha=1.0, av_beta=2.0, av_eps=0.01, eta_C=0.3, rot_sign=1.0,
              g=(0.0, 0.0, 0.0), box=(0.0, 0.0, 0.0), use_correction=1, omega_one=0,
-             grav_G=0.0, grav_eps_over_h=0.5, grav_theta=0.6, adapt_ngb=0.0, adapt_skin=1.25)
+             grav_G=0.0, grav_eps_over_h=0.5, grav_theta=0.6, adapt_ngb=0.0, adapt_skin=1.25,
+             eta_a=0.0, rungs=0)
     p.update(kw)
     return p
 

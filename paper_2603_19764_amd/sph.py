@@ -24,11 +24,13 @@ SPH_KD_DRIFT, SPH_KD_PREDICT, SPH_KD_KICK, SPH_KD_OPEN = 1, 2, 4, 8
 
 # rows of the state buffers (must match include/sph.h)
 SPH_X, SPH_Y, SPH_Z, SPH_VX, SPH_VY, SPH_VZ, SPH_U = range(7)
-SPH_S, SPH_AX, SPH_AY, SPH_AZ, SPH_DUDT, SPH_SDOT, SPH_M, SPH_H, SPH_EPS2, SPH_NF64 = (
-    7, 12, 13, 14, 15, 16, 21, 22, 23, 24)
+SPH_S, SPH_AX, SPH_AY, SPH_AZ, SPH_DUDT, SPH_SDOT, SPH_M, SPH_H, SPH_EPS2 = (
+    7, 12, 13, 14, 15, 16, 21, 22, 23)
+SPH_DTP, SPH_EL, SPH_NF64 = 24, 25, 26
 SPH_MAT, SPH_ID, SPH_FIXED, SPH_RUN, SPH_NI32 = range(5)
 (SPH_W_RHO, SPH_W_OMEGA, SPH_W_P, SPH_W_CS, SPH_W_T, SPH_W_Y, SPH_W_GMOD) = range(7)
-SPH_W_VP, SPH_W_UP, SPH_W_SP, SPH_W_G, SPH_W_DT, SPH_W_PERM, SPH_NW = 7, 10, 11, 16, 25, 26, 27
+SPH_W_VP, SPH_W_UP, SPH_W_SP, SPH_W_G, SPH_W_DT, SPH_W_PERM = 7, 10, 11, 16, 25, 26
+SPH_W_TAU, SPH_W_ACT, SPH_NW = 27, 28, 29
 SPH_T_BUILD, SPH_T_DENSITY, SPH_T_GRADIENTS, SPH_T_FORCES = range(4)
 (SPH_TUNE_LANES_DENSITY, SPH_TUNE_LANES_GRADIENTS, SPH_TUNE_LANES_FORCES, SPH_TUNE_LANES_STEP,
  SPH_TUNE_CELL_SCALE) = range(5)
@@ -59,7 +61,8 @@ class sph_params(C.Structure):
                 ("use_correction_tensor", C.c_int32), ("omega_one", C.c_int32),
                 ("grav_G", C.c_double), ("grav_eps_over_h", C.c_double),
                 ("grav_theta", C.c_double), ("adapt_ngb", C.c_double),
-                ("adapt_skin", C.c_double)]
+                ("adapt_skin", C.c_double), ("eta_a", C.c_double), ("rungs", C.c_int32),
+                ("rungs_pad", C.c_int32)]
 
 
 class sph_state(C.Structure):
@@ -67,7 +70,7 @@ class sph_state(C.Structure):
                 ("f64", C.c_void_p * 2), ("i32", C.c_void_p * 2), ("work", C.c_void_p),
                 ("dt", C.c_void_p), ("dt_next", C.c_void_p), ("n_singular", C.c_void_p),
                 ("cur", C.c_int32), ("n_runs", C.c_int32), ("run_start", C.c_void_p),
-                ("cell_min", C.c_double), ("dt_max", C.c_double)]
+                ("cell_min", C.c_double), ("dt_max", C.c_double), ("clock", C.c_void_p)]
 
 
 _lib = None
@@ -210,6 +213,8 @@ def make_params(d: dict) -> sph_params:
     p.grav_theta = float(d.get("grav_theta", 0.6))
     p.adapt_ngb = float(d.get("adapt_ngb", 0.0))
     p.adapt_skin = float(d.get("adapt_skin", 1.25))
+    p.eta_a = float(d.get("eta_a", 0.0))
+    p.rungs = int(d.get("rungs", 0))
     return p
 
 
@@ -418,6 +423,7 @@ class State:
         # the library swaps the two step scalars after every step
         n_dt = 1 if run_start is None else len(run_start) - 1
         self._dt_pair = (torch.zeros(n_dt, **dd), torch.zeros(n_dt, **dd))
+        self.clock = torch.zeros(n_dt, **dd)   # per run, ticks (individual steps)
         self.n_singular = torch.zeros(1, dtype=torch.int64, device=device)
         F = self.f64[0]
         for k, row in (("x", SPH_X), ("y", SPH_Y), ("z", SPH_Z), ("vx", SPH_VX), ("vy", SPH_VY),
@@ -447,6 +453,7 @@ class State:
         c.run_start = None if self._rs is None else C.cast(self._rs, _P).value
         c.cell_min = float(cell_min)
         c.dt_max = float(dt_max)
+        c.clock = self.clock.data_ptr()
         self.c = c
         self._mats_cache = None
 
@@ -500,7 +507,8 @@ class State:
                    c=W[SPH_W_CS][order], T=W[SPH_W_T][order], Y=W[SPH_W_Y][order],
                    Gam=W[SPH_W_GMOD][order], S_pred=W[SPH_W_SP:SPH_W_SP + 5][:, order],
                    G=W[SPH_W_G:SPH_W_G + 9][:, order], dt=W[SPH_W_DT][order],
-                   id=I[SPH_ID][order])
+                   id=I[SPH_ID][order], step_ticks=F[SPH_DTP][order],
+                   elapsed_ticks=F[SPH_EL][order])
         return out
 
 

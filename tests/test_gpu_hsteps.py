@@ -1,0 +1,157 @@
+"""Individual time steps on the GPU (sph_init / sph_step with rungs) against
+the oracle's integrator: one rung reproduces the shared step; two bodies on
+different rungs, one body whose particles spread over several rungs, and a
+batch of runs with their own clocks follow the oracle substep by substep;
+the acceleration criterion caps the shared step as in the oracle."""
+import numpy as np
+import pytest
+
+from oracle import oracle as orc
+from paper_2603_19764_amd import inputs
+from tests.gpu_harness import norm_err, say
+
+pytestmark = pytest.mark.gpu
+
+FP64 = 0
+KEYS = ("x", "y", "z", "m", "h", "mat", "vx", "vy", "vz", "u", "S", "fixed")
+
+
+def _block(n_side, spacing, offset=0.0, c_min=1.0e4):
+    x, y, z = inputs.lattice(n_side, n_side, n_side, spacing)
+    n = x.size
+    w = inputs._empty(n)
+    w.update(x=x + offset, y=y.copy(), z=z.copy(), m=np.full(n, 2700.0 * spacing ** 3),
+             h=np.full(n, 1.3 * spacing))
+    w["u"][:] = 1.0e4
+    return w, [dict(inputs.basalt_c1(), c_min=c_min)]
+
+
+def _join(a, b):
+    out = {k: np.concatenate([a[k], b[k]]) for k in KEYS if k != "S"}
+    out["S"] = np.concatenate([a["S"], b["S"]], axis=1)
+    return out
+
+
+def _gpu(w, mats, prm, dt_max, steps, prec=FP64, run_start=None):
+    import torch
+    from paper_2603_19764_amd import sph
+    n = w["x"].size
+    ctx = sph.Context(n, 128, max_runs=1 if run_start is None else len(run_start) - 1)
+    st = sph.State(w, run_start=run_start, dt_max=dt_max)
+    sph.sph_init(ctx, st, mats, prm, prec)
+    for _ in range(steps):
+        sph.sph_step(ctx, st, mats, prm, prec)
+    torch.cuda.synchronize()
+    ctx.check(sph.lib().sph_sync_status(ctx.h, None))
+    out = st.to_host()
+    out["clock"] = st.clock.cpu().numpy()
+    out["dt_next"] = st.dt.cpu().numpy()
+    ctx.close()
+    return out
+
+
+def _oracle(w, mats, prm, dt_fixed, steps):
+    it = orc.Integrator({k: w[k] for k in KEYS}, mats, prm, dt_fixed=dt_fixed)
+    it.step(steps)
+    return it
+
+
+def _compare(g, it, label, tol=1e-10):
+    e = {k: norm_err(g[k], it[k]) for k in ("x", "vx", "vy", "vz", "u", "S", "dS", "eps2")}
+    e["a"] = norm_err(g["a"], np.stack([it["ax"], it["ay"], it["az"]]))
+    say(label, {k: f"{v:.2e}" for k, v in e.items()})
+    for k, v in e.items():
+        assert v < tol, (label, k, v)
+
+
+def _cfl(w, mats, prm):
+    return float(np.min(orc.Integrator({k: w[k] for k in KEYS}, mats, prm)["dt_i"]))
+
+
+def test_one_rung_is_the_shared_step():
+    say("[one rung]")
+    w = inputs.c1_block(8, variant="s")
+    mats, prm = w["mats"], w["params"]
+    dt0 = 0.9 * _cfl(w, mats, prm)
+    shared = _gpu(w, mats, prm, dt0, 3)
+    hier = _gpu(w, mats, dict(prm, rungs=6), dt0, 3)
+    for k in ("x", "vx", "vy", "u", "S", "a", "dS", "eps2"):
+        assert norm_err(hier[k], shared[k]) < 1e-14, k
+    assert np.all(hier["step_ticks"] == 32.0) and hier["clock"][0] == 3 * 32.0
+
+
+@pytest.mark.parametrize("substeps", [1, 4, 8])
+def test_two_bodies_on_different_rungs_match_oracle(substeps):
+    say(f"[two bodies, {substeps} substeps]")
+    wb, mats = _block(5, 1.0)
+    wa, _ = _block(5, 0.25, offset=-50.0)
+    wa["vy"][:] = 0.05 * np.cos(4.0 * wa["x"])
+    wb["vy"][:] = 0.05 * np.cos(wb["x"])
+    w = _join(wa, wb)
+    prm = inputs.default_params(rungs=4)
+    dt0 = 0.9 * _cfl(wb, mats, inputs.default_params())
+    it = _oracle(w, mats, prm, dt0, substeps)
+    g = _gpu(w, mats, prm, dt0, substeps)
+    assert np.array_equal(g["step_ticks"], it["dtp"].astype(float))
+    assert np.array_equal(g["elapsed_ticks"], it["el"].astype(float))
+    assert g["clock"][0] == it.ticks
+    _compare(g, it, f"two bodies {substeps}")
+
+
+def _spread_block():
+    # sound speed rising smoothly along x: CFL steps over a factor of ~4
+    w = inputs.c1_block(8)
+    w["u"] = 1.0e4 + 2.0e6 * (w["x"] / w["x"].max()) ** 2
+    return w
+
+
+def test_particles_on_several_rungs_match_oracle():
+    say("[several rungs]")
+    w = _spread_block()
+    mats = w["mats"]
+    prm = dict(w["params"], rungs=6)
+    it0 = orc.Integrator({k: w[k] for k in KEYS}, mats, w["params"])
+    dt0 = float(np.max(it0["dt_i"]))
+    it = orc.Integrator({k: w[k] for k in KEYS}, mats, prm, dt_fixed=dt0)
+    steps = 0
+    while it.time < dt0 * (1 - 1e-12):
+        it.step()
+        steps += 1
+    used = np.unique(it["dtp"])
+    say(f"rungs in use (ticks): {used}, {steps} substeps")
+    assert used.size >= 3
+    g = _gpu(w, mats, prm, dt0, steps)
+    assert np.array_equal(g["step_ticks"], it["dtp"].astype(float))
+    assert np.array_equal(g["elapsed_ticks"], it["el"].astype(float))
+    _compare(g, it, "several rungs", tol=1e-9)
+
+
+def test_runs_keep_their_own_clocks():
+    """Two runs in one state: each follows its own substeps; the batch equals
+    each run alone."""
+    say("[batched rungs]")
+    wb, mats = _block(5, 1.0)
+    wa, _ = _block(5, 0.25)
+    prm = inputs.default_params(rungs=4)
+    dt0 = 0.9 * _cfl(wb, mats, inputs.default_params())
+    w = _join(wa, wb)
+    na = wa["x"].size
+    g = _gpu(w, mats, prm, dt0, 4, run_start=[0, na, w["x"].size])
+    ga = _gpu(wa, mats, prm, dt0, 4)
+    gb = _gpu(wb, mats, prm, dt0, 4)
+    # run A ends a step every substep (4 substeps = 8 ticks); run B every dt0
+    assert g["clock"][0] == ga["clock"][0] == 8.0 and g["clock"][1] == gb["clock"][0] == 32.0
+    for k in ("x", "vx", "vy", "u", "S", "a"):
+        assert norm_err(g[k][..., :na], ga[k]) < 1e-13, k
+        assert norm_err(g[k][..., na:], gb[k]) < 1e-13, k
+
+
+def test_acceleration_criterion_matches_oracle():
+    say("[acceleration criterion]")
+    w, mats = _block(6, 1.0, c_min=1.0)
+    w["u"][:] = 0.0
+    prm = inputs.default_params(g=(0.0, -9.81, 0.0), eta_a=0.05)
+    it = _oracle(w, mats, prm, 0.0, 2)
+    g = _gpu(w, mats, prm, 0.0, 2)
+    assert abs(g["dt_next"][0] - it.dt) <= 1e-12 * it.dt
+    _compare(g, it, "acceleration criterion")
