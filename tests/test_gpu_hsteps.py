@@ -70,11 +70,19 @@ def _cfl(w, mats, prm):
 
 def test_one_rung_is_the_shared_step():
     say("[one rung]")
-    w = inputs.c1_block(8, variant="s")
+    # a base step well below every particle's CFL step, so that both the
+    # shared step (capped at dt_max) and the single rung stay at dt0
+    w = inputs.c1_block(8)
     mats, prm = w["mats"], w["params"]
-    dt0 = 0.9 * _cfl(w, mats, prm)
+    dt0 = 0.5 * _cfl(w, mats, prm)
+    it = _oracle(w, mats, prm, dt0, 3)
     shared = _gpu(w, mats, prm, dt0, 3)
     hier = _gpu(w, mats, dict(prm, rungs=6), dt0, 3)
+    say(f"dt0 {dt0:.6e}: shared next {shared['dt_next']}, hier next {hier['dt_next']}, "
+        f"hier clock {hier['clock']}")
+    assert shared["dt_next"][0] == dt0 and hier["dt_next"][0] == dt0
+    _compare(shared, it, "shared vs oracle")
+    _compare(hier, it, "one rung vs oracle")
     for k in ("x", "vx", "vy", "u", "S", "a", "dS", "eps2"):
         assert norm_err(hier[k], shared[k]) < 1e-14, k
     assert np.all(hier["step_ticks"] == 32.0) and hier["clock"][0] == 3 * 32.0
@@ -109,9 +117,11 @@ def test_particles_on_several_rungs_match_oracle():
     say("[several rungs]")
     w = _spread_block()
     mats = w["mats"]
-    prm = dict(w["params"], rungs=6)
+    prm = dict(w["params"], rungs=8)
     it0 = orc.Integrator({k: w[k] for k in KEYS}, mats, w["params"])
-    dt0 = float(np.max(it0["dt_i"]))
+    # a base step off every particle's own step: the rung of a particle
+    # whose step sits exactly on a rung boundary is decided by rounding
+    dt0 = 1.1 * float(np.max(it0["dt_i"]))
     it = orc.Integrator({k: w[k] for k in KEYS}, mats, prm, dt_fixed=dt0)
     steps = 0
     while it.time < dt0 * (1 - 1e-12):
@@ -119,7 +129,7 @@ def test_particles_on_several_rungs_match_oracle():
         steps += 1
     used = np.unique(it["dtp"])
     say(f"rungs in use (ticks): {used}, {steps} substeps")
-    assert used.size >= 3
+    assert used.size >= 3 and it.n_clamped == 0
     g = _gpu(w, mats, prm, dt0, steps)
     assert np.array_equal(g["step_ticks"], it["dtp"].astype(float))
     assert np.array_equal(g["elapsed_ticks"], it["el"].astype(float))
