@@ -239,6 +239,69 @@ def run_impact_step(steps=4, warmup=2):
     return row
 
 
+def run_hsteps(n_side=64, prec=1, shared_steps=600):
+    """Individual time steps against one shared step on a block with a hot
+    core: a 64^3 lattice block (the spacing, jitter and shear flow of the
+    single-step block) whose central sphere of a fifth of its edge carries
+    u = 3e6 J/kg.  The shared step runs ``shared_steps`` steps (it follows
+    the particle with the shortest CFL step); the rungs (base step: the
+    longest CFL step at the start) then run to the same simulated time.
+    Figure of merit: wall time to that simulated time."""
+    import torch
+    from paper_2603_19764_amd import inputs, sph
+    w = inputs.c1_block(n_side)
+    c = np.array([w[k].mean() for k in ("x", "y", "z")])
+    r = np.sqrt((w["x"] - c[0]) ** 2 + (w["y"] - c[1]) ** 2 + (w["z"] - c[2]) ** 2)
+    hot = r < 0.2 * n_side
+    w["u"] = np.where(hot, 3.0e6, w["u"])
+    n = int(w["x"].size)
+    out = {"workload": f"{n_side}^3 block with a hot core ({int(hot.sum())} of {n} particles "
+                       "at u = 3e6 J/kg)", "precision": "fp32" if prec else "fp64"}
+    t_target = None
+    dt0 = None
+    for mode in ("shared", "rungs"):
+        prm = dict(w["params"])
+        if mode == "rungs":
+            prm["rungs"] = 8
+        ctx = sph.Context(n, 128, max_cells=1 << 22)
+        st = sph.State(w, dt_max=dt0 if mode == "rungs" else 0.0)
+        sph.sph_init(ctx, st, w["mats"], prm, prec)
+        if mode == "shared":
+            torch.cuda.synchronize()
+            dt0 = float(st.wrow(sph.SPH_W_DT).max()) * 1.01
+        sim = torch.zeros(1, dtype=torch.float64, device="cuda")
+        k = 0
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        while True:
+            for _ in range(20):
+                sim += st.dt
+                sph.sph_step(ctx, st, w["mats"], prm, prec)
+            k += 20
+            if mode == "shared" and k >= shared_steps:
+                break
+            if mode == "rungs" and float(sim.item()) >= t_target:
+                break
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        ctx.check(sph.lib().sph_sync_status(ctx.h, None))
+        row = {"steps": k, "wall_s": t1 - t0, "ms_per_step": 1e3 * (t1 - t0) / k,
+               "simulated_s": float(sim.item())}
+        if mode == "shared":
+            t_target = row["simulated_s"]
+        else:
+            steps = st.row(sph.SPH_DTP).cpu().numpy()
+            vals, cnt = np.unique(steps, return_counts=True)
+            row["base_step_s"] = dt0
+            row["particles_per_step_ticks"] = {str(int(v)): int(q) for v, q in zip(vals, cnt)}
+        out[mode] = row
+        ctx.close()
+    out["speedup"] = (out["shared"]["wall_s"] / out["shared"]["simulated_s"]) / (
+        out["rungs"]["wall_s"] / out["rungs"]["simulated_s"])
+    log(f"individual steps: {out}")
+    return out
+
+
 def cpu_baseline(w, budget_s=15.0):
     """The FP64 oracle on a bounded sample of the same workload: the full
     derivative chain (brute-force pair sets, density + EOS for the pair-set
@@ -289,6 +352,8 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-curve", action="store_true",
                     help="skip the size curve (block workload, 32^3 to 160^3)")
+    ap.add_argument("--no-hsteps", action="store_true",
+                    help="skip the individual-step comparison on the hot-core block")
     ap.add_argument("--no-impact", action="store_true",
                     help="skip the 1.1M-particle two-sphere impact steps")
     ap.add_argument("--batch-steps", type=int, default=0,
@@ -342,6 +407,7 @@ def main():
                                 for k, v in r32["kernels"].items()})
     curve = None if args.no_curve else run_curve()
     impact = None if args.no_impact else run_impact_step()
+    hsteps = None if args.no_hsteps else run_hsteps()
     batch = None
     if args.batch_steps > 0:
         batch = run_batch(args.batch_steps, 4, tune=not args.no_tune)
@@ -364,6 +430,7 @@ def main():
             "steps": r64["steps"], "launch_shapes": tuned[0]},
         "size_curve": curve,
         "impact_1p1M": impact,
+        "individual_steps": hsteps,
         "batch_scan": batch,
         "roofline": roof,
         "cpu_baseline": cpu,

@@ -93,27 +93,40 @@ def simulate(cases: list, t_end_ff: float = 2.0, prec: int = sph.SPH_FP32_CELLRE
 
 
 def bracket_rounds(cases: list, judge_batch, tol: float = 0.05, predict_for=None,
-                   max_rounds: int = 12, log=None):
+                   max_rounds: int = 12, log=None, expand: int = 2):
     """Bracket Q_RD* for every case at once, one simulation per unfinished
     bracket per round, all of a round's simulations judged in one batch.
 
     ``cases``: qrd.Case objects; ``judge_batch(list of (case, v)) -> list of
     f_lr``; ``predict_for(round) -> predict`` gives the model for that round
     (None: plain bisection).  The initial bracket is [v_esc, 10 v_esc]; its
-    ends are simulated in the first round.  Returns the brackets and the
-    list of (features, f_lr) outcomes."""
+    ends are simulated in the first round.  A case whose upper end still
+    leaves more than half the mass bound is extended upwards by a factor of
+    three, at most ``expand`` times (batched like the rounds).  Returns the
+    brackets, their validity and the list of (features, f_lr) outcomes."""
     from . import qrd
     brackets = [qrd.Bracket(c, c.v_esc, 10.0 * c.v_esc) for c in cases]
     outcomes = []
     jobs = [(b.case, b.v_lo) for b in brackets] + [(b.case, b.v_hi) for b in brackets]
     f = judge_batch(jobs)
     k = len(brackets)
-    valid = []
     for i, b in enumerate(brackets):
         b.f_lo, b.f_hi = f[i], f[k + i]
         b.sims = 2
         outcomes += [(b.case.features(b.v_lo), b.f_lo), (b.case.features(b.v_hi), b.f_hi)]
-        valid.append(b.f_lo > 0.5 >= b.f_hi)
+    for _ in range(expand):
+        low = [b for b in brackets if b.f_lo > 0.5 and b.f_hi > 0.5]
+        if not low:
+            break
+        f = judge_batch([(b.case, 3.0 * b.v_hi) for b in low])
+        for b, fv in zip(low, f):
+            b.v_lo, b.f_lo = b.v_hi, b.f_hi
+            b.v_hi, b.f_hi = 3.0 * b.v_hi, float(fv)
+            b.sims += 1
+            outcomes.append((b.case.features(b.v_hi), b.f_hi))
+        if log:
+            log(f"extended {len(low)} brackets upwards")
+    valid = [b.f_lo > 0.5 >= b.f_hi for b in brackets]
     for rnd in range(max_rounds):
         open_ = [b for b, ok in zip(brackets, valid) if ok and b.width() > tol]
         if not open_:

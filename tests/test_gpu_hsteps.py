@@ -165,3 +165,40 @@ def test_acceleration_criterion_matches_oracle():
     g = _gpu(w, mats, prm, 0.0, 2)
     assert abs(g["dt_next"][0] - it.dt) <= 1e-12 * it.dt
     _compare(g, it, "acceleration criterion")
+
+
+def test_gravity_reaches_only_the_particles_whose_step_ends():
+    """Self-gravity with individual steps: two bodies in one run, one on a
+    step four times the other's.  While the slow body's step runs its
+    accelerations (SPH and gravity) must stay as its last evaluation left
+    them, and change when its step ends; the fast body's change every
+    substep."""
+    import torch
+    from paper_2603_19764_amd import sph
+    say("[gravity with rungs]")
+    wb, mats = _block(5, 1.0)
+    wa, _ = _block(5, 0.25, offset=-50.0)
+    prm = inputs.default_params(grav_G=2.0e3, grav_eps_over_h=0.5, grav_theta=0.6, rungs=4)
+    dt0 = 0.9 * _cfl(wb, mats, inputs.default_params())
+    w = _join(wa, wb)
+    n, na = w["x"].size, wa["x"].size
+    ctx = sph.Context(n, 128)
+    st = sph.State(w, dt_max=dt0)
+    sph.sph_init(ctx, st, mats, prm, FP64)
+    seen = []
+    for k in range(5):
+        torch.cuda.synchronize()
+        seen.append(st.to_host()["a"].copy())
+        sph.sph_step(ctx, st, mats, prm, FP64)
+    torch.cuda.synchronize()
+    ctx.check(sph.lib().sph_sync_status(ctx.h, None))
+    seen.append(st.to_host()["a"].copy())
+    ctx.close()
+    gmax = float(np.abs(seen[0][:, na:]).max())
+    say(f"slow body max |a| {gmax:.3e}")
+    # seen[k]: after k substeps; substeps 1-3 end at ticks 2, 4, 6, where
+    # the slow body waits; the fourth ends at tick 8, its step's end
+    for k in range(1, 4):
+        assert np.array_equal(seen[k][:, na:], seen[0][:, na:]), k
+        assert not np.array_equal(seen[k][:, :na], seen[k - 1][:, :na]), k
+    assert not np.array_equal(seen[4][:, na:], seen[0][:, na:])

@@ -78,3 +78,26 @@ def test_non_monotone_model_falls_back_to_bisection():
     b2 = qrd.bracket_to(_fresh(c, judge), judge, 0.05, predict=wavy)
     assert b2.sims == b1.sims
     assert all(src == "bisect" for _, _, src in b2.history)
+
+
+def test_batched_rounds_extend_a_bracket_that_does_not_disrupt():
+    # the batched driver with a mock judge: one case's threshold lies above
+    # the initial upper end (10 v_esc), the other's inside; both close
+    from paper_2603_19764_amd import scan
+    c_in = qrd.Case(m_tot=1e21, gamma=0.1, strength=0, v_esc=300.0)
+    c_out = qrd.Case(m_tot=2e21, gamma=0.1, strength=1, v_esc=350.0)
+    q_star = {id(c_in): c_in.q(4.0 * c_in.v_esc), id(c_out): c_out.q(17.0 * c_out.v_esc)}
+    calls = []
+
+    def judge_batch(jobs):
+        calls.append(len(jobs))
+        return [1.0 / (1.0 + (c.q(v) / q_star[id(c)]) ** 2.5) for c, v in jobs]
+
+    brackets, valid, outcomes = scan.bracket_rounds([c_in, c_out], judge_batch)
+    assert valid == [True, True]
+    assert brackets[1].v_hi > 10.0 * c_out.v_esc and brackets[1].v_lo >= 10.0 * c_out.v_esc
+    for b, c in zip(brackets, (c_in, c_out)):
+        assert b.width() <= 0.05
+        assert abs(b.q_rd() / q_star[id(c)] - 1.0) < 0.05
+    assert calls[0] == 4 and calls[1] == 1      # both ends of both, then one extension
+    assert len(outcomes) == sum(b.sims for b in brackets)
