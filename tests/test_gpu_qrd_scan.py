@@ -18,12 +18,12 @@ def test_qrd_scan_with_simulation_judge():
     from paper_2603_19764_amd.proposal import MlpProposer
     t0 = time.perf_counter()
     judge = scan.judge_with_simulation(n_target=2000, t_end_ff=1.5, check_every=100, log=say)
-    train = [scan.case_for(r, s) for r in (6e5, 2.5e6) for s in (0, 1)]
-    held = [scan.case_for(1.2e6, s) for s in (0, 1)]
+    train = [scan.case_for(r, s) for r in (5e5, 9e5, 1.6e6, 2.8e6) for s in (0, 1)]
+    held = [scan.case_for(r, s) for r in (1.2e6, 2.1e6) for s in (0, 1)]
     br_t, ok_t, outs = scan.bracket_rounds(train, judge, log=say)
     say(f"training brackets valid {ok_t}, sims {[b.sims for b in br_t]}, "
         f"{time.perf_counter() - t0:.0f} s")
-    assert sum(ok_t) >= 3
+    assert sum(ok_t) >= 6
     X = np.array([o[0] for o in outs])
     Y = np.array([o[1] for o in outs])
     net = MlpProposer(seed=1, lr=3e-3)
