@@ -486,14 +486,17 @@ sph_status sph_timing_read(sph_ctx *ctx, int32_t which, double *total_ms, int64_
  *   SPH_TUNE_LANES_*   lanes per particle i of a pair pass: 4, 8 or 16
  *                      (per precision);
  *   SPH_TUNE_CELL_SCALE cell edge = max(cell_min, scale * 2 h_max), scale in
- *                      permille, 1000..2000 (precision ignored). */
+ *                      permille, 1000..2000 (precision ignored);
+ *   SPH_TUNE_BUILD_RANGE sorted particles per work-group of the pair-list
+ *                      build: 32, 64, 96 or 128 (precision ignored). */
 enum {
     SPH_TUNE_LANES_DENSITY = 0,   /* density sweep                         */
     SPH_TUNE_LANES_GRADIENTS = 1, /* public gradient pass                  */
     SPH_TUNE_LANES_FORCES = 2,    /* public force pass                     */
     SPH_TUNE_LANES_STEP = 3,      /* fused gradient + force sweep of sph_step */
     SPH_TUNE_CELL_SCALE = 4,
-    SPH_TUNE_COUNT = 5
+    SPH_TUNE_BUILD_RANGE = 5,
+    SPH_TUNE_COUNT = 6
 };
 sph_status sph_set_tuning(sph_ctx *ctx, int32_t knob, sph_precision prec, int32_t value);
 sph_status sph_get_tuning(sph_ctx *ctx, int32_t knob, sph_precision prec, int32_t *value);

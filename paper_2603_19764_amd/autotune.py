@@ -19,15 +19,18 @@ from . import sph
 
 LANES = (4, 8, 16)
 CELL_SCALES = (1000, 1150, 1300)   # permille of 2 h_max
+BUILD_RANGES = (32, 64, 96, 128)   # sorted particles per pair-list build work-group
 
 # knob -> (timer whose per-launch time decides it, candidate values)
 PLAN = (
     (sph.SPH_TUNE_LANES_STEP, sph.SPH_T_FORCES, LANES),
     (sph.SPH_TUNE_LANES_DENSITY, sph.SPH_T_DENSITY, LANES),
     (sph.SPH_TUNE_CELL_SCALE, None, CELL_SCALES),   # None: whole-step time
+    (sph.SPH_TUNE_BUILD_RANGE, sph.SPH_T_BUILD, BUILD_RANGES),
 )
 KNOB_NAMES = {sph.SPH_TUNE_LANES_STEP: "lanes_step", sph.SPH_TUNE_LANES_DENSITY: "lanes_density",
-              sph.SPH_TUNE_CELL_SCALE: "cell_scale_permille"}
+              sph.SPH_TUNE_CELL_SCALE: "cell_scale_permille",
+              sph.SPH_TUNE_BUILD_RANGE: "build_range"}
 
 
 def size_bucket(n: int) -> int:

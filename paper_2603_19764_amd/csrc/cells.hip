@@ -654,7 +654,8 @@ sph_status launch_build_cells(Ctx *ctx, int64_t n, double *x, double *y, double 
     hipLaunchKernelGGL(k_gather, dim3(nb), dim3(tb), 0, s, n, ctx->perm, x, y, z, h, ctx->key,
                        ctx->run_p, nr, ctx->grid, ctx->posh64, ctx->posh32, ctx->cellc,
                        ctx->runid, ctx->skey, perm_out, ex->m, ctx->rec_d, ex->f32);
-    int64_t wgs = (n + 31) / 32;
+    const int64_t per = ctx->build_range;
+    int64_t wgs = (n + per - 1) / per;
     if (wgs > 65536) wgs = 65536;
     {
         TimedLaunch tl(ctx, SPH_T_BUILD, s);

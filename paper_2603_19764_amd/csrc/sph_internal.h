@@ -54,6 +54,7 @@ struct Ctx {
     // passes [knob][precision], and the cell edge as a multiple of 2 h_max
     int32_t lanes[4][2] = {{8, 8}, {8, 8}, {8, 8}, {8, 8}};
     double cell_scale = 1.0;
+    int32_t build_range = 64;  // sorted particles per work-group of the pair-list build
     // self-gravity pyramid (allocated with the context)
     void *grav_lev = nullptr;        // per-run level layout (max_runs entries)
     int64_t *grav_totals = nullptr;  // [upper nodes, groups]

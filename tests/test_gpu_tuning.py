@@ -43,7 +43,8 @@ def test_every_knob_setting_gives_the_same_step(prec):
     tol = 1e-12 if prec == 0 else 4e-5
     for knobs in ({sph.SPH_TUNE_LANES_STEP: 4, sph.SPH_TUNE_LANES_DENSITY: 16},
                   {sph.SPH_TUNE_LANES_STEP: 16, sph.SPH_TUNE_LANES_DENSITY: 4},
-                  {sph.SPH_TUNE_CELL_SCALE: 1300}):
+                  {sph.SPH_TUNE_CELL_SCALE: 1300},
+                  {sph.SPH_TUNE_BUILD_RANGE: 32}, {sph.SPH_TUNE_BUILD_RANGE: 128}):
         got = _steps(w, prec, knobs)
         e = max(norm_err(got[k], ref[k]) for k in FIELDS)
         say(f"prec {prec} knobs {knobs}: max err {e:.1e}")
@@ -53,7 +54,8 @@ def test_every_knob_setting_gives_the_same_step(prec):
 def test_bad_knob_values_are_rejected():
     from paper_2603_19764_amd import sph
     ctx = sph.Context(16, 32)
-    for knob, v in ((sph.SPH_TUNE_LANES_STEP, 3), (sph.SPH_TUNE_CELL_SCALE, 999), (17, 8)):
+    for knob, v in ((sph.SPH_TUNE_LANES_STEP, 3), (sph.SPH_TUNE_CELL_SCALE, 999),
+                    (sph.SPH_TUNE_BUILD_RANGE, 48), (17, 8)):
         with pytest.raises(sph.SphError):
             sph.sph_set_tuning(ctx, knob, 0, v)
     ctx.close()
@@ -68,5 +70,6 @@ def test_tuner_returns_valid_settings(tmp_path):
     s = r["settings"]
     assert s["lanes_step"] in autotune.LANES and s["lanes_density"] in autotune.LANES
     assert s["cell_scale_permille"] in autotune.CELL_SCALES
+    assert s["build_range"] in autotune.BUILD_RANGES
     again = autotune.tune(w, 1, steps=2, cache=cache)
     assert again["cached"] and again["settings"] == s
