@@ -356,7 +356,7 @@ def main():
                     help="skip the individual-step comparison on the hot-core block")
     ap.add_argument("--no-impact", action="store_true",
                     help="skip the 1.1M-particle two-sphere impact steps")
-    ap.add_argument("--batch-steps", type=int, default=0,
+    ap.add_argument("--batch-steps", type=int, default=20,
                     help="steps of the batched 64-impact scan (0: skip it)")
     ap.add_argument("--no-tune", action="store_true",
                     help="keep the default launch shapes (no autotuning before the warmup)")
