@@ -64,15 +64,21 @@ class TuneCache:
             os.replace(tmp, self.path)
 
 
-def choose(values, measure):
-    """Smallest measured time wins; ties keep the earlier candidate.
-    Returns (best value, {value: time})."""
+# A later candidate replaces the best so far only when it is faster by more
+# than this fraction: settings whose times differ by less than the run-to-run
+# noise keep the earlier one, so the choice repeats from run to run.
+MARGIN = 0.03
+
+
+def choose(values, measure, margin: float = MARGIN):
+    """Smallest measured time wins, unless within ``margin`` of an earlier
+    candidate, which then stays.  Returns (best value, {value: time})."""
     times = {}
     best, best_t = None, math.inf
     for v in values:
         t = float(measure(v))
         times[v] = t
-        if t < best_t:
+        if t < best_t * (1.0 - margin):
             best, best_t = v, t
     return best, times
 

@@ -145,23 +145,27 @@ __global__ void k_bbox(double *x, double *y, double *z, const double *h, const i
         }
         hm = fmax(hm, h[k]);
     }
-    __shared__ double sh[7][256];
-    for (int d = 0; d < 3; ++d) {
-        sh[d][threadIdx.x] = lo[d];
-        sh[3 + d][threadIdx.x] = hi[d];
-    }
-    sh[6][threadIdx.x] = hm;
-    __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
-        if (threadIdx.x < (unsigned)o) {
-            for (int d = 0; d < 3; ++d) {
-                sh[d][threadIdx.x] = fmin(sh[d][threadIdx.x], sh[d][threadIdx.x + o]);
-                sh[3 + d][threadIdx.x] = fmax(sh[3 + d][threadIdx.x], sh[3 + d][threadIdx.x + o]);
-            }
-            sh[6][threadIdx.x] = fmax(sh[6][threadIdx.x], sh[6][threadIdx.x + o]);
+    // wave minima/maxima by shuffles, then across the block's waves in LDS
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            lo[d] = fmin(lo[d], __shfl_xor(lo[d], o));
+            hi[d] = fmax(hi[d], __shfl_xor(hi[d], o));
         }
-        __syncthreads();
+        hm = fmax(hm, __shfl_xor(hm, o));
     }
+    constexpr int kW = kBBoxThreads / kWave;
+    __shared__ double sh[7][kW];
+    const int w = threadIdx.x / kWave;
+    if (threadIdx.x % kWave == 0) {
+        for (int d = 0; d < 3; ++d) {
+            sh[d][w] = lo[d];
+            sh[3 + d][w] = hi[d];
+        }
+        sh[6][w] = hm;
+    }
+    __syncthreads();
     if (threadIdx.x == 0) {
         BBox bb;
         for (int d = 0; d < 3; ++d) {
@@ -169,6 +173,13 @@ __global__ void k_bbox(double *x, double *y, double *z, const double *h, const i
             bb.hi[d] = sh[3 + d][0];
         }
         bb.hmax = sh[6][0];
+        for (int v = 1; v < kW; ++v) {
+            for (int d = 0; d < 3; ++d) {
+                bb.lo[d] = fmin(bb.lo[d], sh[d][v]);
+                bb.hi[d] = fmax(bb.hi[d], sh[3 + d][v]);
+            }
+            bb.hmax = fmax(bb.hmax, sh[6][v]);
+        }
         part[r * kBBoxBlocks + blockIdx.x] = bb;
     }
 }
@@ -306,22 +317,24 @@ __global__ void k_keys(int64_t n, const double *x, const double *y, const double
         oct = (tx - cx >= 0.5 ? 1 : 0) | (ty - cy >= 0.5 ? 2 : 0) | (tz - cz >= 0.5 ? 4 : 0);
     }
     // One atomic per distinct key of the wave: lanes with equal keys take
-    // consecutive slots in lane order.
+    // consecutive slots in lane order.  Each group's leader issues the
+    // atomic; every lane reads its leader's result once all are issued.
     const int lane = threadIdx.x % kWave;
     uint64_t todo = __ballot(valid);
-    int my_slot = 0;
+    int my_leader = 0, my_rank = 0, lead_base = 0;
     while (todo) {
         const int leader = __ffsll((long long)todo) - 1;
         const uint32_t lk = __shfl(kk, leader);
         const uint64_t peers = __ballot(valid && kk == lk);
-        int base = 0;
-        if (lane == leader) base = atomicAdd(&cell_count[lk], __popcll(peers));
-        base = __shfl(base, leader);
-        if (valid && kk == lk)
-            my_slot = base + __builtin_amdgcn_mbcnt_hi((uint32_t)(peers >> 32),
-                                                       __builtin_amdgcn_mbcnt_lo((uint32_t)peers, 0u));
+        if (lane == leader) lead_base = atomicAdd(&cell_count[lk], __popcll(peers));
+        if (valid && kk == lk) {
+            my_leader = leader;
+            my_rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(peers >> 32),
+                                                __builtin_amdgcn_mbcnt_lo((uint32_t)peers, 0u));
+        }
         todo &= ~peers;
     }
+    const int my_slot = __shfl(lead_base, my_leader) + my_rank;
     if (valid) slot[k] = my_slot | (oct << kIdxBits);
 }
 
@@ -341,60 +354,54 @@ __global__ void k_scatter(int64_t n, const uint32_t *key, const int32_t *slot,
 // rank by (octant, input index) makes the permutation deterministic and
 // leaves the members of each octant contiguous.  One thread per particle
 // counts the members of its cell that precede it; arrival entries hold the
-// input index in the low kIdxBits bits and the octant above them.
-__global__ void k_cellrank(int64_t n, const int32_t *__restrict__ arrived,
-                           const uint32_t *__restrict__ key,
-                           const int32_t *__restrict__ cell_start,
-                           const int32_t *__restrict__ cell_count, const int32_t *total_keys,
-                           int32_t *__restrict__ perm, uint8_t *__restrict__ octant) {
+// input index in the low kIdxBits bits and the octant above them.  The same
+// thread then writes the sorted copies at the particle's place q: positions
+// and h, cell-relative float offsets, packed cell coordinates, run id,
+// sorted key, the density-pass record, perm (and perm_out for the caller).
+__global__ void k_place(int64_t n, const int32_t *__restrict__ arrived,
+                        const uint32_t *__restrict__ key, const int32_t *__restrict__ cell_start,
+                        const int32_t *__restrict__ cell_count, const int32_t *total_keys,
+                        int32_t *__restrict__ perm, uint8_t *__restrict__ octant,
+                        const double *x, const double *y, const double *z, const double *h,
+                        const int32_t *run_p, int nr, const GridDesc *grid, double4 *posh64,
+                        float4 *posh32, uint32_t *cellc, int16_t *runid, uint32_t *skey,
+                        int32_t *perm_out, const double *m, void *rec_d, int32_t f32) {
     const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (p >= n) return;
     const int32_t e = arrived[p];
     const int32_t o = e & (int32_t)kIdxMask;
-    if (*total_keys == 0) {
-        perm[p] = o;
-        octant[p] = 0;
-        return;
+    const uint32_t ko = key[o];
+    int64_t q = p;
+    uint8_t oct = 0;
+    if (*total_keys != 0) {
+        const int32_t cs = cell_start[ko], c = cell_count[ko];
+        int rank = 0;
+        for (int l = 0; l < c; ++l) rank += arrived[cs + l] < e;
+        q = cs + rank;
+        oct = (uint8_t)(e >> kIdxBits);
     }
-    const uint32_t kk = key[o];
-    const int32_t cs = cell_start[kk], c = cell_count[kk];
-    int rank = 0;
-    for (int l = 0; l < c; ++l) rank += arrived[cs + l] < e;
-    perm[cs + rank] = o;
-    octant[cs + rank] = (uint8_t)(e >> kIdxBits);
-}
-
-// Sorted copies of positions and h, cell-relative float offsets, packed
-// cell coordinates, run id, sorted keys; perm copied out for the caller.
-__global__ void k_gather(int64_t n, const int32_t *perm, const double *x, const double *y,
-                         const double *z, const double *h, const uint32_t *key,
-                         const int32_t *run_p, int nr, const GridDesc *grid,
-                         double4 *posh64, float4 *posh32, uint32_t *cellc, int16_t *runid,
-                         uint32_t *skey, int32_t *perm_out, const double *m, void *rec_d,
-                         int32_t f32) {
-    int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (p >= n) return;
-    int32_t o = perm[p];
-    double xo = x[o], yo = y[o], zo = z[o], ho = h[o];
-    int r = nr > 1 ? run_of(run_p, nr, p) : 0;
-    GridDesc g = grid[r];
+    perm[q] = o;
+    octant[q] = oct;
+    const double xo = x[o], yo = y[o], zo = z[o], ho = h[o];
+    const int r = nr > 1 ? run_of(run_p, nr, q) : 0;
+    const GridDesc g = grid[r];
     int cx, cy, cz;
     cell_of(g, xo, yo, zo, cx, cy, cz);
-    posh64[p] = make_double4(xo, yo, zo, ho);
-    double dx = (xo - g.ox) - (double)cx * g.L;
-    double dy = (yo - g.oy) - (double)cy * g.L;
-    double dz = (zo - g.oz) - (double)cz * g.L;
-    posh32[p] = make_float4((float)dx, (float)dy, (float)dz, (float)ho);
+    posh64[q] = make_double4(xo, yo, zo, ho);
+    const double dx = (xo - g.ox) - (double)cx * g.L;
+    const double dy = (yo - g.oy) - (double)cy * g.L;
+    const double dz = (zo - g.oz) - (double)cz * g.L;
+    posh32[q] = make_float4((float)dx, (float)dy, (float)dz, (float)ho);
     if (m) {  // density-pass record (p, m) of the sorted particle
         if (f32)
-            ((float4 *)rec_d)[p] = make_float4((float)dx, (float)dy, (float)dz, (float)m[o]);
+            ((float4 *)rec_d)[q] = make_float4((float)dx, (float)dy, (float)dz, (float)m[o]);
         else
-            ((double4 *)rec_d)[p] = make_double4(xo, yo, zo, m[o]);
+            ((double4 *)rec_d)[q] = make_double4(xo, yo, zo, m[o]);
     }
-    cellc[p] = (uint32_t)cx | ((uint32_t)cy << 10) | ((uint32_t)cz << 20);
-    runid[p] = (int16_t)r;
-    skey[p] = key[o];
-    if (perm_out) perm_out[p] = o;
+    cellc[q] = (uint32_t)cx | ((uint32_t)cy << 10) | ((uint32_t)cz << 20);
+    runid[q] = (int16_t)r;
+    skey[q] = ko;
+    if (perm_out) perm_out[q] = o;
 }
 
 // ------------------------------------------------------ pair-set builder
@@ -637,7 +644,7 @@ sph_status launch_build_cells(Ctx *ctx, int64_t n, double *x, double *y, double 
     if (!ex) ex = &none;
     const int tb = 256;
     const int nb = (int)((n + tb - 1) / tb);
-    hipLaunchKernelGGL(k_bbox, dim3(kBBoxBlocks, nr), dim3(256), 0, s, x, y, z, h, ctx->run_p,
+    hipLaunchKernelGGL(k_bbox, dim3(kBBoxBlocks, nr), dim3(kBBoxThreads), 0, s, x, y, z, h, ctx->run_p,
                        ctx->bbox_part, ctx->cell_count, ctx->total_keys, ex->dt, ex->vx, ex->vy,
                        ex->vz, ex->fixed);
     hipLaunchKernelGGL(k_grid, dim3(1), dim3(256), 0, s, ctx->bbox_part, ctx->run_p, nr, cell_min,
@@ -649,11 +656,10 @@ sph_status launch_build_cells(Ctx *ctx, int64_t n, double *x, double *y, double 
     if (st != SPH_OK) return st;
     hipLaunchKernelGGL(k_scatter, dim3(nb), dim3(tb), 0, s, n, ctx->key, ctx->slot,
                        ctx->cell_start, ctx->total_keys, ctx->ptmp);
-    hipLaunchKernelGGL(k_cellrank, dim3(nb), dim3(tb), 0, s, n, ctx->ptmp, ctx->key,
-                       ctx->cell_start, ctx->cell_count, ctx->total_keys, ctx->perm, ctx->octant);
-    hipLaunchKernelGGL(k_gather, dim3(nb), dim3(tb), 0, s, n, ctx->perm, x, y, z, h, ctx->key,
-                       ctx->run_p, nr, ctx->grid, ctx->posh64, ctx->posh32, ctx->cellc,
-                       ctx->runid, ctx->skey, perm_out, ex->m, ctx->rec_d, ex->f32);
+    hipLaunchKernelGGL(k_place, dim3(nb), dim3(tb), 0, s, n, ctx->ptmp, ctx->key,
+                       ctx->cell_start, ctx->cell_count, ctx->total_keys, ctx->perm, ctx->octant,
+                       x, y, z, h, ctx->run_p, nr, ctx->grid, ctx->posh64, ctx->posh32,
+                       ctx->cellc, ctx->runid, ctx->skey, perm_out, ex->m, ctx->rec_d, ex->f32);
     const int64_t per = ctx->build_range;
     int64_t wgs = (n + per - 1) / per;
     if (wgs > 65536) wgs = 65536;

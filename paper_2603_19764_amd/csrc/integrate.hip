@@ -147,6 +147,8 @@ sph_status launch_kick_drift(Ctx *ctx, int32_t phase, int64_t n, const double *d
 // One minimum per run: blockIdx.y is the run, whose particles are the
 // contiguous range [run_p[r], run_p[r+1]) of the sorted order (the whole
 // range [0, n) when run_p is null).
+constexpr int kDtUnroll = 4;
+
 __global__ void k_dt_reduce(int64_t n, const int32_t *__restrict__ run_p,
                             const double *__restrict__ dtc, const int32_t *__restrict__ fixed,
                             unsigned long long *bits_all) {
@@ -154,13 +156,23 @@ __global__ void k_dt_reduce(int64_t n, const int32_t *__restrict__ run_p,
     const int64_t a = run_p ? run_p[r] : 0, b = run_p ? run_p[r + 1] : n;
     unsigned long long *bits = bits_all + r;
     unsigned long long best = 0x7ff0000000000000ull;
-    for (int64_t i = a + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < b;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        if (fixed && fixed[i]) continue;
-        const double d = dtc[i];
-        if (d > 0.0) {
-            const unsigned long long b = (unsigned long long)__double_as_longlong(d);
-            best = b < best ? b : best;
+    // kDtUnroll independent loads in flight per thread
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i0 = a + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i0 < b;
+         i0 += kDtUnroll * stride) {
+        double d[kDtUnroll];
+#pragma unroll
+        for (int u = 0; u < kDtUnroll; ++u) {
+            const int64_t i = i0 + u * stride;
+            const bool ok = i < b && !(fixed && fixed[i]);
+            d[u] = ok ? dtc[i] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < kDtUnroll; ++u) {
+            if (d[u] > 0.0) {
+                const unsigned long long v = (unsigned long long)__double_as_longlong(d[u]);
+                best = v < best ? v : best;
+            }
         }
     }
     for (int o = 32; o > 0; o >>= 1) {
@@ -190,9 +202,9 @@ sph_status launch_dt_reduce(Ctx *ctx, int64_t n, const double *dtc, const int32_
                             const int32_t *run_p) {
     if (nr < 1 || nr > ctx->max_runs || (nr > 1 && !run_p)) return SPH_EINVAL;
     if (n > 0) {
-        // about 256 blocks in all, at least one per run
-        int nb = (int)((n / nr + 1023) / 1024);
-        const int cap_b = 256 / nr > 1 ? 256 / nr : 1;
+        // about 64 blocks in all (one atomic each), at least one per run
+        int nb = (int)((n / nr + 1024 * kDtUnroll - 1) / (1024 * kDtUnroll));
+        const int cap_b = 64 / nr > 1 ? 64 / nr : 1;
         nb = nb < 1 ? 1 : (nb > cap_b ? cap_b : nb);
         hipLaunchKernelGGL(k_dt_reduce, dim3(nb, nr), dim3(1024), 0, s, n, nr > 1 ? run_p : nullptr,
                            dtc, fixed, bits);

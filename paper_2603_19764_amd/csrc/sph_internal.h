@@ -111,7 +111,10 @@ struct Ctx {
     char err[512] = {0};
 };
 
-constexpr int kBBoxBlocks = 256;
+// Bounding-box partials: blocks per run (enough waves to cover the loads'
+// latency on every SIMD) and threads per block.
+constexpr int kBBoxBlocks = 1024;
+constexpr int kBBoxThreads = 256;
 constexpr int kScanBlocks = 1024;
 constexpr int kMaxMaterials = 16;
 

@@ -11,6 +11,17 @@ def test_choose_picks_fastest_and_keeps_first_on_ties():
     assert best == 8 and times == t
 
 
+def test_choose_keeps_earlier_candidate_within_margin():
+    # 8 is 2% faster than 4: within the 3% margin, 4 stays; 16 is 5% faster
+    t = {4: 1.00, 8: 0.98, 16: 1.01}
+    assert autotune.choose((4, 8, 16), t.__getitem__)[0] == 4
+    t = {4: 1.00, 8: 0.98, 16: 0.95}
+    assert autotune.choose((4, 8, 16), t.__getitem__)[0] == 16
+    assert autotune.choose((4, 8, 16), t.__getitem__, margin=0.0)[0] == 16
+    t = {4: 1.00, 8: 0.98}
+    assert autotune.choose((4, 8), t.__getitem__, margin=0.0)[0] == 8
+
+
 def test_size_bucket_groups_powers_of_two():
     assert autotune.size_bucket(1) == 0
     assert autotune.size_bucket(226722) == autotune.size_bucket(200000) == 17
