@@ -419,6 +419,7 @@ __global__ void k_place(int64_t n, const int32_t *__restrict__ arrived,
 // test per lane, a ballot, and the hits are appended to i's list in
 // candidate order at offsets from mbcnt.  The lists are deterministic.
 constexpr int kTileMax = 256;
+constexpr int kFillChunks = 2;  // raw-candidate chunks whose loads overlap
 constexpr int kIBatch = 64;
 constexpr double kCullMargin = 1.0 + 0x1p-40;
 
@@ -517,37 +518,75 @@ __global__ __launch_bounds__(64) void k_build_pairs(
             for (int r0 = 0; r0 < T || fill > 0;) {
                 // ---- fill: cull raw candidates into the tile
                 __syncthreads();
-                for (; r0 < T && fill <= kTileMax - kWave; r0 += kWave) {
-                    const int gidx = r0 + lane;
-                    bool keep = false;
-                    double4 c = make_double4(0.0, 0.0, 0.0, 0.0);
-                    uint32_t code = 0;
-                    if (gidx < T) {
-                        int lo = 0, hi = 27;
-                        while (hi - lo > 1) {
-                            const int mid = (lo + hi) >> 1;
-                            if (st_off[mid] <= gidx) lo = mid; else hi = mid;
+                for (; r0 < T && fill <= kTileMax - kWave;) {
+                    // up to kFillChunks chunks of 64 raw candidates at once:
+                    // their searches and loads overlap, then they are
+                    // appended in order (as many as the tile has room for)
+                    int nch = (kTileMax - fill) / kWave;
+                    const int left = (T - r0 + kWave - 1) / kWave;
+                    nch = nch < left ? nch : left;
+                    nch = nch < kFillChunks ? nch : kFillChunks;
+                    int g[kFillChunks], lo[kFillChunks], hi[kFillChunks];
+#pragma unroll
+                    for (int u = 0; u < kFillChunks; ++u) {
+                        g[u] = r0 + u * kWave + lane;
+                        lo[u] = 0;
+                        hi[u] = 27;
+                    }
+                    // stencil cell of each raw candidate: largest lo with
+                    // st_off[lo] <= g (five halvings cover 27 cells; once
+                    // hi - lo = 1, mid = lo and nothing changes)
+#pragma unroll
+                    for (int step = 0; step < 5; ++step) {
+#pragma unroll
+                        for (int u = 0; u < kFillChunks; ++u) {
+                            const int mid = (lo[u] + hi[u]) >> 1;
+                            const bool le = st_off[mid] <= g[u];
+                            lo[u] = le ? mid : lo[u];
+                            hi[u] = le ? hi[u] : mid;
                         }
-                        const int j = st_start[lo] + (gidx - st_off[lo]);
-                        c = posh64[j];
-                        const double H = 2.0 * c.w;
-                        c.w = __dmul_rn(H, H);
-                        code = (uint32_t)j | ((uint32_t)lo << kCodeShift);
-                        const double ex = fmax(fmax(lo0 - c.x, c.x - hi0), 0.0);
-                        const double ey = fmax(fmax(lo1 - c.y, c.y - hi1), 0.0);
-                        const double ez = fmax(fmax(lo2 - c.z, c.z - hi2), 0.0);
-                        const double d2 = (ex * ex + ey * ey) + ez * ez;
-                        keep = !(d2 >= fmax(hm, c.w) * kCullMargin);
                     }
-                    const uint64_t m = wave_ballot(keep);
-                    if (keep) {
-                        const int s = fill + (int)__builtin_amdgcn_mbcnt_hi(
-                                                 (uint32_t)(m >> 32),
-                                                 __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-                        tpos[s] = c;
-                        tj[s] = code;
+                    double4 c[kFillChunks];
+                    uint32_t code[kFillChunks];
+                    bool keep[kFillChunks];
+#pragma unroll
+                    for (int u = 0; u < kFillChunks; ++u) {
+                        keep[u] = false;
+                        c[u] = make_double4(0.0, 0.0, 0.0, 0.0);
+                        code[u] = 0;
+                        if (u < nch && g[u] < T) {
+                            const int j = st_start[lo[u]] + (g[u] - st_off[lo[u]]);
+                            c[u] = posh64[j];
+                            code[u] = (uint32_t)j | ((uint32_t)lo[u] << kCodeShift);
+                        }
                     }
-                    fill += __popcll(m);
+#pragma unroll
+                    for (int u = 0; u < kFillChunks; ++u) {
+                        if (u < nch && g[u] < T) {
+                            const double H = 2.0 * c[u].w;
+                            c[u].w = __dmul_rn(H, H);
+                            const double ex = fmax(fmax(lo0 - c[u].x, c[u].x - hi0), 0.0);
+                            const double ey = fmax(fmax(lo1 - c[u].y, c[u].y - hi1), 0.0);
+                            const double ez = fmax(fmax(lo2 - c[u].z, c[u].z - hi2), 0.0);
+                            const double d2 = (ex * ex + ey * ey) + ez * ez;
+                            keep[u] = !(d2 >= fmax(hm, c[u].w) * kCullMargin);
+                        }
+                    }
+#pragma unroll
+                    for (int u = 0; u < kFillChunks; ++u) {
+                        if (u < nch) {
+                            const uint64_t m = wave_ballot(keep[u]);
+                            if (keep[u]) {
+                                const int s = fill + (int)__builtin_amdgcn_mbcnt_hi(
+                                                         (uint32_t)(m >> 32),
+                                                         __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+                                tpos[s] = c[u];
+                                tj[s] = code[u];
+                            }
+                            fill += __popcll(m);
+                        }
+                    }
+                    r0 += nch * kWave;
                 }
                 __syncthreads();
                 // full columns only while raw candidates remain; the ragged

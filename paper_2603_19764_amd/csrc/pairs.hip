@@ -457,67 +457,81 @@ __global__ __launch_bounds__(kBlock) void k_grad_forces(
         const int c = ncount[i];
         const uint32_t *row = nbr + i * (int64_t)K;
         // Software pipeline (see k_density): entry two ahead, record one
-        // ahead, unconditional loads.
-        uint32_t e = row[lg < K ? lg : K - 1];
-        e = lg < c ? e : (uint32_t)i;
-        uint32_t en = row[lg + L < K ? lg + L : K - 1];
-        R4 pj, vj, Aj, Bj, Hj;
+        // ahead, unconditional loads; two record sets take turns, so no
+        // copies between iterations.
+        auto body = [&](uint32_t e, const R4 &pj, const R4 &vj, const R4 &Aj, const R4 &Bj,
+                        const R4 &Hj) {
+                R dx, dy, dz;
+                separation<F32>(pi, pj, e, shs, L32, dx, dy, dz);
+                const R r2 = dx * dx + dy * dy + dz * dz;
+                const R r = root(r2);
+                R ti = (R)1 - r * pi.w, tj = (R)1 - r * pj.w;
+                ti = ti > (R)0 ? ti : (R)0;
+                tj = tj > (R)0 ? tj : (R)0;
+                const R ti3 = ti * ti * ti, tj3 = tj * tj * tj;
+                const R mti = vj.w * ti3;
+                const R ux = vi.x - vj.x, uy = vi.y - vj.y, uz = vi.z - vj.z;
+                // gradient sums
+                const R nw = mti * Gi + tj3 * Hj.x;
+                const R wx = nw * dx, wy = nw * dy, wz = nw * dz;
+                c_xx += wx * dx; c_yy += wy * dy; c_zz += wz * dz;
+                c_xy += wx * dy; c_xz += wx * dz; c_yz += wy * dz;
+                f[0] += ux * wx; f[1] += ux * wy; f[2] += ux * wz;
+                f[3] += uy * wx; f[4] += uy * wy; f[5] += uy * wz;
+                f[6] += uz * wx; f[7] += uz * wy; f[8] += uz * wz;
+                // forces
+                const R yix = Ai.x * dx + Ai.w * dy + bix * dz;
+                const R yiy = Ai.w * dx + Ai.y * dy + biy * dz;
+                const R yiz = bix * dx + biy * dy + Ai.z * dz;
+                const R yjx = Aj.x * dx + Aj.w * dy + Bj.x * dz;
+                const R yjy = Aj.w * dx + Aj.y * dy + Bj.y * dz;
+                const R yjz = Bj.x * dx + Bj.y * dy + Aj.z * dz;
+                acx += mti * yix; acx += tj3 * yjx;
+                acy += mti * yiy; acy += tj3 * yjy;
+                acz += mti * yiz; acz += tj3 * yjz;
+                du -= mti * (ux * yix + uy * yiy + uz * yiz);
+                const R vr = ux * dx + uy * dy + uz * dz;
+                if (vr < (R)0) {
+                    const R hb = hi2 + Hj.z;
+                    const R D = r2 + reps * hb * hb;
+                    const R rb = ri2 + Bj.z;
+                    const R inv = quot((R)1, D * rb);
+                    const R mu = hb * vr * rb * inv;
+                    const R Pi = mu * (rbe * mu - ral * (ci2 + Bj.w)) * (D * inv);
+                    const R sv = (mti * Xi + tj3 * Hj.y) * Pi;  // m_j Pi mean K
+                    acx -= sv * dx;
+                    acy -= sv * dy;
+                    acz -= sv * dz;
+                    du += (R)0.5 * sv * vr;
+                    mumax = mumax > -mu ? mumax : -mu;
+                }
+        };
+        auto entry = [&](int k) -> uint32_t {
+            const uint32_t v = row[k < K ? k : K - 1];
+            return k < c ? v : (uint32_t)i;
+        };
+        uint32_t e0 = entry(lg), e1 = entry(lg + L);
+        R4 P0, V0, A0, B0, H0, P1, V1, A1, B1, H1;
         {
-            const R4 *rj = rec + kRecBoth * (int64_t)(e & kIdxMask);
-            pj = rj[0]; vj = rj[1]; Aj = rj[2]; Bj = rj[3]; Hj = rj[4];
+            const R4 *rj = rec + kRecBoth * (int64_t)(e0 & kIdxMask);
+            P0 = rj[0]; V0 = rj[1]; A0 = rj[2]; B0 = rj[3]; H0 = rj[4];
         }
-        for (int k = lg; k < c; k += L) {
-            const uint32_t enn = row[k + 2 * L < K ? k + 2 * L : K - 1];
-            const uint32_t e_next = k + L < c ? en : (uint32_t)i;
-            const R4 *rn = rec + kRecBoth * (int64_t)(e_next & kIdxMask);
-            const R4 pn = rn[0], vn = rn[1], An = rn[2], Bn = rn[3], Hn = rn[4];
-            R dx, dy, dz;
-            separation<F32>(pi, pj, e, shs, L32, dx, dy, dz);
-            const R r2 = dx * dx + dy * dy + dz * dz;
-            const R r = root(r2);
-            R ti = (R)1 - r * pi.w, tj = (R)1 - r * pj.w;
-            ti = ti > (R)0 ? ti : (R)0;
-            tj = tj > (R)0 ? tj : (R)0;
-            const R ti3 = ti * ti * ti, tj3 = tj * tj * tj;
-            const R mti = vj.w * ti3;
-            const R ux = vi.x - vj.x, uy = vi.y - vj.y, uz = vi.z - vj.z;
-            // gradient sums
-            const R nw = mti * Gi + tj3 * Hj.x;
-            const R wx = nw * dx, wy = nw * dy, wz = nw * dz;
-            c_xx += wx * dx; c_yy += wy * dy; c_zz += wz * dz;
-            c_xy += wx * dy; c_xz += wx * dz; c_yz += wy * dz;
-            f[0] += ux * wx; f[1] += ux * wy; f[2] += ux * wz;
-            f[3] += uy * wx; f[4] += uy * wy; f[5] += uy * wz;
-            f[6] += uz * wx; f[7] += uz * wy; f[8] += uz * wz;
-            // forces
-            const R yix = Ai.x * dx + Ai.w * dy + bix * dz;
-            const R yiy = Ai.w * dx + Ai.y * dy + biy * dz;
-            const R yiz = bix * dx + biy * dy + Ai.z * dz;
-            const R yjx = Aj.x * dx + Aj.w * dy + Bj.x * dz;
-            const R yjy = Aj.w * dx + Aj.y * dy + Bj.y * dz;
-            const R yjz = Bj.x * dx + Bj.y * dy + Aj.z * dz;
-            acx += mti * yix; acx += tj3 * yjx;
-            acy += mti * yiy; acy += tj3 * yjy;
-            acz += mti * yiz; acz += tj3 * yjz;
-            du -= mti * (ux * yix + uy * yiy + uz * yiz);
-            const R vr = ux * dx + uy * dy + uz * dz;
-            if (vr < (R)0) {
-                const R hb = hi2 + Hj.z;
-                const R D = r2 + reps * hb * hb;
-                const R rb = ri2 + Bj.z;
-                const R inv = quot((R)1, D * rb);
-                const R mu = hb * vr * rb * inv;
-                const R Pi = mu * (rbe * mu - ral * (ci2 + Bj.w)) * (D * inv);
-                const R sv = (mti * Xi + tj3 * Hj.y) * Pi;  // m_j Pi mean K
-                acx -= sv * dx;
-                acy -= sv * dy;
-                acz -= sv * dz;
-                du += (R)0.5 * sv * vr;
-                mumax = mumax > -mu ? mumax : -mu;
+        for (int k = lg; k < c; k += 2 * L) {
+            const uint32_t e2 = entry(k + 2 * L);
+            {
+                const R4 *rj = rec + kRecBoth * (int64_t)(e1 & kIdxMask);
+                P1 = rj[0]; V1 = rj[1]; A1 = rj[2]; B1 = rj[3]; H1 = rj[4];
             }
-            e = e_next;
-            en = enn;
-            pj = pn; vj = vn; Aj = An; Bj = Bn; Hj = Hn;
+            body(e0, P0, V0, A0, B0, H0);
+            if (k + L >= c) break;
+            const uint32_t e3 = entry(k + 3 * L);
+            {
+                const R4 *rj = rec + kRecBoth * (int64_t)(e2 & kIdxMask);
+                P0 = rj[0]; V0 = rj[1]; A0 = rj[2]; B0 = rj[3]; H0 = rj[4];
+            }
+            body(e1, P1, V1, A1, B1, H1);
+            e0 = e2;
+            e1 = e3;
         }
     }
     c_xx = group_sum<L>(c_xx); c_yy = group_sum<L>(c_yy); c_zz = group_sum<L>(c_zz);
