@@ -19,7 +19,7 @@ from . import sph
 
 LANES = (4, 8, 16)
 CELL_SCALES = (1000, 1150, 1300)   # permille of 2 h_max
-BUILD_RANGES = (32, 64, 96, 128)   # sorted particles per pair-list build work-group
+BUILD_RANGES = (64, 32, 96, 128)   # sorted particles per pair-list build work-group (default first)
 
 # knob -> (timer whose per-launch time decides it, candidate values)
 PLAN = (

@@ -128,22 +128,30 @@ __global__ void k_bbox(double *x, double *y, double *z, const double *h, const i
     const double dt = dtp ? dtp[r] : 0.0;  // one time step per run
     double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
     double hm = 0.0;
-    for (int64_t k = a + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < b;
-         k += (int64_t)gridDim.x * blockDim.x) {
-        double v[3] = {x[k], y[k], z[k]};
-        if (dtp && !(fixed && fixed[k])) {
-            v[0] += dt * vx[k];
-            v[1] += dt * vy[k];
-            v[2] += dt * vz[k];
-            x[k] = v[0];
-            y[k] = v[1];
-            z[k] = v[2];
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t k0 = a + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k0 < b;
+         k0 += kBBoxUnroll * stride) {
+        // kBBoxUnroll independent elements: their loads are in flight together
+#pragma unroll
+        for (int u = 0; u < kBBoxUnroll; ++u) {
+            const int64_t k = k0 + u * stride;
+            if (k < b) {
+                double v[3] = {x[k], y[k], z[k]};
+                if (dtp && !(fixed && fixed[k])) {
+                    v[0] += dt * vx[k];
+                    v[1] += dt * vy[k];
+                    v[2] += dt * vz[k];
+                    x[k] = v[0];
+                    y[k] = v[1];
+                    z[k] = v[2];
+                }
+                for (int d = 0; d < 3; ++d) {
+                    lo[d] = fmin(lo[d], v[d]);
+                    hi[d] = fmax(hi[d], v[d]);
+                }
+                hm = fmax(hm, h[k]);
+            }
         }
-        for (int d = 0; d < 3; ++d) {
-            lo[d] = fmin(lo[d], v[d]);
-            hi[d] = fmax(hi[d], v[d]);
-        }
-        hm = fmax(hm, h[k]);
     }
     // wave minima/maxima by shuffles, then across the block's waves in LDS
 #pragma unroll
@@ -193,12 +201,14 @@ __device__ static int bits_for(int n) {
 // Per-run grids that fit the cell table.  The block first reduces each
 // run's bounding-box partials in parallel (into the first partial of the
 // run), then one thread sizes the grids.
-__global__ void k_grid(BBox *part, const int32_t *run_p, int nr, double cell_min,
+__global__ void k_grid(BBox *part, int nbb, const int32_t *run_p, int nr, double cell_min,
                        double cell_scale, int64_t max_cells, GridDesc *grid, int32_t *total_keys, int32_t *flags) {
-    __shared__ double sh[7][256];
-    for (int r = 0; r < nr; ++r) {
+    // per run: the nbb block partials reduced by one wave (waves take runs
+    // in turn); the result goes to the run's first partial
+    const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave, nw = blockDim.x / kWave;
+    for (int r = w; r < nr; r += nw) {
         double v[7] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY, 0.0};
-        for (int b = threadIdx.x; b < kBBoxBlocks; b += blockDim.x) {
+        for (int b = lane; b < nbb; b += kWave) {
             const BBox o = part[r * kBBoxBlocks + b];
             for (int d = 0; d < 3; ++d) {
                 v[d] = fmin(v[d], o.lo[d]);
@@ -206,26 +216,24 @@ __global__ void k_grid(BBox *part, const int32_t *run_p, int nr, double cell_min
             }
             v[6] = fmax(v[6], o.hmax);
         }
-        for (int d = 0; d < 7; ++d) sh[d][threadIdx.x] = v[d];
-        __syncthreads();
-        for (int o = blockDim.x / 2; o > 0; o >>= 1) {
-            if (threadIdx.x < (unsigned)o) {
-                for (int d = 0; d < 3; ++d) sh[d][threadIdx.x] = fmin(sh[d][threadIdx.x], sh[d][threadIdx.x + o]);
-                for (int d = 3; d < 7; ++d) sh[d][threadIdx.x] = fmax(sh[d][threadIdx.x], sh[d][threadIdx.x + o]);
-            }
-            __syncthreads();
+#pragma unroll
+        for (int o = kWave / 2; o > 0; o >>= 1) {
+#pragma unroll
+            for (int d = 0; d < 3; ++d) v[d] = fmin(v[d], __shfl_xor(v[d], o));
+#pragma unroll
+            for (int d = 3; d < 7; ++d) v[d] = fmax(v[d], __shfl_xor(v[d], o));
         }
-        if (threadIdx.x == 0) {
+        if (lane == 0) {
             BBox bb;
             for (int d = 0; d < 3; ++d) {
-                bb.lo[d] = sh[d][0];
-                bb.hi[d] = sh[3 + d][0];
+                bb.lo[d] = v[d];
+                bb.hi[d] = v[3 + d];
             }
-            bb.hmax = sh[6][0];
+            bb.hmax = v[6];
             part[r * kBBoxBlocks] = bb;
         }
-        __syncthreads();
     }
+    __syncthreads();
     if (threadIdx.x != 0) return;
     double grow = 1.0;
     for (int attempt = 0; attempt < 200; ++attempt) {
@@ -371,6 +379,12 @@ __global__ void k_place(int64_t n, const int32_t *__restrict__ arrived,
     const int32_t e = arrived[p];
     const int32_t o = e & (int32_t)kIdxMask;
     const uint32_t ko = key[o];
+    // the particle's own data and run do not depend on its rank (a run's
+    // particles take the same index range before and after the sort)
+    const double xo = x[o], yo = y[o], zo = z[o], ho = h[o];
+    const double mo = m ? m[o] : 0.0;
+    const int r = nr > 1 ? run_of(run_p, nr, o) : 0;
+    const GridDesc g = grid[r];
     int64_t q = p;
     uint8_t oct = 0;
     if (*total_keys != 0) {
@@ -382,9 +396,6 @@ __global__ void k_place(int64_t n, const int32_t *__restrict__ arrived,
     }
     perm[q] = o;
     octant[q] = oct;
-    const double xo = x[o], yo = y[o], zo = z[o], ho = h[o];
-    const int r = nr > 1 ? run_of(run_p, nr, q) : 0;
-    const GridDesc g = grid[r];
     int cx, cy, cz;
     cell_of(g, xo, yo, zo, cx, cy, cz);
     posh64[q] = make_double4(xo, yo, zo, ho);
@@ -394,9 +405,9 @@ __global__ void k_place(int64_t n, const int32_t *__restrict__ arrived,
     posh32[q] = make_float4((float)dx, (float)dy, (float)dz, (float)ho);
     if (m) {  // density-pass record (p, m) of the sorted particle
         if (f32)
-            ((float4 *)rec_d)[q] = make_float4((float)dx, (float)dy, (float)dz, (float)m[o]);
+            ((float4 *)rec_d)[q] = make_float4((float)dx, (float)dy, (float)dz, (float)mo);
         else
-            ((double4 *)rec_d)[q] = make_double4(xo, yo, zo, m[o]);
+            ((double4 *)rec_d)[q] = make_double4(xo, yo, zo, mo);
     }
     cellc[q] = (uint32_t)cx | ((uint32_t)cy << 10) | ((uint32_t)cz << 20);
     runid[q] = (int16_t)r;
@@ -683,10 +694,14 @@ sph_status launch_build_cells(Ctx *ctx, int64_t n, double *x, double *y, double 
     if (!ex) ex = &none;
     const int tb = 256;
     const int nb = (int)((n + tb - 1) / tb);
-    hipLaunchKernelGGL(k_bbox, dim3(kBBoxBlocks, nr), dim3(kBBoxThreads), 0, s, x, y, z, h, ctx->run_p,
+    // blocks per run: about kBBoxUnroll elements per thread (a run's average
+    // size), at most kBBoxBlocks
+    int64_t nbb = (n / nr + kBBoxThreads * kBBoxUnroll - 1) / (kBBoxThreads * kBBoxUnroll);
+    nbb = nbb < 1 ? 1 : (nbb > kBBoxBlocks ? kBBoxBlocks : nbb);
+    hipLaunchKernelGGL(k_bbox, dim3((unsigned)nbb, nr), dim3(kBBoxThreads), 0, s, x, y, z, h, ctx->run_p,
                        ctx->bbox_part, ctx->cell_count, ctx->total_keys, ex->dt, ex->vx, ex->vy,
                        ex->vz, ex->fixed);
-    hipLaunchKernelGGL(k_grid, dim3(1), dim3(256), 0, s, ctx->bbox_part, ctx->run_p, nr, cell_min,
+    hipLaunchKernelGGL(k_grid, dim3(1), dim3(1024), 0, s, ctx->bbox_part, (int)nbb, ctx->run_p, nr, cell_min,
                        ctx->cell_scale, ctx->max_cells, ctx->grid, ctx->total_keys, ctx->flags);
     hipLaunchKernelGGL(k_keys, dim3(nb), dim3(tb), 0, s, n, x, y, z, ctx->run_p, nr, ctx->grid,
                        ctx->total_keys, ctx->key, ctx->slot, ctx->cell_count);

@@ -202,9 +202,10 @@ sph_status launch_dt_reduce(Ctx *ctx, int64_t n, const double *dtc, const int32_
                             const int32_t *run_p) {
     if (nr < 1 || nr > ctx->max_runs || (nr > 1 && !run_p)) return SPH_EINVAL;
     if (n > 0) {
-        // about 64 blocks in all (one atomic each), at least one per run
+        // about kDtUnroll elements per thread, at most 64 blocks (one atomic
+        // each) per run
         int nb = (int)((n / nr + 1024 * kDtUnroll - 1) / (1024 * kDtUnroll));
-        const int cap_b = 64 / nr > 1 ? 64 / nr : 1;
+        const int cap_b = 64;
         nb = nb < 1 ? 1 : (nb > cap_b ? cap_b : nb);
         hipLaunchKernelGGL(k_dt_reduce, dim3(nb, nr), dim3(1024), 0, s, n, nr > 1 ? run_p : nullptr,
                            dtc, fixed, bits);

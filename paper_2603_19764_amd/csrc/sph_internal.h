@@ -111,10 +111,11 @@ struct Ctx {
     char err[512] = {0};
 };
 
-// Bounding-box partials: blocks per run (enough waves to cover the loads'
-// latency on every SIMD) and threads per block.
+// Bounding-box partials: at most kBBoxBlocks blocks per run (enough waves to
+// cover the loads' latency on every SIMD), threads per block.
 constexpr int kBBoxBlocks = 1024;
 constexpr int kBBoxThreads = 256;
+constexpr int kBBoxUnroll = 2;  // elements per thread in flight together
 constexpr int kScanBlocks = 1024;
 constexpr int kMaxMaterials = 16;
 
