@@ -28,6 +28,7 @@ constexpr int kCand = 1024;   // candidates of one level (>= 1) of one group wal
 constexpr int kIL = 128;      // accepted monopoles held before evaluation
 constexpr int kStage = 64;    // near-field source particles held before evaluation
 constexpr int kSlots = 8;     // targets per lane per pass
+constexpr int kEvalStep = 2;  // list entries evaluated together
 
 struct GravLevels {
     int32_t nlev;                      // levels 0 .. nlev-1
@@ -267,38 +268,49 @@ __global__ __launch_bounds__(64) void k_grav_walk(
                 }
             }
             int n_il = 0, n_st = 0;
-            auto flush_il = [&]() {
-                __syncthreads();
-                for (int e = 0; e < n_il; ++e) {
-                    const float4 q = il[e];
+            // Entries are evaluated kEvalStep at a time: per slot their
+            // contributions are independent and are added in list order.
+            auto eval = [&](const float4 *lst, const int32_t *lj, int cnt) {
+                int e = 0;
+                for (; e + kEvalStep <= cnt; e += kEvalStep) {
+                    float4 q[kEvalStep];
+                    int j[kEvalStep];
+#pragma unroll
+                    for (int u = 0; u < kEvalStep; ++u) {
+                        q[u] = lst[e + u];
+                        j[u] = lj ? lj[e + u] : -1;
+                    }
 #pragma unroll
                     for (int s = 0; s < kSlots; ++s) {
                         if (s >= ns) break;
-                        const float dx = q.x - A.tx[s], dy = q.y - A.ty[s], dz = q.z - A.tz[s];
-                        const float r2 = dx * dx + dy * dy + dz * dz + e2;
-                        const float ri = __frsqrt_rn(r2);
-                        const float mr = q.w * ri;
-                        const float mr3 = mr * ri * ri;
-                        A.ax[s] += mr3 * dx;
-                        A.ay[s] += mr3 * dy;
-                        A.az[s] += mr3 * dz;
-                        A.ph[s] += mr;
+                        float dx[kEvalStep], dy[kEvalStep], dz[kEvalStep], mr[kEvalStep],
+                            m3[kEvalStep];
+#pragma unroll
+                        for (int u = 0; u < kEvalStep; ++u) {
+                            dx[u] = q[u].x - A.tx[s];
+                            dy[u] = q[u].y - A.ty[s];
+                            dz[u] = q[u].z - A.tz[s];
+                            const float ri = __frsqrt_rn(dx[u] * dx[u] + dy[u] * dy[u] + dz[u] * dz[u] + e2);
+                            mr[u] = (j[u] == A.ti[s]) ? 0.f : q[u].w * ri;
+                            m3[u] = mr[u] * ri * ri;
+                        }
+#pragma unroll
+                        for (int u = 0; u < kEvalStep; ++u) {
+                            A.ax[s] += m3[u] * dx[u];
+                            A.ay[s] += m3[u] * dy[u];
+                            A.az[s] += m3[u] * dz[u];
+                            A.ph[s] += mr[u];
+                        }
                     }
                 }
-                n_il = 0;
-                __syncthreads();
-            };
-            auto flush_st = [&]() {
-                __syncthreads();
-                for (int e = 0; e < n_st; ++e) {
-                    const float4 q = stg[e];
-                    const int j = stg_j[e];
+                for (; e < cnt; ++e) {
+                    const float4 q = lst[e];
+                    const int j = lj ? lj[e] : -1;
 #pragma unroll
                     for (int s = 0; s < kSlots; ++s) {
                         if (s >= ns) break;
                         const float dx = q.x - A.tx[s], dy = q.y - A.ty[s], dz = q.z - A.tz[s];
-                        const float r2 = dx * dx + dy * dy + dz * dz + e2;
-                        const float ri = __frsqrt_rn(r2);
+                        const float ri = __frsqrt_rn(dx * dx + dy * dy + dz * dz + e2);
                         const float mr = (j == A.ti[s]) ? 0.f : q.w * ri;
                         const float mr3 = mr * ri * ri;
                         A.ax[s] += mr3 * dx;
@@ -307,6 +319,16 @@ __global__ __launch_bounds__(64) void k_grav_walk(
                         A.ph[s] += mr;
                     }
                 }
+            };
+            auto flush_il = [&]() {
+                __syncthreads();
+                eval(il, nullptr, n_il);
+                n_il = 0;
+                __syncthreads();
+            };
+            auto flush_st = [&]() {
+                __syncthreads();
+                eval(stg, stg_j, n_st);
                 n_st = 0;
                 __syncthreads();
             };
