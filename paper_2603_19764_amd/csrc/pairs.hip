@@ -100,6 +100,8 @@ __global__ void k_pack_density(int64_t n, const double4 *p64, const float4 *p32,
     rec[i] = {x, y, z, (R)m[i]};
 }
 
+constexpr int kDensStep = 2;  // pairs per lane evaluated per iteration
+
 template <int L, bool F32>
 __global__ __launch_bounds__(kBlock) void k_density(
     int64_t n, const double4 *__restrict__ posh64, const int16_t *__restrict__ runid,
@@ -127,18 +129,13 @@ __global__ __launch_bounds__(kBlock) void k_density(
         if constexpr (F32) L32 = grid[runid[i]].L32;
         const int c = ncount[i];
         const uint32_t *row = nbr + i * (int64_t)K;
-        // Software pipeline: the entry two ahead and the record one ahead are
-        // in flight while a pair is evaluated.  Loads are unconditional (the
-        // entry index is clamped into the row, a record index past the list
-        // is replaced by i), so no branch hides them from the wait counters.
-        uint32_t e = row[lg < K ? lg : K - 1];
-        e = lg < c ? e : (uint32_t)i;
-        uint32_t en = row[lg + L < K ? lg + L : K - 1];
-        R4 pj = rec[e & kIdxMask];
-        for (int k = lg; k < c; k += L) {
-            const uint32_t enn = row[k + 2 * L < K ? k + 2 * L : K - 1];
-            const uint32_t e_next = k + L < c ? en : (uint32_t)i;
-            const R4 pn = rec[e_next & kIdxMask];
+        // An iteration takes kDensStep pairs (k, k + L, ...): their records
+        // are loaded together and the next iteration's entries are loaded
+        // while they are evaluated.  Entry indices are clamped into the row;
+        // a pair past the list is i itself, whose entry has no density flag
+        // and adds exact zeros, so every pair of an iteration is evaluated
+        // and no branch separates the record loads (their latencies overlap).
+        auto body = [&](uint32_t e, const R4 &pj) {
             R dx, dy, dz;
             separation<F32>(pi, pj, e, shs, L32, dx, dy, dz);
             const R q = root(dx * dx + dy * dy + dz * dz) * Hinv;
@@ -150,9 +147,25 @@ __global__ __launch_bounds__(kBlock) void k_density(
             const R dh = mj * (t3 * ((R)3 + q * ((R)9 - (R)32 * q)));
             sw += (double)w;
             sd += (double)dh;
-            e = e_next;
-            en = enn;
-            pj = pn;
+        };
+        auto entry = [&](int k) -> uint32_t {
+            const uint32_t v = row[k < K ? k : K - 1];
+            return k < c ? v : (uint32_t)i;
+        };
+        uint32_t e[kDensStep];
+#pragma unroll
+        for (int u = 0; u < kDensStep; ++u) e[u] = entry(lg + u * L);
+        for (int k = lg; k < c; k += kDensStep * L) {
+            R4 P[kDensStep];
+#pragma unroll
+            for (int u = 0; u < kDensStep; ++u) P[u] = rec[e[u] & kIdxMask];
+            uint32_t en[kDensStep];
+#pragma unroll
+            for (int u = 0; u < kDensStep; ++u) en[u] = entry(k + (kDensStep + u) * L);
+#pragma unroll
+            for (int u = 0; u < kDensStep; ++u) body(e[u], P[u]);
+#pragma unroll
+            for (int u = 0; u < kDensStep; ++u) e[u] = en[u];
         }
     }
     sw = group_sum<L>(sw);
