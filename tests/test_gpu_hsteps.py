@@ -2,7 +2,8 @@
 the oracle's integrator: one rung reproduces the shared step; two bodies on
 different rungs, one body whose particles spread over several rungs, and a
 batch of runs with their own clocks follow the oracle substep by substep;
-the acceleration criterion caps the shared step as in the oracle."""
+the acceleration criterion caps the shared step as in the oracle; the FP32
+pair sums take the same rungs as the oracle."""
 import numpy as np
 import pytest
 
@@ -13,6 +14,7 @@ from tests.gpu_harness import norm_err, say
 pytestmark = pytest.mark.gpu
 
 FP64 = 0
+FP32 = 1
 KEYS = ("x", "y", "z", "m", "h", "mat", "vx", "vy", "vz", "u", "S", "fixed")
 
 
@@ -202,3 +204,24 @@ def test_gravity_reaches_only_the_particles_whose_step_ends():
         assert np.array_equal(seen[k][:, na:], seen[0][:, na:]), k
         assert not np.array_equal(seen[k][:, :na], seen[k - 1][:, :na]), k
     assert not np.array_equal(seen[4][:, na:], seen[0][:, na:])
+
+
+def test_two_bodies_fp32_match_oracle():
+    """The FP32 cell-relative pair sums with individual steps: the same rungs,
+    elapsed ticks and clock as the FP64 oracle, the state within the FP32
+    tolerance (the bodies' own steps sit 11% away from a rung boundary, so
+    FP32 rounding of the CFL step cannot move a particle to another rung)."""
+    say("[two bodies, fp32]")
+    wb, mats = _block(5, 1.0)
+    wa, _ = _block(5, 0.25, offset=-50.0)
+    wa["vy"][:] = 0.05 * np.cos(4.0 * wa["x"])
+    wb["vy"][:] = 0.05 * np.cos(wb["x"])
+    w = _join(wa, wb)
+    prm = inputs.default_params(rungs=4)
+    dt0 = 0.9 * _cfl(wb, mats, inputs.default_params())
+    it = _oracle(w, mats, prm, dt0, 6)
+    g = _gpu(w, mats, prm, dt0, 6, prec=FP32)
+    assert np.array_equal(g["step_ticks"], it["dtp"].astype(float))
+    assert np.array_equal(g["elapsed_ticks"], it["el"].astype(float))
+    assert g["clock"][0] == it.ticks
+    _compare(g, it, "two bodies fp32", tol=2e-5)
