@@ -15,6 +15,7 @@
 //   grad_i W = K x_ij,  K = -210/(pi H^5) t^3
 //   dW/dh = -21/(pi H^4) t^3 (3 + 9q - 32 q^2)
 #include "physics.h"
+#include "records.h"
 
 namespace sph {
 
@@ -23,8 +24,7 @@ constexpr int kBlock = 256;
 
 // Record sizes in 16-byte (float) or 32-byte (double) slots.
 constexpr int kRecDensity = 1;    // (p, m)
-constexpr int kRecGrad = 3;       // (p, 1/H) (v, m) (Kn/(Omega rho), -, -, -)
-constexpr int kRecForces = 5;     // (p, 1/H) (v, m) (KnA xx yy zz xy) (KnA xz yz, rho, c) (Kn, h, -, -)
+// gradient, force and fused records: slot counts and the (v, m) slots in records.h
 
 // ---------------------------------------------------------- common helpers
 __device__ __forceinline__ void stencil_offsets(float *sh) {
@@ -210,10 +210,10 @@ __global__ void k_pack_grad(int64_t n, const double4 *p64, const float4 *p32, co
     load_p<F32>(p64, p32, i, x, y, z);
     const double H = 2.0 * p64[i].w;
     const double kn = -210.0 / (kPi * H * H * H * H * H);
-    typename Real<F32>::T4 *r = rec + kRecGrad * i;
+    typename Real<F32>::T4 *r = rec + kRecGradSlots<F32> * i;
     r[0] = {x, y, z, (R)(1.0 / H)};
-    r[1] = {(R)vx[i], (R)vy[i], (R)vz[i], (R)m[i]};
-    r[2] = {(R)(kn / (omega[i] * rho[i])), (R)0, (R)0, (R)0};
+    store_vm<F32>(r + 1, vx[i], vy[i], vz[i], m[i]);
+    r[1 + kVelSlots<F32>] = {(R)(kn / (omega[i] * rho[i])), (R)0, (R)0, (R)0};
 }
 
 // Raw sums per particle (15 rows): C^-1 (xx, yy, zz, xy, xz, yz) and F (row-major 9).
@@ -235,8 +235,9 @@ __global__ __launch_bounds__(kBlock) void k_gradients(
     R c_xx = 0, c_yy = 0, c_zz = 0, c_xy = 0, c_xz = 0, c_yz = 0;
     R f[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     if (active) {
-        const R4 pi = rec[kRecGrad * i], vi = rec[kRecGrad * i + 1];
-        const R ai = rec[kRecGrad * i + 2].x;
+        const R4 pi = rec[kRecGradSlots<F32> * i];
+        const VM<R> vi = load_vm<F32, R>(rec + kRecGradSlots<F32> * i + 1);
+        const R ai = rec[kRecGradSlots<F32> * i + 1 + kVelSlots<F32>].x;
         float L32 = 0.f;
         if constexpr (F32) L32 = grid[runid[i]].L32;
         const int c = ncount[i];
@@ -245,9 +246,10 @@ __global__ __launch_bounds__(kBlock) void k_gradients(
         for (int k = lg; k < c; k += L) {
             const uint32_t e = en;
             en = k + L < c ? row[k + L] : 0u;  // next entry in flight
-            const R4 *rj = rec + kRecGrad * (int64_t)(e & kIdxMask);
-            const R4 pj = rj[0], vj = rj[1];
-            const R aj = rj[2].x;
+            const R4 *rj = rec + kRecGradSlots<F32> * (int64_t)(e & kIdxMask);
+            const R4 pj = rj[0];
+            const VM<R> vj = load_vm<F32, R>(rj + 1);
+            const R aj = rj[1 + kVelSlots<F32>].x;
             R dx, dy, dz;
             separation<F32>(pi, pj, e, shs, L32, dx, dy, dz);
             const R r = root(dx * dx + dy * dy + dz * dz);
@@ -255,8 +257,8 @@ __global__ __launch_bounds__(kBlock) void k_gradients(
             ti = ti > (R)0 ? ti : (R)0;
             tj = tj > (R)0 ? tj : (R)0;
             // -w = -1/2 m_j (K_i/(Om rho)_i + K_j/(Om rho)_j)
-            const R nw = (R)(-0.5) * vj.w * (ai * ti * ti * ti + aj * tj * tj * tj);
-            const R ux = vi.x - vj.x, uy = vi.y - vj.y, uz = vi.z - vj.z;
+            const R nw = (R)(-0.5) * vj.m * (ai * ti * ti * ti + aj * tj * tj * tj);
+            const R ux = (R)(vi.x - vj.x), uy = (R)(vi.y - vj.y), uz = (R)(vi.z - vj.z);
             const R wx = nw * dx, wy = nw * dy, wz = nw * dz;
             c_xx += wx * dx; c_yy += wy * dy; c_zz += wz * dz;
             c_xy += wx * dy; c_xz += wx * dz; c_yz += wy * dz;
@@ -317,12 +319,13 @@ __global__ void k_pack_forces(int64_t n, const double4 *p64, const float4 *p32, 
     const double sxx = S[i], syy = S[n + i], sxy = S[2 * n + i], sxz = S[3 * n + i],
                  syz = S[4 * n + i];
     const double p = P[i];
-    typename Real<F32>::T4 *r = rec + kRecForces * i;
+    typename Real<F32>::T4 *r = rec + kRecForceSlots<F32> * i;
+    constexpr int o = kVelSlots<F32>;
     r[0] = {x, y, z, (R)(1.0 / H)};
-    r[1] = {(R)vx[i], (R)vy[i], (R)vz[i], (R)m[i]};
-    r[2] = {(R)(sc * (sxx - p)), (R)(sc * (syy - p)), (R)(sc * (-sxx - syy - p)), (R)(sc * sxy)};
-    r[3] = {(R)(sc * sxz), (R)(sc * syz), (R)rho[i], (R)cs[i]};
-    r[4] = {(R)kn, (R)h, (R)0, (R)0};
+    store_vm<F32>(r + 1, vx[i], vy[i], vz[i], m[i]);
+    r[1 + o] = {(R)(sc * (sxx - p)), (R)(sc * (syy - p)), (R)(sc * (-sxx - syy - p)), (R)(sc * sxy)};
+    r[2 + o] = {(R)(sc * sxz), (R)(sc * syz), (R)rho[i], (R)cs[i]};
+    r[3 + o] = {(R)kn, (R)h, (R)0, (R)0};
 }
 
 template <int L, bool F32>
@@ -346,10 +349,12 @@ __global__ __launch_bounds__(kBlock) void k_forces(
     R acx = 0, acy = 0, acz = 0, du = 0, mumax = 0;
     R4 Bi = {0, 0, 0, 0}, Hi = {0, 0, 0, 0};
     if (active) {
-        const R4 *ri = rec + kRecForces * i;
-        const R4 pi = ri[0], vi = ri[1], Ai = ri[2];
-        Bi = ri[3];
-        Hi = ri[4];
+        constexpr int o = kVelSlots<F32>;
+        const R4 *ri = rec + kRecForceSlots<F32> * i;
+        const R4 pi = ri[0], Ai = ri[1 + o];
+        const VM<R> vi = load_vm<F32, R>(ri + 1);
+        Bi = ri[2 + o];
+        Hi = ri[3 + o];
         const R ral = (R)al, rbe = (R)be, reps = (R)eps;
         float L32 = 0.f;
         if constexpr (F32) L32 = grid[runid[i]].L32;
@@ -359,8 +364,9 @@ __global__ __launch_bounds__(kBlock) void k_forces(
         for (int k = lg; k < c; k += L) {
             const uint32_t e = en;
             en = k + L < c ? row[k + L] : 0u;  // next entry in flight
-            const R4 *rj = rec + kRecForces * (int64_t)(e & kIdxMask);
-            const R4 pj = rj[0], vj = rj[1], Aj = rj[2], Bj = rj[3], Hj = rj[4];
+            const R4 *rj = rec + kRecForceSlots<F32> * (int64_t)(e & kIdxMask);
+            const R4 pj = rj[0], Aj = rj[1 + o], Bj = rj[2 + o], Hj = rj[3 + o];
+            const VM<R> vj = load_vm<F32, R>(rj + 1);
             R dx, dy, dz;
             separation<F32>(pi, pj, e, shs, L32, dx, dy, dz);
             const R r2 = dx * dx + dy * dy + dz * dz;
@@ -376,11 +382,11 @@ __global__ __launch_bounds__(kBlock) void k_forces(
             const R yjx = Aj.x * dx + Aj.w * dy + Bj.x * dz;
             const R yjy = Aj.w * dx + Aj.y * dy + Bj.y * dz;
             const R yjz = Bj.x * dx + Bj.y * dy + Aj.z * dz;
-            const R mj = vj.w;
+            const R mj = vj.m;
             acx += mj * (ti3 * yix + tj3 * yjx);
             acy += mj * (ti3 * yiy + tj3 * yjy);
             acz += mj * (ti3 * yiz + tj3 * yjz);
-            const R ux = vi.x - vj.x, uy = vi.y - vj.y, uz = vi.z - vj.z;
+            const R ux = (R)(vi.x - vj.x), uy = (R)(vi.y - vj.y), uz = (R)(vi.z - vj.z);
             du -= mj * ti3 * (ux * yix + uy * yiy + uz * yiz);
             const R vr = ux * dx + uy * dy + uz * dz;
             if (vr < (R)0) {
@@ -430,7 +436,6 @@ __global__ __launch_bounds__(kBlock) void k_forces(
 // and the viscosity term takes one reciprocal, of D rho_bar with
 // D = r^2 + eps h_bar^2:  mu = h_bar v.x rho_bar / (D rho_bar),
 // Pi = mu (beta mu - alpha c_bar) D / (D rho_bar).
-constexpr int kRecBoth = 5;
 
 template <int L, bool F32>
 __global__ __launch_bounds__(kBlock) void k_grad_forces(
@@ -455,8 +460,10 @@ __global__ __launch_bounds__(kBlock) void k_grad_forces(
     R acx = 0, acy = 0, acz = 0, du = 0, mumax = 0;
     R hi2 = 0, ci2 = 0;
     if (active) {
-        const R4 *ri = rec + kRecBoth * i;
-        const R4 pi = ri[0], vi = ri[1], A2 = ri[2], B2 = ri[3], H2 = ri[4];
+        constexpr int o = kVelSlots<F32>;
+        const R4 *ri = rec + kRecBothSlots<F32> * i;
+        const R4 pi = ri[0], A2 = ri[1 + o], B2 = ri[2 + o], H2 = ri[3 + o];
+        const VM<R> vi = load_vm<F32, R>(ri + 1);
         const R im = H2.w;
         const R4 Ai = {A2.x * im, A2.y * im, A2.z * im, A2.w * im};
         const R bix = B2.x * im, biy = B2.y * im;
@@ -472,7 +479,7 @@ __global__ __launch_bounds__(kBlock) void k_grad_forces(
         // Software pipeline (see k_density): entry two ahead, record one
         // ahead, unconditional loads; two record sets take turns, so no
         // copies between iterations.
-        auto body = [&](uint32_t e, const R4 &pj, const R4 &vj, const R4 &Aj, const R4 &Bj,
+        auto body = [&](uint32_t e, const R4 &pj, const VM<R> &vj, const R4 &Aj, const R4 &Bj,
                         const R4 &Hj) {
                 R dx, dy, dz;
                 separation<F32>(pi, pj, e, shs, L32, dx, dy, dz);
@@ -482,8 +489,8 @@ __global__ __launch_bounds__(kBlock) void k_grad_forces(
                 ti = ti > (R)0 ? ti : (R)0;
                 tj = tj > (R)0 ? tj : (R)0;
                 const R ti3 = ti * ti * ti, tj3 = tj * tj * tj;
-                const R mti = vj.w * ti3;
-                const R ux = vi.x - vj.x, uy = vi.y - vj.y, uz = vi.z - vj.z;
+                const R mti = vj.m * ti3;
+                const R ux = (R)(vi.x - vj.x), uy = (R)(vi.y - vj.y), uz = (R)(vi.z - vj.z);
                 // gradient sums
                 const R nw = mti * Gi + tj3 * Hj.x;
                 const R wx = nw * dx, wy = nw * dy, wz = nw * dz;
@@ -524,23 +531,24 @@ __global__ __launch_bounds__(kBlock) void k_grad_forces(
             return k < c ? v : (uint32_t)i;
         };
         uint32_t e0 = entry(lg), e1 = entry(lg + L);
-        R4 P0, V0, A0, B0, H0, P1, V1, A1, B1, H1;
+        R4 P0, A0, B0, H0, P1, A1, B1, H1;
+        VM<R> V0, V1;
         {
-            const R4 *rj = rec + kRecBoth * (int64_t)(e0 & kIdxMask);
-            P0 = rj[0]; V0 = rj[1]; A0 = rj[2]; B0 = rj[3]; H0 = rj[4];
+            const R4 *rj = rec + kRecBothSlots<F32> * (int64_t)(e0 & kIdxMask);
+            P0 = rj[0]; V0 = load_vm<F32, R>(rj + 1); A0 = rj[1 + o]; B0 = rj[2 + o]; H0 = rj[3 + o];
         }
         for (int k = lg; k < c; k += 2 * L) {
             const uint32_t e2 = entry(k + 2 * L);
             {
-                const R4 *rj = rec + kRecBoth * (int64_t)(e1 & kIdxMask);
-                P1 = rj[0]; V1 = rj[1]; A1 = rj[2]; B1 = rj[3]; H1 = rj[4];
+                const R4 *rj = rec + kRecBothSlots<F32> * (int64_t)(e1 & kIdxMask);
+                P1 = rj[0]; V1 = load_vm<F32, R>(rj + 1); A1 = rj[1 + o]; B1 = rj[2 + o]; H1 = rj[3 + o];
             }
             body(e0, P0, V0, A0, B0, H0);
             if (k + L >= c) break;
             const uint32_t e3 = entry(k + 3 * L);
             {
-                const R4 *rj = rec + kRecBoth * (int64_t)(e2 & kIdxMask);
-                P0 = rj[0]; V0 = rj[1]; A0 = rj[2]; B0 = rj[3]; H0 = rj[4];
+                const R4 *rj = rec + kRecBothSlots<F32> * (int64_t)(e2 & kIdxMask);
+                P0 = rj[0]; V0 = load_vm<F32, R>(rj + 1); A0 = rj[1 + o]; B0 = rj[2 + o]; H0 = rj[3 + o];
             }
             body(e1, P1, V1, A1, B1, H1);
             e0 = e2;

@@ -9,6 +9,7 @@
 //                                 strain-rate invariant)
 //   kicks                        (closing kick with rescaling, opening kick)
 #include "physics.h"
+#include "records.h"
 
 namespace sph {
 
@@ -64,7 +65,8 @@ __global__ void k_reorder_predict(int64_t n, const int32_t *__restrict__ perm, S
 }
 
 // ------------------------------------------------------------------ state
-// Record of the fused gradient + force pass (5 slots): (p, 1/H) (v, m)
+// Record of the fused gradient + force pass (5 slots, 6 in the FP32 form
+// whose (v, m) takes two, see records.h): (p, 1/H) (v, m)
 // (m Kn A xx yy zz xy) (m Kn A xz yz, rho/2, c/2)
 // (-m Kn/(2 Omega rho), m Kn/2, h/2, 1/m) with
 // A = (-P I + S_pred)/(Omega rho^2), Kn = -210/(pi H^5).
@@ -114,14 +116,15 @@ __global__ void k_state(int64_t n, const double4 *__restrict__ posh64,
     const double mi = m[i];
     const double kn = -210.0 / (kPiD * H * H * H * H * H);
     const double sc = mi * kn / (om * r * r);
-    R4 *rf = (R4 *)rec_f_v + 5 * i;
+    R4 *rf = (R4 *)rec_f_v + kRecBothSlots<F32> * i;
+    constexpr int o = kVelSlots<F32>;
     rf[0] = {px, py, pz, (R)(1.0 / H)};
-    rf[1] = {(R)vpx[i], (R)vpy[i], (R)vpz[i], (R)mi};
-    rf[2] = {(R)(sc * (s[0] - p)), (R)(sc * (s[1] - p)), (R)(sc * (-s[0] - s[1] - p)),
-             (R)(sc * s[2])};
-    rf[3] = {(R)(sc * s[3]), (R)(sc * s[4]), (R)(0.5 * r), (R)(0.5 * c)};
-    rf[4] = {(R)(-0.5 * mi * kn / (om * r)), (R)(0.5 * mi * kn), (R)(0.5 * q64.w),
-             (R)(mi > 0.0 ? 1.0 / mi : 0.0)};
+    store_vm<F32>(rf + 1, vpx[i], vpy[i], vpz[i], mi);
+    rf[1 + o] = {(R)(sc * (s[0] - p)), (R)(sc * (s[1] - p)), (R)(sc * (-s[0] - s[1] - p)),
+                 (R)(sc * s[2])};
+    rf[2 + o] = {(R)(sc * s[3]), (R)(sc * s[4]), (R)(0.5 * r), (R)(0.5 * c)};
+    rf[3 + o] = {(R)(-0.5 * mi * kn / (om * r)), (R)(0.5 * mi * kn), (R)(0.5 * q64.w),
+                 (R)(mi > 0.0 ? 1.0 / mi : 0.0)};
 }
 
 // ------------------------------------------- gradient epilogue + stress rate

@@ -167,12 +167,27 @@ def test_gpu_conservation_and_determinism():
     assert abs(pw.sum()) < 1e-12 * np.abs(pw).sum()
 
 
+def _stir(w, seed, v0, s0, length):
+    """A smooth velocity field of amplitude v0 (wavelength `length`) on the
+    mobile particles and random deviatoric stresses of scale s0, so that the
+    velocity gradient, the stress rate and du/dt are not zero at t = 0."""
+    rng = np.random.default_rng(seed)
+    k = 2.0 * np.pi / length
+    mob = w["fixed"] == 0
+    w["vx"] = w["vx"] + np.where(mob, v0 * np.sin(k * w["y"] + 0.3), 0.0)
+    w["vy"] = w["vy"] + np.where(mob, v0 * np.sin(k * w["z"] + 1.1), 0.0)
+    w["vz"] = w["vz"] + np.where(mob, v0 * np.sin(k * w["x"] + 2.3), 0.0)
+    w["S"] = w["S"] + np.where(mob, s0 * rng.standard_normal(w["S"].shape), 0.0)
+    return w
+
+
 def test_c2_full_size_sampled(orc):
     """Granular column at full size (196,794 + floor particles) in the launch
-    configuration of the benchmark: sampled outputs against the oracle, which
-    evaluates them one by one."""
+    configuration of the benchmark, stirred (smooth velocities of 0.1 m/s,
+    random stresses of 1 kPa) so that every derivative is exercised: sampled
+    outputs against the oracle, which evaluates them one by one."""
     say("[c2 full size sampled]")
-    w = inputs.c2_column()
+    w = _stir(inputs.c2_column(), 10, 0.1, 1.0e3, 0.44)
     n = w["x"].size
     rng = np.random.default_rng(8)
     tar = np.unique(np.concatenate([rng.choice(n, 40, replace=False), [0, n - 1, w["n_mobile"] - 1]]))
@@ -189,11 +204,12 @@ def test_c2_full_size_sampled(orc):
 
 def test_c3_full_size_sampled(orc):
     """Two-sphere impact at full size (about 1.1M particles: granite target
-    and projectile at 45 deg and 3 km/s, glass-like arrangement): sampled
+    and projectile at 45 deg and 3 km/s, glass-like arrangement), stirred
+    (smooth velocities of 30 m/s on top, random stresses of 10 MPa): sampled
     outputs of both precisions against the oracle, which evaluates them one
     by one."""
     say("[c3 full size sampled]")
-    w = inputs.c3_impact()
+    w = _stir(inputs.c3_impact(), 11, 30.0, 1.0e7, 1.0e5)
     n = w["x"].size
     rng = np.random.default_rng(9)
     tar = np.unique(np.concatenate([rng.choice(n, 30, replace=False),
