@@ -44,7 +44,8 @@ FLOPS_PAIR = {1: 122, 0: 116}
 # WRITE_SIZE per dispatch, scaled by the same counters on a plain copy of
 # known size).  Valid only for the kernel source it was taken on.
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_grad_forces_c2_fp32_traffic.md")
-TRAFFIC_SOURCES = ("paper_2603_19764_amd/csrc/pairs.hip", "paper_2603_19764_amd/csrc/device_util.h")
+TRAFFIC_SOURCES = ("paper_2603_19764_amd/csrc/pairs.hip", "paper_2603_19764_amd/csrc/device_util.h",
+                   "paper_2603_19764_amd/csrc/records.h")
 
 
 def log(*a):
