@@ -350,3 +350,36 @@ def test_tillotson_tension_cut_parity(orc):
     cut = ref["rho"] < 0.95 * w["mats"][0]["rho0"]
     assert cut.sum() > 50 and np.all(ref["P"][cut] == 0.0)
     ctx.close()
+
+
+@pytest.mark.parametrize("prec", [FP64, FP32])
+def test_c2_full_size_whole_step_sampled(orc, prec):
+    """The fused step path the benchmark times (sph_init: sort, density,
+    state, fused gradient + force sweep, stress rate; FP32 with the tuned
+    four lanes per particle) on the stirred granular column at full size:
+    sampled derivatives against the oracle, which evaluates them one by
+    one."""
+    import torch
+    from paper_2603_19764_amd import sph
+    say(f"[c2 full size, whole step path, prec={prec}]")
+    w = _stir(inputs.c2_column(), 10, 0.1, 1.0e3, 0.44)
+    n = w["x"].size
+    rng = np.random.default_rng(12)
+    tar = np.unique(np.concatenate([rng.choice(n, 40, replace=False), [0, n - 1, w["n_mobile"] - 1]]))
+    ref = _oracle(orc, w, tar)
+    ctx = sph.Context(n, 128)
+    if prec == FP32:
+        sph.sph_set_tuning(ctx, sph.SPH_TUNE_LANES_STEP, prec, 4)
+    st = sph.State(w)
+    sph.sph_init(ctx, st, w["mats"], w["params"], prec)
+    torch.cuda.synchronize()
+    ctx.check(sph.lib().sph_sync_status(ctx.h, None))
+    g = st.to_host()
+    ctx.close()
+    got = {k: g[k][..., tar] for k in ("rho", "omega", "P", "G", "dS", "a", "dudt", "dt")}
+    got["cs"] = g["c"][tar]
+    sub_ref = {k: (v[..., tar] if isinstance(v, np.ndarray) and v.shape[-1] == n else v)
+               for k, v in ref.items()}
+    _compare(sub_ref, got, TOL64 if prec == FP64 else TOL32,
+             ("rho", "omega", "P", "cs", "G", "dS", "a", "dudt", "dt"),
+             f"c2 whole step prec={prec}")
