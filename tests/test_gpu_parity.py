@@ -383,3 +383,44 @@ def test_c2_full_size_whole_step_sampled(orc, prec):
     _compare(sub_ref, got, TOL64 if prec == FP64 else TOL32,
              ("rho", "omega", "P", "cs", "G", "dS", "a", "dudt", "dt"),
              f"c2 whole step prec={prec}")
+
+
+def test_batched_scan_full_size_sampled(orc):
+    """The 64-impact batch at full size (7.16M particles, FP32, as the
+    benchmark's batched leg; self-gravity off here, its tree is checked in
+    the gravity tests), stirred: sampled particles of the smallest and the
+    largest run with strength and the largest without, against the oracle
+    evaluated on that run alone."""
+    import torch
+    from paper_2603_19764_amd import sph
+    say("[batched scan full size sampled]")
+    b = _stir(inputs.scan_batch(64, seed=5), 13, 1.0, 1.0e6, 3.0e4)
+    prm = dict(b["params"], grav_G=0.0)
+    rs = [int(v) for v in b["run_start"]]
+    n = int(b["x"].size)
+    ctx = sph.Context(n, 256, max_cells=1 << 24, max_runs=64)
+    st = sph.State(b, run_start=rs)
+    sph.sph_init(ctx, st, b["mats"], prm, FP32)
+    torch.cuda.synchronize()
+    ctx.check(sph.lib().sph_sync_status(ctx.h, None))
+    g = st.to_host()
+    ctx.close()
+    sizes = np.diff(rs)
+    strong = np.array([c["strength"] for c in b["cases"]]) == 1
+    on, off = np.flatnonzero(strong), np.flatnonzero(~strong)
+    picks = (on[np.argmin(sizes[on])], on[np.argmax(sizes[on])], off[np.argmax(sizes[off])])
+    rng = np.random.default_rng(14)
+    for r in (int(p) for p in picks):
+        a, e = rs[r], rs[r + 1]
+        w = {k: (b[k][..., a:e] if isinstance(b[k], np.ndarray) and b[k].shape[-1] == n else b[k])
+             for k in ("x", "y", "z", "m", "h", "mat", "vx", "vy", "vz", "u", "S")}
+        w.update(mats=b["mats"], params=prm)
+        tar = np.unique(rng.choice(e - a, 12, replace=False))
+        ref = _oracle(orc, w, tar)
+        nr = e - a
+        sub_ref = {k: (v[..., tar] if isinstance(v, np.ndarray) and v.shape[-1] == nr else v)
+                   for k, v in ref.items()}
+        got = {k: g[k][..., a:e][..., tar] for k in ("rho", "omega", "P", "G", "dS", "a", "dudt", "dt")}
+        got["cs"] = g["c"][a:e][tar]
+        _compare(sub_ref, got, TOL32, ("rho", "omega", "P", "cs", "G", "dS", "a", "dudt", "dt"),
+                 f"batch run {r} ({nr} particles, strength {int(strong[r])})")
