@@ -659,7 +659,8 @@ static sph_status eval(sph_ctx *h, const sph_state *st, const Rows &R, int32_t n
                             prm->grav_theta, 1, R.f[SPH_AX], R.f[SPH_AY], R.f[SPH_AZ], nullptr,
                             s, act)))
         return e;
-    if ((e = launch_step_grad_rate(ctx, n, prm, R.w[SPH_W_SP], R.w[SPH_W_GMOD], fixed,
+    if ((e = launch_step_grad_rate(ctx, n, prm, prec == SPH_FP32_CELLREL ? 1 : 0, R.w[SPH_W_SP],
+                                   R.w[SPH_W_GMOD], fixed,
                                    R.w[SPH_W_TAU], act, R.w[SPH_W_G], R.f[SPH_SDOT],
                                    accumulate_eps2 ? R.f[SPH_EPS2] : nullptr, st->n_singular, s)))
         return e;

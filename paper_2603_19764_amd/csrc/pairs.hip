@@ -442,7 +442,7 @@ __global__ __launch_bounds__(kBlock) void k_grad_forces(
     int64_t n, const int16_t *__restrict__ runid, const GridDesc *__restrict__ grid,
     const uint32_t *__restrict__ nbr, const int32_t *__restrict__ ncount, int32_t K,
     const typename Real<F32>::T4 *__restrict__ rec, double al, double be, double eps,
-    double etaC, double gx, double gy, double gz, double *__restrict__ gsum,
+    double etaC, double gx, double gy, double gz, void *__restrict__ gsum_v,
     double *__restrict__ ax, double *__restrict__ ay, double *__restrict__ az,
     double *__restrict__ dudt, double *__restrict__ dtc, const int32_t *__restrict__ act) {
     using R = typename Real<F32>::T;
@@ -565,7 +565,9 @@ __global__ __launch_bounds__(kBlock) void k_grad_forces(
     du = group_sum<L>(du);
     mumax = group_max<L>(mumax);
     if (active && lg == 0) {
-        double *o = gsum + i;
+        // the raw sums in the sweep's own precision (exact: they are
+        // accumulated in it)
+        R *o = (R *)gsum_v + i;
         o[0 * n] = c_xx; o[1 * n] = c_yy; o[2 * n] = c_zz;
         o[3 * n] = c_xy; o[4 * n] = c_xz; o[5 * n] = c_yz;
 #pragma unroll

@@ -255,7 +255,7 @@ sph_status launch_step_state(Ctx *ctx, int64_t n, sph_precision prec, const doub
                              const double *tau, const double *S_half, const double *Sdot,
                              double *P, double *cs, double *T, double *Y, double *Gmod,
                              double *S_pred, hipStream_t s);
-sph_status launch_step_grad_rate(Ctx *ctx, int64_t n, const sph_params *prm,
+sph_status launch_step_grad_rate(Ctx *ctx, int64_t n, const sph_params *prm, int32_t gsum_f32,
                                  const double *S_pred, const double *Gmod, const int32_t *fixed,
                                  const double *tau, const int32_t *act, double *G,
                                  double *Sdot, double *eps2, int64_t *n_singular, hipStream_t s);

@@ -128,7 +128,7 @@ __global__ void k_state(int64_t n, const double4 *__restrict__ posh64,
 }
 
 // ------------------------------------------- gradient epilogue + stress rate
-__global__ void k_grad_rate(int64_t n, const double *__restrict__ gsum,
+__global__ void k_grad_rate(int64_t n, const void *__restrict__ gsum_v, int32_t gsum_f32,
                             const int32_t *__restrict__ ncount, int32_t use_corr,
                             const double *__restrict__ S_pred, const double *__restrict__ Gmod,
                             const int32_t *__restrict__ fixed, double rot,
@@ -139,8 +139,13 @@ __global__ void k_grad_rate(int64_t n, const double *__restrict__ gsum,
     int sing = 0;
     if (i < n && (!act || act[i])) {
         double ci[6], F[9], g[9], s[5], ds[5], e2;
-        for (int k = 0; k < 6; ++k) ci[k] = gsum[k * n + i];
-        for (int k = 0; k < 9; ++k) F[k] = gsum[(6 + k) * n + i];
+        // raw sums of the fused sweep: float in the FP32 form, else double
+        const float *g32 = (const float *)gsum_v;
+        const double *g64 = (const double *)gsum_v;
+        for (int k = 0; k < 15; ++k) {
+            const double v = gsum_f32 ? (double)g32[k * n + i] : g64[k * n + i];
+            if (k < 6) ci[k] = v; else F[k - 6] = v;
+        }
         sing = corrected_gradient(ci, F, ncount[i], use_corr, g) ? 0 : (use_corr ? 1 : 0);
         for (int k = 0; k < 9; ++k) G[k * n + i] = g[k];
         for (int k = 0; k < 5; ++k) s[k] = S_pred[k * n + i];
@@ -341,14 +346,14 @@ sph_status launch_step_state(Ctx *ctx, int64_t n, sph_precision prec, const doub
     return SPH_OK;
 }
 
-sph_status launch_step_grad_rate(Ctx *ctx, int64_t n, const sph_params *prm,
+sph_status launch_step_grad_rate(Ctx *ctx, int64_t n, const sph_params *prm, int32_t gsum_f32,
                                  const double *S_pred, const double *Gmod, const int32_t *fixed,
                                  const double *tau, const int32_t *act, double *G,
                                  double *Sdot, double *eps2,
                                  int64_t *n_singular, hipStream_t s) {
     if (n == 0) return SPH_OK;
     hipLaunchKernelGGL(k_grad_rate, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n,
-                       ctx->gsum, ctx->ncount, prm->use_correction_tensor, S_pred, Gmod, fixed,
+                       (const void *)ctx->gsum, gsum_f32, ctx->ncount, prm->use_correction_tensor, S_pred, Gmod, fixed,
                        prm->rot_sign, tau, act, G, Sdot, eps2, n_singular);
     SPH_HIP(hipGetLastError());
     return SPH_OK;
