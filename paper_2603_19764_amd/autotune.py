@@ -17,7 +17,7 @@ import os
 
 from . import sph
 
-LANES = (4, 8, 16)
+LANES = (8, 4, 16)   # default first
 CELL_SCALES = (1000, 1150, 1300)   # permille of 2 h_max
 BUILD_RANGES = (64, 32, 96, 128)   # sorted particles per pair-list build work-group (default first)
 
@@ -67,7 +67,7 @@ class TuneCache:
 # A later candidate replaces the best so far only when it is faster by more
 # than this fraction: settings whose times differ by less than the run-to-run
 # noise keep the earlier one, so the choice repeats from run to run.
-MARGIN = 0.03
+MARGIN = 0.05
 
 
 def choose(values, measure, margin: float = MARGIN):

@@ -356,7 +356,7 @@ def test_tillotson_tension_cut_parity(orc):
 def test_c2_full_size_whole_step_sampled(orc, prec):
     """The fused step path the benchmark times (sph_init: sort, density,
     state, fused gradient + force sweep, stress rate; FP32 with the tuned
-    four lanes per particle) on the stirred granular column at full size:
+    eight lanes per particle) on the stirred granular column at full size:
     sampled derivatives against the oracle, which evaluates them one by
     one."""
     import torch
@@ -369,7 +369,7 @@ def test_c2_full_size_whole_step_sampled(orc, prec):
     ref = _oracle(orc, w, tar)
     ctx = sph.Context(n, 128)
     if prec == FP32:
-        sph.sph_set_tuning(ctx, sph.SPH_TUNE_LANES_STEP, prec, 4)
+        sph.sph_set_tuning(ctx, sph.SPH_TUNE_LANES_STEP, prec, 8)
     st = sph.State(w)
     sph.sph_init(ctx, st, w["mats"], w["params"], prec)
     torch.cuda.synchronize()
