@@ -26,7 +26,9 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "sph_oracle.c")
 _SRC_GRAV = os.path.join(_HERE, "gravity_oracle.c")
-_LIB = os.path.join(_HERE, "liboracle.so")
+# SPH_ORACLE_LIB names another build of the same source to load instead (a
+# build with a planted mistake, to check that the pins catch it)
+_LIB = os.environ.get("SPH_ORACLE_LIB") or os.path.join(_HERE, "liboracle.so")
 _lock = threading.Lock()
 _lib = None
 
