@@ -26,8 +26,9 @@
  *     (sph_state.run_start), which uploads it.
  *   - Argument errors are returned synchronously (SPH_EINVAL, SPH_ESTATE,
  *     SPH_ECAPACITY).  Conditions found on the device (neighbour list
- *     overflow, cell table overflow) raise a device flag that
- *     sph_sync_status() reports after synchronising the stream.
+ *     overflow, cell table overflow, a NaN or infinite value) raise a
+ *     device flag that sph_sync_status() reports after synchronising the
+ *     stream.
  *   - After sph_build_cells the pair passes expect every per-particle array
  *     in the cell order the call produced: the caller permutes its arrays
  *     with sph_reorder (perm[k] = input index of the k-th particle).
@@ -138,7 +139,17 @@ sph_status sph_destroy(sph_ctx *ctx);
 const char *sph_last_error(const sph_ctx *ctx);
 
 /* Synchronise `stream` and report (then clear) device-side flags:
- * SPH_ECAPACITY after a neighbour-list or cell-table overflow. */
+ * SPH_ECAPACITY after a neighbour-list, cell-table or gravity-list overflow
+ * or a step below the shortest rung; SPH_ENONFINITE after a kernel met a NaN
+ * or infinite value in what it computes: a position or smoothing length
+ * binned by the neighbour search (after the drift of sph_step), density or
+ * Omega, EOS state (P, c, T, Y, Gamma), predicted or kicked stress, velocity
+ * gradient, stress rate, acceleration, energy rate, CFL step, drifted,
+ * predicted or kicked position, velocity or energy.  Each kernel raises the
+ * flag with one atomic per wavefront; the values themselves are written as
+ * computed (NaN propagates; a NaN CFL step is left out of the step minimum).
+ * When several flags are up, the first in the order above is returned and
+ * all are cleared. */
 sph_status sph_sync_status(sph_ctx *ctx, sph_stream stream);
 
 /* ---------------------------------------------------- neighbour search (a1) */

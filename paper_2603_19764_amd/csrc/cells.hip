@@ -115,7 +115,7 @@ __device__ __forceinline__ int run_of(const int32_t *run_p, int nr, int64_t k) {
 __global__ void k_bbox(double *x, double *y, double *z, const double *h, const int32_t *run_p,
                        BBox *part, int32_t *cell_count, const int32_t *total_keys_prev,
                        const double *dtp, const double *vx, const double *vy, const double *vz,
-                       const int32_t *fixed) {
+                       const int32_t *fixed, int32_t *flags) {
     {
         const int64_t nz = *total_keys_prev;
         const int64_t nthr = (int64_t)gridDim.x * gridDim.y * blockDim.x;
@@ -128,6 +128,7 @@ __global__ void k_bbox(double *x, double *y, double *z, const double *h, const i
     const double dt = dtp ? dtp[r] : 0.0;  // one time step per run
     double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
     double hm = 0.0;
+    bool bad = false;  // a non-finite position or length (binned at the grid's edge, reported)
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t k0 = a + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k0 < b;
          k0 += kBBoxUnroll * stride) {
@@ -150,9 +151,11 @@ __global__ void k_bbox(double *x, double *y, double *z, const double *h, const i
                     hi[d] = fmax(hi[d], v[d]);
                 }
                 hm = fmax(hm, h[k]);
+                bad |= nonfinite(v[0], v[1], v[2], h[k]);
             }
         }
     }
+    flag_if(bad, flags, FLAG_NONFINITE);
     // wave minima/maxima by shuffles, then across the block's waves in LDS
 #pragma unroll
     for (int o = kWave / 2; o > 0; o >>= 1) {
@@ -700,7 +703,7 @@ sph_status launch_build_cells(Ctx *ctx, int64_t n, double *x, double *y, double 
     nbb = nbb < 1 ? 1 : (nbb > kBBoxBlocks ? kBBoxBlocks : nbb);
     hipLaunchKernelGGL(k_bbox, dim3((unsigned)nbb, nr), dim3(kBBoxThreads), 0, s, x, y, z, h, ctx->run_p,
                        ctx->bbox_part, ctx->cell_count, ctx->total_keys, ex->dt, ex->vx, ex->vy,
-                       ex->vz, ex->fixed);
+                       ex->vz, ex->fixed, ctx->flags);
     hipLaunchKernelGGL(k_grid, dim3(1), dim3(1024), 0, s, ctx->bbox_part, (int)nbb, ctx->run_p, nr, cell_min,
                        ctx->cell_scale, ctx->max_cells, ctx->grid, ctx->total_keys, ctx->flags);
     hipLaunchKernelGGL(k_keys, dim3(nb), dim3(tb), 0, s, n, x, y, z, ctx->run_p, nr, ctx->grid,

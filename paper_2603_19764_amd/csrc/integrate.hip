@@ -12,7 +12,8 @@ __global__ void k_stress(int32_t phase, int64_t n, const double *__restrict__ dt
                          const double *__restrict__ dtnp, const double *__restrict__ G,
                          const double *__restrict__ Y, const double *__restrict__ Gmod,
                          const int32_t *__restrict__ fixed, double rot, double *S_half,
-                         double *S_pred, double *Sdot, double *eps2) {
+                         double *S_pred, double *Sdot, double *eps2,
+                         int32_t *__restrict__ flags) {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n) return;
     const bool fx = fixed && fixed[i];
@@ -23,6 +24,7 @@ __global__ void k_stress(int32_t phase, int64_t n, const double *__restrict__ dt
             s[c] = fx ? S_half[c * n + i] : S_half[c * n + i] + hd * Sdot[c * n + i];
         plastic_return(s, Y[i]);
         for (int c = 0; c < 5; ++c) S_pred[c * n + i] = s[c];
+        flag_if(nonfinite(s[0], s[1], s[2], s[3], s[4]), flags, FLAG_NONFINITE);
     } else if (phase == SPH_STRESS_RATE) {
         double g[9];
         for (int c = 0; c < 9; ++c) g[c] = G[c * n + i];
@@ -38,6 +40,7 @@ __global__ void k_stress(int32_t phase, int64_t n, const double *__restrict__ dt
         const double tr3 = (E[0][0] + E[1][1] + E[2][2]) / 3.0;
         const double gm = Gmod[i];
         const int ia[5] = {0, 1, 0, 0, 1}, ib[5] = {0, 1, 1, 2, 2};
+        bool bad = false;
         for (int c = 0; c < 5; ++c) {
             const int a = ia[c], b = ib[c];
             double rs = 0.0, sr = 0.0;
@@ -45,8 +48,11 @@ __global__ void k_stress(int32_t phase, int64_t n, const double *__restrict__ dt
                 rs += R[a][k] * S[k][b];
                 sr += S[a][k] * R[k][b];
             }
-            Sdot[c * n + i] = 2.0 * gm * (E[a][b] - (a == b ? tr3 : 0.0)) + rot * (rs - sr);
+            const double d = 2.0 * gm * (E[a][b] - (a == b ? tr3 : 0.0)) + rot * (rs - sr);
+            Sdot[c * n + i] = d;
+            bad |= nonfinite(d);
         }
+        flag_if(bad, flags, FLAG_NONFINITE);
     } else if (phase == SPH_STRESS_KICK) {
         if (fx) return;
         const double dt = *dtp, hd = 0.5 * dt, hn = 0.5 * *dtnp;
@@ -56,7 +62,12 @@ __global__ void k_stress(int32_t phase, int64_t n, const double *__restrict__ dt
             s[c] = S_half[c * n + i] + hd * d[c];
         }
         plastic_return(s, Y[i]);
-        for (int c = 0; c < 5; ++c) S_half[c * n + i] = s[c] + hn * d[c];
+        bool bad = false;
+        for (int c = 0; c < 5; ++c) {
+            S_half[c * n + i] = s[c] + hn * d[c];
+            bad |= nonfinite(s[c] + hn * d[c]);
+        }
+        flag_if(bad, flags, FLAG_NONFINITE);
         if (eps2) {
             double ee = 0.0;
             for (int a = 0; a < 3; ++a)
@@ -69,7 +80,13 @@ __global__ void k_stress(int32_t phase, int64_t n, const double *__restrict__ dt
     } else {  // opening kick from the predicted stress (start of a run)
         if (fx) return;
         const double hn = 0.5 * *dtnp;
-        for (int c = 0; c < 5; ++c) S_half[c * n + i] = S_pred[c * n + i] + hn * Sdot[c * n + i];
+        bool bad = false;
+        for (int c = 0; c < 5; ++c) {
+            const double v = S_pred[c * n + i] + hn * Sdot[c * n + i];
+            S_half[c * n + i] = v;
+            bad |= nonfinite(v);
+        }
+        flag_if(bad, flags, FLAG_NONFINITE);
     }
 }
 
@@ -80,7 +97,8 @@ sph_status launch_stress(Ctx *ctx, int32_t phase, int64_t n, const double *dt,
                          hipStream_t s) {
     if (n == 0) return SPH_OK;
     hipLaunchKernelGGL(k_stress, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, phase, n, dt,
-                       dt_next, G, Y, Gmod, fixed, prm->rot_sign, S_half, S_pred, Sdot, eps2);
+                       dt_next, G, Y, Gmod, fixed, prm->rot_sign, S_half, S_pred, Sdot, eps2,
+                       ctx->flags);
     SPH_HIP(hipGetLastError());
     return SPH_OK;
 }
@@ -90,7 +108,7 @@ __global__ void k_kick_drift(int32_t phase, int64_t n, const double *__restrict_
                              double *x, double *y, double *z, double *vx, double *vy,
                              double *vz, double *u, const double *ax, const double *ay,
                              const double *az, const double *dudt, double *vpx, double *vpy,
-                             double *vpz, double *up) {
+                             double *vpz, double *up, int32_t *__restrict__ flags) {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n) return;
     const bool fx = fixed && fixed[i];
@@ -100,6 +118,7 @@ __global__ void k_kick_drift(int32_t phase, int64_t n, const double *__restrict_
         x[i] += dt * vx[i];
         y[i] += dt * vy[i];
         z[i] += dt * vz[i];
+        flag_if(nonfinite(x[i], y[i], z[i]), flags, FLAG_NONFINITE);
     } else if (phase == SPH_KD_PREDICT) {
         const double hd = fx ? 0.0 : 0.5 * *dtp;
         if (fx) {
@@ -110,6 +129,7 @@ __global__ void k_kick_drift(int32_t phase, int64_t n, const double *__restrict_
             vpz[i] = vz[i] + hd * az[i];
             up[i] = u[i] + hd * dudt[i];
         }
+        flag_if(nonfinite(vpx[i], vpy[i], vpz[i], up[i]), flags, FLAG_NONFINITE);
     } else if (phase == SPH_KD_KICK) {
         if (fx) return;
         const double hd = 0.5 * *dtp, hn = 0.5 * *dtnp;
@@ -117,6 +137,7 @@ __global__ void k_kick_drift(int32_t phase, int64_t n, const double *__restrict_
         vy[i] = (vy[i] + hd * ay[i]) + hn * ay[i];
         vz[i] = (vz[i] + hd * az[i]) + hn * az[i];
         u[i] = (u[i] + hd * dudt[i]) + hn * dudt[i];
+        flag_if(nonfinite(vx[i], vy[i], vz[i], u[i]), flags, FLAG_NONFINITE);
     } else {  // opening kick only (start of a run)
         if (fx) return;
         const double hn = 0.5 * *dtnp;
@@ -124,6 +145,7 @@ __global__ void k_kick_drift(int32_t phase, int64_t n, const double *__restrict_
         vy[i] += hn * ay[i];
         vz[i] += hn * az[i];
         u[i] += hn * dudt[i];
+        flag_if(nonfinite(vx[i], vy[i], vz[i], u[i]), flags, FLAG_NONFINITE);
     }
 }
 
@@ -136,7 +158,7 @@ sph_status launch_kick_drift(Ctx *ctx, int32_t phase, int64_t n, const double *d
     if (n == 0) return SPH_OK;
     hipLaunchKernelGGL(k_kick_drift, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, phase, n,
                        dt, dt_next, fixed, x, y, z, vx, vy, vz, u, ax, ay, az, dudt, vpx, vpy,
-                       vpz, up);
+                       vpz, up, ctx->flags);
     SPH_HIP(hipGetLastError());
     return SPH_OK;
 }
@@ -151,11 +173,12 @@ constexpr int kDtUnroll = 4;
 
 __global__ void k_dt_reduce(int64_t n, const int32_t *__restrict__ run_p,
                             const double *__restrict__ dtc, const int32_t *__restrict__ fixed,
-                            unsigned long long *bits_all) {
+                            unsigned long long *bits_all, int32_t *__restrict__ flags) {
     const int r = blockIdx.y;
     const int64_t a = run_p ? run_p[r] : 0, b = run_p ? run_p[r + 1] : n;
     unsigned long long *bits = bits_all + r;
     unsigned long long best = 0x7ff0000000000000ull;
+    bool bad = false;  // a NaN step (skipped by the minimum, reported)
     // kDtUnroll independent loads in flight per thread
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i0 = a + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i0 < b;
@@ -169,12 +192,14 @@ __global__ void k_dt_reduce(int64_t n, const int32_t *__restrict__ run_p,
         }
 #pragma unroll
         for (int u = 0; u < kDtUnroll; ++u) {
+            bad |= d[u] != d[u];
             if (d[u] > 0.0) {
                 const unsigned long long v = (unsigned long long)__double_as_longlong(d[u]);
                 best = v < best ? v : best;
             }
         }
     }
+    flag_if(bad, flags, FLAG_NONFINITE);
     for (int o = 32; o > 0; o >>= 1) {
         const unsigned long long v = __shfl_xor(best, o);
         best = v < best ? v : best;
@@ -208,7 +233,7 @@ sph_status launch_dt_reduce(Ctx *ctx, int64_t n, const double *dtc, const int32_
         const int cap_b = 64;
         nb = nb < 1 ? 1 : (nb > cap_b ? cap_b : nb);
         hipLaunchKernelGGL(k_dt_reduce, dim3(nb, nr), dim3(1024), 0, s, n, nr > 1 ? run_p : nullptr,
-                           dtc, fixed, bits);
+                           dtc, fixed, bits, ctx->flags);
     }
     SPH_HIP(hipGetLastError());
     return SPH_OK;

@@ -107,7 +107,8 @@ __global__ __launch_bounds__(kBlock) void k_density(
     int64_t n, const double4 *__restrict__ posh64, const int16_t *__restrict__ runid,
     const GridDesc *__restrict__ grid, const uint32_t *__restrict__ nbr,
     const int32_t *__restrict__ ncount, int32_t K, const typename Real<F32>::T4 *__restrict__ rec,
-    double *__restrict__ rho, double *__restrict__ omega, int32_t omega_one) {
+    double *__restrict__ rho, double *__restrict__ omega, int32_t omega_one,
+    int32_t *__restrict__ flags) {
     using R = typename Real<F32>::T;
     using R4 = typename Real<F32>::T4;
     __shared__ float shs[81];
@@ -170,6 +171,7 @@ __global__ __launch_bounds__(kBlock) void k_density(
     }
     sw = group_sum<L>(sw);
     sd = group_sum<L>(sd);
+    bool bad = false;
     if (active && lg == 0) {
         const double H = 2.0 * hi;
         const double Wn = 21.0 / (2.0 * kPi * H * H * H);
@@ -177,15 +179,18 @@ __global__ __launch_bounds__(kBlock) void k_density(
         const double mi = (double)pi.w;
         const double r = Wn * (mi + sw);           // self term W(0) = Wn
         const double dsum = Dn * (3.0 * mi + sd);  // self term dW/dh(0) = 3 Dn
+        const double om = omega_one ? 1.0 : 1.0 + hi / (3.0 * r) * dsum;
         rho[i] = r;
-        omega[i] = omega_one ? 1.0 : 1.0 + hi / (3.0 * r) * dsum;
+        omega[i] = om;
+        bad = nonfinite(r, om);
     }
+    flag_if(bad, flags, FLAG_NONFINITE);
 }
 
 // -------------------------------------------- EOS, yield, shear modulus
 __global__ void k_eos(int64_t n, const double *__restrict__ rho, const double *__restrict__ u,
                       const int32_t *__restrict__ mat, MatTable mt, double *P, double *cs,
-                      double *T, double *Y, double *Gmod) {
+                      double *T, double *Y, double *Gmod, int32_t *__restrict__ flags) {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n) return;
     double p, c, t, y, gm;
@@ -195,6 +200,7 @@ __global__ void k_eos(int64_t n, const double *__restrict__ rho, const double *_
     T[i] = t;
     Y[i] = y;
     Gmod[i] = gm;
+    flag_if(nonfinite(p, c, t, y, gm), flags, FLAG_NONFINITE);
 }
 
 // ============================================================== gradients
@@ -283,16 +289,20 @@ __global__ __launch_bounds__(kBlock) void k_gradients(
 // C = (C^-1)^-1 from the adjugate (identity if singular), G = F C.
 __global__ void k_grad_epilogue(int64_t n, const double *__restrict__ gsum,
                                 const int32_t *__restrict__ ncount, int32_t use_corr,
-                                double *__restrict__ G, int64_t *n_singular) {
+                                double *__restrict__ G, int64_t *n_singular,
+                                int32_t *__restrict__ flags) {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     int sing = 0;
+    bool bad = false;
     if (i < n) {
         double ci[6], F[9], g[9];
         for (int k = 0; k < 6; ++k) ci[k] = gsum[k * n + i];
         for (int k = 0; k < 9; ++k) F[k] = gsum[(6 + k) * n + i];
         sing = corrected_gradient(ci, F, ncount[i], use_corr, g) ? 0 : (use_corr ? 1 : 0);
         for (int k = 0; k < 9; ++k) G[k * n + i] = g[k];
+        bad = nonfinite(g[0], g[1], g[2], g[3], g[4], g[5], g[6], g[7], g[8]);
     }
+    flag_if(bad, flags, FLAG_NONFINITE);
     if (n_singular) {
         const uint64_t m = __ballot(sing);
         if (m && (threadIdx.x % kWave) == 0) atomicAdd((unsigned long long *)n_singular,
@@ -335,7 +345,7 @@ __global__ __launch_bounds__(kBlock) void k_forces(
     const typename Real<F32>::T4 *__restrict__ rec, double al, double be, double eps,
     double etaC, double gx, double gy, double gz, double *__restrict__ ax,
     double *__restrict__ ay, double *__restrict__ az, double *__restrict__ dudt,
-    double *__restrict__ dtc) {
+    double *__restrict__ dtc, int32_t *__restrict__ flags) {
     using R = typename Real<F32>::T;
     using R4 = typename Real<F32>::T4;
     __shared__ float shs[81];
@@ -410,15 +420,19 @@ __global__ __launch_bounds__(kBlock) void k_forces(
     acz = group_sum<L>(acz);
     du = group_sum<L>(du);
     mumax = group_max<L>(mumax);
+    bool bad = false;
     if (active && lg == 0) {
         const double hi = (double)Hi.y;
         const double ci = (double)Bi.w;
+        const double d = etaC * hi / ((1.0 + 0.6 * al) * ci + 0.6 * be * (double)mumax);
         ax[i] = (double)acx + gx;
         ay[i] = (double)acy + gy;
         az[i] = (double)acz + gz;
         dudt[i] = (double)du;
-        dtc[i] = etaC * hi / ((1.0 + 0.6 * al) * ci + 0.6 * be * (double)mumax);
+        dtc[i] = d;
+        bad = nonfinite((double)acx, (double)acy, (double)acz, (double)du, d);
     }
+    flag_if(bad, flags, FLAG_NONFINITE);
 }
 
 // ==================================================== gradients + forces
@@ -444,7 +458,8 @@ __global__ __launch_bounds__(kBlock) void k_grad_forces(
     const typename Real<F32>::T4 *__restrict__ rec, double al, double be, double eps,
     double etaC, double gx, double gy, double gz, void *__restrict__ gsum_v,
     double *__restrict__ ax, double *__restrict__ ay, double *__restrict__ az,
-    double *__restrict__ dudt, double *__restrict__ dtc, const int32_t *__restrict__ act) {
+    double *__restrict__ dudt, double *__restrict__ dtc, const int32_t *__restrict__ act,
+    int32_t *__restrict__ flags) {
     using R = typename Real<F32>::T;
     using R4 = typename Real<F32>::T4;
     __shared__ float shs[81];
@@ -564,6 +579,7 @@ __global__ __launch_bounds__(kBlock) void k_grad_forces(
     acz = group_sum<L>(acz);
     du = group_sum<L>(du);
     mumax = group_max<L>(mumax);
+    bool bad = false;
     if (active && lg == 0) {
         // the raw sums in the sweep's own precision (exact: they are
         // accumulated in it)
@@ -574,12 +590,16 @@ __global__ __launch_bounds__(kBlock) void k_grad_forces(
         for (int a = 0; a < 9; ++a) o[(6 + a) * n] = f[a];
         const double hi = 2.0 * (double)hi2;
         const double ci = 2.0 * (double)ci2;
+        const double d = etaC * hi / ((1.0 + 0.6 * al) * ci + 0.6 * be * (double)mumax);
         ax[i] = (double)acx + gx;
         ay[i] = (double)acy + gy;
         az[i] = (double)acz + gz;
         dudt[i] = (double)du;
-        dtc[i] = etaC * hi / ((1.0 + 0.6 * al) * ci + 0.6 * be * (double)mumax);
+        dtc[i] = d;
+        // non-finite gradient sums show in G (checked with the stress rate)
+        bad = nonfinite((double)acx, (double)acy, (double)acz, (double)du, d);
     }
+    flag_if(bad, flags, FLAG_NONFINITE);
 }
 
 // =============================================================== launches
@@ -592,7 +612,7 @@ static void density_launch(Ctx *ctx, int64_t n, const sph_params *prm, double *r
     const int nb = (int)((n * L + kBlock - 1) / kBlock);
     hipLaunchKernelGGL((k_density<L, F32>), dim3(nb), dim3(kBlock), 0, s, n, ctx->posh64,
                        ctx->runid, ctx->grid, ctx->nbr, ctx->ncount, ctx->max_nbr,
-                       (const R4 *)ctx->rec_d, rho, omega, prm->omega_one);
+                       (const R4 *)ctx->rec_d, rho, omega, prm->omega_one, ctx->flags);
 }
 
 template <bool F32>
@@ -635,7 +655,8 @@ sph_status launch_density(Ctx *ctx, int64_t n, const double *m, const double *h,
     MatTable mt;
     mt.n = nmat;
     for (int k = 0; k < nmat; ++k) mt.m[k] = ctx->mats[k].m;
-    hipLaunchKernelGGL(k_eos, dim3(nb), dim3(256), 0, s, n, rho, u, mat, mt, P, cs, T, Y, Gmod);
+    hipLaunchKernelGGL(k_eos, dim3(nb), dim3(256), 0, s, n, rho, u, mat, mt, P, cs, T, Y, Gmod,
+                       ctx->flags);
     SPH_HIP(hipGetLastError());
     return SPH_OK;
 }
@@ -683,7 +704,7 @@ sph_status launch_gradients(Ctx *ctx, int64_t n, const double *vx, const double 
     sph_status st = launch_gradient_pairs(ctx, n, prec, s);
     if (st != SPH_OK) return st;
     hipLaunchKernelGGL(k_grad_epilogue, dim3(nb), dim3(256), 0, s, n, ctx->gsum, ctx->ncount,
-                       prm->use_correction_tensor, G, n_singular);
+                       prm->use_correction_tensor, G, n_singular, ctx->flags);
     SPH_HIP(hipGetLastError());
     return SPH_OK;
 }
@@ -696,7 +717,7 @@ static void forces_launch(Ctx *ctx, int64_t n, const sph_params *prm, double *ax
     hipLaunchKernelGGL((k_forces<L, F32>), dim3(nb), dim3(kBlock), 0, s, n, ctx->runid, ctx->grid,
                        ctx->nbr, ctx->ncount, ctx->max_nbr, (const R4 *)ctx->rec_f, prm->av_alpha,
                        prm->av_beta, prm->av_eps, prm->eta_C, prm->g[0], prm->g[1], prm->g[2], ax,
-                       ay, az, dudt, dtc);
+                       ay, az, dudt, dtc, ctx->flags);
 }
 
 template <bool F32>
@@ -737,7 +758,7 @@ static void both_launch(Ctx *ctx, int64_t n, const sph_params *prm, double *ax, 
     hipLaunchKernelGGL((k_grad_forces<L, F32>), dim3(nb), dim3(kBlock), 0, s, n, ctx->runid,
                        ctx->grid, ctx->nbr, ctx->ncount, ctx->max_nbr, (const R4 *)ctx->rec_f,
                        prm->av_alpha, prm->av_beta, prm->av_eps, prm->eta_C, prm->g[0], prm->g[1],
-                       prm->g[2], ctx->gsum, ax, ay, az, dudt, dtc, act);
+                       prm->g[2], ctx->gsum, ax, ay, az, dudt, dtc, act, ctx->flags);
 }
 
 template <bool F32>

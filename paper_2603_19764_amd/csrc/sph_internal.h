@@ -22,6 +22,21 @@ enum {
     FLAG_COUNT = 5
 };
 
+// Raise flags[which] when `bad` holds on any lane of the wave: one atomic
+// per wave, issued by the first lane that saw it.  Lanes that already left
+// the kernel take no part, so it may follow an early return.
+__device__ __forceinline__ void flag_if(bool bad, int32_t *flags, int which) {
+    const uint64_t m = __ballot(bad);
+    if (m && (int)__lane_id() == __ffsll((long long)m) - 1) atomicOr(&flags[which], 1);
+}
+
+// True when any of the values is NaN or infinite.
+__device__ __forceinline__ bool nonfinite(double a) { return !__builtin_isfinite(a); }
+template <typename... T>
+__device__ __forceinline__ bool nonfinite(double a, T... rest) {
+    return nonfinite(a) | nonfinite(rest...);
+}
+
 // Uniform cell grid of one run.
 struct GridDesc {
     double ox, oy, oz;      // origin
@@ -92,7 +107,7 @@ struct Ctx {
     // that a step's kick can read one while clearing the other
     unsigned long long *dtbits = nullptr;  // 3 * max_runs
     int32_t dt_parity = 0;
-    double *diag = nullptr;         // 16 doubles
+    double *diag = nullptr;         // diagnostics partial sums: 256 x 13 doubles
     // pair-pass records (array of structures, see the pair kernels)
     void *rec_d = nullptr;          // density: capacity * 32 bytes
     void *rec_g = nullptr;          // gradients: capacity * 96 bytes

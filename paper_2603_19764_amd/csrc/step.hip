@@ -81,7 +81,8 @@ __global__ void k_state(int64_t n, const double4 *__restrict__ posh64,
                         const double *__restrict__ S_half, const double *__restrict__ Sdot,
                         double *__restrict__ P, double *__restrict__ cs, double *__restrict__ T,
                         double *__restrict__ Y, double *__restrict__ Gmod,
-                        double *__restrict__ S_pred, void *rec_f_v) {
+                        double *__restrict__ S_pred, void *rec_f_v,
+                        int32_t *__restrict__ flags) {
     using R = typename std::conditional<F32, float, double>::type;
     using R4 = typename std::conditional<F32, float4, double4>::type;
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -100,6 +101,7 @@ __global__ void k_state(int64_t n, const double4 *__restrict__ posh64,
     for (int k = 0; k < 5; ++k) s[k] = S_half[k * n + i] + hd * Sdot[k * n + i];
     plastic_return(s, y);
     for (int k = 0; k < 5; ++k) S_pred[k * n + i] = s[k];
+    flag_if(nonfinite(p, c, t, y, gm, s[0], s[1], s[2], s[3], s[4]), flags, FLAG_NONFINITE);
     // records
     const double4 q64 = posh64[i];
     R px, py, pz;
@@ -134,9 +136,11 @@ __global__ void k_grad_rate(int64_t n, const void *__restrict__ gsum_v, int32_t 
                             const int32_t *__restrict__ fixed, double rot,
                             const double *__restrict__ tau, const int32_t *__restrict__ act,
                             double *__restrict__ G, double *__restrict__ Sdot,
-                            double *__restrict__ eps2, int64_t *n_singular) {
+                            double *__restrict__ eps2, int64_t *n_singular,
+                            int32_t *__restrict__ flags) {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     int sing = 0;
+    bool bad = false;
     if (i < n && (!act || act[i])) {
         double ci[6], F[9], g[9], s[5], ds[5], e2;
         // raw sums of the fused sweep: float in the FP32 form, else double
@@ -151,9 +155,12 @@ __global__ void k_grad_rate(int64_t n, const void *__restrict__ gsum_v, int32_t 
         for (int k = 0; k < 5; ++k) s[k] = S_pred[k * n + i];
         stress_rate(g, s, Gmod[i], rot, ds, e2);
         for (int k = 0; k < 5; ++k) Sdot[k * n + i] = ds[k];
+        bad = nonfinite(g[0], g[1], g[2], g[3], g[4], g[5], g[6], g[7], g[8]) |
+              nonfinite(ds[0], ds[1], ds[2], ds[3], ds[4]);
         // the step that ends here is twice the predictor interval
         if (eps2 && !(fixed && fixed[i])) eps2[i] += 2.0 * tau[i] * e2;
     }
+    flag_if(bad, flags, FLAG_NONFINITE);
     if (n_singular) {
         const uint64_t mk = __ballot(sing);
         if (mk && (threadIdx.x % kWave) == 0)
@@ -181,7 +188,8 @@ __global__ void k_kick_all(int64_t n, int32_t mode, const double *__restrict__ d
                            const double *__restrict__ ax, const double *__restrict__ ay,
                            const double *__restrict__ az, const double *__restrict__ dudt,
                            double *S_half, const double *__restrict__ S_pred,
-                           const double *__restrict__ Sdot, const double *__restrict__ Y) {
+                           const double *__restrict__ Sdot, const double *__restrict__ Y,
+                           int32_t *__restrict__ flags) {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i < nr) {
         dt_next[i] = dt_from_bits(bits_cur[i], dt_cap);
@@ -210,6 +218,9 @@ __global__ void k_kick_all(int64_t n, int32_t mode, const double *__restrict__ d
         u[i] += hn * dudt[i];
         for (int k = 0; k < 5; ++k) S_half[k * n + i] = S_pred[k * n + i] + hn * Sdot[k * n + i];
     }
+    flag_if(nonfinite(vx[i], vy[i], vz[i], u[i], S_half[i], S_half[n + i], S_half[2 * n + i],
+                      S_half[3 * n + i], S_half[4 * n + i]),
+            flags, FLAG_NONFINITE);
 }
 
 // ------------------------------------------------ acceleration criterion
@@ -294,6 +305,9 @@ __global__ void k_kick_hier(int64_t n, int32_t init, int32_t rungs, double tick,
     step[i] = st;
     elapsed[i] = 0.0;
     rem[i] = st * tick;
+    flag_if(nonfinite(vx[i], vy[i], vz[i], u[i], S_half[i], S_half[n + i], S_half[2 * n + i],
+                      S_half[3 * n + i], S_half[4 * n + i]),
+            flags, FLAG_NONFINITE);
 }
 
 // Per run: the next substep from the reduced minimum, the run's clock
@@ -337,11 +351,11 @@ sph_status launch_step_state(Ctx *ctx, int64_t n, sph_precision prec, const doub
     if (prec == SPH_FP32_CELLREL)
         hipLaunchKernelGGL((k_state<true>), dim3(nb), dim3(256), 0, s, n, ctx->posh64,
                            ctx->posh32, rho, omega, up, vpx, vpy, vpz, m, mat, fixed, mt, tau,
-                           S_half, Sdot, P, cs, T, Y, Gmod, S_pred, ctx->rec_f);
+                           S_half, Sdot, P, cs, T, Y, Gmod, S_pred, ctx->rec_f, ctx->flags);
     else
         hipLaunchKernelGGL((k_state<false>), dim3(nb), dim3(256), 0, s, n, ctx->posh64,
                            ctx->posh32, rho, omega, up, vpx, vpy, vpz, m, mat, fixed, mt, tau,
-                           S_half, Sdot, P, cs, T, Y, Gmod, S_pred, ctx->rec_f);
+                           S_half, Sdot, P, cs, T, Y, Gmod, S_pred, ctx->rec_f, ctx->flags);
     SPH_HIP(hipGetLastError());
     return SPH_OK;
 }
@@ -354,7 +368,7 @@ sph_status launch_step_grad_rate(Ctx *ctx, int64_t n, const sph_params *prm, int
     if (n == 0) return SPH_OK;
     hipLaunchKernelGGL(k_grad_rate, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n,
                        (const void *)ctx->gsum, gsum_f32, ctx->ncount, prm->use_correction_tensor, S_pred, Gmod, fixed,
-                       prm->rot_sign, tau, act, G, Sdot, eps2, n_singular);
+                       prm->rot_sign, tau, act, G, Sdot, eps2, n_singular, ctx->flags);
     SPH_HIP(hipGetLastError());
     return SPH_OK;
 }
@@ -371,7 +385,7 @@ sph_status launch_step_kick(Ctx *ctx, int64_t n, int32_t mode, const double *dt,
     if (m == 0) return SPH_OK;
     hipLaunchKernelGGL(k_kick_all, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, n, mode,
                        dt, bits_cur, dt_cap, dt_next, bits_clear, nr, runid, fixed, vx, vy, vz, u,
-                       ax, ay, az, dudt, S_half, S_pred, Sdot, Y);
+                       ax, ay, az, dudt, S_half, S_pred, Sdot, Y, ctx->flags);
     SPH_HIP(hipGetLastError());
     return SPH_OK;
 }

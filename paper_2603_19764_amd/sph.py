@@ -106,7 +106,7 @@ def lib():
             "sph_gradients": [_P, i64] + [_P] * 7 + [C.POINTER(sph_params), i32, _P, _P, _P],
             "sph_stress_update": [_P, i32, i64] + [_P] * 6 + [C.POINTER(sph_params)] + [_P] * 5,
             "sph_forces_stress": [_P, i64] + [_P] * 10 + [C.POINTER(sph_params), i32] + [_P] * 6,
-            "sph_kick_drift": [_P, i32, i64] + [_P] * 18,
+            "sph_kick_drift": [_P, i32, i64] + [_P] * 19,
             "sph_dt_min": [_P, i64, _P, _P, _P, _P],
             "sph_diagnostics": [_P, i64] + [_P] * 13,
             "sph_init": [_P, C.POINTER(sph_state), C.POINTER(sph_material), i32,

@@ -55,6 +55,32 @@ def test_null_context_and_bad_create_arguments(lib):
     assert lib.sph_last_error(None) == b"null context"
 
 
+def declared_arity():
+    """Number of parameters of every function declared in the header."""
+    src = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    out = {}
+    for m in re.finditer(r"\b(sph_[a-z0-9_]+)\s*\(([^;{]*?)\)\s*;", src):
+        args = m.group(2).strip()
+        out[m.group(1)] = 0 if args in ("", "void") else args.count(",") + 1
+    return out
+
+
+def test_binding_signatures_match_the_header():
+    """Every entry point the Python binding declares takes as many arguments
+    as the header gives it (a missing one would shift the stream handle)."""
+    from paper_2603_19764_amd import sph
+    L = sph.lib()
+    arity = declared_arity()
+    checked = 0
+    for name, n in arity.items():
+        f = getattr(L, name)
+        if f.argtypes is None:
+            continue
+        assert len(f.argtypes) == n, (name, len(f.argtypes), n)
+        checked += 1
+    assert checked >= 25
+
+
 def test_product_path_does_not_reference_the_oracle():
     pkg = os.path.join(ROOT, "paper_2603_19764_amd")
     for dirpath, _, files in os.walk(pkg):
