@@ -136,6 +136,8 @@ typedef struct {
 sph_status sph_create(sph_ctx **ctx, int64_t capacity, int32_t max_neighbors,
                       int64_t max_cells, int32_t max_runs, int32_t device);
 sph_status sph_destroy(sph_ctx *ctx);
+/* Message of the last failure of `ctx`; with ctx = NULL, of the last failed
+ * context-free call (sph_diagnostics_noalloc) on the calling thread. */
 const char *sph_last_error(const sph_ctx *ctx);
 
 /* Synchronise `stream` and report (then clear) device-side flags:
@@ -296,6 +298,27 @@ sph_status sph_diagnostics(sph_ctx *ctx, int64_t n, const double *x, const doubl
                            const double *vz, const double *m, const double *ax,
                            const double *ay, const double *az, const double *dudt,
                            double *out13, sph_stream stream);
+
+/* The diagnostics above without a context, for callers that cannot allocate
+ * device memory (code under hipGraph capture, tight serving loops, hosts
+ * that forbid hipMalloc): the same kernels and the same 13 results, bit for
+ * bit, with the partial sums kept in a fixed device array of the library
+ * (256 x 13 doubles, 26,624 bytes) that each GPU holds from the first call
+ * on it until the process ends.  Runs on the current device; `stream` must
+ * belong to it.  Allocates nothing and needs no initialisation by the
+ * caller (the first call on a device looks up the array's address).  Every
+ * call on a GPU shares its array, so calls that overlap on one GPU (two
+ * streams, two host threads) race and may return wrong sums; calls in
+ * sequence on one stream are safe (each call overwrites every partial sum it
+ * reads).  n at most SPH_NOALLOC_MAX_N (the library's particle limit);
+ * SPH_EINVAL for a larger n or a null array, with the reason in
+ * sph_last_error(NULL). */
+#define SPH_NOALLOC_MAX_N ((int64_t)1 << 26)
+sph_status sph_diagnostics_noalloc(int64_t n, const double *x, const double *y,
+                                   const double *z, const double *vx, const double *vy,
+                                   const double *vz, const double *m, const double *ax,
+                                   const double *ay, const double *az, const double *dudt,
+                                   double *out13, sph_stream stream);
 
 /* ------------------------------------------------- adaptive smoothing length */
 

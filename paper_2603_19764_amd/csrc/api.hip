@@ -201,7 +201,11 @@ sph_status sph_destroy(sph_ctx *h) {
     return SPH_OK;
 }
 
-const char *sph_last_error(const sph_ctx *h) { return h ? h->c.err : "null context"; }
+const char *sph_last_error(const sph_ctx *h) {
+    if (h) return h->c.err;
+    const char *e = noalloc_last_error();
+    return e ? e : "null context";
+}
 
 sph_status sph_sync_status(sph_ctx *h, sph_stream stream) {
     CHECK_CTX();

@@ -4,6 +4,11 @@
 // rescaling eq.), Jaumann stress rate (Deviatoric_Stress_derivative eq.),
 // closing and opening kicks (sec. 2.4), drift, global time step from the
 // CFL condition, and conservation diagnostics.
+#include <stdarg.h>
+#include <stdio.h>
+
+#include <mutex>
+
 #include "physics.h"
 
 namespace sph {
@@ -293,16 +298,98 @@ __global__ void k_diag_final(const double *part, double *out) {
     out[k] = s;
 }
 
+// The two kernels of the diagnostics with the partial sums in `part`
+// (kDiagBlocks x 13 doubles, every entry written before it is read).
+static void diag_kernels(int64_t n, const double *x, const double *y, const double *z,
+                         const double *vx, const double *vy, const double *vz, const double *m,
+                         const double *ax, const double *ay, const double *az,
+                         const double *dudt, double *part, double *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_diag, dim3(kDiagBlocks), dim3(256), 0, s, n, x, y, z, vx, vy, vz, m, ax,
+                       ay, az, dudt, part);
+    hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(64), 0, s, part, out);
+}
+
 sph_status launch_diag(Ctx *ctx, int64_t n, const double *x, const double *y, const double *z,
                        const double *vx, const double *vy, const double *vz, const double *m,
                        const double *ax, const double *ay, const double *az,
                        const double *dudt, double *out, hipStream_t s) {
-    hipLaunchKernelGGL(k_diag, dim3(kDiagBlocks), dim3(256), 0, s, n, x, y, z, vx, vy, vz, m, ax,
-                       ay, az, dudt, ctx->diag);
-    hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(64), 0, s, ctx->diag, out);
+    diag_kernels(n, x, y, z, vx, vy, vz, m, ax, ay, az, dudt, ctx->diag, out, s);
     SPH_HIP(hipGetLastError());
     return SPH_OK;
 }
+
+// ------------------------------------- diagnostics without a context
+// The partial sums of sph_diagnostics_noalloc live in this array (26,624
+// bytes).  Host code never passes its name to a kernel: the device address
+// of each GPU's copy is looked up once per device, with that device
+// current, and kept in g_scratch.
+constexpr int kNoAllocDoubles = kDiagBlocks * 13;
+static __device__ __align__(256) double scratch[kNoAllocDoubles];
+
+constexpr int kNoAllocMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static double *g_scratch[kNoAllocMaxDevices];
+static thread_local char g_noalloc_err[256];
+
+static sph_status noalloc_fail(sph_status code, const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_noalloc_err, sizeof g_noalloc_err, fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+const char *noalloc_last_error() { return g_noalloc_err[0] ? g_noalloc_err : nullptr; }
+
+// Device address of the current device's scratch (looked up on first use).
+static sph_status noalloc_scratch(double **out) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess)
+        return noalloc_fail(SPH_EHIP, "hipGetDevice: %s", hipGetErrorString(e));
+    if (dev < 0 || dev >= kNoAllocMaxDevices)
+        return noalloc_fail(SPH_EINVAL, "device %d beyond the %d supported", dev,
+                            kNoAllocMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return noalloc_fail(SPH_EHIP, "hipGetSymbolAddress(scratch) on device %d: %s", dev,
+                                hipGetErrorString(e));
+        g_scratch[dev] = (double *)p;
+    }
+    *out = g_scratch[dev];
+    return SPH_OK;
+}
+
+}  // namespace sph
+
+extern "C" sph_status sph_diagnostics_noalloc(int64_t n, const double *x, const double *y,
+                                              const double *z, const double *vx,
+                                              const double *vy, const double *vz,
+                                              const double *m, const double *ax,
+                                              const double *ay, const double *az,
+                                              const double *dudt, double *out13,
+                                              sph_stream stream) {
+    using namespace sph;
+    g_noalloc_err[0] = 0;
+    if (n < 0 || n > SPH_NOALLOC_MAX_N)
+        return noalloc_fail(SPH_EINVAL, "sph_diagnostics_noalloc: n = %lld outside [0, %lld]",
+                            (long long)n, (long long)SPH_NOALLOC_MAX_N);
+    if (!out13 || (n > 0 && !(x && y && z && vx && vy && vz && m && ax && ay && az && dudt)))
+        return noalloc_fail(SPH_EINVAL, "sph_diagnostics_noalloc: null array");
+    double *part = nullptr;
+    sph_status st = noalloc_scratch(&part);
+    if (st != SPH_OK) return st;
+    diag_kernels(n, x, y, z, vx, vy, vz, m, ax, ay, az, dudt, part, out13, (hipStream_t)stream);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return noalloc_fail(SPH_EHIP, "sph_diagnostics_noalloc launch: %s", hipGetErrorString(e));
+    return SPH_OK;
+}
+
+namespace sph {
 
 __global__ void k_copy_u64(const unsigned long long *src, unsigned long long *dst) { *dst = *src; }
 

@@ -240,6 +240,8 @@ sph_status launch_diag(Ctx *ctx, int64_t n, const double *x, const double *y, co
                        const double *ax, const double *ay, const double *az,
                        const double *dudt, double *out, hipStream_t s);
 sph_status launch_fill_i32(Ctx *ctx, int32_t *p, int32_t v, int64_t n, hipStream_t s);
+// Message of the last failed context-free call on this thread (or NULL).
+const char *noalloc_last_error();
 // pair kernels alone (records already written)
 sph_status launch_density_pairs(Ctx *ctx, int64_t n, const sph_params *prm, sph_precision prec,
                                 double *rho, double *omega, hipStream_t s);

@@ -109,6 +109,7 @@ def lib():
             "sph_kick_drift": [_P, i32, i64] + [_P] * 19,
             "sph_dt_min": [_P, i64, _P, _P, _P, _P],
             "sph_diagnostics": [_P, i64] + [_P] * 13,
+            "sph_diagnostics_noalloc": [i64] + [_P] * 13,
             "sph_init": [_P, C.POINTER(sph_state), C.POINTER(sph_material), i32,
                          C.POINTER(sph_params), i32, _P],
             "sph_step": [_P, C.POINTER(sph_state), C.POINTER(sph_material), i32,
@@ -393,6 +394,17 @@ def sph_dt_min(ctx: Context, dt_cfl, fixed, dt_out, stream=None):
 def sph_diagnostics(ctx: Context, x, y, z, vx, vy, vz, m, ax, ay, az, dudt, out13, stream=None):
     ctx.check(lib().sph_diagnostics(ctx.h, m.numel(), *[_ptr(t) for t in (
         x, y, z, vx, vy, vz, m, ax, ay, az, dudt, out13)], _stream(stream)))
+
+
+def sph_diagnostics_noalloc(x, y, z, vx, vy, vz, m, ax, ay, az, dudt, out13, n=None,
+                            stream=None):
+    """sph_diagnostics without a context (no allocation by the library);
+    ``n`` defaults to the length of ``m``."""
+    n = m.numel() if n is None else int(n)
+    code = lib().sph_diagnostics_noalloc(n, *[_ptr(t) for t in (
+        x, y, z, vx, vy, vz, m, ax, ay, az, dudt, out13)], _stream(stream))
+    if code != SPH_OK:
+        raise SphError(code, (lib().sph_last_error(None) or b"").decode())
 
 
 def sph_init(ctx: Context, st: "State", mats, prm, prec, stream=None):
