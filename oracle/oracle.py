@@ -288,6 +288,19 @@ def _targets(n, targets):
     return np.ascontiguousarray(targets, dtype=np.int64)
 
 
+def pair_counts(x, y, z, h, prm: dict, targets=None):
+    """|N_i| for the targets by brute force (one sweep over all particles
+    per target)."""
+    x, y, z, h = map(_f64, (x, y, z, h))
+    n = x.size
+    tar = _targets(n, targets)
+    p = params(prm)
+    cnt = np.empty(tar.size, dtype=np.int64)
+    lib().or_pair_counts(C.c_int64(n), _p(x), _p(y), _p(z), _p(h), C.byref(p),
+                         C.c_int64(tar.size), _p(tar, _I64), _p(cnt, _I64))
+    return cnt
+
+
 def pair_lists(x, y, z, h, prm: dict, targets=None):
     """Brute-force pair sets N_i (ascending j) for the targets.
 
@@ -387,20 +400,39 @@ def forces(x, y, z, vx, vy, vz, m, h, rho, omega, P, cs, S, prm: dict, targets=N
     return a, du, dt
 
 
+def term_scales(x, y, z, vx, vy, vz, m, h, rho, omega, P, cs, S, Gam, prm: dict,
+                targets=None):
+    """Per-particle scales of the pair sums (sum over the pair set of the
+    magnitude of each pair's contribution): returns dict a, dudt, G, dS of
+    (n,) arrays (NaN where not computed).  S is the rescaled predicted stress
+    the passes use; Gam the shear modulus."""
+    arrs = list(map(_f64, (x, y, z, vx, vy, vz, m, h, rho, omega, P, cs)))
+    S, Gam = _f64(S), _f64(Gam)
+    n = arrs[0].size
+    tar = _targets(n, targets)
+    out = {k: np.full(n, np.nan) for k in ("a", "dudt", "G", "dS")}
+    p = params(prm)
+    lib().or_term_scales(C.c_int64(n), *[_p(v) for v in arrs], _p(S), _p(Gam), C.byref(p),
+                         C.c_int64(tar.size), _p(tar, _I64), _p(out["a"]), _p(out["dudt"]),
+                         _p(out["G"]), _p(out["dS"]))
+    return out
+
+
 def closure(x, y, z, h, prm: dict, targets):
     """Targets together with every member of their pair sets (sorted)."""
     off, nbr, _ = pair_lists(x, y, z, h, prm, targets)
     return np.unique(np.concatenate([np.asarray(targets, dtype=np.int64), nbr]))
 
 
-def derivs(st: dict, mats: list, prm: dict, targets=None):
+def derivs(st: dict, mats: list, prm: dict, targets=None, scales=False):
     """One derivative evaluation of the strength-SPH step.
 
     ``st`` holds x, y, z, m, h, mat, the predicted velocity vx, vy, vz, the
     predicted energy u and the predicted (not yet rescaled) stress S (5,n).
     The density, EOS, yield and rescaling run on the targets and their pair
     sets; gradients, stress rate and forces on the targets.  Returns a dict of
-    full-length arrays (NaN where not computed).
+    full-length arrays (NaN where not computed); with ``scales`` also
+    ``scale``, the per-particle scales of the pair sums (``term_scales``).
     """
     x, y, z, h = st["x"], st["y"], st["z"], st["h"]
     n = np.asarray(x).size
@@ -413,8 +445,12 @@ def derivs(st: dict, mats: list, prm: dict, targets=None):
     dS, e2 = stress_rate(G, Sp, Gam, prm["rot_sign"], tar)
     a, du, dt = forces(x, y, z, st["vx"], st["vy"], st["vz"], st["m"], h, rho, om, P, c, Sp,
                        prm, tar)
-    return dict(rho=rho, omega=om, P=P, c=c, T=T, Y=Y, Gam=Gam, S_pred=Sp, G=G, dS=dS,
-                eps2_rate=e2, a=a, dudt=du, dt=dt, n_singular=nsing, targets=tar)
+    out = dict(rho=rho, omega=om, P=P, c=c, T=T, Y=Y, Gam=Gam, S_pred=Sp, G=G, dS=dS,
+               eps2_rate=e2, a=a, dudt=du, dt=dt, n_singular=nsing, targets=tar)
+    if scales:
+        out["scale"] = term_scales(x, y, z, st["vx"], st["vy"], st["vz"], st["m"], h, rho, om,
+                                   P, c, Sp, Gam, prm, tar)
+    return out
 
 
 class Integrator:

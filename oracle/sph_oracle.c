@@ -851,6 +851,133 @@ void or_forces(int64_t n, const double *x, const double *y, const double *z,
 }
 
 /* ----------------------------------------------------------------------- */
+/* Scales of the pair sums, for per-particle error metrics: for each target */
+/* the sum over its pair set of the magnitude of each pair's contribution   */
+/* to the result,                                                           */
+/*   sa_i  = sum_j | m_j [-(P_i/o_i dW_i + P_j/o_j dW_j)                    */
+/*                        + (S_i/o_i dW_i + S_j/o_j dW_j)] - m_j Pi dWbar | */
+/*   sdu_i = sum_j | P_i/o_i m_j v.dW_i - S_i/o_i : m_j v (x) dW_i          */
+/*                   + 1/2 m_j Pi v.dWbar |                                 */
+/*   sG_i  = sum_j | g_ij |_F,  g_ij = -1/2 m_j v (x) gw_ij C_i, the pair's */
+/*           share of G_i = F_i C_i (Velocity_Gradient, Corrected_Gradients)*/
+/*   sdS_i = sum_j | dS(g_ij) |, the same share of the stress rate (the     */
+/*           rate is linear in G at fixed S; 5 stored components)           */
+/* with o = Omega rho^2 and the AV term only for approaching pairs, as in   */
+/* or_forces and or_gradients.  Triangle inequality: |a_i - g| <= sa_i etc. */
+/* ----------------------------------------------------------------------- */
+void or_term_scales(int64_t n, const double *x, const double *y, const double *z,
+                    const double *vx, const double *vy, const double *vz,
+                    const double *m, const double *h, const double *rho,
+                    const double *omega, const double *P, const double *cs,
+                    const double *S, const double *Gam, const or_params *p,
+                    int64_t nt, const int64_t *tar,
+                    double *sa, double *sdu, double *sG, double *sdS)
+{
+    const double al = p->av_alpha, be = p->av_beta, eps = p->av_eps;
+    #pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t k = 0; k < nt; ++k) {
+        int64_t i = tar[k];
+        double Si[3][3], s5[5];
+        for (int c = 0; c < 5; ++c) s5[c] = S[c * n + i];
+        S_full(s5, Si);
+        double Hi2 = supp2(h[i]);
+        double oi = omega[i] * rho[i] * rho[i];
+        double wi = 1.0 / (omega[i] * rho[i]);
+        double d[3];
+        /* the correction tensor of i, as in or_gradients */
+        double Ci[3][3] = {{0}};
+        int64_t cnt = 0;
+        for (int64_t j = 0; j < n; ++j) {
+            if (j == i) continue;
+            double r2 = sep2(x, y, z, i, j, p->box, d);
+            double Hj2 = supp2(h[j]);
+            if (!(r2 < (Hi2 > Hj2 ? Hi2 : Hj2))) continue;
+            ++cnt;
+            double r = sqrt(r2);
+            double Ki = or_K(r, h[i]), Kj = or_K(r, h[j]);
+            double wj = 1.0 / (omega[j] * rho[j]);
+            for (int a = 0; a < 3; ++a)
+                for (int b = 0; b < 3; ++b)
+                    Ci[a][b] -= 0.5 * m[j] * d[a] * (Ki * d[b] * wi + Kj * d[b] * wj);
+        }
+        double Cm[3][3];
+        int ok = 0;
+        if (p->use_correction) {
+            double fro = 0.0;
+            for (int a = 0; a < 3; ++a)
+                for (int b = 0; b < 3; ++b) fro += Ci[a][b] * Ci[a][b];
+            fro = sqrt(fro);
+            double det;
+            ok = inverse3(Ci, Cm, &det);
+            if (!ok || cnt < 4 || fabs(det) < 1e-12 * fro * fro * fro) ok = 0;
+        }
+        if (!ok)
+            for (int a = 0; a < 3; ++a)
+                for (int b = 0; b < 3; ++b) Cm[a][b] = (a == b) ? 1.0 : 0.0;
+        double ta = 0.0, tdu = 0.0, tG = 0.0, tdS = 0.0;
+        for (int64_t j = 0; j < n; ++j) {
+            if (j == i) continue;
+            double r2 = sep2(x, y, z, i, j, p->box, d);
+            double Hj2 = supp2(h[j]);
+            if (!(r2 < (Hi2 > Hj2 ? Hi2 : Hj2))) continue;
+            double r = sqrt(r2);
+            double Ki = or_K(r, h[i]), Kj = or_K(r, h[j]);
+            double oj = omega[j] * rho[j] * rho[j];
+            double wj = 1.0 / (omega[j] * rho[j]);
+            double Sj[3][3], t5[5];
+            for (int c = 0; c < 5; ++c) t5[c] = S[c * n + j];
+            S_full(t5, Sj);
+            double v[3] = { vx[i] - vx[j], vy[i] - vy[j], vz[i] - vz[j] };
+            double dWi[3] = { Ki * d[0], Ki * d[1], Ki * d[2] };
+            double dWj[3] = { Kj * d[0], Kj * d[1], Kj * d[2] };
+            double ta3[3], tu = 0.0;
+            for (int a = 0; a < 3; ++a) {
+                double sum = 0.0;
+                for (int b = 0; b < 3; ++b)
+                    sum += Si[a][b] / oi * dWi[b] + Sj[a][b] / oj * dWj[b];
+                ta3[a] = -m[j] * (P[i] / oi * dWi[a] + P[j] / oj * dWj[a]) + m[j] * sum;
+            }
+            tu += P[i] / oi * m[j] * (v[0] * dWi[0] + v[1] * dWi[1] + v[2] * dWi[2]);
+            for (int a = 0; a < 3; ++a)
+                for (int b = 0; b < 3; ++b) tu -= Si[a][b] / oi * m[j] * v[a] * dWi[b];
+            double vr = v[0] * d[0] + v[1] * d[1] + v[2] * d[2];
+            if (vr < 0.0) {
+                double hb = 0.5 * (h[i] + h[j]);
+                double mu = hb * vr / (r2 + eps * hb * hb);
+                double cb = 0.5 * (cs[i] + cs[j]);
+                double rb = 0.5 * (rho[i] + rho[j]);
+                double Pi = (-al * cb * mu + be * mu * mu) / rb;
+                double dWb[3];
+                for (int a = 0; a < 3; ++a) dWb[a] = 0.5 * (dWi[a] + dWj[a]);
+                for (int a = 0; a < 3; ++a) ta3[a] -= m[j] * Pi * dWb[a];
+                tu += 0.5 * m[j] * Pi * (v[0] * dWb[0] + v[1] * dWb[1] + v[2] * dWb[2]);
+            }
+            ta += sqrt(ta3[0] * ta3[0] + ta3[1] * ta3[1] + ta3[2] * ta3[2]);
+            tdu += fabs(tu);
+            /* the pair's share of G: -1/2 m_j v (x) gw, times C */
+            double g9[9], gg = 0.0;
+            for (int a = 0; a < 3; ++a)
+                for (int b = 0; b < 3; ++b) {
+                    double acc = 0.0;
+                    for (int c = 0; c < 3; ++c)
+                        acc += -0.5 * m[j] * v[a] * (Ki * d[c] * wi + Kj * d[c] * wj) * Cm[c][b];
+                    g9[3 * a + b] = acc;
+                    gg += acc * acc;
+                }
+            tG += sqrt(gg);
+            double ds5[5];
+            or_stress_rate_one(g9, s5, Gam[i], p->rot_sign, ds5, NULL);
+            tdS += sqrt(ds5[0] * ds5[0] + ds5[1] * ds5[1] + ds5[2] * ds5[2] + ds5[3] * ds5[3] +
+                        ds5[4] * ds5[4]);
+        }
+        sa[i] = ta;
+        sdu[i] = tdu;
+        sG[i] = tG;
+        sdS[i] = tdS;
+    }
+}
+
+/* ----------------------------------------------------------------------- */
 /* Full state integrator (used by multi-step tests).                        */
 /* ----------------------------------------------------------------------- */
 typedef struct {

@@ -503,3 +503,46 @@ def test_tabulated_melting_temperature(orc):
         f = orc.yield_strength(tab, P, T, rho)[0] / y0
         tm_back = T * (1.0 + math.atanh(f) / base["xi"])
         assert math.isclose(tm_back, tm, rel_tol=1e-10)
+
+
+# ------------------------------------------------ scales of the pair sums
+def _scale_case(orc, w):
+    st = {k: w[k] for k in ("x", "y", "z", "m", "h", "mat", "vx", "vy", "vz", "u", "S")}
+    return orc.derivs(st, w["mats"], w["params"], scales=True)
+
+
+@pytest.mark.parametrize("variant", ["", "s", "y"])
+def test_term_scales_bound_the_sums(orc, variant):
+    """Each per-particle scale is the sum of the magnitudes of the pair
+    contributions, so it bounds the magnitude of their sum (triangle
+    inequality) for a, du/dt, G and the stress rate; where the sum cancels
+    (an interior particle of the block under near-uniform stress) it is far
+    larger than the result."""
+    w = inputs.c1_block(10, variant=variant)
+    ref = _scale_case(orc, w)
+    sc = ref["scale"]
+    g = np.asarray(w["params"]["g"])[:, None]
+    mag = dict(a=np.linalg.norm(ref["a"] - g, axis=0), dudt=np.abs(ref["dudt"]),
+               G=np.linalg.norm(ref["G"], axis=0), dS=np.linalg.norm(ref["dS"], axis=0))
+    for k in ("a", "dudt", "G", "dS"):
+        assert np.all(mag[k] <= sc[k] * (1 + 1e-12) + 1e-300), k
+        assert np.all(sc[k] > 0), k
+    assert np.median(mag["a"] / sc["a"]) < 0.5
+
+
+def test_term_scales_of_an_isolated_pair_are_the_results(orc):
+    """Two particles: each result is a single pair term, so its magnitude is
+    its scale (an approaching pair under stress, so the pressure, stress and
+    viscosity parts all enter; with two particles C is the identity)."""
+    mat = inputs.basalt_c1()
+    w = dict(x=np.array([0.3, -0.4]), y=np.array([0.1, 0.2]), z=np.array([-0.2, 0.25]),
+             vx=np.array([-2.0, 3.0]), vy=np.array([0.5, -1.0]), vz=np.array([1.0, 0.0]),
+             m=np.array([2700.0, 2500.0]), h=np.array([1.0, 1.2]), u=np.array([1e4, 2e4]),
+             S=np.array([[3e6, -1e6], [1e6, 2e6], [-2e6, 5e5], [4e5, -3e5], [1e5, 7e5]]),
+             mat=np.zeros(2, np.int32), mats=[mat], params=inputs.default_params())
+    ref = _scale_case(orc, w)
+    sc = ref["scale"]
+    np.testing.assert_allclose(np.linalg.norm(ref["a"], axis=0), sc["a"], rtol=1e-13)
+    np.testing.assert_allclose(np.abs(ref["dudt"]), sc["dudt"], rtol=1e-13)
+    np.testing.assert_allclose(np.linalg.norm(ref["G"], axis=0), sc["G"], rtol=1e-13)
+    np.testing.assert_allclose(np.linalg.norm(ref["dS"], axis=0), sc["dS"], rtol=1e-13)
