@@ -522,7 +522,11 @@ sph_status sph_timing_read(sph_ctx *ctx, int32_t which, double *total_ms, int64_
  *   SPH_TUNE_CELL_SCALE cell edge = max(cell_min, scale * 2 h_max), scale in
  *                      permille, 1000..2000 (precision ignored);
  *   SPH_TUNE_BUILD_RANGE sorted particles per work-group of the pair-list
- *                      build: 32, 64, 96 or 128 (precision ignored). */
+ *                      build: 32, 64, 96 or 128 (precision ignored);
+ *   SPH_TUNE_SWEEP_DEPTH neighbour records in flight per lane of the fused
+ *                      gradient + force sweep of sph_step: 1 or 2 (per
+ *                      precision; 2 hides more latency, 1 needs fewer
+ *                      registers and so runs more waves per SIMD). */
 enum {
     SPH_TUNE_LANES_DENSITY = 0,   /* density sweep                         */
     SPH_TUNE_LANES_GRADIENTS = 1, /* public gradient pass                  */
@@ -530,7 +534,8 @@ enum {
     SPH_TUNE_LANES_STEP = 3,      /* fused gradient + force sweep of sph_step */
     SPH_TUNE_CELL_SCALE = 4,
     SPH_TUNE_BUILD_RANGE = 5,
-    SPH_TUNE_COUNT = 6
+    SPH_TUNE_SWEEP_DEPTH = 6,
+    SPH_TUNE_COUNT = 7
 };
 sph_status sph_set_tuning(sph_ctx *ctx, int32_t knob, sph_precision prec, int32_t value);
 sph_status sph_get_tuning(sph_ctx *ctx, int32_t knob, sph_precision prec, int32_t *value);

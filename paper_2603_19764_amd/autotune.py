@@ -20,9 +20,11 @@ from . import sph
 LANES = (8, 4, 16)   # default first
 CELL_SCALES = (1000, 1150, 1300)   # permille of 2 h_max
 BUILD_RANGES = (64, 32, 96, 128)   # sorted particles per pair-list build work-group (default first)
+SWEEP_DEPTHS = (2, 1)   # neighbour records in flight per lane of the fused sweep
 
 # knob -> (timer whose per-launch time decides it, candidate values)
 PLAN = (
+    (sph.SPH_TUNE_SWEEP_DEPTH, sph.SPH_T_FORCES, SWEEP_DEPTHS),
     (sph.SPH_TUNE_LANES_STEP, sph.SPH_T_FORCES, LANES),
     (sph.SPH_TUNE_LANES_DENSITY, sph.SPH_T_DENSITY, LANES),
     (sph.SPH_TUNE_CELL_SCALE, None, CELL_SCALES),   # None: whole-step time
@@ -30,7 +32,7 @@ PLAN = (
 )
 KNOB_NAMES = {sph.SPH_TUNE_LANES_STEP: "lanes_step", sph.SPH_TUNE_LANES_DENSITY: "lanes_density",
               sph.SPH_TUNE_CELL_SCALE: "cell_scale_permille",
-              sph.SPH_TUNE_BUILD_RANGE: "build_range"}
+              sph.SPH_TUNE_BUILD_RANGE: "build_range", sph.SPH_TUNE_SWEEP_DEPTH: "sweep_depth"}
 
 
 def size_bucket(n: int) -> int:

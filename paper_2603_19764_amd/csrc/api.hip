@@ -806,6 +806,12 @@ sph_status sph_set_tuning(sph_ctx *h, int32_t knob, sph_precision prec, int32_t 
         ctx->build_range = value;
         return SPH_OK;
     }
+    if (knob == SPH_TUNE_SWEEP_DEPTH) {
+        REQUIRE(value == 1 || value == 2, SPH_EINVAL, "sweep depth must be 1 or 2 (got %d)",
+                value);
+        ctx->sweep_depth[prec == SPH_FP32_CELLREL ? 1 : 0] = value;
+        return SPH_OK;
+    }
     REQUIRE(value == 4 || value == 8 || value == 16, SPH_EINVAL,
             "lanes per particle must be 4, 8 or 16 (got %d)", value);
     ctx->lanes[knob][prec == SPH_FP32_CELLREL ? 1 : 0] = value;
@@ -817,9 +823,11 @@ sph_status sph_get_tuning(sph_ctx *h, int32_t knob, sph_precision prec, int32_t 
     REQUIRE(knob >= 0 && knob < SPH_TUNE_COUNT && value, SPH_EINVAL, "bad argument");
     REQUIRE(prec == SPH_FP64 || prec == SPH_FP32_CELLREL, SPH_EINVAL, "bad precision");
     const Ctx *ctx = &h->c;
+    const int pi = prec == SPH_FP32_CELLREL ? 1 : 0;
     *value = knob == SPH_TUNE_CELL_SCALE    ? (int32_t)(ctx->cell_scale * 1000.0 + 0.5)
              : knob == SPH_TUNE_BUILD_RANGE ? ctx->build_range
-                                            : ctx->lanes[knob][prec == SPH_FP32_CELLREL ? 1 : 0];
+             : knob == SPH_TUNE_SWEEP_DEPTH ? ctx->sweep_depth[pi]
+                                            : ctx->lanes[knob][pi];
     return SPH_OK;
 }
 

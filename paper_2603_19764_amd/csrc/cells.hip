@@ -438,6 +438,12 @@ constexpr int kIBatch = 64;
 constexpr double kCullMargin = 1.0 + 0x1p-40;
 
 __device__ __forceinline__ uint64_t wave_ballot(bool b) { return __builtin_amdgcn_ballot_w64(b); }
+// This lane's bit of a wave mask, as a lane predicate (no vector instruction).
+__device__ __forceinline__ bool lane_bit(uint64_t m) { return __builtin_amdgcn_inverse_ballot_w64(m); }
+// Number of set bits of m below this lane.
+__device__ __forceinline__ uint32_t lanes_below(uint64_t m) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
 
 __global__ __launch_bounds__(64) void k_build_pairs(
     int64_t n, const double4 *__restrict__ posh64, const uint32_t *__restrict__ skey,
@@ -602,11 +608,25 @@ __global__ __launch_bounds__(64) void k_build_pairs(
                     }
                     r0 += nch * kWave;
                 }
-                __syncthreads();
                 // full columns only while raw candidates remain; the ragged
-                // rest is carried to the front of the tile for the next chunk
-                const int cols = r0 < T ? (fill / kWave) * kWave : fill;
-                // ---- tests: four i at a time against every column of the tile
+                // rest is carried to the front of the tile for the next chunk.
+                // After the last chunk the ragged column is padded with
+                // entries that pair with nothing (NaN position), so every
+                // lane of every column loads and tests without a bounds check.
+                int cols = (fill / kWave) * kWave;
+                if (r0 >= T && cols < fill) {
+                    cols += kWave;
+                    if (fill + lane < cols) {
+                        tpos[fill + lane] = make_double4(NAN, NAN, NAN, -1.0);
+                        tj[fill + lane] = 0u;
+                    }
+                }
+                __syncthreads();
+                // ---- tests: four i at a time against every column of the tile.
+                // The masks are wave ballots of the compares (scalar
+                // registers); a lane stores when its bit is set, at the
+                // particle's running count plus the hits below it.  Whether
+                // the row can overflow is decided once per column (scalar).
                 for (int q0 = 0; q0 < ni; q0 += 4) {
                     const int l = ni - 1;
                     const int q1 = q0 + 1 < l ? q0 + 1 : l, q2 = q0 + 2 < l ? q0 + 2 : l,
@@ -615,23 +635,20 @@ __global__ __launch_bounds__(64) void k_build_pairs(
                     const int qq[4] = {q0, q1, q2, q3};
                     double H2[4];
                     int base[4];
+                    uint32_t self[4];
                     uint32_t *row[4];
 #pragma unroll
                     for (int k = 0; k < 4; ++k) {
                         const double H = 2.0 * P[k].w;
                         H2[k] = __dmul_rn(H, H);
                         base[k] = __builtin_amdgcn_readlane(cnt_reg, qq[k]);
+                        self[k] = (uint32_t)(ib + qq[k]);
                         row[k] = nbr + (ib + qq[k]) * (int64_t)K;
                     }
                     const int nk = ni - q0 < 4 ? ni - q0 : 4;  // distinct i in this group
                     for (int col = 0; col < cols; col += kWave) {
-                        const int s = col + lane;
-                        double4 c = make_double4(NAN, 0.0, 0.0, -1.0);
-                        uint32_t e = 0;
-                        if (s < cols) {
-                            c = tpos[s];
-                            e = tj[s];
-                        }
+                        const double4 c = tpos[col + lane];
+                        const uint32_t e = tj[col + lane];
                         const uint32_t jj = e & kIdxMask;
                         const uint32_t ed = e | kDensityBit;
 #pragma unroll
@@ -639,16 +656,24 @@ __global__ __launch_bounds__(64) void k_build_pairs(
                             if (k < nk) {
                                 const double r2 =
                                     sep2_exact(P[k].x, P[k].y, P[k].z, c.x, c.y, c.z);
-                                const bool dens = r2 < H2[k];
-                                const bool hit =
-                                    (dens || r2 < c.w) && jj != (uint32_t)(ib + qq[k]);
-                                const uint64_t m = wave_ballot(hit);
-                                // slot = base + rank; rows hold at most K entries
-                                const uint32_t rank = __builtin_amdgcn_mbcnt_hi(
-                                    (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+                                const uint64_t md = wave_ballot(r2 < H2[k]);   // density set of i
+                                const uint64_t mj = wave_ballot(r2 < c.w);     // support of j
+                                const uint64_t ms = wave_ballot(jj == self[k]);
+                                const uint64_t m = (md | mj) & ~ms;
                                 const int b = base[k];
-                                if (hit && (int)rank < K - b) row[k][b + rank] = dens ? ed : e;
-                                base[k] = __builtin_amdgcn_readfirstlane(b + (int)__popcll(m));
+                                const int pc = (int)__popcll(m);
+                                char *dst = (char *)(row[k] + b);
+                                const uint32_t rank = lanes_below(m);
+                                const uint32_t v = lane_bit(md) ? ed : e;
+                                // rows hold at most K entries: checked per lane
+                                // only when this column could overflow the row
+                                if (b + pc <= K) {
+                                    if (lane_bit(m)) *(uint32_t *)(dst + (rank << 2)) = v;
+                                } else {
+                                    if (lane_bit(m) && (int)rank < K - b)
+                                        *(uint32_t *)(dst + (rank << 2)) = v;
+                                }
+                                base[k] = __builtin_amdgcn_readfirstlane(b + pc);
                             }
                         }
                     }
@@ -657,7 +682,7 @@ __global__ __launch_bounds__(64) void k_build_pairs(
                         if (k < nk && lane == qq[k]) cnt_reg = base[k];
                 }
                 // carry the kept candidates not tested yet (fewer than 64)
-                const int rest = fill - cols;
+                const int rest = fill > cols ? fill - cols : 0;
                 double4 cr = make_double4(0.0, 0.0, 0.0, 0.0);
                 uint32_t er = 0;
                 if (lane < rest) {

@@ -442,6 +442,9 @@ __global__ __launch_bounds__(kBlock) void k_forces(
 // written by the whole-step state kernel; A = sigma/(Omega rho^2)):
 //   (p, 1/H) (v, m) (m Kn A: xx yy zz xy) (m Kn A: xz yz, rho/2, c/2)
 //   (-m Kn/(2 Omega rho), m Kn/2, h/2, 1/m).
+// Depth 1 keeps one neighbour record in registers: 79 VGPRs in float (six
+// waves per SIMD, against four at 104 with two records) and 138 in double
+// (three waves against two).
 // Neighbour j's factors are used as stored; particle i's are divided by m_i
 // once, so every pair term carries m_j without a product of its own:
 //   -w_ij    = (m_j t_i^3) G_i + t_j^3 G'_j          (G = -Kn/(2 Omega rho))
@@ -451,8 +454,9 @@ __global__ __launch_bounds__(kBlock) void k_forces(
 // D = r^2 + eps h_bar^2:  mu = h_bar v.x rho_bar / (D rho_bar),
 // Pi = mu (beta mu - alpha c_bar) D / (D rho_bar).
 
-template <int L, bool F32>
-__global__ __launch_bounds__(kBlock) void k_grad_forces(
+template <int L, bool F32, int Depth>
+__global__ __launch_bounds__(kBlock)
+__attribute__((amdgpu_waves_per_eu(Depth == 1 ? (F32 ? 6 : 3) : 1, 8))) void k_grad_forces(
     int64_t n, const int16_t *__restrict__ runid, const GridDesc *__restrict__ grid,
     const uint32_t *__restrict__ nbr, const int32_t *__restrict__ ncount, int32_t K,
     const typename Real<F32>::T4 *__restrict__ rec, double al, double be, double eps,
@@ -491,9 +495,10 @@ __global__ __launch_bounds__(kBlock) void k_grad_forces(
         if constexpr (F32) L32 = grid[runid[i]].L32;
         const int c = ncount[i];
         const uint32_t *row = nbr + i * (int64_t)K;
-        // Software pipeline (see k_density): entry two ahead, record one
-        // ahead, unconditional loads; two record sets take turns, so no
-        // copies between iterations.
+        // Depth 2: software pipeline (see k_density): entry two ahead, record
+        // one ahead, unconditional loads; two record sets take turns, so no
+        // copies between iterations.  Depth 1: one record set, the next
+        // entry in flight (fewer registers, more waves per SIMD).
         auto body = [&](uint32_t e, const R4 &pj, const VM<R> &vj, const R4 &Aj, const R4 &Bj,
                         const R4 &Hj) {
                 R dx, dy, dz;
@@ -545,29 +550,42 @@ __global__ __launch_bounds__(kBlock) void k_grad_forces(
             const uint32_t v = row[k < K ? k : K - 1];
             return k < c ? v : (uint32_t)i;
         };
-        uint32_t e0 = entry(lg), e1 = entry(lg + L);
-        R4 P0, A0, B0, H0, P1, A1, B1, H1;
-        VM<R> V0, V1;
-        {
-            const R4 *rj = rec + kRecBothSlots<F32> * (int64_t)(e0 & kIdxMask);
-            P0 = rj[0]; V0 = load_vm<F32, R>(rj + 1); A0 = rj[1 + o]; B0 = rj[2 + o]; H0 = rj[3 + o];
-        }
-        for (int k = lg; k < c; k += 2 * L) {
-            const uint32_t e2 = entry(k + 2 * L);
+        if constexpr (Depth == 2) {
+            uint32_t e0 = entry(lg), e1 = entry(lg + L);
+            R4 P0, A0, B0, H0, P1, A1, B1, H1;
+            VM<R> V0, V1;
             {
-                const R4 *rj = rec + kRecBothSlots<F32> * (int64_t)(e1 & kIdxMask);
-                P1 = rj[0]; V1 = load_vm<F32, R>(rj + 1); A1 = rj[1 + o]; B1 = rj[2 + o]; H1 = rj[3 + o];
-            }
-            body(e0, P0, V0, A0, B0, H0);
-            if (k + L >= c) break;
-            const uint32_t e3 = entry(k + 3 * L);
-            {
-                const R4 *rj = rec + kRecBothSlots<F32> * (int64_t)(e2 & kIdxMask);
+                const R4 *rj = rec + kRecBothSlots<F32> * (int64_t)(e0 & kIdxMask);
                 P0 = rj[0]; V0 = load_vm<F32, R>(rj + 1); A0 = rj[1 + o]; B0 = rj[2 + o]; H0 = rj[3 + o];
             }
-            body(e1, P1, V1, A1, B1, H1);
-            e0 = e2;
-            e1 = e3;
+            for (int k = lg; k < c; k += 2 * L) {
+                const uint32_t e2 = entry(k + 2 * L);
+                {
+                    const R4 *rj = rec + kRecBothSlots<F32> * (int64_t)(e1 & kIdxMask);
+                    P1 = rj[0]; V1 = load_vm<F32, R>(rj + 1); A1 = rj[1 + o]; B1 = rj[2 + o]; H1 = rj[3 + o];
+                }
+                body(e0, P0, V0, A0, B0, H0);
+                if (k + L >= c) break;
+                const uint32_t e3 = entry(k + 3 * L);
+                {
+                    const R4 *rj = rec + kRecBothSlots<F32> * (int64_t)(e2 & kIdxMask);
+                    P0 = rj[0]; V0 = load_vm<F32, R>(rj + 1); A0 = rj[1 + o]; B0 = rj[2 + o]; H0 = rj[3 + o];
+                }
+                body(e1, P1, V1, A1, B1, H1);
+                e0 = e2;
+                e1 = e3;
+            }
+    
+        } else {
+            uint32_t en = entry(lg);
+            for (int k = lg; k < c; k += L) {
+                const uint32_t e = en;
+                en = entry(k + L);  // next entry in flight
+                const R4 *rj = rec + kRecBothSlots<F32> * (int64_t)(e & kIdxMask);
+                const R4 Pj = rj[0], Aj = rj[1 + o], Bj = rj[2 + o], Hj = rj[3 + o];
+                const VM<R> Vj = load_vm<F32, R>(rj + 1);
+                body(e, Pj, Vj, Aj, Bj, Hj);
+            }
         }
     }
     c_xx = group_sum<L>(c_xx); c_yy = group_sum<L>(c_yy); c_zz = group_sum<L>(c_zz);
@@ -749,27 +767,37 @@ sph_status launch_forces(Ctx *ctx, int64_t n, const double *vx, const double *vy
     return launch_force_pairs(ctx, n, prm, prec, ax, ay, az, dudt, dtc, s);
 }
 
-template <int L, bool F32>
+template <int L, bool F32, int D>
 static void both_launch(Ctx *ctx, int64_t n, const sph_params *prm, double *ax, double *ay,
                         double *az, double *dudt, double *dtc, const int32_t *act,
                         hipStream_t s) {
     using R4 = typename Real<F32>::T4;
     const int nb = (int)((n * L + kBlock - 1) / kBlock);
-    hipLaunchKernelGGL((k_grad_forces<L, F32>), dim3(nb), dim3(kBlock), 0, s, n, ctx->runid,
+    hipLaunchKernelGGL((k_grad_forces<L, F32, D>), dim3(nb), dim3(kBlock), 0, s, n, ctx->runid,
                        ctx->grid, ctx->nbr, ctx->ncount, ctx->max_nbr, (const R4 *)ctx->rec_f,
                        prm->av_alpha, prm->av_beta, prm->av_eps, prm->eta_C, prm->g[0], prm->g[1],
                        prm->g[2], ctx->gsum, ax, ay, az, dudt, dtc, act, ctx->flags);
+}
+
+template <bool F32, int D>
+static void both_dispatch_d(Ctx *ctx, int64_t n, const sph_params *prm, double *ax, double *ay,
+                            double *az, double *dudt, double *dtc, const int32_t *act,
+                            hipStream_t s) {
+    switch (lanes_of(ctx, SPH_TUNE_LANES_STEP, F32)) {
+        case 4: both_launch<4, F32, D>(ctx, n, prm, ax, ay, az, dudt, dtc, act, s); break;
+        case 16: both_launch<16, F32, D>(ctx, n, prm, ax, ay, az, dudt, dtc, act, s); break;
+        default: both_launch<8, F32, D>(ctx, n, prm, ax, ay, az, dudt, dtc, act, s); break;
+    }
 }
 
 template <bool F32>
 static void both_dispatch(Ctx *ctx, int64_t n, const sph_params *prm, double *ax, double *ay,
                           double *az, double *dudt, double *dtc, const int32_t *act,
                           hipStream_t s) {
-    switch (lanes_of(ctx, SPH_TUNE_LANES_STEP, F32)) {
-        case 4: both_launch<4, F32>(ctx, n, prm, ax, ay, az, dudt, dtc, act, s); break;
-        case 16: both_launch<16, F32>(ctx, n, prm, ax, ay, az, dudt, dtc, act, s); break;
-        default: both_launch<8, F32>(ctx, n, prm, ax, ay, az, dudt, dtc, act, s); break;
-    }
+    if (ctx->sweep_depth[F32 ? 1 : 0] == 1)
+        both_dispatch_d<F32, 1>(ctx, n, prm, ax, ay, az, dudt, dtc, act, s);
+    else
+        both_dispatch_d<F32, 2>(ctx, n, prm, ax, ay, az, dudt, dtc, act, s);
 }
 
 // Gradient raw sums and forces in one sweep (records written by the

@@ -70,6 +70,7 @@ struct Ctx {
     int32_t lanes[4][2] = {{8, 8}, {8, 8}, {8, 8}, {8, 8}};
     double cell_scale = 1.0;
     int32_t build_range = 64;  // sorted particles per work-group of the pair-list build
+    int32_t sweep_depth[2] = {2, 2};  // records in flight per lane of the fused sweep [precision]
     // self-gravity pyramid (allocated with the context)
     void *grav_lev = nullptr;        // per-run level layout (max_runs entries)
     int64_t *grav_totals = nullptr;  // [upper nodes, groups]

@@ -33,7 +33,7 @@ SPH_W_VP, SPH_W_UP, SPH_W_SP, SPH_W_G, SPH_W_DT, SPH_W_PERM = 7, 10, 11, 16, 25,
 SPH_W_TAU, SPH_W_ACT, SPH_NW = 27, 28, 29
 SPH_T_BUILD, SPH_T_DENSITY, SPH_T_GRADIENTS, SPH_T_FORCES = range(4)
 (SPH_TUNE_LANES_DENSITY, SPH_TUNE_LANES_GRADIENTS, SPH_TUNE_LANES_FORCES, SPH_TUNE_LANES_STEP,
- SPH_TUNE_CELL_SCALE, SPH_TUNE_BUILD_RANGE) = range(6)
+ SPH_TUNE_CELL_SCALE, SPH_TUNE_BUILD_RANGE, SPH_TUNE_SWEEP_DEPTH) = range(7)
 
 
 class SphError(RuntimeError):
