@@ -1,16 +1,20 @@
 """Benchmark of the strength-SPH step on one MI355X.
 
-Workload: the granular column (196,794 mobile particles in a 0.2 x 0.1 x 0.05 m
-block on a 4-layer floor of 29,928 fixed particles, cubic lattice spacing
-1.70998 mm, h = 1.3 spacing, Drucker-Prager friction tan 30 deg, g = 9.81),
-advanced with the FP32 cell-relative pair arithmetic; the same steps in the
-plain FP64 path are timed next to it.  One step = neighbour search (cell
-sort + pair sets), reorder of the state, predictor, density + EOS + yield,
-stress predict and rescale, corrected gradients, stress rate, forces, CFL
-minimum, kicks.  Metric: ordered neighbour pairs per second,
-sum_steps sum_i |N_i| / wall time.
+Headline workload: the two-sphere impact of about 1.1M particles (granite
+target of radius 50 km with 1,000,162 particles and a projectile of equal
+particle mass with 100,090, relaxed glass-like packings, h = 1.3 spacing,
+projectile at 45 deg and 3 km/s, Collins yield with thermal softening,
+Poisson-route shear modulus, gravity excluded), advanced by whole strength
+steps with the FP32 cell-relative pair arithmetic; the plain FP64 path is
+timed on the same workload beside it.  One step = drift, neighbour search
+(cell sort + pair sets), reorder of the state, predictor, density + EOS +
+yield, stress predict and rescale, corrected gradients, stress rate,
+forces, CFL minimum, closing and opening kicks.  Metric: ordered neighbour
+pairs per second, sum over the timed steps of sum_i |N_i| / wall time,
+inputs resident in HBM.
 
-Prints one JSON line.  ``--gpus N`` with N > 1 is not supported (one GPU).
+Prints one JSON line (progress goes to stderr).  ``--gpus N`` with N > 1 is
+not supported: one GPU.
 """
 from __future__ import annotations
 
@@ -26,26 +30,33 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-PEAK_FP32_VALU = 157.3e12   # MI355X FP32 vector, published
-PEAK_FP64_VALU = 78.6e12    # MI355X FP64 vector, published
+METRIC = "SPH strength-step pair interactions/s (FP32 vs FP64 plain, 1 GPU) at 1e-5 rel err"
+PEAK_FP32_VALU = 157.3e12   # MI355X FP32 vector, published (packed instructions)
+PEAK_FP32_UNPACKED = 78.6e12  # the same pipes without packed FP32 (this build's code)
+PEAK_FP64_VALU = 78.6e12
 PEAK_HBM = 8.0e12
 
-# Algorithmic flops per ordered pair of the fused gradient + force sweep of
-# the step (FMA = 2, sqrt = 1), counted from the pair term without the
-# artificial-viscosity branch: separation (9 in float incl. the cell shift,
-# 3 in double), r^2 (5), sqrt (1), kernel factors t_i^3, t_j^3 (8), v_ij (3);
-# force part: (K A)_i x and (K A)_j x (30), momentum sum (15), energy term
-# (8), v_ij . x_ij (5); gradient part: pair weight (5), w x_ij (3),
-# C^-1 sums (12), F sums (18).
-FLOPS_PAIR = {1: 122, 0: 116}
-
+# Algorithmic flops per ordered pair of the fused gradient + force sweep.
+# The scope table's estimates per pass (FMA = 2, sqrt and division 1 each):
+# gradients ~60, forces ~110 plus ~25 when the pair approaches (the AV
+# term); both passes' work is credited, each with its own separation,
+# square root and kernel factors, as a two-pass code would do it.
+SURVEY_GRADIENTS, SURVEY_FORCES, SURVEY_AV = 60.0, 110.0, 25.0
+# The same work counted from the fused pair term, shared parts once:
+# separation 3, r^2 5, sqrt 1, kernel factors t_i^3, t_j^3 with Kn 10, v_ij 3;
+# gradient weight 8, C^-1 sums 12, F sums 18; (K A)_i x and (K A)_j x 30,
+# their combination into the momentum sum 15, energy term 8, v_ij . x_ij 5
+# -> 118; the viscosity of an approaching pair adds 40 (two means, the
+# softened mu with one division, Pi with one division, mean kernel
+# gradient, momentum and energy updates, the CFL maximum).
+RECOUNT, RECOUNT_AV = 118.0, 40.0
 
 # Measured HBM traffic of the dominant pair kernel (rocprofv3 FETCH_SIZE and
 # WRITE_SIZE per dispatch, scaled by the same counters on a plain copy of
 # known size).  Valid only for the kernel source it was taken on.
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_grad_forces_c2_fp32_traffic.md")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_grad_forces_c3_fp32_traffic.md")
 TRAFFIC_SOURCES = ("paper_2603_19764_amd/csrc/pairs.hip", "paper_2603_19764_amd/csrc/device_util.h",
-                   "paper_2603_19764_amd/csrc/records.h")
+                   "paper_2603_19764_amd/csrc/records.h", "paper_2603_19764_amd/csrc/sph_internal.h")
 
 
 def log(*a):
@@ -62,7 +73,7 @@ def kernel_source_sha256() -> str:
 
 
 def measured_traffic(kernel: str):
-    """Bytes per launch of ``kernel`` (e.g. "k_grad_forces<4,fp32>") from the
+    """Bytes per launch of ``kernel`` (e.g. "k_grad_forces<8,fp32,2>") from the
     committed counter summary, or None when it is missing, does not list that
     instantiation, or was taken on another version of the kernel source."""
     import re
@@ -92,12 +103,29 @@ def copy_calibration(mib: int):
     del a, b
 
 
-def run_steps(w, prec, steps, warmup, use_graph, timing=True, tuned=None):
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown CPU"
+
+
+# ------------------------------------------------------------- GPU steps
+def run_steps(w, prec, steps, warmup, use_graph=False, timing=True, tuned=None, keep=False,
+              max_neighbors=128):
+    """Whole steps of workload ``w``: sph_init, ``warmup`` steps, then exactly
+    ``steps`` timed steps (HIP events around each step on the launch stream,
+    wall clock around all of them, synchronised on both sides).  With
+    ``timing`` the library's event timers record the pass kernels over the
+    timed region."""
     import torch
     from paper_2603_19764_amd import autotune, sph
 
     n = int(w["x"].size)
-    ctx = sph.Context(n, max_neighbors=128, max_cells=1 << 22)
+    ctx = sph.Context(n, max_neighbors=max_neighbors, max_cells=1 << 22)
     if tuned:
         autotune.apply(ctx, prec, tuned)
     st = sph.State(w)
@@ -126,30 +154,295 @@ def run_steps(w, prec, steps, warmup, use_graph, timing=True, tuned=None):
     if timing and not use_graph:
         sph.sph_timing(ctx, True)
     p0 = sph.sph_pair_count(ctx)
+    reps = steps // 2 if use_graph else steps
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    if use_graph:
-        for _ in range(steps // 2):
+    ev[0].record()
+    for k in range(reps):
+        if use_graph:
             graph.replay()
-    else:
-        for _ in range(steps):
+        else:
             sph.sph_step(ctx, st, mats, prm, prec)
+        ev[k + 1].record()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     p1 = sph.sph_pair_count(ctx)
     ctx.check(sph.lib().sph_sync_status(ctx.h, None))
-    k_steps = (steps // 2) * 2 if use_graph else steps
+    k_steps = reps * 2 if use_graph else steps
+    per = np.array([ev[k].elapsed_time(ev[k + 1]) for k in range(reps)]) / (2 if use_graph else 1)
     kern = {}
     if timing and not use_graph:
-        for name, kid in (("build", 0), ("density", 1), ("grad_forces", 3)):
+        for name, kid in (("build", sph.SPH_T_BUILD), ("density", sph.SPH_T_DENSITY),
+                          ("grad_forces", sph.SPH_T_FORCES)):
             kern[name] = sph.sph_timing_read(ctx, kid)
         sph.sph_timing(ctx, False)
-    out = dict(seconds=t1 - t0, steps=k_steps, pairs=p1 - p0, kernels=kern, n=n)
+    out = dict(seconds=t1 - t0, steps=k_steps, pairs=p1 - p0, kernels=kern, n=n,
+               ms_median=float(np.median(per)) if per.size else None)
+    if keep:
+        out["state"], out["ctx"] = st, ctx
+    else:
+        ctx.close()
     del graph
-    ctx.close()
     return out
 
 
+def approaching_fraction(st, h_max, sample=20000, seed=3):
+    """Fraction of ordered pairs (r < max(H_i, H_j), H = 2h) that approach,
+    v_ij . x_ij < 0, at the state of the last evaluation (positions and the
+    predicted velocities the sweep used), on a random sample of particles."""
+    from scipy.spatial import cKDTree
+    from paper_2603_19764_amd import sph
+    n = st.n
+    x = np.stack([st.row(k).cpu().numpy() for k in (sph.SPH_X, sph.SPH_Y, sph.SPH_Z)], 1)
+    v = np.stack([st.wrow(sph.SPH_W_VP + k).cpu().numpy() for k in range(3)], 1)
+    h = st.row(sph.SPH_H).cpu().numpy()
+    rng = np.random.default_rng(seed)
+    idx = rng.choice(n, min(sample, n), replace=False)
+    tree = cKDTree(x)
+    lists = tree.query_ball_point(x[idx], 2.0 * h_max)
+    app = tot = 0
+    for i, js in zip(idx, lists):
+        js = np.asarray(js)
+        js = js[js != i]
+        d = x[i] - x[js]
+        r2 = np.einsum("ij,ij->i", d, d)
+        H = np.maximum(2.0 * h[i], 2.0 * h[js])
+        ok = r2 < H * H
+        vr = np.einsum("ij,ij->i", v[i] - v[js][ok], d[ok])
+        app += int((vr < 0.0).sum())
+        tot += int(ok.sum())
+    return app / max(tot, 1)
+
+
+def stir(w, seed, v0, s0, length):
+    """A smooth velocity field of amplitude v0 (wavelength `length`) on the
+    mobile particles and random deviatoric stresses of scale s0, so that every
+    derivative is non-zero at t = 0 (accuracy sample)."""
+    rng = np.random.default_rng(seed)
+    k = 2.0 * np.pi / length
+    mob = w["fixed"] == 0
+    w = dict(w)
+    w["vx"] = w["vx"] + np.where(mob, v0 * np.sin(k * w["y"] + 0.3), 0.0)
+    w["vy"] = w["vy"] + np.where(mob, v0 * np.sin(k * w["z"] + 1.1), 0.0)
+    w["vz"] = w["vz"] + np.where(mob, v0 * np.sin(k * w["x"] + 2.3), 0.0)
+    w["S"] = w["S"] + np.where(mob, s0 * rng.standard_normal(w["S"].shape), 0.0)
+    return w
+
+
+def gpu_evaluation(w, prec, tuned):
+    """One derivative evaluation in the benchmark's launch configuration (the
+    fused path of sph_init with the tuned shapes); fields in input order."""
+    import torch
+    from paper_2603_19764_amd import autotune, sph
+    n = int(w["x"].size)
+    ctx = sph.Context(n, 128, max_cells=1 << 22)
+    if tuned:
+        autotune.apply(ctx, prec, tuned)
+    st = sph.State(w)
+    sph.sph_init(ctx, st, w["mats"], w["params"], prec)
+    torch.cuda.synchronize()
+    ctx.check(sph.lib().sph_sync_status(ctx.h, None))
+    g = st.to_host()
+    ctx.close()
+    return g
+
+
+# ------------------------------------------------------ oracle on the host
+def oracle_sample(w, targets):
+    """The FP64 oracle's full derivative chain (brute-force O(N^2) pair sets
+    against all particles, density + EOS of the pair-set closure, gradients,
+    stress rate, forces) for ``targets``; returns (reference dict, seconds)."""
+    from oracle import oracle
+    st = {k: w[k] for k in ("x", "y", "z", "m", "h", "mat", "vx", "vy", "vz", "u", "S")}
+    t0 = time.perf_counter()
+    ref = oracle.derivs(st, w["mats"], w["params"], targets)
+    return ref, time.perf_counter() - t0
+
+
+def search_seconds(w, targets):
+    """Time of the brute-force neighbour search alone, as the oracle's chain
+    performs it: a sweep over all particles per target in each of the two
+    passes of the pair-set closure, the gradients and the forces, and per
+    member of the closure in the density (each sweep timed as the count of
+    the pair set, which tests every particle once).  Returns (seconds,
+    ordered pairs of the targets, closure size)."""
+    from oracle import oracle
+    x, y, z, h, prm = w["x"], w["y"], w["z"], w["h"], w["params"]
+    off, nbr, _ = oracle.pair_lists(x, y, z, h, prm, targets)
+    near = np.unique(np.concatenate([np.asarray(targets, dtype=np.int64), nbr]))
+    t0 = time.perf_counter()
+    oracle.pair_counts(x, y, z, h, prm, targets)
+    t_tar = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    oracle.pair_counts(x, y, z, h, prm, near)
+    t_near = time.perf_counter() - t0
+    return 4.0 * t_tar + t_near, int(off[-1]), int(near.size)
+
+
+class _Sampler:
+    """Compact samples of a workload: the k particles nearest a random
+    particle (their pair-set closure stays close to the sample), and the
+    sub-volume around a sample that holds everything its derivatives read
+    (particles within two supports of it: pair sets, and the pair sets of
+    their members for the densities)."""
+
+    def __init__(self, w, seed):
+        from scipy.spatial import cKDTree
+        self.w = w
+        self.x = np.stack([w["x"], w["y"], w["z"]], 1)
+        self.tree = cKDTree(self.x)
+        self.rng = np.random.default_rng(seed)
+        self.c = self.x[self.rng.integers(self.x.shape[0])]
+        self.H = 2.0 * float(np.max(w["h"]))
+
+    def targets(self, k, c=None):
+        c = self.c if c is None else c
+        d, idx = self.tree.query(c, k=min(k, self.x.shape[0]))
+        idx = np.atleast_1d(idx)
+        return np.sort(idx).astype(np.int64), float(np.max(d))
+
+    def new_centre(self):
+        return self.x[self.rng.integers(self.x.shape[0])]
+
+    def sub(self, radius, c=None):
+        """(sub-workload, index map sub -> full) of the particles within
+        radius + 2 H (+5%) of the centre."""
+        c = self.c if c is None else c
+        keep = np.sort(np.asarray(self.tree.query_ball_point(c, radius + 2.1 * self.H),
+                                  dtype=np.int64))
+        n = self.x.shape[0]
+        sub = {k: (v[..., keep] if isinstance(v, np.ndarray) and v.shape[-1] == n else v)
+               for k, v in self.w.items()}
+        return sub, keep
+
+
+def _omp():
+    """Handle to the OpenMP runtime the oracle uses (to run it on one core)."""
+    import ctypes
+    g = ctypes.CDLL("libgomp.so.1")
+    g.omp_get_max_threads.restype = ctypes.c_int
+    g.omp_set_num_threads.argtypes = [ctypes.c_int]
+    return g
+
+
+def _scaled(measure, budget_s, k0=32, n_max=None):
+    """Grow the sample size k until one measurement takes about
+    0.3-0.6 of ``budget_s``; returns the last (k, result, seconds)."""
+    k = k0
+    while True:
+        res, t = measure(k)
+        if t > 0.3 * budget_s or (n_max is not None and k >= n_max):
+            return k, res, t
+        k = int(k * max(2.0, min(8.0, 0.6 * budget_s / max(t, 1e-3))))
+
+
+def cpu_baseline(w, budget_s=6.0, ball=300):
+    """The oracle as it stands, timed on the host on compact samples of the
+    workload (each measurement about half of ``budget_s``): all threads, then
+    one thread.  Rate = ordered pairs of the sample / time of the FP64
+    derivative chain.  Two figures per thread count: the chain as the oracle
+    runs it on the whole workload, its brute-force O(N^2) search against all
+    particles; and the chain on small sub-volumes (``ball`` particles nearest
+    a random particle, with everything their derivatives read: same results
+    for them, a brute-force search over a few thousand particles only), with
+    the time of that search measured alone and subtracted for the
+    search-excluded rate."""
+    from oracle import oracle
+    oracle.lib()
+    omp = _omp()
+    threads = omp.omp_get_max_threads()
+    smp = _Sampler(w, seed=17)
+    n = int(w["x"].size)
+    out = {}
+    for leg, nthr in (("all", threads), ("one", 1)):
+        omp.omp_set_num_threads(nthr)
+
+        def full(k):
+            tar, _ = smp.targets(k)
+            _, t = oracle_sample(w, tar)
+            return tar, t
+
+        k, tar, t = _scaled(full, budget_s, n_max=n)
+        off, _, _ = oracle.pair_lists(w["x"], w["y"], w["z"], w["h"], w["params"], tar)
+        pairs = int(off[-1])
+        # sub-volumes until about half the budget is spent in their chains
+        t_sub = s_sub = 0.0
+        p_sub = m_sub = nb = 0
+        while t_sub < 0.5 * budget_s and nb < 4096:
+            c = smp.new_centre()
+            tar_k, rad = smp.targets(ball, c)
+            sub, keep = smp.sub(rad, c)
+            tar_s = np.searchsorted(keep, tar_k)
+            _, ts = oracle_sample(sub, tar_s)
+            ss, ps, _ = search_seconds(sub, tar_s)
+            t_sub += ts
+            s_sub += ss
+            p_sub += ps
+            m_sub += int(keep.size)
+            nb += 1
+        phys = t_sub - s_sub
+        out[leg] = dict(threads=nthr, targets=int(tar.size), pairs=pairs, chain_s=t,
+                        value=pairs / t, sub_volumes=nb, sub_particles=m_sub // max(nb, 1),
+                        sub_pairs=p_sub, sub_chain_s=t_sub, sub_search_s=s_sub,
+                        value_sub=p_sub / t_sub,
+                        value_search_excluded=(p_sub / phys) if phys > 0.0 else None)
+        log(f"cpu baseline ({leg}, {nthr} threads): {tar.size} targets, {pairs} pairs, chain "
+            f"{t:.2f} s; {nb} sub-volumes of ~{m_sub // max(nb, 1)} with {ball} targets: "
+            f"chains {t_sub:.2f} s, their search {s_sub:.2f} s")
+    omp.omp_set_num_threads(threads)
+    a, o = out["all"], out["one"]
+    return dict(value=a["value"], unit="pairs/s", cores=a["threads"], kind="oracle",
+                sample=f"{cpu_model()}, {a['threads']} threads: the {a['targets']} particles "
+                       f"nearest a random particle of the {n}-particle impact ({a['pairs']} "
+                       f"ordered pairs), full FP64 derivative chain with brute-force O(N^2) "
+                       f"neighbour search over all particles, {a['chain_s']:.2f} s",
+                search_restricted=dict(
+                    value=a["value_sub"], value_search_excluded=a["value_search_excluded"],
+                    sub_volumes=a["sub_volumes"], targets_each=ball,
+                    particles_each=a["sub_particles"], pairs=a["sub_pairs"],
+                    chain_s=a["sub_chain_s"], search_s=a["sub_search_s"]),
+                single_core=dict(
+                    value=o["value"], targets=o["targets"], pairs=o["pairs"],
+                    chain_s=o["chain_s"], value_search_restricted=o["value_sub"],
+                    value_search_excluded=o["value_search_excluded"],
+                    sub_volumes=o["sub_volumes"], sub_chain_s=o["sub_chain_s"],
+                    sub_search_s=o["sub_search_s"]))
+
+
+def accuracy(w, tuned, ntar=200, seed=9):
+    """FP32 form against the FP64 oracle on a stirred copy of the workload
+    (smooth velocities of 30 m/s, random stresses of 10 MPa): per field the
+    normwise error max_i |dX_i| / max_i |X_i| and the median and 99th
+    percentile of the per-particle error |dX_i| / (|X_i| + s_i), s_i the
+    summed magnitudes of the pair contributions, on random particles."""
+    from oracle import oracle
+    ws = stir(w, 11, 30.0, 1.0e7, 1.0e5)
+    n = int(ws["x"].size)
+    rng = np.random.default_rng(seed)
+    tar = np.unique(rng.choice(n, ntar, replace=False))
+    st = {k: ws[k] for k in ("x", "y", "z", "m", "h", "mat", "vx", "vy", "vz", "u", "S")}
+    ref = oracle.derivs(st, ws["mats"], ws["params"], tar, scales=True)
+    g = gpu_evaluation(ws, 1, tuned)
+    out = {}
+    for k in ("a", "dS", "G", "dudt", "rho"):
+        r, x = ref[k][..., tar], g[k][..., tar]
+        rr = np.atleast_2d(r)
+        d = np.sqrt(((np.atleast_2d(x) - rr) ** 2).sum(0))
+        e = dict(normwise=float(d.max() / np.sqrt((rr ** 2).sum(0)).max()))
+        if k in ref["scale"]:
+            den = np.sqrt((rr ** 2).sum(0)) + ref["scale"][k][tar]
+            pe = np.where(den > 0, d / np.where(den > 0, den, 1.0), np.where(d > 0, np.inf, 0.0))
+            e.update(median=float(np.median(pe)), p99=float(np.percentile(pe, 99)),
+                     max=float(pe.max()))
+        out[k] = e
+    out["sample"] = (f"{tar.size} random particles of the stirred workload, FP32 evaluation "
+                     "in the benchmark's launch configuration against the FP64 oracle")
+    log(f"accuracy: {out}")
+    return out
+
+
+# ------------------------------------------------------------ extra legs
 def run_batch(steps, warmup, gravity=True, tune=True):
     """The batched Q_RD* scan: 64 head-on impacts of uneven sizes (targets
     20k-300k particles, ~7.2M in all) in one set of buffers, FP32 pair
@@ -207,6 +500,23 @@ def run_batch(steps, warmup, gravity=True, tune=True):
             "dt_spread": float(dt.max() / dt.min())}
 
 
+def run_column(steps, warmup, tune=True):
+    """The granular column (196,794 mobile particles on a floor of 29,928
+    fixed ones, FP32 and FP64 whole steps)."""
+    from paper_2603_19764_amd import autotune, inputs
+    w = inputs.c2_column()
+    row = {"workload": "granular column, 196794 mobile + 29928 fixed particles, Drucker-Prager "
+                       "tan 30, g = 9.81", "particles": int(w["x"].size)}
+    for prec, name in ((1, "fp32"), (0, "fp64")):
+        tuned = autotune.tune(w, prec, steps=3)["settings"] if tune else None
+        r = run_steps(w, prec, steps, warmup, timing=False, tuned=tuned)
+        row[name] = {"pairs_per_s": r["pairs"] / r["seconds"],
+                     "ms_per_step": 1e3 * r["seconds"] / r["steps"],
+                     "pairs_per_step": r["pairs"] / r["steps"], "launch_shapes": tuned}
+    log(f"column: {row}")
+    return row
+
+
 def run_curve(sizes=(32, 64, 128, 160), steps=40, warmup=3):
     """Throughput against size: the single-step block workload (16^3 lattice,
     spacing 1 m, jitter, shear flow) scaled to n_side^3 particles, FP32 and
@@ -217,7 +527,7 @@ def run_curve(sizes=(32, 64, 128, 160), steps=40, warmup=3):
         w = inputs.c1_block(k)
         row = {"n_side": k, "particles": int(w["x"].size)}
         for prec, name in ((1, "fp32"), (0, "fp64")):
-            r = run_steps(w, prec, steps, warmup, False, timing=False)
+            r = run_steps(w, prec, steps, warmup, timing=False)
             row[name] = {"pairs_per_s": r["pairs"] / r["seconds"],
                          "ms_per_step": 1e3 * r["seconds"] / r["steps"]}
         log(f"curve {k}^3: {row}")
@@ -225,19 +535,14 @@ def run_curve(sizes=(32, 64, 128, 160), steps=40, warmup=3):
     return out
 
 
-def run_impact_step(steps=4, warmup=2):
-    """The two-sphere impact (about 1.1M particles, glass-like bodies, 45 deg,
-    3 km/s, gravity excluded): whole steps in FP32 and in FP64."""
-    from paper_2603_19764_amd import inputs
-    w = inputs.c3_impact()
-    row = {"particles": int(w["x"].size)}
-    for prec, name in ((1, "fp32"), (0, "fp64")):
-        r = run_steps(w, prec, steps, warmup, False, timing=False)
-        row[name] = {"pairs_per_s": r["pairs"] / r["seconds"],
-                     "ms_per_step": 1e3 * r["seconds"] / r["steps"],
-                     "pairs_per_step": r["pairs"] / r["steps"]}
-    log(f"impact: {row}")
-    return row
+def _conserved(st, mats):
+    """Total momentum and energy (kinetic + internal, half-step velocities
+    and energies) of a state, in FP64 on the host."""
+    from paper_2603_19764_amd import sph
+    m = st.row(sph.SPH_M).cpu().numpy()
+    v = np.stack([st.row(k).cpu().numpy() for k in (sph.SPH_VX, sph.SPH_VY, sph.SPH_VZ)])
+    u = st.row(sph.SPH_U).cpu().numpy()
+    return (m * v).sum(1), float((m * (0.5 * (v * v).sum(0) + u)).sum())
 
 
 def run_hsteps(n_side=64, prec=1, shared_steps=600):
@@ -247,7 +552,9 @@ def run_hsteps(n_side=64, prec=1, shared_steps=600):
     u = 3e6 J/kg.  The shared step runs ``shared_steps`` steps (it follows
     the particle with the shortest CFL step); the rungs (base step: the
     longest CFL step at the start) then run to the same simulated time.
-    Figure of merit: wall time to that simulated time."""
+    Figure of merit: wall time to that simulated time; accuracy: the drift
+    of total momentum and energy in each run and the difference of the
+    final states (positions, velocities, energies) between the two."""
     import torch
     from paper_2603_19764_amd import inputs, sph
     w = inputs.c1_block(n_side)
@@ -260,6 +567,7 @@ def run_hsteps(n_side=64, prec=1, shared_steps=600):
                        "at u = 3e6 J/kg)", "precision": "fp32" if prec else "fp64"}
     t_target = None
     dt0 = None
+    final = {}
     for mode in ("shared", "rungs"):
         prm = dict(w["params"])
         if mode == "rungs":
@@ -267,100 +575,80 @@ def run_hsteps(n_side=64, prec=1, shared_steps=600):
         ctx = sph.Context(n, 128, max_cells=1 << 22)
         st = sph.State(w, dt_max=dt0 if mode == "rungs" else 0.0)
         sph.sph_init(ctx, st, w["mats"], prm, prec)
+        torch.cuda.synchronize()
         if mode == "shared":
-            torch.cuda.synchronize()
             dt0 = float(st.wrow(sph.SPH_W_DT).max()) * 1.01
-        sim = torch.zeros(1, dtype=torch.float64, device="cuda")
+        p0, e0 = _conserved(st, w["mats"])
+        sim_d = torch.zeros(1, dtype=torch.float64, device="cuda")
         k = 0
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         while True:
             for _ in range(20):
-                sim += st.dt
+                sim_d += st.dt          # on the device: no synchronisation per step
                 sph.sph_step(ctx, st, w["mats"], prm, prec)
             k += 20
             if mode == "shared" and k >= shared_steps:
                 break
-            if mode == "rungs" and float(sim.item()) >= t_target:
+            if mode == "rungs" and float(sim_d.item()) >= t_target:
                 break
         torch.cuda.synchronize()
         t1 = time.perf_counter()
+        sim = float(sim_d.item())
         ctx.check(sph.lib().sph_sync_status(ctx.h, None))
+        p1, e1 = _conserved(st, w["mats"])
+        pscale = float((st.row(sph.SPH_M).cpu().numpy() * np.abs(
+            st.row(sph.SPH_VX).cpu().numpy())).sum()) + 1e-300
         row = {"steps": k, "wall_s": t1 - t0, "ms_per_step": 1e3 * (t1 - t0) / k,
-               "simulated_s": float(sim.item())}
+               "simulated_s": sim, "energy_drift": (e1 - e0) / abs(e0),
+               "momentum_drift": float(np.abs(p1 - p0).max() / pscale)}
         if mode == "shared":
-            t_target = row["simulated_s"]
+            t_target = sim
         else:
             steps = st.row(sph.SPH_DTP).cpu().numpy()
             vals, cnt = np.unique(steps, return_counts=True)
             row["base_step_s"] = dt0
             row["particles_per_step_ticks"] = {str(int(v)): int(q) for v, q in zip(vals, cnt)}
+        final[mode] = st.to_host()
         out[mode] = row
         ctx.close()
+    # the two runs end at slightly different times (the rungs stop at the
+    # first substep at or past the shared run's time): compare the states
+    a, b = final["shared"], final["rungs"]
+    disp = np.stack([a[k] - w[k] for k in "xyz"])
+    out["state_difference"] = {
+        "position": float(np.abs(np.stack([b[k] - a[k] for k in "xyz"])).max()
+                          / np.abs(disp).max()),
+        "velocity": float(np.abs(np.stack([b[k] - a[k] for k in ("vx", "vy", "vz")])).max()
+                          / np.abs(np.stack([a[k] for k in ("vx", "vy", "vz")])).max()),
+        "energy": float(np.abs(b["u"] - a["u"]).max() / np.abs(a["u"] - w["u"]).max()),
+        "time_difference": (out["rungs"]["simulated_s"] - t_target) / t_target}
     out["speedup"] = (out["shared"]["wall_s"] / out["shared"]["simulated_s"]) / (
         out["rungs"]["wall_s"] / out["rungs"]["simulated_s"])
     log(f"individual steps: {out}")
     return out
 
 
-def cpu_baseline(w, budget_s=15.0):
-    """The FP64 oracle on a bounded sample of the same workload: the full
-    derivative chain (brute-force pair sets, density + EOS for the pair-set
-    closure, gradients, stress rate, forces) for randomly chosen target
-    particles.  Rate = ordered pairs of the targets per second."""
-    from oracle import oracle
-
-    st = {k: w[k] for k in ("x", "y", "z", "m", "h", "mat", "vx", "vy", "vz", "u", "S")}
-    n = w["x"].size
-    rng = np.random.default_rng(123)
-    oracle.lib()
-    ntar = 8
-    t_used = 0.0
-    while True:
-        tar = np.sort(rng.choice(n, ntar, replace=False))
-        t0 = time.perf_counter()
-        oracle.derivs(st, w["mats"], w["params"], tar)
-        dt = time.perf_counter() - t0
-        if dt > 0.25 * budget_s or ntar >= n:
-            break
-        t_used += dt
-        ntar = int(min(n, ntar * max(2.0, min(8.0, 0.5 * budget_s / max(dt, 1e-3)))))
-    off, _, _ = oracle.pair_lists(w["x"], w["y"], w["z"], w["h"], w["params"], tar)
-    pairs = int(off[-1])
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    model = "unknown CPU"
-    try:
-        for line in open("/proc/cpuinfo"):
-            if line.startswith("model name"):
-                model = line.split(":", 1)[1].strip()
-                break
-    except OSError:
-        pass
-    return dict(value=pairs / dt, unit="pairs/s", cores=threads, kind="oracle",
-                sample=f"{model}, {threads} threads: "
-                       f"{ntar} random targets of the {n}-particle column, full FP64 derivative "
-                       f"chain with brute-force O(N^2) neighbour search, {pairs} target pairs in "
-                       f"{dt:.2f} s")
-
-
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1000)
-    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--graph", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-curve", action="store_true",
                     help="skip the size curve (block workload, 32^3 to 160^3)")
+    ap.add_argument("--no-column", action="store_true", help="skip the granular column")
     ap.add_argument("--no-hsteps", action="store_true",
                     help="skip the individual-step comparison on the hot-core block")
-    ap.add_argument("--no-impact", action="store_true",
-                    help="skip the 1.1M-particle two-sphere impact steps")
     ap.add_argument("--batch-steps", type=int, default=20,
                     help="steps of the batched 64-impact scan (0: skip it)")
     ap.add_argument("--no-tune", action="store_true",
                     help="keep the default launch shapes (no autotuning before the warmup)")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="only the timed FP32 steps of the headline workload (profiling)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first copy MIB MiB device to device (counter calibration)")
     args = ap.parse_args()
@@ -375,8 +663,9 @@ def main():
     torch.cuda.set_device(0)
     if args.copy_calibration:
         copy_calibration(args.copy_calibration)
-    w = inputs.c2_column()
-    log(f"workload {w['name']}: n={w['x'].size}")
+    w = inputs.c3_impact()
+    n = int(w["x"].size)
+    log(f"workload {w['name']}: n={n}")
     tuned = {0: None, 1: None}
     if not args.no_tune:
         from paper_2603_19764_amd import autotune
@@ -384,57 +673,83 @@ def main():
             t = autotune.tune(w, prec, steps=3)
             tuned[prec] = t["settings"]
             log(f"autotune prec {prec}: {t['settings']} {t['times_ms']}")
-    r32 = run_steps(w, 1, args.steps, args.warmup, bool(args.graph), tuned=tuned[1])
-    log(f"fp32: {r32['seconds']:.3f} s for {r32['steps']} steps, {r32['pairs']} pairs")
+    r32 = run_steps(w, 1, args.steps, args.warmup, bool(args.graph), tuned=tuned[1], keep=True)
+    log(f"fp32: {r32['seconds']:.4f} s for {r32['steps']} steps, {r32['pairs']} pairs")
+    if args.headline_only:
+        r32["ctx"].close()
+        line = {"metric": METRIC, "value": r32["pairs"] / r32["seconds"],
+                "ms_per_step": 1e3 * r32["seconds"] / r32["steps"]}
+        if not args.no_fp64:
+            r64 = run_steps(w, 0, args.steps, args.warmup, bool(args.graph), tuned=tuned[0])
+            line["fp64_plain"] = {"value": r64["pairs"] / r64["seconds"],
+                                  "ms_per_step": 1e3 * r64["seconds"] / r64["steps"]}
+        print(json.dumps(line), flush=True)
+        return
+    f_av = approaching_fraction(r32["state"], float(w["h"].max()))
+    r32["ctx"].close()
+    del r32["state"], r32["ctx"]
     r64 = None
     if not args.no_fp64:
-        r64 = run_steps(w, 0, max(args.steps // 4, 2), args.warmup, bool(args.graph),
-                        tuned=tuned[0])
-        log(f"fp64: {r64['seconds']:.3f} s for {r64['steps']} steps, {r64['pairs']} pairs")
+        r64 = run_steps(w, 0, args.steps, args.warmup, bool(args.graph), tuned=tuned[0])
+        log(f"fp64: {r64['seconds']:.4f} s for {r64['steps']} steps, {r64['pairs']} pairs")
     value = r32["pairs"] / r32["seconds"]
     ms_step = 1e3 * r32["seconds"] / r32["steps"]
     roof = None
     if r32["kernels"]:
         ms, cnt = r32["kernels"]["grad_forces"]
         avg_s = ms / cnt * 1e-3
-        pairs_per_launch = r32["pairs"] / r32["steps"]
-        achieved = FLOPS_PAIR[1] * pairs_per_launch / avg_s
-        kname = f"k_grad_forces<{(tuned[1] or {}).get('lanes_step', 8)},fp32>"
+        ppl = r32["pairs"] / r32["steps"]
+        fl_survey = SURVEY_GRADIENTS + SURVEY_FORCES + SURVEY_AV * f_av
+        fl_recount = RECOUNT + RECOUNT_AV * f_av
+        achieved = fl_survey * ppl / avg_s
+        lanes = (tuned[1] or {}).get("lanes_step", 8)
+        depth = (tuned[1] or {}).get("sweep_depth", 2)
+        kname = f"k_grad_forces<{lanes},fp32,{depth}>"
         roof = dict(bound="alu", achieved=achieved / 1e12, peak=PEAK_FP32_VALU / 1e12,
                     unit="TFLOP/s", frac=achieved / PEAK_FP32_VALU,
-                    traffic=measured_traffic(kname), kernel=kname,
-                    avg_launch_us=avg_s * 1e6,
+                    frac_unpacked=achieved / PEAK_FP32_UNPACKED,
+                    traffic=measured_traffic(kname), kernel=kname, avg_launch_us=avg_s * 1e6,
+                    pairs_per_launch=ppl, flops_per_pair=fl_survey,
+                    flops_per_pair_recount=fl_recount,
+                    frac_recount=fl_recount * ppl / avg_s / PEAK_FP32_VALU,
+                    approaching_pair_fraction=f_av,
                     kernels_us={k: (v[0] / v[1] * 1e3 if v[1] else None)
                                 for k, v in r32["kernels"].items()})
+    acc = None if args.no_accuracy else accuracy(w, tuned[1])
+    column = None if args.no_column else run_column(max(args.steps, 20), args.warmup,
+                                                    tune=not args.no_tune)
     curve = None if args.no_curve else run_curve()
-    impact = None if args.no_impact else run_impact_step()
     hsteps = None if args.no_hsteps else run_hsteps()
     batch = None
     if args.batch_steps > 0:
         batch = run_batch(args.batch_steps, 4, tune=not args.no_tune)
         log(f"batch: {batch['ms_per_step']:.3f} ms/step, {batch['value']:.3e} pairs/s")
-    cpu = None
-    if not args.no_cpu_baseline:
-        cpu = cpu_baseline(w)
+    cpu = None if args.no_cpu_baseline else cpu_baseline(w)
     line = {
-        "metric": "SPH strength-step pair interactions/s (FP32 vs FP64 plain, 1 GPU) at 1e-5 rel err",
-        "value": value, "unit": "pairs/s", "n_gpus": 1, "steps": r32["steps"],
-        "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f32 pair terms, f64 state",
-        "data": "synthetic",
-        "config": {"workload": "granular column collapse, 196794 mobile + 29928 fixed particles, "
-                               "FP32 cell-relative pair loop, Drucker-Prager tan 30, g = 9.81",
-                   "particles": r32["n"], "pairs_per_step": r32["pairs"] / r32["steps"],
-                   "graph": bool(args.graph), "launch_shapes": tuned[1]},
+        "metric": METRIC, "value": value, "unit": "pairs/s", "n_gpus": 1,
+        "steps": r32["steps"], "warmup": args.warmup, "ms_per_step": ms_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32 pair terms, f64 state", "data": "synthetic",
+        "config": {"workload": f"two-sphere impact: granite target {w['n_target']} + projectile "
+                               f"{n - w['n_target']} particles (relaxed glass, h = 1.3 spacing), "
+                               "45 deg, 3 km/s, Collins yield with thermal softening, gravity "
+                               "excluded; whole strength steps, FP32 cell-relative pair loop",
+                   "particles": n, "pairs_per_step": r32["pairs"] / r32["steps"],
+                   "ms_per_step_median": r32["ms_median"], "graph": bool(args.graph),
+                   "launch_shapes": tuned[1]},
         "fp64_plain": None if r64 is None else {
-            "value": r64["pairs"] / r64["seconds"], "ms_per_step": 1e3 * r64["seconds"] / r64["steps"],
-            "steps": r64["steps"], "launch_shapes": tuned[0]},
-        "size_curve": curve,
-        "impact_1p1M": impact,
-        "individual_steps": hsteps,
-        "batch_scan": batch,
+            "value": r64["pairs"] / r64["seconds"],
+            "ms_per_step": 1e3 * r64["seconds"] / r64["steps"],
+            "ms_per_step_median": r64["ms_median"], "steps": r64["steps"],
+            "launch_shapes": tuned[0],
+            "fp32_speedup": (r64["seconds"] / r64["steps"]) / (r32["seconds"] / r32["steps"])},
+        "accuracy": acc,
         "roofline": roof,
         "cpu_baseline": cpu,
+        "granular_column": column,
+        "size_curve": curve,
+        "individual_steps": hsteps,
+        "batch_scan": batch,
     }
     print(json.dumps(line), flush=True)
 

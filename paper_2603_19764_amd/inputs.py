@@ -192,11 +192,40 @@ def c2_column(scale: float = 1.0) -> dict:
     return w
 
 
-def stratified_ball(n_target: int, radius: float, seed: int):
-    """Glass-like points in a ball: one uniform random point per cubic cell of
-    a lattice whose spacing gives ~n_target points inside the ball, followed
-    by three passes that push close pairs apart (a relaxed random packing)."""
+def _cache_path(tag: str) -> str:
+    """File under the temporary directory for a generated input, keyed by the
+    text of this module (a changed generator never reads an old file)."""
+    import hashlib
+    import os
+    import tempfile
+    with open(__file__, "rb") as f:
+        key = hashlib.sha256(f.read() + tag.encode()).hexdigest()[:24]
+    d = os.path.join(tempfile.gettempdir(), "sph_inputs_cache")
+    os.makedirs(d, exist_ok=True)
+    return os.path.join(d, f"{key}.npy")
+
+
+GLASS_PASSES = 16
+GLASS_STEP = 0.25
+
+
+def stratified_ball(n_target: int, radius: float, seed: int, passes: int = GLASS_PASSES):
+    """Glass-like points in a ball (a seeded, relaxed random packing): one
+    uniform random point per cubic cell of a lattice whose spacing sp gives
+    ~n_target points inside the ball, then `passes` relaxation passes in
+    which every pair closer than sp pushes its two points apart by
+    GLASS_STEP sp (1 - r/sp)^2 along their separation (a damped soft
+    repulsion), points leaving the ball being put back on its surface.
+    Sixteen passes take the nearest-neighbour distance from >= 0.36 sp
+    (median 0.70) to >= 0.71 sp (median 0.87) for a million points.  The
+    result is cached on disk (keyed by this module's text and the
+    arguments), since the passes take ~20 s for a million points."""
     sp = radius * (4.0 / 3.0 * math.pi / n_target) ** (1.0 / 3.0)
+    path = _cache_path(f"ball|{n_target}|{radius!r}|{seed}|{passes}")
+    try:
+        return np.load(path), sp
+    except (OSError, ValueError):
+        pass
     nside = int(math.ceil(2 * radius / sp)) + 2
     rng = np.random.Generator(np.random.PCG64(seed))
     c = (np.arange(nside) - nside / 2.0) * sp
@@ -204,19 +233,27 @@ def stratified_ball(n_target: int, radius: float, seed: int):
     P = np.stack([X.ravel(), Y.ravel(), Z.ravel()], axis=1)
     P = P + rng.uniform(0.0, sp, size=P.shape)
     P = P[np.einsum("ij,ij->i", P, P) < radius * radius]
+    n = P.shape[0]
+    from scipy.spatial import cKDTree
+    for _ in range(passes):
+        pr = cKDTree(P).query_pairs(sp, output_type="ndarray")
+        if pr.size == 0:
+            break
+        d = P[pr[:, 0]] - P[pr[:, 1]]
+        r = np.sqrt(np.einsum("ij,ij->i", d, d)) + 1e-12 * sp
+        wgt = GLASS_STEP * sp * (1.0 - r / sp) ** 2 / r
+        for a in range(3):
+            f = wgt * d[:, a]
+            P[:, a] += np.bincount(pr[:, 0], f, n) - np.bincount(pr[:, 1], f, n)
+        rr = np.sqrt(np.einsum("ij,ij->i", P, P))
+        out = rr > radius
+        P[out] *= (radius / rr[out])[:, None]
     try:
-        from scipy.spatial import cKDTree
-        for _ in range(3):
-            tree = cKDTree(P)
-            pairs = tree.query_pairs(0.8 * sp, output_type="ndarray")
-            if pairs.size == 0:
-                break
-            d = P[pairs[:, 0]] - P[pairs[:, 1]]
-            r = np.sqrt(np.einsum("ij,ij->i", d, d)) + 1e-12 * sp
-            push = (0.5 * (0.8 * sp - r) / r)[:, None] * d * 0.5
-            np.add.at(P, pairs[:, 0], push)
-            np.add.at(P, pairs[:, 1], -push)
-    except ImportError:  # pragma: no cover - scipy is part of the image
+        tmp = path + ".tmp.npy"
+        np.save(tmp, P)
+        import os
+        os.replace(tmp, path)
+    except OSError:
         pass
     return P, sp
 

@@ -25,6 +25,44 @@ def norm_err(got, ref):
     return float(d.max() / s)
 
 
+def particle_err(got, ref, scale):
+    """Per-particle relative errors |got_i - ref_i| / (|ref_i| + s_i) with
+    vector norms over the rows and s_i the oracle's scale of the pair sum
+    (the summed magnitudes of its pair contributions).  Returns (median,
+    99th percentile, max)."""
+    g = np.atleast_2d(np.asarray(got, dtype=np.float64))
+    r = np.atleast_2d(np.asarray(ref, dtype=np.float64))
+    d = np.sqrt(((g - r) ** 2).sum(0))
+    den = np.sqrt((r ** 2).sum(0)) + np.asarray(scale, dtype=np.float64)
+    # a particle with no contribution at all (a fixed particle among fixed
+    # ones) counts as exact when the result is exactly zero
+    e = np.where(den > 0, d / np.where(den > 0, den, 1.0), np.where(d > 0, np.inf, 0.0))
+    return float(np.median(e)), float(np.percentile(e, 99)), float(e.max())
+
+
+def gpu_pair_sets_of(ctx, perm: np.ndarray, targets):
+    """Pair sets of the given input indices from the last build, as
+    {input index: (sorted input indices j, density flags)}; only the CSR
+    rows of the targets are mapped."""
+    from paper_2603_19764_amd import sph
+
+    n = perm.size
+    off, nbr, dfl = sph.sph_neighbors_csr(ctx, n)
+    off = off.cpu().numpy()
+    inv = np.empty(n, dtype=np.int64)
+    inv[perm] = np.arange(n)
+    nbr_d, dfl_d = nbr, dfl
+    out = {}
+    for t in targets:
+        k = int(inv[int(t)])
+        a, b = int(off[k]), int(off[k + 1])
+        js = perm[nbr_d[a:b].cpu().numpy()]
+        fl = dfl_d[a:b].cpu().numpy()
+        o = np.argsort(js, kind="stable")
+        out[int(t)] = (js[o], fl[o])
+    return out
+
+
 def gpu_derivs(w: dict, prec: int, ctx=None, max_neighbors: int = 128, state=None):
     """One derivative evaluation (neighbour search, density + EOS, stress
     predict with dt = 0, gradients, stress rate, forces) via the C-ABI.

@@ -9,7 +9,8 @@ import numpy as np
 import pytest
 
 from paper_2603_19764_amd import inputs
-from tests.gpu_harness import gpu_derivs, gpu_neighbour_sets, norm_err, say
+from tests.gpu_harness import (gpu_derivs, gpu_neighbour_sets, gpu_pair_sets_of, norm_err,
+                               particle_err, say)
 
 pytestmark = pytest.mark.gpu
 
@@ -29,10 +30,42 @@ TOL64 = 1e-10
 TOL32 = dict(rho=1e-6, omega=1e-6, P=1e-6, cs=1e-5, G=1e-5, dS=1e-5, a=1e-5, dudt=2e-5, dt=1e-4)
 
 
-def _oracle(orc, w, targets=None):
+def _oracle(orc, w, targets=None, scales=False):
     st = dict(x=w["x"], y=w["y"], z=w["z"], m=w["m"], h=w["h"], mat=w["mat"], vx=w["vx"],
               vy=w["vy"], vz=w["vz"], u=w["u"], S=w["S"])
-    return orc.derivs(st, w["mats"], w["params"], targets)
+    return orc.derivs(st, w["mats"], w["params"], targets, scales=scales)
+
+
+# Per-particle metric of the FP32 form: the 99th percentile of
+# |dX_i| / (|X_i| + s_i), s_i the summed magnitudes of the pair contributions
+# (oracle.term_scales), on accelerations and stress rates.
+P99_32 = 1e-5
+
+
+def _particle_errs(ref, got, label, fields=("a", "dS", "G", "dudt"), idx=None):
+    out = {}
+    for k in fields:
+        r, g, sc = ref[k], got[k], ref["scale"][k]
+        if idx is not None:
+            r, g, sc = r[..., idx], g[..., idx], sc[idx]
+        out[k] = particle_err(g, r, sc)
+    say(label, "per-particle median/p99/max",
+        {k: "/".join(f"{x:.1e}" for x in v) for k, v in out.items()})
+    for k in ("a", "dS"):
+        assert out[k][1] <= P99_32, f"{label}: p99 of {k} {out[k][1]:.2e} above {P99_32:.0e}"
+    return out
+
+
+def _check_target_sets(orc, w, ctx, perm, tar):
+    """Pair sets of sampled targets at full size, bit-exact against the
+    oracle's brute force."""
+    off, nbr, dfl = orc.pair_lists(w["x"], w["y"], w["z"], w["h"], w["params"], tar)
+    sets = gpu_pair_sets_of(ctx, perm, tar)
+    for q, t in enumerate(tar):
+        js, fl = sets[int(t)]
+        assert np.array_equal(js, nbr[off[q]:off[q + 1]]), f"pair set of {t} differs"
+        assert np.array_equal(fl, dfl[off[q]:off[q + 1]]), f"density flags of {t} differ"
+    return int(off[-1])
 
 
 def _check_sets(orc, w, ctx, perm):
@@ -84,11 +117,12 @@ def test_c1_fp64_parity(orc, variant):
 def test_c1_fp32_cellrel_parity(orc, variant):
     say(f"[c1 fp32 variant={variant!r}]")
     w = inputs.c1_block(16, variant=variant)
-    ref = _oracle(orc, w)
+    ref = _oracle(orc, w, scales=True)
     got, ctx, perm = gpu_derivs(w, FP32)
     _check_sets(orc, w, ctx, perm)
     _compare(ref, got, TOL32, ("rho", "omega", "P", "cs", "G", "dS", "a", "dudt", "dt"),
              f"c1{variant} fp32")
+    _particle_errs(ref, got, f"c1{variant} fp32")
 
 
 @pytest.mark.parametrize("seed,spread", [(21, 0.0), (22, 0.35)])
@@ -102,7 +136,7 @@ def test_random_cloud_variable_h(orc, seed, spread):
     _check_sets(orc, w, ctx, perm)
     _compare(ref, got, TOL64, FIELDS, f"cloud{seed} fp64")
     got32, _, _ = gpu_derivs(w, FP32, ctx=ctx)
-    _compare(ref, got32, dict(TOL32, dudt=3e-4), ("rho", "G", "dS", "a", "dudt"), f"cloud{seed} fp32")
+    _compare(ref, got32, dict(TOL32, dudt=2e-5), ("rho", "G", "dS", "a", "dudt"), f"cloud{seed} fp32")
 
 
 def test_dense_clump_spans_several_tiles(orc):
@@ -191,15 +225,19 @@ def test_c2_full_size_sampled(orc):
     n = w["x"].size
     rng = np.random.default_rng(8)
     tar = np.unique(np.concatenate([rng.choice(n, 40, replace=False), [0, n - 1, w["n_mobile"] - 1]]))
-    ref = _oracle(orc, w, tar)
+    ref = _oracle(orc, w, tar, scales=True)
     for prec, tol in ((FP64, TOL64), (FP32, TOL32)):
         got, ctx, perm = gpu_derivs(w, prec)
+        if prec == FP64:
+            _check_target_sets(orc, w, ctx, perm, tar)
         sub_ref = {k: (v[..., tar] if isinstance(v, np.ndarray) and v.shape[-1] == n else v)
                    for k, v in ref.items()}
         sub = {k: (v[..., tar] if isinstance(v, np.ndarray) and v.shape[-1] == n else v)
                for k, v in got.items()}
         fields = ("rho", "omega", "P", "cs", "G", "dS", "a", "dudt", "dt")
         _compare(sub_ref, sub, tol, fields, f"c2 sampled prec={prec}")
+        if prec == FP32:
+            _particle_errs(ref, got, "c2 sampled fp32", idx=tar)
 
 
 def test_c3_full_size_sampled(orc):
@@ -214,15 +252,19 @@ def test_c3_full_size_sampled(orc):
     rng = np.random.default_rng(9)
     tar = np.unique(np.concatenate([rng.choice(n, 30, replace=False),
                                     [0, n - 1, w["n_target"] - 1, w["n_target"]]]))
-    ref = _oracle(orc, w, tar)
+    ref = _oracle(orc, w, tar, scales=True)
     for prec, tol in ((FP64, TOL64), (FP32, TOL32)):
         got, ctx, perm = gpu_derivs(w, prec)
+        if prec == FP64:
+            _check_target_sets(orc, w, ctx, perm, tar)
         sub_ref = {k: (v[..., tar] if isinstance(v, np.ndarray) and v.shape[-1] == n else v)
                    for k, v in ref.items()}
         sub = {k: (v[..., tar] if isinstance(v, np.ndarray) and v.shape[-1] == n else v)
                for k, v in got.items()}
         fields = ("rho", "omega", "P", "cs", "G", "dS", "a", "dudt", "dt")
         _compare(sub_ref, sub, tol, fields, f"c3 sampled prec={prec}")
+        if prec == FP32:
+            _particle_errs(ref, got, "c3 sampled fp32", idx=tar)
         ctx.close()
 
 
@@ -262,6 +304,55 @@ def test_multistep_fp64_matches_oracle_integrator(orc, steps):
     say("multistep", {k: f"{v:.2e}" for k, v in e.items()})
     for k, v in e.items():
         assert v < 1e-9, (k, v)
+
+
+# FP32 form over whole steps, bounds per field after 1 and 6 steps: the
+# derivative errors of the form (~1e-6 of each field's scale) carried by the
+# FP64 integration, except the stress.  Stresses on the yield surface are
+# scaled to Y = mu_d P+, and P moves with the FP32 rounding of the density
+# (<= 3e-7 of rho) by up to K 3e-7 with the bulk modulus K = A = 26.7 GPa:
+# ~8 kPa against Y ~ 43 MPa on this block, 2e-4 of the stress scale (the
+# returned stress is reset to the yield surface every step, so this does
+# not grow).  Measured growth in the design notes.
+TOL32_STEPS = {1: dict(x=2e-5, v=2e-5, u=2e-5, S=2e-4, a=2e-5, dS=2e-5, eps2=2e-5),
+               6: dict(x=5e-5, v=5e-5, u=5e-5, S=2e-4, a=5e-5, dS=5e-5, eps2=5e-5)}
+
+
+@pytest.mark.parametrize("steps", [1, 6])
+def test_multistep_fp32_matches_oracle_integrator(orc, steps):
+    """Whole steps in the FP32 form (sph_init / sph_step) against the FP64
+    oracle integrator on the stressed block, both at the same fixed step
+    (half the CFL step) so that only the FP32 pair arithmetic differs."""
+    say(f"[multistep fp32 steps={steps}]")
+    import torch
+    from paper_2603_19764_amd import sph
+    w = inputs.c1_block(8, variant="s")
+    st = {k: w[k] for k in ("x", "y", "z", "m", "h", "mat", "vx", "vy", "vz", "u", "S", "fixed")}
+    dt0 = 0.5 * orc.Integrator(st, w["mats"], w["params"]).dt
+    it = orc.Integrator(st, w["mats"], w["params"], dt_fixed=dt0)
+    it.step(steps)
+    n = w["x"].size
+    ctx = sph.Context(n, 128)
+    S = sph.State(w, dt_max=dt0)
+    sph.sph_init(ctx, S, w["mats"], w["params"], FP32)
+    for _ in range(steps):
+        sph.sph_step(ctx, S, w["mats"], w["params"], FP32)
+    torch.cuda.synchronize()
+    ctx.check(sph.lib().sph_sync_status(ctx.h, None))
+    g = S.to_host()
+    e = dict(x=norm_err(np.stack([g[k] - w[k] for k in "xyz"]),
+                        np.stack([it[k] - w[k] for k in "xyz"])),
+             v=norm_err(np.stack([g[k] for k in ("vx", "vy", "vz")]),
+                        np.stack([it[k] for k in ("vx", "vy", "vz")])),
+             u=norm_err(g["u"] - w["u"], it["u"] - w["u"]),
+             S=norm_err(g["S"], it["S"]),
+             a=norm_err(g["a"], np.stack([it["ax"], it["ay"], it["az"]])),
+             dS=norm_err(g["dS"], it["dS"]),
+             eps2=norm_err(g["eps2"], it["eps2"]))
+    assert float(S.dt.item()) == dt0
+    say("multistep fp32", {k: f"{v:.2e}" for k, v in e.items()})
+    for k, v in e.items():
+        assert v <= TOL32_STEPS[steps][k], (k, v)
 
 
 def test_tabulated_melting_temperature_parity(orc):
@@ -404,7 +495,7 @@ def test_batched_scan_full_size_sampled(orc):
     torch.cuda.synchronize()
     ctx.check(sph.lib().sph_sync_status(ctx.h, None))
     g = st.to_host()
-    ctx.close()
+    perm = st.to_host(by_id=False)["id"].astype(np.int64)   # sorted -> input index
     sizes = np.diff(rs)
     strong = np.array([c["strength"] for c in b["cases"]]) == 1
     on, off = np.flatnonzero(strong), np.flatnonzero(~strong)
@@ -417,6 +508,13 @@ def test_batched_scan_full_size_sampled(orc):
         w.update(mats=b["mats"], params=prm)
         tar = np.unique(rng.choice(e - a, 12, replace=False))
         ref = _oracle(orc, w, tar)
+        # pair sets of the sampled particles in the batch (runs never mix)
+        sets = gpu_pair_sets_of(ctx, perm, tar + a)
+        off, nbr, dfl = orc.pair_lists(w["x"], w["y"], w["z"], w["h"], prm, tar)
+        for q, t in enumerate(tar):
+            js, fl = sets[int(t) + a]
+            assert np.array_equal(js - a, nbr[off[q]:off[q + 1]]), f"run {r}: pair set of {t}"
+            assert np.array_equal(fl, dfl[off[q]:off[q + 1]]), f"run {r}: density flags of {t}"
         nr = e - a
         sub_ref = {k: (v[..., tar] if isinstance(v, np.ndarray) and v.shape[-1] == nr else v)
                    for k, v in ref.items()}
@@ -424,3 +522,4 @@ def test_batched_scan_full_size_sampled(orc):
         got["cs"] = g["c"][a:e][tar]
         _compare(sub_ref, got, TOL32, ("rho", "omega", "P", "cs", "G", "dS", "a", "dudt", "dt"),
                  f"batch run {r} ({nr} particles, strength {int(strong[r])})")
+    ctx.close()
