@@ -393,7 +393,9 @@ enum {
     SPH_SDOT = 16,                  /* 5 rows */
     SPH_M = 21, SPH_H, SPH_EPS2,
     SPH_DTP = 24,                   /* individual steps: the particle's step and   */
-    SPH_EL = 25,                    /* the time elapsed in it, in ticks (exact)    */
+    SPH_EL = 25,                    /* the time elapsed in it, in ticks (exact);
+                                       kept (and carried through the sorts) only
+                                       while sph_params.rungs > 0               */
     SPH_NF64 = 26
 };
 /* Rows of the persistent int32 state buffer: material id, particle id (any
@@ -439,6 +441,10 @@ typedef struct {
     double *clock;               /* device, one double per run (individual steps
                                     only, else may be NULL): the run's time in ticks
                                     of the shortest rung, dt0 2^-(rungs-1)           */
+    double *time;                /* device, one double per run, or NULL: the run's
+                                    simulated time, set to 0 by sph_init and advanced
+                                    by every sph_step by the step (substep) the run
+                                    took                                            */
 } sph_state;
 
 /* Start a run: neighbour search and reorder (buffers flip), derivatives at
@@ -493,6 +499,11 @@ sph_status sph_mlp_backward(int32_t batch, const float *X, const float *Y, const
                             const float *out, const float *h1, const float *h2, float *work,
                             float *grads, sph_stream stream);
 
+/* *loss = (1/batch) sum_s (out_s - Y_s)^2 (device float), summed in a fixed
+ * order (deterministic). */
+sph_status sph_mlp_loss(int32_t batch, const float *out, const float *Y, float *loss,
+                        sph_stream stream);
+
 /* One bias-corrected Adam step (step >= 1) on params with moments m, v. */
 sph_status sph_mlp_adam(float *params, const float *grads, float *m, float *v, int32_t step,
                         float lr, float beta1, float beta2, float eps, sph_stream stream);
@@ -526,7 +537,10 @@ sph_status sph_timing_read(sph_ctx *ctx, int32_t which, double *total_ms, int64_
  *   SPH_TUNE_SWEEP_DEPTH neighbour records in flight per lane of the fused
  *                      gradient + force sweep of sph_step: 1 or 2 (per
  *                      precision; 2 hides more latency, 1 needs fewer
- *                      registers and so runs more waves per SIMD). */
+ *                      registers and so runs more waves per SIMD);
+ *   SPH_TUNE_BUILD_TILE candidates held in the local-memory tile of the
+ *                      pair-list build: 128, 192 or 256 (precision ignored;
+ *                      a smaller tile lets more work-groups share a CU). */
 enum {
     SPH_TUNE_LANES_DENSITY = 0,   /* density sweep                         */
     SPH_TUNE_LANES_GRADIENTS = 1, /* public gradient pass                  */
@@ -535,7 +549,8 @@ enum {
     SPH_TUNE_CELL_SCALE = 4,
     SPH_TUNE_BUILD_RANGE = 5,
     SPH_TUNE_SWEEP_DEPTH = 6,
-    SPH_TUNE_COUNT = 7
+    SPH_TUNE_BUILD_TILE = 7,
+    SPH_TUNE_COUNT = 8
 };
 sph_status sph_set_tuning(sph_ctx *ctx, int32_t knob, sph_precision prec, int32_t value);
 sph_status sph_get_tuning(sph_ctx *ctx, int32_t knob, sph_precision prec, int32_t *value);

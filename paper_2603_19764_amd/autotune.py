@@ -21,6 +21,7 @@ LANES = (8, 4, 16)   # default first
 CELL_SCALES = (1000, 1150, 1300)   # permille of 2 h_max
 BUILD_RANGES = (64, 32, 96, 128)   # sorted particles per pair-list build work-group (default first)
 SWEEP_DEPTHS = (2, 1)   # neighbour records in flight per lane of the fused sweep
+BUILD_TILES = (256, 192, 128)   # candidates in the pair-list build's LDS tile
 
 # knob -> (timer whose per-launch time decides it, candidate values)
 PLAN = (
@@ -29,10 +30,12 @@ PLAN = (
     (sph.SPH_TUNE_LANES_DENSITY, sph.SPH_T_DENSITY, LANES),
     (sph.SPH_TUNE_CELL_SCALE, None, CELL_SCALES),   # None: whole-step time
     (sph.SPH_TUNE_BUILD_RANGE, sph.SPH_T_BUILD, BUILD_RANGES),
+    (sph.SPH_TUNE_BUILD_TILE, sph.SPH_T_BUILD, BUILD_TILES),
 )
 KNOB_NAMES = {sph.SPH_TUNE_LANES_STEP: "lanes_step", sph.SPH_TUNE_LANES_DENSITY: "lanes_density",
               sph.SPH_TUNE_CELL_SCALE: "cell_scale_permille",
-              sph.SPH_TUNE_BUILD_RANGE: "build_range", sph.SPH_TUNE_SWEEP_DEPTH: "sweep_depth"}
+              sph.SPH_TUNE_BUILD_RANGE: "build_range", sph.SPH_TUNE_SWEEP_DEPTH: "sweep_depth",
+              sph.SPH_TUNE_BUILD_TILE: "build_tile"}
 
 
 def size_bucket(n: int) -> int:

@@ -694,7 +694,7 @@ static sph_status kick_hier(sph_ctx *h, sph_state *st, const Rows &R, const sph_
                               nr, ctx->run_p)))
         return e;
     e = launch_hier_next(ctx, nr, init, tick, step_bits(ctx, 0), step_bits(ctx, 1), st->dt,
-                         st->dt_next, st->clock, s);
+                         st->dt_next, st->clock, st->time, s);
     ctx->dt_parity ^= 1;
     return e;
 }
@@ -717,7 +717,7 @@ static sph_status kick(sph_ctx *h, sph_state *st, const Rows &R, int32_t mode, h
         ctx, st->n, mode, st->dt, step_bits(ctx, 0), st->dt_max, st->dt_next, step_bits(ctx, 1),
         nr, runid, R.i[SPH_FIXED], R.f[SPH_VX], R.f[SPH_VY], R.f[SPH_VZ], R.f[SPH_U],
         R.f[SPH_AX], R.f[SPH_AY], R.f[SPH_AZ], R.f[SPH_DUDT], R.f[SPH_S], R.w[SPH_W_SP],
-        R.f[SPH_SDOT], R.w[SPH_W_Y], s);
+        R.f[SPH_SDOT], R.w[SPH_W_Y], st->time, s);
     ctx->dt_parity ^= 1;
     return e;
 }
@@ -806,6 +806,12 @@ sph_status sph_set_tuning(sph_ctx *h, int32_t knob, sph_precision prec, int32_t 
         ctx->build_range = value;
         return SPH_OK;
     }
+    if (knob == SPH_TUNE_BUILD_TILE) {
+        REQUIRE(value == 128 || value == 192 || value == 256, SPH_EINVAL,
+                "build tile must be 128, 192 or 256 (got %d)", value);
+        ctx->build_tile = value;
+        return SPH_OK;
+    }
     if (knob == SPH_TUNE_SWEEP_DEPTH) {
         REQUIRE(value == 1 || value == 2, SPH_EINVAL, "sweep depth must be 1 or 2 (got %d)",
                 value);
@@ -827,6 +833,7 @@ sph_status sph_get_tuning(sph_ctx *h, int32_t knob, sph_precision prec, int32_t 
     *value = knob == SPH_TUNE_CELL_SCALE    ? (int32_t)(ctx->cell_scale * 1000.0 + 0.5)
              : knob == SPH_TUNE_BUILD_RANGE ? ctx->build_range
              : knob == SPH_TUNE_SWEEP_DEPTH ? ctx->sweep_depth[pi]
+             : knob == SPH_TUNE_BUILD_TILE  ? ctx->build_tile
                                             : ctx->lanes[knob][pi];
     return SPH_OK;
 }

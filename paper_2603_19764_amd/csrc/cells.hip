@@ -201,6 +201,31 @@ __device__ static int bits_for(int n) {
     return b;
 }
 
+// Cell grid of one run over its bounding box for an edge L (raised where an
+// axis would need more than 2^kMaxMortonBits - 2 cells): origin, cells and
+// Morton bits per axis, dense key count.
+__device__ static void size_grid(GridDesc &g, const BBox &bb, double L) {
+    if (!(L > 0.0)) L = 1.0;
+    for (int d = 0; d < 3; ++d) {
+        const double ext = bb.hi[d] - bb.lo[d];
+        if (ext / L > (double)((1 << kMaxMortonBits) - 2)) L = ext / (double)((1 << kMaxMortonBits) - 2);
+    }
+    int dims[3];
+    for (int d = 0; d < 3; ++d) {
+        const double ext = bb.hi[d] - bb.lo[d];
+        const int nd = (int)floor(ext / L) + 1;
+        dims[d] = nd < 1 ? 1 : nd;
+    }
+    g.ox = bb.lo[0]; g.oy = bb.lo[1]; g.oz = bb.lo[2];
+    g.L = L;
+    g.invL = 1.0 / L;
+    g.L32 = (float)L;
+    g.nx = dims[0]; g.ny = dims[1]; g.nz = dims[2];
+    g.bx = bits_for(dims[0]); g.by = bits_for(dims[1]); g.bz = bits_for(dims[2]);
+    g.key_count = 1 << (g.bx + g.by + g.bz);
+    g.key_off = 0;
+}
+
 // Per-run grids that fit the cell table.  The block first reduces each
 // run's bounding-box partials in parallel (into the first partial of the
 // run), then one thread sizes the grids.
@@ -238,50 +263,66 @@ __global__ void k_grid(BBox *part, int nbb, const int32_t *run_p, int nr, double
     }
     __syncthreads();
     if (threadIdx.x != 0) return;
-    double grow = 1.0;
-    for (int attempt = 0; attempt < 200; ++attempt) {
-        int64_t total = 0;
+    // Every run at its natural edge first; while the dense key ranges do not
+    // fit the table, the run holding the most keys (the one whose particles
+    // spread widest, e.g. the ejecta of a disruptive impact) coarsens its own
+    // grid by 1.25, so one dispersing run does not coarsen the others.
+    int64_t total = 0;
+    for (int r = 0; r < nr; ++r) {
+        BBox bb = part[r * kBBoxBlocks];
+        GridDesc g;
+        g.p0 = run_p[r];
+        g.p1 = run_p[r + 1];
+        if (g.p1 <= g.p0) {  // empty run
+            for (int d = 0; d < 3; ++d) { bb.lo[d] = 0.0; bb.hi[d] = 0.0; }
+            bb.hmax = 0.0;
+        }
+        // Edge at least the largest support 2h (so every pair lies in the
+        // 27-cell stencil), slightly enlarged so that rounding of
+        // (x - origin)/L can never separate a pair by two cells.
+        const double L = fmax(cell_min, 2.0 * bb.hmax * cell_scale) * (1.0 + 1.0 / 1099511627776.0);
+        size_grid(g, bb, L);
+        grid[r] = g;
+        total += g.key_count;
+    }
+    // (the search for the largest run is a scan over the runs, done by one
+    // thread: beyond 1024 runs every run coarsens together instead)
+    for (int attempt = 0; nr > 1024 && attempt < 64 && total > max_cells; ++attempt) {
+        total = 0;
         for (int r = 0; r < nr; ++r) {
+            GridDesc g = grid[r];
             BBox bb = part[r * kBBoxBlocks];
-            GridDesc g;
-            g.p0 = run_p[r];
-            g.p1 = run_p[r + 1];
-            if (g.p1 <= g.p0) {  // empty run
+            if (g.p1 <= g.p0) {
                 for (int d = 0; d < 3; ++d) { bb.lo[d] = 0.0; bb.hi[d] = 0.0; }
-                bb.hmax = 0.0;
             }
-            // Edge at least the largest support 2h (so every pair lies in the
-            // 27-cell stencil), slightly enlarged so that rounding of
-            // (x - origin)/L can never separate a pair by two cells.
-            double L = fmax(cell_min, 2.0 * bb.hmax * cell_scale) * grow *
-                       (1.0 + 1.0 / 1099511627776.0);
-            if (!(L > 0.0)) L = 1.0;
-            int dims[3];
-            for (int d = 0; d < 3; ++d) {
-                const double ext = bb.hi[d] - bb.lo[d];
-                if (ext / L > (double)((1 << kMaxMortonBits) - 2)) L = ext / (double)((1 << kMaxMortonBits) - 2);
-            }
-            for (int d = 0; d < 3; ++d) {
-                const double ext = bb.hi[d] - bb.lo[d];
-                const int nd = (int)floor(ext / L) + 1;
-                dims[d] = nd < 1 ? 1 : nd;
-            }
-            g.ox = bb.lo[0]; g.oy = bb.lo[1]; g.oz = bb.lo[2];
-            g.L = L;
-            g.invL = 1.0 / L;
-            g.L32 = (float)L;
-            g.nx = dims[0]; g.ny = dims[1]; g.nz = dims[2];
-            g.bx = bits_for(dims[0]); g.by = bits_for(dims[1]); g.bz = bits_for(dims[2]);
-            g.key_count = 1 << (g.bx + g.by + g.bz);
-            g.key_off = (int32_t)total;
-            total += g.key_count;
+            size_grid(g, bb, g.L * 1.25);
             grid[r] = g;
+            total += g.key_count;
         }
-        if (total <= max_cells) {
-            *total_keys = (int32_t)total;
-            return;
+    }
+    for (int attempt = 0; attempt < 4096 && total > max_cells; ++attempt) {
+        int big = 0;
+        for (int r = 1; r < nr; ++r)
+            if (grid[r].key_count > grid[big].key_count) big = r;
+        GridDesc g = grid[big];
+        if (g.key_count <= 1) break;
+        BBox bb = part[big * kBBoxBlocks];
+        if (g.p1 <= g.p0) {
+            for (int d = 0; d < 3; ++d) { bb.lo[d] = 0.0; bb.hi[d] = 0.0; }
         }
-        grow *= 1.25;
+        total -= g.key_count;
+        size_grid(g, bb, g.L * 1.25);
+        grid[big] = g;
+        total += g.key_count;
+    }
+    if (total <= max_cells) {
+        int64_t off = 0;
+        for (int r = 0; r < nr; ++r) {
+            grid[r].key_off = (int32_t)off;
+            off += grid[r].key_count;
+        }
+        *total_keys = (int32_t)total;
+        return;
     }
     flags[FLAG_CELL_OVERFLOW] = 1;
     *total_keys = 0;
@@ -432,7 +473,6 @@ __global__ void k_place(int64_t n, const int32_t *__restrict__ arrived,
 // each lane holds one candidate of a 64-wide column of the tile; one exact
 // test per lane, a ballot, and the hits are appended to i's list in
 // candidate order at offsets from mbcnt.  The lists are deterministic.
-constexpr int kTileMax = 256;
 constexpr int kFillChunks = 2;  // raw-candidate chunks whose loads overlap
 constexpr int kIBatch = 64;
 constexpr double kCullMargin = 1.0 + 0x1p-40;
@@ -445,14 +485,18 @@ __device__ __forceinline__ uint32_t lanes_below(uint64_t m) {
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
 }
 
+// Tile: candidates the LDS tile holds (36 B each): 256 entries take 9.4 KB per
+// single-wave work-group (17 work-groups, 4.25 waves per SIMD), 192 take 7.1 KB
+// (5 waves, the register limit), 128 take 4.8 KB.
+template <int Tile>
 __global__ __launch_bounds__(64) void k_build_pairs(
     int64_t n, const double4 *__restrict__ posh64, const uint32_t *__restrict__ skey,
     const uint32_t *__restrict__ cellc, const int16_t *__restrict__ runid,
     const GridDesc *__restrict__ grid, const int32_t *__restrict__ cell_start,
     const int32_t *__restrict__ cell_count, const int32_t *total_keys, uint32_t *nbr,
     int32_t *ncount, int32_t K, int32_t *flags, unsigned long long *pairs) {
-    __shared__ double4 tpos[kTileMax];  // x, y, z, H_j^2
-    __shared__ uint32_t tj[kTileMax];   // j | stencil code
+    __shared__ double4 tpos[Tile];  // x, y, z, H_j^2
+    __shared__ uint32_t tj[Tile];   // j | stencil code
     __shared__ int32_t st_start[27];
     __shared__ int32_t st_off[28];
 
@@ -538,11 +582,11 @@ __global__ __launch_bounds__(64) void k_build_pairs(
             for (int r0 = 0; r0 < T || fill > 0;) {
                 // ---- fill: cull raw candidates into the tile
                 __syncthreads();
-                for (; r0 < T && fill <= kTileMax - kWave;) {
+                for (; r0 < T && fill <= Tile - kWave;) {
                     // up to kFillChunks chunks of 64 raw candidates at once:
                     // their searches and loads overlap, then they are
                     // appended in order (as many as the tile has room for)
-                    int nch = (kTileMax - fill) / kWave;
+                    int nch = (Tile - fill) / kWave;
                     const int left = (T - r0 + kWave - 1) / kWave;
                     nch = nch < left ? nch : left;
                     nch = nch < kFillChunks ? nch : kFillChunks;
@@ -747,10 +791,17 @@ sph_status launch_build_cells(Ctx *ctx, int64_t n, double *x, double *y, double 
     if (wgs > 65536) wgs = 65536;
     {
         TimedLaunch tl(ctx, SPH_T_BUILD, s);
-        hipLaunchKernelGGL(k_build_pairs, dim3((unsigned)wgs), dim3(64), 0, s, n, ctx->posh64,
-                           ctx->skey, ctx->cellc, ctx->runid, ctx->grid, ctx->cell_start,
-                           ctx->cell_count, ctx->total_keys, ctx->nbr, ctx->ncount, ctx->max_nbr,
-                           ctx->flags, ctx->pairs);
+#define SPH_BUILD_LAUNCH(T)                                                                    \
+    hipLaunchKernelGGL(k_build_pairs<T>, dim3((unsigned)wgs), dim3(64), 0, s, n, ctx->posh64, \
+                       ctx->skey, ctx->cellc, ctx->runid, ctx->grid, ctx->cell_start,          \
+                       ctx->cell_count, ctx->total_keys, ctx->nbr, ctx->ncount, ctx->max_nbr, \
+                       ctx->flags, ctx->pairs)
+        switch (ctx->build_tile) {
+            case 128: SPH_BUILD_LAUNCH(128); break;
+            case 192: SPH_BUILD_LAUNCH(192); break;
+            default: SPH_BUILD_LAUNCH(256); break;
+        }
+#undef SPH_BUILD_LAUNCH
     }
     SPH_HIP(hipGetLastError());
     ctx->n_built = n;

@@ -136,6 +136,26 @@ __global__ void k_mlp_adam(int32_t n, float *__restrict__ P, const float *__rest
     P[p] -= lr * mh / (sqrtf(vh) + eps);
 }
 
+// loss = (1/B) sum_s (out_s - y_s)^2: one work-group, each thread sums a
+// fixed stride of samples, then a fixed-order tree (deterministic).
+__global__ __launch_bounds__(256) void k_mlp_loss(int32_t B, const float *__restrict__ out,
+                                                  const float *__restrict__ Y,
+                                                  float *__restrict__ loss) {
+    __shared__ float part[256];
+    float a = 0.0f;
+    for (int s = threadIdx.x; s < B; s += blockDim.x) {
+        const float d = out[s] - Y[s];
+        a += d * d;
+    }
+    part[threadIdx.x] = a;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) part[threadIdx.x] += part[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *loss = B > 0 ? part[0] / (float)B : 0.0f;
+}
+
 }  // namespace sph
 
 using namespace sph;
@@ -166,6 +186,14 @@ sph_status sph_mlp_backward(int32_t batch, const float *X, const float *Y, const
                            params, out, h1, h2, D1, D2, D3);
     hipLaunchKernelGGL(k_mlp_grads, dim3((kNumParams + 255) / 256), dim3(256), 0, s, batch, X, h1,
                        h2, D1, D2, D3, grads);
+    return hipGetLastError() == hipSuccess ? SPH_OK : SPH_EHIP;
+}
+
+sph_status sph_mlp_loss(int32_t batch, const float *out, const float *Y, float *loss,
+                        sph_stream stream) {
+    if (batch < 0 || !loss || (batch > 0 && (!out || !Y))) return SPH_EINVAL;
+    hipLaunchKernelGGL(k_mlp_loss, dim3(1), dim3(256), 0, (hipStream_t)stream, batch, out, Y,
+                       loss);
     return hipGetLastError() == hipSuccess ? SPH_OK : SPH_EHIP;
 }
 

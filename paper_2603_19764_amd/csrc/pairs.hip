@@ -480,7 +480,7 @@ __attribute__((amdgpu_waves_per_eu(Depth == 1 ? (F32 ? 6 : 3) : 1, 8))) void k_g
     R hi2 = 0, ci2 = 0;
     if (active) {
         constexpr int o = kVelSlots<F32>;
-        const R4 *ri = rec + kRecBothSlots<F32> * i;
+        const R4 *ri = rec + kRecBothStride<F32> * i;
         const R4 pi = ri[0], A2 = ri[1 + o], B2 = ri[2 + o], H2 = ri[3 + o];
         const VM<R> vi = load_vm<F32, R>(ri + 1);
         const R im = H2.w;
@@ -555,20 +555,20 @@ __attribute__((amdgpu_waves_per_eu(Depth == 1 ? (F32 ? 6 : 3) : 1, 8))) void k_g
             R4 P0, A0, B0, H0, P1, A1, B1, H1;
             VM<R> V0, V1;
             {
-                const R4 *rj = rec + kRecBothSlots<F32> * (int64_t)(e0 & kIdxMask);
+                const R4 *rj = rec + kRecBothStride<F32> * (int64_t)(e0 & kIdxMask);
                 P0 = rj[0]; V0 = load_vm<F32, R>(rj + 1); A0 = rj[1 + o]; B0 = rj[2 + o]; H0 = rj[3 + o];
             }
             for (int k = lg; k < c; k += 2 * L) {
                 const uint32_t e2 = entry(k + 2 * L);
                 {
-                    const R4 *rj = rec + kRecBothSlots<F32> * (int64_t)(e1 & kIdxMask);
+                    const R4 *rj = rec + kRecBothStride<F32> * (int64_t)(e1 & kIdxMask);
                     P1 = rj[0]; V1 = load_vm<F32, R>(rj + 1); A1 = rj[1 + o]; B1 = rj[2 + o]; H1 = rj[3 + o];
                 }
                 body(e0, P0, V0, A0, B0, H0);
                 if (k + L >= c) break;
                 const uint32_t e3 = entry(k + 3 * L);
                 {
-                    const R4 *rj = rec + kRecBothSlots<F32> * (int64_t)(e2 & kIdxMask);
+                    const R4 *rj = rec + kRecBothStride<F32> * (int64_t)(e2 & kIdxMask);
                     P0 = rj[0]; V0 = load_vm<F32, R>(rj + 1); A0 = rj[1 + o]; B0 = rj[2 + o]; H0 = rj[3 + o];
                 }
                 body(e1, P1, V1, A1, B1, H1);
@@ -581,7 +581,7 @@ __attribute__((amdgpu_waves_per_eu(Depth == 1 ? (F32 ? 6 : 3) : 1, 8))) void k_g
             for (int k = lg; k < c; k += L) {
                 const uint32_t e = en;
                 en = entry(k + L);  // next entry in flight
-                const R4 *rj = rec + kRecBothSlots<F32> * (int64_t)(e & kIdxMask);
+                const R4 *rj = rec + kRecBothStride<F32> * (int64_t)(e & kIdxMask);
                 const R4 Pj = rj[0], Aj = rj[1 + o], Bj = rj[2 + o], Hj = rj[3 + o];
                 const VM<R> Vj = load_vm<F32, R>(rj + 1);
                 body(e, Pj, Vj, Aj, Bj, Hj);

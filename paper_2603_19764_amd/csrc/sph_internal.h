@@ -71,6 +71,7 @@ struct Ctx {
     double cell_scale = 1.0;
     int32_t build_range = 64;  // sorted particles per work-group of the pair-list build
     int32_t sweep_depth[2] = {2, 2};  // records in flight per lane of the fused sweep [precision]
+    int32_t build_tile = 256;         // candidates in the LDS tile of the pair-list build
     // self-gravity pyramid (allocated with the context)
     void *grav_lev = nullptr;        // per-run level layout (max_runs entries)
     int64_t *grav_totals = nullptr;  // [upper nodes, groups]
@@ -290,7 +291,8 @@ sph_status launch_kick_hier(Ctx *ctx, int64_t n, int32_t init, int32_t rungs, do
                             hipStream_t s);
 sph_status launch_hier_next(Ctx *ctx, int32_t nr, int32_t init, double tick,
                             const unsigned long long *bits_cur, unsigned long long *bits_clear,
-                            const double *dt, double *dt_next, double *clock, hipStream_t s);
+                            const double *dt, double *dt_next, double *clock, double *time,
+                            hipStream_t s);
 // Kicks; the next step of each run is taken from the minima in bits_cur
 // (capped at dt_cap when > 0) and written to dt_next[0..nr); bits_clear is
 // set to +inf for the following reduction.
@@ -301,6 +303,6 @@ sph_status launch_step_kick(Ctx *ctx, int64_t n, int32_t mode, const double *dt,
                             double *vz, double *u, const double *ax, const double *ay,
                             const double *az, const double *dudt, double *S_half,
                             const double *S_pred, const double *Sdot, const double *Y,
-                            hipStream_t s);
+                            double *time, hipStream_t s);
 
 }  // namespace sph

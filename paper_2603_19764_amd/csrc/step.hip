@@ -20,6 +20,8 @@ namespace sph {
 // advanced, a repeated reorder of the same step) less half of that step,
 // and act = 1 where the step ends now.  predict = 0 (start of a run):
 // tau = 0, every particle evaluated.
+// The rows of the individual steps (SPH_DTP, SPH_EL, the last two) are
+// carried only when they are in use (hier).
 __global__ void k_reorder_predict(int64_t n, const int32_t *__restrict__ perm, StepRows r,
                                   const double *__restrict__ dtp,
                                   const int16_t *__restrict__ runid, int32_t predict,
@@ -27,14 +29,19 @@ __global__ void k_reorder_predict(int64_t n, const int32_t *__restrict__ perm, S
                                   double *__restrict__ vpy, double *__restrict__ vpz,
                                   double *__restrict__ up, double *__restrict__ tau,
                                   int32_t *__restrict__ act) {
+    static_assert(SPH_DTP == SPH_NF64 - 2 && SPH_EL == SPH_NF64 - 1, "step rows last");
     const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (k >= n) return;
     const int64_t o = perm[k];
     double f[SPH_NF64];
 #pragma unroll
     for (int c = 0; c < SPH_NF64; ++c) {
-        f[c] = r.f_src[c][o];
-        r.f_dst[c][k] = f[c];
+        if (c < SPH_DTP || hier) {
+            f[c] = r.f_src[c][o];
+            r.f_dst[c][k] = f[c];
+        } else {
+            f[c] = 0.0;
+        }
     }
     int32_t fx = 0;
 #pragma unroll
@@ -118,7 +125,7 @@ __global__ void k_state(int64_t n, const double4 *__restrict__ posh64,
     const double mi = m[i];
     const double kn = -210.0 / (kPiD * H * H * H * H * H);
     const double sc = mi * kn / (om * r * r);
-    R4 *rf = (R4 *)rec_f_v + kRecBothSlots<F32> * i;
+    R4 *rf = (R4 *)rec_f_v + kRecBothStride<F32> * i;
     constexpr int o = kVelSlots<F32>;
     rf[0] = {px, py, pz, (R)(1.0 / H)};
     store_vm<F32>(rf + 1, vpx[i], vpy[i], vpz[i], mi);
@@ -189,11 +196,13 @@ __global__ void k_kick_all(int64_t n, int32_t mode, const double *__restrict__ d
                            const double *__restrict__ az, const double *__restrict__ dudt,
                            double *S_half, const double *__restrict__ S_pred,
                            const double *__restrict__ Sdot, const double *__restrict__ Y,
-                           int32_t *__restrict__ flags) {
+                           int32_t *__restrict__ flags, double *__restrict__ time) {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i < nr) {
         dt_next[i] = dt_from_bits(bits_cur[i], dt_cap);
         bits_clear[i] = 0x7ff0000000000000ull;
+        // the run's time: 0 at the start of a run, else advanced by its step
+        if (time) time[i] = mode == 0 ? time[i] + dtp[i] : 0.0;
     }
     if (i >= n) return;
     if (fixed && fixed[i]) return;
@@ -316,11 +325,12 @@ __global__ void k_kick_hier(int64_t n, int32_t init, int32_t rungs, double tick,
 __global__ void k_hier_next(int32_t nr, int32_t init, double tick,
                             const unsigned long long *__restrict__ bits_cur,
                             unsigned long long *bits_clear, const double *__restrict__ dt,
-                            double *dt_next, double *clock) {
+                            double *dt_next, double *clock, double *time) {
     const int r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= nr) return;
     dt_next[r] = __longlong_as_double((long long)bits_cur[r]);
     clock[r] = init ? 0.0 : clock[r] + rint(dt[r] / tick);
+    if (time) time[r] = clock[r] * tick;   // whole ticks: exact
     bits_clear[r] = 0x7ff0000000000000ull;
 }
 
@@ -380,12 +390,12 @@ sph_status launch_step_kick(Ctx *ctx, int64_t n, int32_t mode, const double *dt,
                             double *vz, double *u, const double *ax, const double *ay,
                             const double *az, const double *dudt, double *S_half,
                             const double *S_pred, const double *Sdot, const double *Y,
-                            hipStream_t s) {
+                            double *time, hipStream_t s) {
     const int64_t m = n > nr ? n : nr;
     if (m == 0) return SPH_OK;
     hipLaunchKernelGGL(k_kick_all, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, n, mode,
                        dt, bits_cur, dt_cap, dt_next, bits_clear, nr, runid, fixed, vx, vy, vz, u,
-                       ax, ay, az, dudt, S_half, S_pred, Sdot, Y, ctx->flags);
+                       ax, ay, az, dudt, S_half, S_pred, Sdot, Y, ctx->flags, time);
     SPH_HIP(hipGetLastError());
     return SPH_OK;
 }
@@ -419,10 +429,11 @@ sph_status launch_kick_hier(Ctx *ctx, int64_t n, int32_t init, int32_t rungs, do
 
 sph_status launch_hier_next(Ctx *ctx, int32_t nr, int32_t init, double tick,
                             const unsigned long long *bits_cur, unsigned long long *bits_clear,
-                            const double *dt, double *dt_next, double *clock, hipStream_t s) {
+                            const double *dt, double *dt_next, double *clock, double *time,
+                            hipStream_t s) {
     (void)ctx;
     hipLaunchKernelGGL(k_hier_next, dim3((unsigned)((nr + 255) / 256)), dim3(256), 0, s, nr,
-                       init, tick, bits_cur, bits_clear, dt, dt_next, clock);
+                       init, tick, bits_cur, bits_clear, dt, dt_next, clock, time);
     SPH_HIP(hipGetLastError());
     return SPH_OK;
 }

@@ -33,7 +33,7 @@ SPH_W_VP, SPH_W_UP, SPH_W_SP, SPH_W_G, SPH_W_DT, SPH_W_PERM = 7, 10, 11, 16, 25,
 SPH_W_TAU, SPH_W_ACT, SPH_NW = 27, 28, 29
 SPH_T_BUILD, SPH_T_DENSITY, SPH_T_GRADIENTS, SPH_T_FORCES = range(4)
 (SPH_TUNE_LANES_DENSITY, SPH_TUNE_LANES_GRADIENTS, SPH_TUNE_LANES_FORCES, SPH_TUNE_LANES_STEP,
- SPH_TUNE_CELL_SCALE, SPH_TUNE_BUILD_RANGE, SPH_TUNE_SWEEP_DEPTH) = range(7)
+ SPH_TUNE_CELL_SCALE, SPH_TUNE_BUILD_RANGE, SPH_TUNE_SWEEP_DEPTH, SPH_TUNE_BUILD_TILE) = range(8)
 
 
 class SphError(RuntimeError):
@@ -70,7 +70,8 @@ class sph_state(C.Structure):
                 ("f64", C.c_void_p * 2), ("i32", C.c_void_p * 2), ("work", C.c_void_p),
                 ("dt", C.c_void_p), ("dt_next", C.c_void_p), ("n_singular", C.c_void_p),
                 ("cur", C.c_int32), ("n_runs", C.c_int32), ("run_start", C.c_void_p),
-                ("cell_min", C.c_double), ("dt_max", C.c_double), ("clock", C.c_void_p)]
+                ("cell_min", C.c_double), ("dt_max", C.c_double), ("clock", C.c_void_p),
+                ("time", C.c_void_p)]
 
 
 _lib = None
@@ -119,6 +120,7 @@ def lib():
             "sph_mlp_forward": [i32, _P, _P, _P, _P, _P, _P],
             "sph_mlp_backward": [i32, _P, _P, _P, _P, _P, _P, _P, _P, _P],
             "sph_mlp_adam": [_P, _P, _P, _P, i32, C.c_float, C.c_float, C.c_float, C.c_float, _P],
+            "sph_mlp_loss": [i32, _P, _P, _P, _P],
         })
         for name, args in sig.items():
             f = getattr(L, name)
@@ -436,6 +438,7 @@ class State:
         n_dt = 1 if run_start is None else len(run_start) - 1
         self._dt_pair = (torch.zeros(n_dt, **dd), torch.zeros(n_dt, **dd))
         self.clock = torch.zeros(n_dt, **dd)   # per run, ticks (individual steps)
+        self.time = torch.zeros(n_dt, **dd)    # per run, simulated time since sph_init
         self.n_singular = torch.zeros(1, dtype=torch.int64, device=device)
         F = self.f64[0]
         for k, row in (("x", SPH_X), ("y", SPH_Y), ("z", SPH_Z), ("vx", SPH_VX), ("vy", SPH_VY),
@@ -466,6 +469,7 @@ class State:
         c.cell_min = float(cell_min)
         c.dt_max = float(dt_max)
         c.clock = self.clock.data_ptr()
+        c.time = self.time.data_ptr()
         self.c = c
         self._mats_cache = None
 
@@ -539,6 +543,12 @@ def sph_mlp_backward(X, Y, params, out, h1, h2, work, grads, stream=None):
     _mlp_check(lib().sph_mlp_backward(X.shape[0], _ptr(X), _ptr(Y), _ptr(params), _ptr(out),
                                       _ptr(h1), _ptr(h2), _ptr(work), _ptr(grads),
                                       _stream(stream)))
+
+
+def sph_mlp_loss(out, Y, loss, stream=None):
+    """loss[0] = mean of (out - Y)^2 (float32 device tensors)."""
+    _mlp_check(lib().sph_mlp_loss(int(out.numel()), _ptr(out), _ptr(Y), _ptr(loss),
+                                  _stream(stream)))
 
 
 def sph_mlp_adam(params, grads, m, v, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8,

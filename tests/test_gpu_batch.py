@@ -39,6 +39,7 @@ def _evolve(w, prec, steps, run_start=None):
     torch.cuda.synchronize()
     ctx.check(sph.lib().sph_sync_status(ctx.h, None))
     out = st.to_host()
+    out["time"] = st.time.cpu().numpy().copy()
     dt = st.dt.cpu().numpy().copy()
     ctx.close()
     return out, dt
@@ -62,6 +63,8 @@ def test_batched_runs_equal_single_runs(prec):
         part = _slice(gb, rs[r], rs[r + 1])
         e = {k: norm_err(part[k], gs[k]) for k in FIELDS}
         e["dt"] = abs(dtb[r] - dts[0]) / dts[0]
+        # each run's simulated time kept by the library: the sum of its steps
+        e["time"] = abs(gb["time"][r] - gs["time"][0]) / gs["time"][0]
         say(f"run {r} prec {prec}", {k: f"{v:.1e}" for k, v in e.items()})
         worst = max(worst, max(e.values()))
     assert worst <= 1e-12

@@ -47,6 +47,7 @@ def _gpu(w, mats, prm, dt_max, steps, prec=FP64, run_start=None):
     ctx.check(sph.lib().sph_sync_status(ctx.h, None))
     out = st.to_host()
     out["clock"] = st.clock.cpu().numpy()
+    out["time"] = st.time.cpu().numpy()
     out["dt_next"] = st.dt.cpu().numpy()
     ctx.close()
     return out
@@ -105,6 +106,8 @@ def test_two_bodies_on_different_rungs_match_oracle(substeps):
     assert np.array_equal(g["step_ticks"], it["dtp"].astype(float))
     assert np.array_equal(g["elapsed_ticks"], it["el"].astype(float))
     assert g["clock"][0] == it.ticks
+    # the simulated time the library keeps: whole ticks, exact
+    assert g["time"][0] == it.time
     _compare(g, it, f"two bodies {substeps}")
 
 

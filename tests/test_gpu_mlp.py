@@ -53,6 +53,11 @@ def test_forward_backward_adam_match_oracle():
     e_p = norm_err(P.cpu().numpy() - p, rp - p)
     say("mlp", dict(out=f"{e_out:.1e}", h1=f"{e_h1:.1e}", grad=f"{e_g:.1e}", adam=f"{e_p:.1e}"))
     assert e_out < 1e-5 and e_h1 < 1e-5
+    # the loss kernel: mean squared error of the forward outputs
+    loss = torch.empty(1, device="cuda")
+    sph.sph_mlp_loss(out, Yd, loss)
+    o64 = out.cpu().numpy().astype(np.float64)
+    assert abs(float(loss.item()) - np.mean((o64 - Y) ** 2)) <= 1e-6 * np.mean((o64 - Y) ** 2)
     assert e_g < 1e-4
     assert e_p < 1e-4
 

@@ -301,6 +301,8 @@ def test_multistep_fp64_matches_oracle_integrator(orc, steps):
     e["eps2"] = norm_err(g["eps2"], it["eps2"]) if steps else 0.0
     dt_gpu = float(S.dt.item())
     e["dt"] = abs(dt_gpu - it.dt) / it.dt
+    # the run's simulated time kept by the library
+    e["time"] = abs(float(S.time.item()) - it.time) / it.time if steps else float(S.time.item())
     say("multistep", {k: f"{v:.2e}" for k, v in e.items()})
     for k, v in e.items():
         assert v < 1e-9, (k, v)

@@ -46,6 +46,7 @@ def test_every_knob_setting_gives_the_same_step(prec):
                   {sph.SPH_TUNE_CELL_SCALE: 1300},
                   {sph.SPH_TUNE_BUILD_RANGE: 32}, {sph.SPH_TUNE_BUILD_RANGE: 128},
                   {sph.SPH_TUNE_SWEEP_DEPTH: 1},
+                  {sph.SPH_TUNE_BUILD_TILE: 128}, {sph.SPH_TUNE_BUILD_TILE: 192},
                   {sph.SPH_TUNE_SWEEP_DEPTH: 1, sph.SPH_TUNE_LANES_STEP: 4}):
         got = _steps(w, prec, knobs)
         e = max(norm_err(got[k], ref[k]) for k in FIELDS)
@@ -57,7 +58,8 @@ def test_bad_knob_values_are_rejected():
     from paper_2603_19764_amd import sph
     ctx = sph.Context(16, 32)
     for knob, v in ((sph.SPH_TUNE_LANES_STEP, 3), (sph.SPH_TUNE_CELL_SCALE, 999),
-                    (sph.SPH_TUNE_BUILD_RANGE, 48), (sph.SPH_TUNE_SWEEP_DEPTH, 3), (17, 8)):
+                    (sph.SPH_TUNE_BUILD_RANGE, 48), (sph.SPH_TUNE_SWEEP_DEPTH, 3),
+                    (sph.SPH_TUNE_BUILD_TILE, 100), (17, 8)):
         with pytest.raises(sph.SphError):
             sph.sph_set_tuning(ctx, knob, 0, v)
     ctx.close()
@@ -74,5 +76,6 @@ def test_tuner_returns_valid_settings(tmp_path):
     assert s["cell_scale_permille"] in autotune.CELL_SCALES
     assert s["build_range"] in autotune.BUILD_RANGES
     assert s["sweep_depth"] in autotune.SWEEP_DEPTHS
+    assert s["build_tile"] in autotune.BUILD_TILES
     again = autotune.tune(w, 1, steps=2, cache=cache)
     assert again["cached"] and again["settings"] == s
