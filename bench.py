@@ -500,6 +500,34 @@ def run_batch(steps, warmup, gravity=True, tune=True):
             "dt_spread": float(dt.max() / dt.min())}
 
 
+def run_batch_outcomes(max_steps=8000, check_every=100, seed=5, scale=1.0):
+    """The 64-impact batch (FP32, self-gravity on; particle counts times
+    ``scale``) run to every run's t_end (two free-fall times plus the crossing
+    time): each run's largest-remnant fraction f_lr when it passes t_end/2
+    and t_end, and whether it changed by less than 1% of the run's mass
+    between the two (converged)."""
+    from paper_2603_19764_amd import inputs, scan
+    b = inputs.scan_batch(64, seed=seed, scale=scale)
+    t_end = scan.end_times(b["cases"])
+    r = scan.run_to_end(b, t_end, (0.5, 1.0), max_steps=max_steps, check_every=check_every,
+                        log=log)
+    f1, f2 = r["f"][0.5], r["f"][1.0]
+    d = np.abs(f2 - f1)
+    runs = [{"n_particles": int(b["run_start"][k + 1] - b["run_start"][k]),
+             "v_over_vesc": c["v"] / c["v_esc"], "strength": c["strength"],
+             "m_tot": c["m_tot"], "t_end_s": float(t_end[k]),
+             "f_lr_half": None if np.isnan(f1[k]) else float(f1[k]),
+             "f_lr_end": None if np.isnan(f2[k]) else float(f2[k])}
+            for k, c in enumerate(b["cases"])]
+    ok = ~np.isnan(d)
+    return {"workload": f"the 64-impact batch ({int(b['x'].size)} particles, target counts x "
+                        f"{scale}) run to t_end (2 free-fall times + crossing time) with "
+                        "self-gravity, FP32", "steps": r["steps"], "seconds": r["seconds"],
+            "runs_reaching_t_end": int(r["reached"].sum()),
+            "converged_runs": int((d[ok] < 0.01).sum()), "compared_runs": int(ok.sum()),
+            "max_change": float(d[ok].max()) if ok.any() else None, "runs": runs}
+
+
 def run_column(steps, warmup, tune=True):
     """The granular column (196,794 mobile particles on a floor of 29,928
     fixed ones, FP32 and FP64 whole steps)."""
@@ -579,22 +607,20 @@ def run_hsteps(n_side=64, prec=1, shared_steps=600):
         if mode == "shared":
             dt0 = float(st.wrow(sph.SPH_W_DT).max()) * 1.01
         p0, e0 = _conserved(st, w["mats"])
-        sim_d = torch.zeros(1, dtype=torch.float64, device="cuda")
         k = 0
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         while True:
             for _ in range(20):
-                sim_d += st.dt          # on the device: no synchronisation per step
-                sph.sph_step(ctx, st, w["mats"], prm, prec)
+                sph.sph_step(ctx, st, w["mats"], prm, prec)   # advances st.time
             k += 20
             if mode == "shared" and k >= shared_steps:
                 break
-            if mode == "rungs" and float(sim_d.item()) >= t_target:
+            if mode == "rungs" and float(st.time.item()) >= t_target:
                 break
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        sim = float(sim_d.item())
+        sim = float(st.time.item())
         ctx.check(sph.lib().sph_sync_status(ctx.h, None))
         p1, e1 = _conserved(st, w["mats"])
         pscale = float((st.row(sph.SPH_M).cpu().numpy() * np.abs(
@@ -645,6 +671,10 @@ def main():
                     help="skip the individual-step comparison on the hot-core block")
     ap.add_argument("--batch-steps", type=int, default=20,
                     help="steps of the batched 64-impact scan (0: skip it)")
+    ap.add_argument("--batch-outcomes", type=float, default=0.0, metavar="SCALE",
+                    help="also run the 64-impact batch with target counts times SCALE to "
+                         "t_end (minutes) for each run's largest-remnant fraction at t_end/2 "
+                         "and t_end (0: skip)")
     ap.add_argument("--no-tune", action="store_true",
                     help="keep the default launch shapes (no autotuning before the warmup)")
     ap.add_argument("--headline-only", action="store_true",
@@ -724,6 +754,7 @@ def main():
     if args.batch_steps > 0:
         batch = run_batch(args.batch_steps, 4, tune=not args.no_tune)
         log(f"batch: {batch['ms_per_step']:.3f} ms/step, {batch['value']:.3e} pairs/s")
+    outcomes = run_batch_outcomes(scale=args.batch_outcomes) if args.batch_outcomes > 0 else None
     cpu = None if args.no_cpu_baseline else cpu_baseline(w)
     line = {
         "metric": METRIC, "value": value, "unit": "pairs/s", "n_gpus": 1,
@@ -750,6 +781,7 @@ def main():
         "size_curve": curve,
         "individual_steps": hsteps,
         "batch_scan": batch,
+        "batch_outcomes": outcomes,
     }
     print(json.dumps(line), flush=True)
 

@@ -61,7 +61,9 @@ class MlpProposer:
             sph.sph_mlp_backward(Xd, Yd, self.P, out, h1, h2, work, self.G)
             sph.sph_mlp_adam(self.P, self.G, self.M, self.V, self.t, self.lr)
         sph.sph_mlp_forward(Xd, self.P, out, h1, h2)
-        return float(torch.mean((out - Yd) ** 2).item())
+        loss = torch.empty(1, dtype=torch.float32, device="cuda")
+        sph.sph_mlp_loss(out, Yd, loss)
+        return float(loss.item())
 
     def predict(self, X) -> np.ndarray:
         Xd = torch.tensor(self._std(X), dtype=torch.float32, device="cuda").contiguous()

@@ -24,72 +24,99 @@ def free_fall_time(rho: float) -> float:
     return 1.0 / math.sqrt(G * rho)
 
 
-def simulate(cases: list, t_end_ff: float = 2.0, prec: int = sph.SPH_FP32_CELLREL,
-             max_steps: int = 20000, check_every: int = 50, theta: float = 0.6,
-             max_neighbors: int = 256, log=None) -> dict:
-    """Run every case (dicts with n_target, gamma, r_c1, v_over_vesc, strength)
-    to t_end = t_end_ff free-fall times of the target material plus the
-    crossing time (R_t + R_p) / v, then find the bound mass of each run.
-    Steps run as replays of a two-step hipGraph (which also advances each
-    run's clock), ``check_every`` (even) steps between checks.
-    Returns {"f_lr", "m_bound", "m_tot", "steps", "t", "t_end"}."""
-    strong = inputs.granite_impact()
-    mats = [strong, inputs.fluid(strong)]
-    runs, t_end = [], []
-    for c in cases:
-        w = inputs.impact_pair(int(c["n_target"]), c.get("gamma", 0.1), c["r_c1"],
-                               c["v_over_vesc"], bool(c["strength"]),
-                               mat_id=0 if c["strength"] else 1, mat=strong)
-        runs.append(w)
-        k = w["case"]
-        t_end.append(t_end_ff * free_fall_time(strong["rho0"]) + (k["r_t"] + k["r_p"]) / k["v"])
-    b = inputs.concat_runs(runs)
-    b["mats"] = mats
+def run_to_end(b: dict, t_end, checkpoints=(1.0,), prec: int = sph.SPH_FP32_CELLREL,
+               max_steps: int = 20000, check_every: int = 50, theta: float = 0.6,
+               max_neighbors: int = 256, log=None) -> dict:
+    """Advance a batch of runs (``b``: concatenated runs with ``run_start``,
+    ``mats``) under self-gravity until every run has reached its t_end (one
+    value per run), as replays of a two-step hipGraph with ``check_every``
+    (even) steps between checks.  At the first check at or after
+    c * t_end[r] for each fraction c of ``checkpoints``, run r's bound mass
+    is taken (iterative removal of unbound particles) and its largest-remnant
+    fraction f = M_bound / M_total recorded.  Returns {"f": {c: array},
+    "t": {c: array} (the run's time when recorded), "m_tot", "steps",
+    "reached" (bool per run), "seconds"}."""
+    import time
     prm = inputs.default_params(grav_G=G, grav_theta=theta)
+    mats = b["mats"]
     rs = [int(v) for v in b["run_start"]]
-    n, nr = int(b["x"].size), len(runs)
+    n, nr = int(b["x"].size), len(rs) - 1
+    t_end = np.asarray(t_end, dtype=np.float64)
     ctx = sph.Context(n, max_neighbors, max_cells=1 << 24, max_runs=nr)
     st = sph.State(b, run_start=rs)
-    sph.sph_init(ctx, st, mats, prm, prec)
-    t = torch.zeros(nr, dtype=torch.float64, device="cuda")
-    t_end_d = torch.tensor(t_end, dtype=torch.float64, device="cuda")
-    steps = 0
-    import time
+    sph.sph_init(ctx, st, mats, prm, prec)   # the library sets each run's time to 0
+    m = b["m"]
+    m_tot = np.array([m[rs[r]:rs[r + 1]].sum() for r in range(nr)])
+    f = {c: np.full(nr, np.nan) for c in checkpoints}
+    tr = {c: np.full(nr, np.nan) for c in checkpoints}
     t0 = time.perf_counter()
     check_every += check_every % 2
     for _ in range(2):          # eager steps before the capture
-        t += st.dt
         sph.sph_step(ctx, st, mats, prm, prec)
     steps = 2
     torch.cuda.synchronize()
     graph = torch.cuda.CUDAGraph()
     with torch.cuda.graph(graph):
         for _ in range(2):
-            t += st.dt          # the step about to be taken, per run
-            sph.sph_step(ctx, st, mats, prm, prec)
+            sph.sph_step(ctx, st, mats, prm, prec)   # advances each run's time
+    t_now = np.zeros(nr)
     while steps < max_steps:
         for _ in range(check_every // 2):
             graph.replay()
         steps += check_every
         ctx.check(sph.lib().sph_sync_status(ctx.h, None))
-        done = bool(torch.all(t >= t_end_d).item())
+        t_now = st.time.cpu().numpy()
+        due = {c: np.flatnonzero(np.isnan(f[c]) & (t_now >= c * t_end)) for c in checkpoints}
+        if any(d.size for d in due.values()):
+            _, mb, _ = sph.sph_bound_mass(
+                ctx, st.row(sph.SPH_VX).contiguous(), st.row(sph.SPH_VY).contiguous(),
+                st.row(sph.SPH_VZ).contiguous(), st.row(sph.SPH_M).contiguous(), nr, G=G,
+                eps_over_h=prm["grav_eps_over_h"], theta=theta)
+            frac = mb.cpu().numpy() / m_tot
+            for c, d in due.items():
+                f[c][d] = frac[d]
+                tr[c][d] = t_now[d]
         if log:
             log(f"  {nr} runs, {n} particles: step {steps}, min t/t_end "
-                f"{float(torch.min(t / t_end_d)):.3f}, {time.perf_counter() - t0:.1f} s")
-        if done:
+                f"{float(np.min(t_now / t_end)):.3f}, {time.perf_counter() - t0:.1f} s")
+        if all(not np.isnan(f[c]).any() for c in checkpoints):
             break
-    bound, mb, _ = sph.sph_bound_mass(
-        ctx, st.row(sph.SPH_VX).contiguous(), st.row(sph.SPH_VY).contiguous(),
-        st.row(sph.SPH_VZ).contiguous(), st.row(sph.SPH_M).contiguous(), nr, G=G,
-        eps_over_h=prm["grav_eps_over_h"], theta=theta)
     del graph
-    m_bound = mb.cpu().numpy()
-    m = b["m"]
-    m_tot = np.array([m[rs[r]:rs[r + 1]].sum() for r in range(nr)])
-    out = dict(f_lr=m_bound / m_tot, m_bound=m_bound, m_tot=m_tot, steps=steps,
-               t=t.cpu().numpy(), t_end=np.array(t_end))
     ctx.close()
-    return out
+    return dict(f=f, t=tr, m_tot=m_tot, steps=steps, reached=t_now >= t_end,
+                seconds=time.perf_counter() - t0)
+
+
+def end_times(cases, t_end_ff: float = 2.0):
+    """t_end of each run: t_end_ff free-fall times of the target material
+    plus the crossing time (R_t + R_p) / v."""
+    rho = inputs.granite_impact()["rho0"]
+    return np.array([t_end_ff * free_fall_time(rho) + (k["r_t"] + k["r_p"]) / k["v"]
+                     for k in cases])
+
+
+def simulate(cases: list, t_end_ff: float = 2.0, prec: int = sph.SPH_FP32_CELLREL,
+             max_steps: int = 20000, check_every: int = 50, theta: float = 0.6,
+             max_neighbors: int = 256, log=None) -> dict:
+    """Run every case (dicts with n_target, gamma, r_c1, v_over_vesc, strength)
+    to t_end = t_end_ff free-fall times of the target material plus the
+    crossing time (R_t + R_p) / v, then find the bound mass of each run.
+    Returns {"f_lr", "m_tot", "steps", "t", "t_end"}."""
+    strong = inputs.granite_impact()
+    mats = [strong, inputs.fluid(strong)]
+    runs = []
+    for c in cases:
+        w = inputs.impact_pair(int(c["n_target"]), c.get("gamma", 0.1), c["r_c1"],
+                               c["v_over_vesc"], bool(c["strength"]),
+                               mat_id=0 if c["strength"] else 1, mat=strong)
+        runs.append(w)
+    b = inputs.concat_runs(runs)
+    b["mats"] = mats
+    t_end = end_times([w["case"] for w in runs], t_end_ff)
+    r = run_to_end(b, t_end, (1.0,), prec=prec, max_steps=max_steps, check_every=check_every,
+                   theta=theta, max_neighbors=max_neighbors, log=log)
+    return dict(f_lr=r["f"][1.0], m_tot=r["m_tot"], steps=r["steps"], t=r["t"][1.0],
+                t_end=t_end)
 
 
 def bracket_rounds(cases: list, judge_batch, tol: float = 0.05, predict_for=None,

@@ -41,3 +41,11 @@ def test_qrd_scan_with_simulation_judge():
     for b, ok in zip(br_b + br_n, ok_b + ok_n):
         if ok:
             assert b.width() <= 0.05
+    # the simulations each method needed to reach the same 5% brackets are
+    # reported (and recorded in the design notes); at this resolution the
+    # network's proposals do not reliably beat bisection, so no gain is
+    # asserted here (the mock-judge test asserts the mechanism's gain)
+    say(f"simulations: network {sum(sims_n)}, bisection {sum(sims_b)}")
+    # both methods bracket the same thresholds
+    for qb, qn in zip(q_b, q_n):
+        assert abs(qn - qb) <= 0.05 * qb
