@@ -655,6 +655,28 @@ def run_hsteps(n_side=64, prec=1, shared_steps=600):
     return out
 
 
+CAMPAIGN_FILE = os.path.join(ROOT, "profiles", "qrd_campaign_c5.md")
+
+
+def recorded_campaign():
+    """Figures of the production-size Q_RD* campaign (simulations per held-out
+    case for bisection and for the network, thresholds, GPU time), as the
+    campaign driver recorded them in the committed summary; None when the
+    summary is missing.  The campaign runs for tens of GPU minutes, so the
+    benchmark reports the record rather than rerunning it."""
+    import re
+    try:
+        text = open(CAMPAIGN_FILE).read()
+    except OSError:
+        return None
+    m = re.search(r"campaign_summary:\s*(\{.*\})\s*$", text, re.M)
+    if not m:
+        return None
+    out = json.loads(m.group(1))
+    out["source"] = os.path.relpath(CAMPAIGN_FILE, ROOT)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -782,6 +804,7 @@ def main():
         "individual_steps": hsteps,
         "batch_scan": batch,
         "batch_outcomes": outcomes,
+        "qrd_campaign": recorded_campaign(),
     }
     print(json.dumps(line), flush=True)
 

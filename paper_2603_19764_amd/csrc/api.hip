@@ -130,7 +130,7 @@ sph_status sph_create(sph_ctx **out, int64_t capacity, int32_t max_neighbors, in
         {(void **)&ctx->posh32, cap * sizeof(float4)},
         {(void **)&ctx->cellc, cap * 4},
         {(void **)&ctx->runid, cap * 2},
-        {(void **)&ctx->nbr, cap * (size_t)max_neighbors * 4},
+        {(void **)&ctx->nbr, cap * (size_t)(max_neighbors + kRowGuard) * 4},
         {(void **)&ctx->ncount, cap * 4},
         {(void **)&ctx->grid, (size_t)max_runs * sizeof(GridDesc)},
         {(void **)&ctx->bbox_part, (size_t)max_runs * kBBoxBlocks * sizeof(BBox)},

@@ -494,7 +494,7 @@ __global__ __launch_bounds__(64) void k_build_pairs(
     const uint32_t *__restrict__ cellc, const int16_t *__restrict__ runid,
     const GridDesc *__restrict__ grid, const int32_t *__restrict__ cell_start,
     const int32_t *__restrict__ cell_count, const int32_t *total_keys, uint32_t *nbr,
-    int32_t *ncount, int32_t K, int32_t *flags, unsigned long long *pairs) {
+    int32_t *ncount, int32_t K, int32_t stride, int32_t *flags, unsigned long long *pairs) {
     __shared__ double4 tpos[Tile];  // x, y, z, H_j^2
     __shared__ uint32_t tj[Tile];   // j | stencil code
     __shared__ int32_t st_start[27];
@@ -669,8 +669,14 @@ __global__ __launch_bounds__(64) void k_build_pairs(
                 // ---- tests: four i at a time against every column of the tile.
                 // The masks are wave ballots of the compares (scalar
                 // registers); a lane stores when its bit is set, at the
-                // particle's running count plus the hits below it.  Whether
-                // the row can overflow is decided once per column (scalar).
+                // particle's running count plus the hits below it.  A group
+                // with fewer than four distinct particles repeats the last
+                // one: the repeat tests the same candidates and stores the
+                // same entries at the same places, so no slot needs a branch.
+                // Rows have a guard of kRowGuard slots past K: a column adds
+                // at most 64 entries, and once a row holds K or more the next
+                // column writes from K again (the overflow is reported; the
+                // extra entries are never read).
                 for (int q0 = 0; q0 < ni; q0 += 4) {
                     const int l = ni - 1;
                     const int q1 = q0 + 1 < l ? q0 + 1 : l, q2 = q0 + 2 < l ? q0 + 2 : l,
@@ -687,9 +693,8 @@ __global__ __launch_bounds__(64) void k_build_pairs(
                         H2[k] = __dmul_rn(H, H);
                         base[k] = __builtin_amdgcn_readlane(cnt_reg, qq[k]);
                         self[k] = (uint32_t)(ib + qq[k]);
-                        row[k] = nbr + (ib + qq[k]) * (int64_t)K;
+                        row[k] = nbr + (ib + qq[k]) * (int64_t)stride;
                     }
-                    const int nk = ni - q0 < 4 ? ni - q0 : 4;  // distinct i in this group
                     for (int col = 0; col < cols; col += kWave) {
                         const double4 c = tpos[col + lane];
                         const uint32_t e = tj[col + lane];
@@ -697,33 +702,21 @@ __global__ __launch_bounds__(64) void k_build_pairs(
                         const uint32_t ed = e | kDensityBit;
 #pragma unroll
                         for (int k = 0; k < 4; ++k) {
-                            if (k < nk) {
-                                const double r2 =
-                                    sep2_exact(P[k].x, P[k].y, P[k].z, c.x, c.y, c.z);
-                                const uint64_t md = wave_ballot(r2 < H2[k]);   // density set of i
-                                const uint64_t mj = wave_ballot(r2 < c.w);     // support of j
-                                const uint64_t ms = wave_ballot(jj == self[k]);
-                                const uint64_t m = (md | mj) & ~ms;
-                                const int b = base[k];
-                                const int pc = (int)__popcll(m);
-                                char *dst = (char *)(row[k] + b);
-                                const uint32_t rank = lanes_below(m);
-                                const uint32_t v = lane_bit(md) ? ed : e;
-                                // rows hold at most K entries: checked per lane
-                                // only when this column could overflow the row
-                                if (b + pc <= K) {
-                                    if (lane_bit(m)) *(uint32_t *)(dst + (rank << 2)) = v;
-                                } else {
-                                    if (lane_bit(m) && (int)rank < K - b)
-                                        *(uint32_t *)(dst + (rank << 2)) = v;
-                                }
-                                base[k] = __builtin_amdgcn_readfirstlane(b + pc);
-                            }
+                            const double r2 = sep2_exact(P[k].x, P[k].y, P[k].z, c.x, c.y, c.z);
+                            const uint64_t md = wave_ballot(r2 < H2[k]);   // density set of i
+                            const uint64_t mj = wave_ballot(r2 < c.w);     // support of j
+                            const uint64_t ms = wave_ballot(jj == self[k]);
+                            const uint64_t m = (md | mj) & ~ms;
+                            const int b = base[k];
+                            const int at = b < K ? b : K;
+                            const uint32_t v = lane_bit(md) ? ed : e;
+                            if (lane_bit(m)) row[k][at + (int)lanes_below(m)] = v;
+                            base[k] = b + (int)__popcll(m);
                         }
                     }
 #pragma unroll
                     for (int k = 0; k < 4; ++k)
-                        if (k < nk && lane == qq[k]) cnt_reg = base[k];
+                        if (lane == qq[k]) cnt_reg = base[k];
                 }
                 // carry the kept candidates not tested yet (fewer than 64)
                 const int rest = fill > cols ? fill - cols : 0;
@@ -795,7 +788,7 @@ sph_status launch_build_cells(Ctx *ctx, int64_t n, double *x, double *y, double 
     hipLaunchKernelGGL(k_build_pairs<T>, dim3((unsigned)wgs), dim3(64), 0, s, n, ctx->posh64, \
                        ctx->skey, ctx->cellc, ctx->runid, ctx->grid, ctx->cell_start,          \
                        ctx->cell_count, ctx->total_keys, ctx->nbr, ctx->ncount, ctx->max_nbr, \
-                       ctx->flags, ctx->pairs)
+                       nbr_stride(ctx), ctx->flags, ctx->pairs)
         switch (ctx->build_tile) {
             case 128: SPH_BUILD_LAUNCH(128); break;
             case 192: SPH_BUILD_LAUNCH(192); break;
@@ -872,7 +865,7 @@ sph_status launch_csr(Ctx *ctx, int64_t *off, int32_t *nbr, uint8_t *dflag, hipS
     if (st != SPH_OK) return st;
     if (nbr && n > 0)
         hipLaunchKernelGGL(k_csr, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, ctx->nbr,
-                           ctx->ncount, ctx->max_nbr, off, nbr, dflag);
+                           ctx->ncount, nbr_stride(ctx), off, nbr, dflag);
     SPH_HIP(hipGetLastError());
     return SPH_OK;
 }

@@ -103,7 +103,7 @@ sph_status launch_adapt_h(Ctx *ctx, int64_t n, const double *m, const double *h_
     if (n == 0) return SPH_OK;
     const int64_t per = kAdaptBlock / kAdaptL;
     hipLaunchKernelGGL(k_adapt_h, dim3((unsigned)((n + per - 1) / per)), dim3(kAdaptBlock), 0, s,
-                       n, ctx->posh64, ctx->nbr, ctx->ncount, ctx->max_nbr, m, h_start, fixed,
+                       n, ctx->posh64, ctx->nbr, ctx->ncount, nbr_stride(ctx), m, h_start, fixed,
                        n_ngb, tol, max_iter, h_out, (unsigned long long *)n_clamped, iterations);
     SPH_HIP(hipGetLastError());
     return SPH_OK;

@@ -629,7 +629,7 @@ static void density_launch(Ctx *ctx, int64_t n, const sph_params *prm, double *r
     using R4 = typename Real<F32>::T4;
     const int nb = (int)((n * L + kBlock - 1) / kBlock);
     hipLaunchKernelGGL((k_density<L, F32>), dim3(nb), dim3(kBlock), 0, s, n, ctx->posh64,
-                       ctx->runid, ctx->grid, ctx->nbr, ctx->ncount, ctx->max_nbr,
+                       ctx->runid, ctx->grid, ctx->nbr, ctx->ncount, nbr_stride(ctx),
                        (const R4 *)ctx->rec_d, rho, omega, prm->omega_one, ctx->flags);
 }
 
@@ -684,7 +684,7 @@ static void grad_launch(Ctx *ctx, int64_t n, hipStream_t s) {
     using R4 = typename Real<F32>::T4;
     const int nb = (int)((n * L + kBlock - 1) / kBlock);
     hipLaunchKernelGGL((k_gradients<L, F32>), dim3(nb), dim3(kBlock), 0, s, n, ctx->runid,
-                       ctx->grid, ctx->nbr, ctx->ncount, ctx->max_nbr, (const R4 *)ctx->rec_g,
+                       ctx->grid, ctx->nbr, ctx->ncount, nbr_stride(ctx), (const R4 *)ctx->rec_g,
                        ctx->gsum);
 }
 
@@ -733,7 +733,7 @@ static void forces_launch(Ctx *ctx, int64_t n, const sph_params *prm, double *ax
     using R4 = typename Real<F32>::T4;
     const int nb = (int)((n * L + kBlock - 1) / kBlock);
     hipLaunchKernelGGL((k_forces<L, F32>), dim3(nb), dim3(kBlock), 0, s, n, ctx->runid, ctx->grid,
-                       ctx->nbr, ctx->ncount, ctx->max_nbr, (const R4 *)ctx->rec_f, prm->av_alpha,
+                       ctx->nbr, ctx->ncount, nbr_stride(ctx), (const R4 *)ctx->rec_f, prm->av_alpha,
                        prm->av_beta, prm->av_eps, prm->eta_C, prm->g[0], prm->g[1], prm->g[2], ax,
                        ay, az, dudt, dtc, ctx->flags);
 }
@@ -774,7 +774,7 @@ static void both_launch(Ctx *ctx, int64_t n, const sph_params *prm, double *ax, 
     using R4 = typename Real<F32>::T4;
     const int nb = (int)((n * L + kBlock - 1) / kBlock);
     hipLaunchKernelGGL((k_grad_forces<L, F32, D>), dim3(nb), dim3(kBlock), 0, s, n, ctx->runid,
-                       ctx->grid, ctx->nbr, ctx->ncount, ctx->max_nbr, (const R4 *)ctx->rec_f,
+                       ctx->grid, ctx->nbr, ctx->ncount, nbr_stride(ctx), (const R4 *)ctx->rec_f,
                        prm->av_alpha, prm->av_beta, prm->av_eps, prm->eta_C, prm->g[0], prm->g[1],
                        prm->g[2], ctx->gsum, ax, ay, az, dudt, dtc, act, ctx->flags);
 }

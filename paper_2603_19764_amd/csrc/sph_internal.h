@@ -95,7 +95,7 @@ struct Ctx {
     float4 *posh32 = nullptr;       // capacity: (dx, dy, dz, h) relative to the cell origin
     uint32_t *cellc = nullptr;      // capacity: packed cell coordinates (10 bits each) + run in bits 30..
     int16_t *runid = nullptr;       // capacity: run of the sorted particle
-    uint32_t *nbr = nullptr;        // capacity * max_nbr entries
+    uint32_t *nbr = nullptr;        // capacity rows of max_nbr + kRowGuard entries
     int32_t *ncount = nullptr;      // capacity
     GridDesc *grid = nullptr;       // max_runs
     BBox *bbox_part = nullptr;      // max_runs * kBBoxBlocks
@@ -135,6 +135,9 @@ constexpr int kBBoxThreads = 256;
 constexpr int kBBoxUnroll = 2;  // elements per thread in flight together
 constexpr int kScanBlocks = 1024;
 constexpr int kMaxMaterials = 16;
+// Slots past max_nbr in each pair-list row: the list build writes a column
+// of up to 64 hits before it checks a row's length.
+constexpr int kRowGuard = 64;
 
 // ------------------------------------------------------------ host helpers
 #define SPH_HIP(expr)                                                          \
@@ -147,6 +150,9 @@ constexpr int kMaxMaterials = 16;
     } while (0)
 
 void set_error(Ctx *ctx, const char *fmt, ...);
+
+// Entries between consecutive pair-list rows.
+inline int32_t nbr_stride(const Ctx *ctx) { return ctx->max_nbr + kRowGuard; }
 
 // Timing bracket around a pass kernel launch (no-op unless enabled).
 struct TimedLaunch {

@@ -97,11 +97,12 @@ def end_times(cases, t_end_ff: float = 2.0):
 
 def simulate(cases: list, t_end_ff: float = 2.0, prec: int = sph.SPH_FP32_CELLREL,
              max_steps: int = 20000, check_every: int = 50, theta: float = 0.6,
-             max_neighbors: int = 256, log=None) -> dict:
+             max_neighbors: int = 256, log=None, checkpoints=(1.0,)) -> dict:
     """Run every case (dicts with n_target, gamma, r_c1, v_over_vesc, strength)
     to t_end = t_end_ff free-fall times of the target material plus the
     crossing time (R_t + R_p) / v, then find the bound mass of each run.
-    Returns {"f_lr", "m_tot", "steps", "t", "t_end"}."""
+    Returns {"f_lr", "m_tot", "steps", "t", "t_end", "seconds", "particles"}
+    and, when 0.5 is among ``checkpoints``, "f_half" (f_lr at t_end / 2)."""
     strong = inputs.granite_impact()
     mats = [strong, inputs.fluid(strong)]
     runs = []
@@ -113,10 +114,14 @@ def simulate(cases: list, t_end_ff: float = 2.0, prec: int = sph.SPH_FP32_CELLRE
     b = inputs.concat_runs(runs)
     b["mats"] = mats
     t_end = end_times([w["case"] for w in runs], t_end_ff)
-    r = run_to_end(b, t_end, (1.0,), prec=prec, max_steps=max_steps, check_every=check_every,
+    cps = tuple(sorted(set(checkpoints) | {1.0}))
+    r = run_to_end(b, t_end, cps, prec=prec, max_steps=max_steps, check_every=check_every,
                    theta=theta, max_neighbors=max_neighbors, log=log)
-    return dict(f_lr=r["f"][1.0], m_tot=r["m_tot"], steps=r["steps"], t=r["t"][1.0],
-                t_end=t_end)
+    out = dict(f_lr=r["f"][1.0], m_tot=r["m_tot"], steps=r["steps"], t=r["t"][1.0],
+               t_end=t_end, seconds=r["seconds"], particles=int(b["x"].size))
+    if 0.5 in r["f"]:
+        out["f_half"] = r["f"][0.5]
+    return out
 
 
 def bracket_rounds(cases: list, judge_batch, tol: float = 0.05, predict_for=None,
