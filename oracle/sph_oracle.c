@@ -235,7 +235,9 @@ void or_pair_lists(int64_t n, const double *x, const double *y, const double *z,
 /* eq. that follows it):                                                   */
 /*   rho_i   = sum_j m_j W(r_ij, h_i)                                      */
 /*   Omega_i = 1 + h_i/(3 rho_i) sum_j m_j dW(r_ij, h_i)/dh_i              */
-/* The sums run over j in D_i and the self term j = i (reading K2).        */
+/* The sums run over j in D_i and the self term j = i (reading K2).  When  */
+/* D_i holds no particle but i, Omega as defined vanishes (the self term's  */
+/* dW/dh cancels the 1): such a particle takes Omega = 1 (reading K2b).    */
 /* ----------------------------------------------------------------------- */
 void or_density(int64_t n, const double *x, const double *y, const double *z,
                 const double *m, const double *h, const or_params *p,
@@ -246,6 +248,7 @@ void or_density(int64_t n, const double *x, const double *y, const double *z,
         int64_t i = tar[k];
         double Hi2 = supp2(h[i]);
         double sum_w = 0.0, sum_dh = 0.0;
+        int64_t others = 0;
         double d[3];
         for (int64_t j = 0; j < n; ++j) {
             double r;
@@ -255,12 +258,14 @@ void or_density(int64_t n, const double *x, const double *y, const double *z,
                 double r2 = sep2(x, y, z, i, j, p->box, d);
                 if (!(r2 < Hi2)) continue;
                 r = sqrt(r2);
+                ++others;
             }
             sum_w += m[j] * or_W(r, h[i]);
             sum_dh += m[j] * or_dWdh(r, h[i]);
         }
         rho[i] = sum_w;
-        omega[i] = p->omega_one ? 1.0 : 1.0 + h[i] / (3.0 * sum_w) * sum_dh;
+        omega[i] = (p->omega_one || others == 0) ? 1.0
+                                                 : 1.0 + h[i] / (3.0 * sum_w) * sum_dh;
     }
 }
 

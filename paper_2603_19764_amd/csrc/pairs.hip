@@ -119,7 +119,7 @@ __global__ __launch_bounds__(kBlock) void k_density(
     const int64_t i = (int64_t)xcd_block(blockIdx.x, gridDim.x) * (kBlock / L) + threadIdx.x / L;
     const int lg = threadIdx.x % L;
     const bool active = i < n;
-    double sw = 0.0, sd = 0.0;
+    double sw = 0.0, sd = 0.0, nd = 0.0;  // nd: members of the density set other than i
     double hi = 0.0;
     R4 pi = {0, 0, 0, 0};
     if (active) {
@@ -143,11 +143,13 @@ __global__ __launch_bounds__(kBlock) void k_density(
             R t = (R)1 - q;
             t = t > (R)0 ? t : (R)0;
             const R t3 = t * t * t;
-            const R mj = (e & kDensityBit) ? pj.w : (R)0;
+            const bool in_d = (e & kDensityBit) != 0;
+            const R mj = in_d ? pj.w : (R)0;
             const R w = mj * (t3 * t * ((R)1 + (R)4 * q));
             const R dh = mj * (t3 * ((R)3 + q * ((R)9 - (R)32 * q)));
             sw += (double)w;
             sd += (double)dh;
+            nd += in_d ? 1.0 : 0.0;
         };
         auto entry = [&](int k) -> uint32_t {
             const uint32_t v = row[k < K ? k : K - 1];
@@ -171,6 +173,7 @@ __global__ __launch_bounds__(kBlock) void k_density(
     }
     sw = group_sum<L>(sw);
     sd = group_sum<L>(sd);
+    nd = group_sum<L>(nd);
     bool bad = false;
     if (active && lg == 0) {
         const double H = 2.0 * hi;
@@ -179,7 +182,9 @@ __global__ __launch_bounds__(kBlock) void k_density(
         const double mi = (double)pi.w;
         const double r = Wn * (mi + sw);           // self term W(0) = Wn
         const double dsum = Dn * (3.0 * mi + sd);  // self term dW/dh(0) = 3 Dn
-        const double om = omega_one ? 1.0 : 1.0 + hi / (3.0 * r) * dsum;
+        // a density set of i alone gives Omega = 0 by the definition (the
+        // self term cancels the 1): such a particle takes Omega = 1
+        const double om = (omega_one || nd == 0.0) ? 1.0 : 1.0 + hi / (3.0 * r) * dsum;
         rho[i] = r;
         omega[i] = om;
         bad = nonfinite(r, om);

@@ -137,6 +137,35 @@ def test_lattice_density_and_omega(orc):
     np.testing.assert_allclose(om - 1.0, h0 / (3 * rho) * drdh, rtol=1e-5, atol=1e-9)
 
 
+def test_isolated_particle_density_and_omega(orc):
+    """A particle whose density set holds only itself: rho = m W(0, h)
+    (Density_estimate eq. with the self term alone) and, since the
+    definition gives Omega = 1 + h/(3 rho) m dW/dh(0) = 1 - 2h/H = 0 for the
+    Wendland C2 kernel with H = 2h, Omega = 1 (reading K2b).  A neighbour
+    inside the support restores Omega as defined, which the finite
+    difference of rho(h) pins."""
+    h0 = 1.3
+    m = np.array([2700.0, 2500.0])
+    prm = inputs.default_params()
+    x = np.array([0.0, 10.0])
+    zero = np.zeros(2)
+    rho, om = orc.density(x, zero, zero, m, np.full(2, h0), prm)
+    W0 = orc.kernel(np.zeros(1), np.full(1, h0))[0][0]
+    np.testing.assert_allclose(rho, m * W0, rtol=1e-15)
+    assert np.all(om == 1.0)
+    # the definition itself vanishes here: 1 + h/(3 m W(0)) m dW/dh(0) = 0
+    W0_, _, D0 = orc.kernel(np.zeros(1), np.full(1, h0))
+    assert abs(1.0 + h0 / (3.0 * W0_[0]) * D0[0]) < 1e-14
+    x2 = np.array([0.0, 1.7])
+    rho2, om2 = orc.density(x2, zero, zero, m, np.full(2, h0), prm)
+    e = 1e-6
+    rp, _ = orc.density(x2, zero, zero, m, np.full(2, h0 * (1 + e)), prm)
+    rm, _ = orc.density(x2, zero, zero, m, np.full(2, h0 * (1 - e)), prm)
+    drdh = (rp - rm) / (2 * e * h0)
+    np.testing.assert_allclose(om2 - 1.0, h0 / (3 * rho2) * drdh, rtol=1e-5)
+    assert np.all(np.abs(om2 - 1.0) > 1e-3)
+
+
 # --------------------------------------------------------------------- EOS
 def test_tillotson_reference_state(orc):
     """At rho = rho0 (mu = 0): P = (a + b/(1 + u/E0)) rho0 u.  Basalt, u = 1e4:
