@@ -500,17 +500,20 @@ def run_batch(steps, warmup, gravity=True, tune=True):
             "dt_spread": float(dt.max() / dt.min())}
 
 
-def run_batch_outcomes(max_steps=8000, check_every=100, seed=5, scale=1.0):
+def run_batch_outcomes(max_steps=12000, check_every=200, seed=5, scale=1.0, far_factor=1.5,
+                       t_end_sound=6.0):
     """The 64-impact batch (FP32, self-gravity on; particle counts times
-    ``scale``) run to every run's t_end (two free-fall times plus the crossing
-    time): each run's largest-remnant fraction f_lr when it passes t_end/2
-    and t_end, and whether it changed by less than 1% of the run's mass
-    between the two (converged)."""
+    ``scale``; each run in its centre-of-mass frame) run to every run's t_end
+    (the crossing time plus the shorter of ``t_end_sound`` sound-crossing
+    times of the target and two free-fall times), ejecta beyond the run's far
+    cube (``far_factor``) counted unbound: each run's largest-remnant
+    fraction f_lr when it passes t_end/2 and t_end, and whether it changed
+    by less than 1% of the run's mass between the two (converged)."""
     from paper_2603_19764_amd import inputs, scan
-    b = inputs.scan_batch(64, seed=seed, scale=scale)
-    t_end = scan.end_times(b["cases"])
+    b = inputs.scan_batch(64, seed=seed, scale=scale, cm_frame=True)
+    t_end = scan.end_times(b["cases"], t_end_sound=t_end_sound)
     r = scan.run_to_end(b, t_end, (0.5, 1.0), max_steps=max_steps, check_every=check_every,
-                        log=log)
+                        log=log, max_cells=1 << 26, far_factor=far_factor)
     f1, f2 = r["f"][0.5], r["f"][1.0]
     d = np.abs(f2 - f1)
     runs = [{"n_particles": int(b["run_start"][k + 1] - b["run_start"][k]),
@@ -521,8 +524,9 @@ def run_batch_outcomes(max_steps=8000, check_every=100, seed=5, scale=1.0):
             for k, c in enumerate(b["cases"])]
     ok = ~np.isnan(d)
     return {"workload": f"the 64-impact batch ({int(b['x'].size)} particles, target counts x "
-                        f"{scale}) run to t_end (2 free-fall times + crossing time) with "
-                        "self-gravity, FP32", "steps": r["steps"], "seconds": r["seconds"],
+                        f"{scale}) run to t_end (crossing time + min({t_end_sound} sound "
+                        f"crossings, 2 free-fall times)) with self-gravity, FP32, far cube "
+                        f"{far_factor}", "steps": r["steps"], "seconds": r["seconds"],
             "runs_reaching_t_end": int(r["reached"].sum()),
             "converged_runs": int((d[ok] < 0.01).sum()), "compared_runs": int(ok.sum()),
             "max_change": float(d[ok].max()) if ok.any() else None, "runs": runs}
@@ -703,6 +707,9 @@ def main():
                     help="only the timed FP32 steps of the headline workload (profiling)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first copy MIB MiB device to device (counter calibration)")
+    ap.add_argument("--batch-only", type=int, default=0, metavar="STEPS",
+                    help="only the batched 64-impact scan, STEPS graph-replayed steps "
+                         "(profiling)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -715,6 +722,9 @@ def main():
     torch.cuda.set_device(0)
     if args.copy_calibration:
         copy_calibration(args.copy_calibration)
+    if args.batch_only:
+        print(json.dumps(run_batch(args.batch_only, 4, tune=not args.no_tune)), flush=True)
+        return
     w = inputs.c3_impact()
     n = int(w["x"].size)
     log(f"workload {w['name']}: n={n}")

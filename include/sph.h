@@ -124,6 +124,16 @@ typedef struct {
                            r = 0 .. rungs-1 (<= 40), dt0 = sph_state.dt_max;
                            0: one step per run                              */
     int32_t rungs_pad;
+    double far_factor;  /* > 0: sph_init fixes for each run the cube centred
+                           on its bounding box, of half-edge far_factor times
+                           the box's largest half-extent; from then on the
+                           run's search grid covers only that cube, and a
+                           particle outside it (ejecta far from a collision)
+                           enters no pair set, feels no pair force and no
+                           self-gravity, is no source of self-gravity, drifts
+                           with its velocity, and counts as unbound in
+                           sph_bound_mass.  The grid of a dispersing run then
+                           stays bounded.  0: the grid covers every particle */
 } sph_params;
 
 /* ---------------------------------------------------------------- context */

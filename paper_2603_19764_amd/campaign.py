@@ -369,6 +369,11 @@ def main(argv=None):
     ap.add_argument("--n-max", type=float, default=5.0e5)
     ap.add_argument("--train-rounds", type=int, default=8)
     ap.add_argument("--t-end-ff", type=float, default=2.0)
+    ap.add_argument("--t-end-sound", type=float, default=6.0,
+                    help="end each run this many target sound-crossing times after contact "
+                         "(0: use --t-end-ff free-fall times)")
+    ap.add_argument("--max-cells", type=int, default=1 << 26)
+    ap.add_argument("--far-factor", type=float, default=1.5)
     ap.add_argument("--check-every", type=int, default=200)
     a = ap.parse_args(argv)
 
@@ -391,7 +396,8 @@ def main(argv=None):
     import torch
     torch.cuda.set_device(0)
     run(state, a.rounds, a.budget, log=log, train_rounds=a.train_rounds, save=save,
-        t_end_ff=a.t_end_ff, check_every=a.check_every)
+        t_end_ff=a.t_end_ff, t_end_sound=a.t_end_sound, check_every=a.check_every,
+        max_cells=a.max_cells, far_factor=a.far_factor)
     print(json.dumps(summary(state)), flush=True)
 
 

@@ -131,6 +131,7 @@ sph_status sph_create(sph_ctx **out, int64_t capacity, int32_t max_neighbors, in
         {(void **)&ctx->cellc, cap * 4},
         {(void **)&ctx->runid, cap * 2},
         {(void **)&ctx->nbr, cap * (size_t)(max_neighbors + kRowGuard) * 4},
+        {(void **)&ctx->far_box, (size_t)max_runs * sizeof(BBox)},
         {(void **)&ctx->ncount, cap * 4},
         {(void **)&ctx->grid, (size_t)max_runs * sizeof(GridDesc)},
         {(void **)&ctx->bbox_part, (size_t)max_runs * kBBoxBlocks * sizeof(BBox)},
@@ -146,7 +147,8 @@ sph_status sph_create(sph_ctx **out, int64_t capacity, int32_t max_neighbors, in
         {(void **)&ctx->rec_f, cap * 160},
         {(void **)&ctx->gsum, cap * 15 * 8},
         {(void **)&ctx->grav_lev, gravity_levels_bytes(max_runs)},
-        {(void **)&ctx->grav_totals, 16},
+        {(void **)&ctx->grav_totals, 24},
+        {(void **)&ctx->grav_groups, ((size_t)max_cells / 8 + 8 * (size_t)max_runs + 1024) * sizeof(int4)},
         {(void **)&ctx->grav_mom0, ((size_t)max_cells + 1) * sizeof(float4)},
         {(void **)&ctx->grav_mom8, ((size_t)max_cells + 1) * 8 * sizeof(float4)},
         {(void **)&ctx->grav_momU, ((size_t)max_cells + 1) * sizeof(float4)},
@@ -155,6 +157,7 @@ sph_status sph_create(sph_ctx **out, int64_t capacity, int32_t max_neighbors, in
         {(void **)&ctx->bm_removed, 4},
     };
     ctx->grav_cap_upper = max_cells;
+    ctx->grav_cap_groups = (int64_t)max_cells / 8 + 8 * (int64_t)max_runs + 1024;
     for (auto &a : allocs) {
         if (hipMalloc(a.p, a.bytes) != hipSuccess) {
             sph_destroy(h);
@@ -186,7 +189,8 @@ sph_status sph_destroy(sph_ctx *h) {
                     ctx->total_keys, ctx->scan_part, ctx->flags, ctx->pairs, ctx->dtbits,
                     ctx->diag, ctx->rec_d, ctx->rec_g, ctx->rec_f, ctx->gsum,
                     ctx->grav_lev, ctx->grav_totals, ctx->grav_mom0, ctx->grav_momU,
-                    ctx->bm_part, ctx->bm_vcm, ctx->bm_removed, ctx->octant, ctx->grav_mom8};
+                    ctx->bm_part, ctx->bm_vcm, ctx->bm_removed, ctx->octant, ctx->grav_mom8,
+                    ctx->far_box, ctx->grav_groups};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     for (int w = 0; w < SPH_T_COUNT; ++w) {
@@ -561,7 +565,7 @@ static double tick_of(const sph_state *st, const sph_params *prm) {
 
 static sph_status search_and_sort(sph_ctx *h, sph_state *st, const sph_params *prm,
                                   sph_precision prec, bool drift, int32_t predict, hipStream_t s,
-                                  const double *h_build = nullptr) {
+                                  const double *h_build = nullptr, bool far_init = false) {
     Ctx *ctx = &h->c;
     const int64_t n = st->n;
     const int cur = st->cur, alt = 1 - cur;
@@ -581,6 +585,8 @@ static sph_status search_and_sort(sph_ctx *h, sph_state *st, const sph_params *p
     }
     ex.m = A.f[SPH_M];  // the gather reads the unsorted state: records in sorted order
     ex.f32 = prec == SPH_FP32_CELLREL;
+    ex.far_factor = prm->far_factor > 0.0 ? prm->far_factor : 0.0;
+    ex.far_init = far_init ? 1 : 0;
     if ((e = launch_build_cells(ctx, n, A.f[SPH_X], A.f[SPH_Y], A.f[SPH_Z],
                                 h_build ? h_build : A.f[SPH_H], nr, st->cell_min, perm, &ex, s)))
         return e;
@@ -612,15 +618,17 @@ constexpr double kAdaptTol = 1e-10;
 constexpr int32_t kAdaptIter = 30;
 
 static sph_status step_search(sph_ctx *h, sph_state *st, const sph_params *prm,
-                              sph_precision prec, bool drift, int32_t predict, hipStream_t s) {
-    if (!(prm->adapt_ngb > 0.0)) return search_and_sort(h, st, prm, prec, drift, predict, s);
+                              sph_precision prec, bool drift, int32_t predict, hipStream_t s,
+                              bool far_init = false) {
+    if (!(prm->adapt_ngb > 0.0))
+        return search_and_sort(h, st, prm, prec, drift, predict, s, nullptr, far_init);
     Ctx *ctx = &h->c;
     const int64_t n = st->n;
     Rows A = rows_of(st, st->cur);
     double *hs = A.w[SPH_W_T];  // free until the state kernel of this step
     sph_status e;
     if ((e = launch_scale(ctx, n, A.f[SPH_H], prm->adapt_skin, hs, s))) return e;
-    if ((e = search_and_sort(h, st, prm, prec, drift, predict, s, hs))) return e;
+    if ((e = search_and_sort(h, st, prm, prec, drift, predict, s, hs, far_init))) return e;
     Rows R = rows_of(st, st->cur);
     if ((e = launch_adapt_h(ctx, n, R.f[SPH_M], R.f[SPH_H], R.i[SPH_FIXED], prm->adapt_ngb,
                             kAdaptTol, kAdaptIter, R.f[SPH_H], nullptr, nullptr, s)))
@@ -673,7 +681,8 @@ static sph_status eval(sph_ctx *h, const sph_state *st, const Rows &R, int32_t n
                                 R.f[SPH_H], act, R.w[SPH_W_DT], s)))
         return e;
     if (hier) return SPH_OK;  // the kick takes the new steps
-    return launch_dt_reduce(ctx, n, R.w[SPH_W_DT], fixed, step_bits(ctx, 0), s, nr, ctx->run_p);
+    return launch_dt_reduce(ctx, n, R.w[SPH_W_DT], fixed, step_bits(ctx, 0), s, nr, ctx->run_p,
+                            true);
 }
 
 // Individual steps: kicks and new steps of the particles whose step ended,
@@ -745,8 +754,10 @@ sph_status sph_init(sph_ctx *h, sph_state *st, const sph_material *mats, int32_t
     hipStream_t s = S(stream);
     REQUIRE(!(prm->adapt_ngb > 0.0) || prm->adapt_skin >= 1.0, SPH_EINVAL,
             "adapt_skin must be >= 1");
+    REQUIRE(!(prm->far_factor > 0.0) || prm->far_factor >= 1.0, SPH_EINVAL,
+            "far_factor must be 0 or >= 1");
     if ((e = check_rungs(h, st, prm))) return e;
-    if ((e = step_search(h, st, prm, prec, false, 0, s))) return e;
+    if ((e = step_search(h, st, prm, prec, false, 0, s, true))) return e;
     Rows R = rows_of(st, st->cur);
     // predicted values are the current ones: v, u as they are, S rescaled
     if ((e = eval(h, st, R, n_materials, prm, prec, 0, false, s))) return e;
@@ -768,6 +779,8 @@ sph_status sph_step(sph_ctx *h, sph_state *st, const sph_material *mats, int32_t
     hipStream_t s = S(stream);
     REQUIRE(!(prm->adapt_ngb > 0.0) || prm->adapt_skin >= 1.0, SPH_EINVAL,
             "adapt_skin must be >= 1");
+    REQUIRE(!(prm->far_factor > 0.0) || prm->far_factor >= 1.0, SPH_EINVAL,
+            "far_factor must be 0 or >= 1");
     if ((e = check_rungs(h, st, prm))) return e;
     if ((e = step_search(h, st, prm, prec, true, 1, s))) return e;
     Rows R = rows_of(st, st->cur);

@@ -8,6 +8,8 @@
 #include <stdarg.h>
 #include <stdio.h>
 
+#include <type_traits>
+
 #include "sph_internal.h"
 
 namespace sph {
@@ -115,7 +117,7 @@ __device__ __forceinline__ int run_of(const int32_t *run_p, int nr, int64_t k) {
 __global__ void k_bbox(double *x, double *y, double *z, const double *h, const int32_t *run_p,
                        BBox *part, int32_t *cell_count, const int32_t *total_keys_prev,
                        const double *dtp, const double *vx, const double *vy, const double *vz,
-                       const int32_t *fixed, int32_t *flags) {
+                       const int32_t *fixed, const BBox *far, int32_t *flags) {
     {
         const int64_t nz = *total_keys_prev;
         const int64_t nthr = (int64_t)gridDim.x * gridDim.y * blockDim.x;
@@ -126,6 +128,9 @@ __global__ void k_bbox(double *x, double *y, double *z, const double *h, const i
     const int r = blockIdx.y;
     const int64_t a = run_p[r], b = run_p[r + 1];
     const double dt = dtp ? dtp[r] : 0.0;  // one time step per run
+    // with far cubes, particles outside the run's cube stay out of its box
+    BBox fb;
+    if (far) fb = far[r];
     double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
     double hm = 0.0;
     bool bad = false;  // a non-finite position or length (binned at the grid's edge, reported)
@@ -146,11 +151,16 @@ __global__ void k_bbox(double *x, double *y, double *z, const double *h, const i
                     y[k] = v[1];
                     z[k] = v[2];
                 }
-                for (int d = 0; d < 3; ++d) {
-                    lo[d] = fmin(lo[d], v[d]);
-                    hi[d] = fmax(hi[d], v[d]);
+                bool in = true;
+                if (far)
+                    for (int d = 0; d < 3; ++d) in = in && v[d] >= fb.lo[d] && v[d] <= fb.hi[d];
+                if (in) {
+                    for (int d = 0; d < 3; ++d) {
+                        lo[d] = fmin(lo[d], v[d]);
+                        hi[d] = fmax(hi[d], v[d]);
+                    }
+                    hm = fmax(hm, h[k]);
                 }
-                hm = fmax(hm, h[k]);
                 bad |= nonfinite(v[0], v[1], v[2], h[k]);
             }
         }
@@ -230,7 +240,8 @@ __device__ static void size_grid(GridDesc &g, const BBox &bb, double L) {
 // run's bounding-box partials in parallel (into the first partial of the
 // run), then one thread sizes the grids.
 __global__ void k_grid(BBox *part, int nbb, const int32_t *run_p, int nr, double cell_min,
-                       double cell_scale, int64_t max_cells, GridDesc *grid, int32_t *total_keys, int32_t *flags) {
+                       double cell_scale, int64_t max_cells, GridDesc *grid, int32_t *total_keys,
+                       double far_factor, BBox *far_set, int32_t *flags) {
     // per run: the nbb block partials reduced by one wave (waves take runs
     // in turn); the result goes to the run's first partial
     const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave, nw = blockDim.x / kWave;
@@ -266,24 +277,45 @@ __global__ void k_grid(BBox *part, int nbb, const int32_t *run_p, int nr, double
     // Every run at its natural edge first; while the dense key ranges do not
     // fit the table, the run holding the most keys (the one whose particles
     // spread widest, e.g. the ejecta of a disruptive impact) coarsens its own
-    // grid by 1.25, so one dispersing run does not coarsen the others.
+    // grid by 1.25, so one dispersing run does not coarsen the others.  With
+    // far cubes every run has one more key after its cells, for the particles
+    // outside its cube.
+    const int sink = far_factor > 0.0 ? 1 : 0;
     int64_t total = 0;
     for (int r = 0; r < nr; ++r) {
         BBox bb = part[r * kBBoxBlocks];
         GridDesc g;
         g.p0 = run_p[r];
         g.p1 = run_p[r + 1];
-        if (g.p1 <= g.p0) {  // empty run
+        g.sink = sink;
+        g.pad = 0;
+        if (g.p1 <= g.p0 || !(bb.lo[0] <= bb.hi[0])) {  // empty run (or no particle in its cube)
             for (int d = 0; d < 3; ++d) { bb.lo[d] = 0.0; bb.hi[d] = 0.0; }
             bb.hmax = 0.0;
         }
+        if (far_set) {
+            // the cube: centred on the box, half-edge far_factor times its
+            // largest half-extent (at least one cell edge)
+            double half = 0.0;
+            for (int d = 0; d < 3; ++d) half = fmax(half, 0.5 * (bb.hi[d] - bb.lo[d]));
+            half = far_factor * fmax(half, fmax(cell_min, 2.0 * bb.hmax));
+            BBox c;
+            for (int d = 0; d < 3; ++d) {
+                const double mid = 0.5 * (bb.lo[d] + bb.hi[d]);
+                c.lo[d] = mid - half;
+                c.hi[d] = mid + half;
+            }
+            c.hmax = 0.0;
+            far_set[r] = c;
+        }
+        part[r * kBBoxBlocks] = bb;
         // Edge at least the largest support 2h (so every pair lies in the
         // 27-cell stencil), slightly enlarged so that rounding of
         // (x - origin)/L can never separate a pair by two cells.
         const double L = fmax(cell_min, 2.0 * bb.hmax * cell_scale) * (1.0 + 1.0 / 1099511627776.0);
         size_grid(g, bb, L);
         grid[r] = g;
-        total += g.key_count;
+        total += g.key_count + sink;
     }
     // (the search for the largest run is a scan over the runs, done by one
     // thread: beyond 1024 runs every run coarsens together instead)
@@ -297,7 +329,7 @@ __global__ void k_grid(BBox *part, int nbb, const int32_t *run_p, int nr, double
             }
             size_grid(g, bb, g.L * 1.25);
             grid[r] = g;
-            total += g.key_count;
+            total += g.key_count + sink;
         }
     }
     for (int attempt = 0; attempt < 4096 && total > max_cells; ++attempt) {
@@ -319,7 +351,7 @@ __global__ void k_grid(BBox *part, int nbb, const int32_t *run_p, int nr, double
         int64_t off = 0;
         for (int r = 0; r < nr; ++r) {
             grid[r].key_off = (int32_t)off;
-            off += grid[r].key_count;
+            off += grid[r].key_count + sink;
         }
         *total_keys = (int32_t)total;
         return;
@@ -340,7 +372,7 @@ __device__ __forceinline__ void cell_of(const GridDesc &g, double x, double y, d
 
 __global__ void k_keys(int64_t n, const double *x, const double *y, const double *z,
                        const int32_t *run_p, int nr, const GridDesc *grid,
-                       const int32_t *total_keys, uint32_t *key, int32_t *slot,
+                       const int32_t *total_keys, const BBox *far, uint32_t *key, int32_t *slot,
                        int32_t *cell_count) {
     const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     const bool valid = k < n;
@@ -363,10 +395,20 @@ __global__ void k_keys(int64_t n, const double *x, const double *y, const double
         cy = cy < 0 ? 0 : (cy >= g.ny ? g.ny - 1 : cy);
         cz = cz < 0 ? 0 : (cz >= g.nz ? g.nz - 1 : cz);
         kk = (uint32_t)g.key_off + morton(cx, cy, cz, g.bx, g.by, g.bz);
-        key[k] = kk;
         // octant of the particle in its cell (the half-cells of the gravity
         // tree below the search cells)
         oct = (tx - cx >= 0.5 ? 1 : 0) | (ty - cy >= 0.5 ? 2 : 0) | (tz - cz >= 0.5 ? 4 : 0);
+        if (far) {  // outside the run's far cube: the run's far slot
+            const BBox fb = far[r];
+            const double p[3] = {x[k], y[k], z[k]};
+            bool in = true;
+            for (int d = 0; d < 3; ++d) in = in && p[d] >= fb.lo[d] && p[d] <= fb.hi[d];
+            if (!in) {
+                kk = far_key(g);
+                oct = 0;
+            }
+        }
+        key[k] = kk;
     }
     // One atomic per distinct key of the wave: lanes with equal keys take
     // consecutive slots in lane order.  Each group's leader issues the
@@ -522,6 +564,14 @@ __global__ __launch_bounds__(64) void k_build_pairs(
             if (lane == 0) atomicOr(&flags[FLAG_CELL_OVERFLOW], 2);
             break;
         }
+        {
+            const GridDesc gr = grid[runid[p]];
+            if (gr.sink && key == far_key(gr)) {  // outside the far cube: no pair set
+                for (int64_t q = i_lo + lane; q < i_hi; q += kWave) ncount[q] = 0;
+                p = i_hi;
+                continue;
+            }
+        }
         // ---- stencil: 27 neighbour cells (lane t handles cell t)
         const uint32_t cc = cellc[p];
         const GridDesc g = grid[runid[p]];
@@ -666,29 +716,30 @@ __global__ __launch_bounds__(64) void k_build_pairs(
                     }
                 }
                 __syncthreads();
-                // ---- tests: four i at a time against every column of the tile.
+                // ---- tests: G = 4 particles i at a time against every column
+                // of the tile (G = 2 or 1 for the last two or one of a batch).
                 // The masks are wave ballots of the compares (scalar
                 // registers); a lane stores when its bit is set, at the
-                // particle's running count plus the hits below it.  A group
-                // with fewer than four distinct particles repeats the last
-                // one: the repeat tests the same candidates and stores the
-                // same entries at the same places, so no slot needs a branch.
-                // Rows have a guard of kRowGuard slots past K: a column adds
-                // at most 64 entries, and once a row holds K or more the next
-                // column writes from K again (the overflow is reported; the
-                // extra entries are never read).
-                for (int q0 = 0; q0 < ni; q0 += 4) {
+                // particle's running count plus the hits below it.  A last
+                // group of three repeats its last particle: the repeat tests
+                // the same candidates and stores the same entries at the same
+                // places, so no slot needs a branch.  Rows have a guard of
+                // kRowGuard slots past K: a column adds at most 64 entries,
+                // and once a row holds K or more the next column writes from K
+                // again (the overflow is reported; the extra entries are never
+                // read).
+                auto test_group = [&](auto gsz, int q0) {
+                    constexpr int G = decltype(gsz)::value;
                     const int l = ni - 1;
-                    const int q1 = q0 + 1 < l ? q0 + 1 : l, q2 = q0 + 2 < l ? q0 + 2 : l,
-                              q3 = q0 + 3 < l ? q0 + 3 : l;
-                    const double4 P[4] = {ipos[q0], ipos[q1], ipos[q2], ipos[q3]};
-                    const int qq[4] = {q0, q1, q2, q3};
-                    double H2[4];
-                    int base[4];
-                    uint32_t self[4];
-                    uint32_t *row[4];
+                    double4 P[G];
+                    double H2[G];
+                    int qq[G], base[G];
+                    uint32_t self[G];
+                    uint32_t *row[G];
 #pragma unroll
-                    for (int k = 0; k < 4; ++k) {
+                    for (int k = 0; k < G; ++k) {
+                        qq[k] = q0 + k < l ? q0 + k : l;
+                        P[k] = ipos[qq[k]];
                         const double H = 2.0 * P[k].w;
                         H2[k] = __dmul_rn(H, H);
                         base[k] = __builtin_amdgcn_readlane(cnt_reg, qq[k]);
@@ -701,7 +752,7 @@ __global__ __launch_bounds__(64) void k_build_pairs(
                         const uint32_t jj = e & kIdxMask;
                         const uint32_t ed = e | kDensityBit;
 #pragma unroll
-                        for (int k = 0; k < 4; ++k) {
+                        for (int k = 0; k < G; ++k) {
                             const double r2 = sep2_exact(P[k].x, P[k].y, P[k].z, c.x, c.y, c.z);
                             const uint64_t md = wave_ballot(r2 < H2[k]);   // density set of i
                             const uint64_t mj = wave_ballot(r2 < c.w);     // support of j
@@ -715,9 +766,17 @@ __global__ __launch_bounds__(64) void k_build_pairs(
                         }
                     }
 #pragma unroll
-                    for (int k = 0; k < 4; ++k)
+                    for (int k = 0; k < G; ++k)
                         if (lane == qq[k]) cnt_reg = base[k];
-                }
+                };
+                int q0 = 0;
+                for (; q0 + 4 <= ni; q0 += 4) test_group(std::integral_constant<int, 4>{}, q0);
+                if (ni - q0 == 3)
+                    test_group(std::integral_constant<int, 4>{}, q0);
+                else if (ni - q0 == 2)
+                    test_group(std::integral_constant<int, 2>{}, q0);
+                else if (ni - q0 == 1)
+                    test_group(std::integral_constant<int, 1>{}, q0);
                 // carry the kept candidates not tested yet (fewer than 64)
                 const int rest = fill > cols ? fill - cols : 0;
                 double4 cr = make_double4(0.0, 0.0, 0.0, 0.0);
@@ -753,6 +812,7 @@ sph_status launch_build_cells(Ctx *ctx, int64_t n, double *x, double *y, double 
     if (n == 0) {
         ctx->n_built = 0;
         ctx->n_runs_built = nr;
+        ctx->far_built = false;
         return SPH_OK;
     }
     BuildExtras none;
@@ -763,13 +823,18 @@ sph_status launch_build_cells(Ctx *ctx, int64_t n, double *x, double *y, double 
     // size), at most kBBoxBlocks
     int64_t nbb = (n / nr + kBBoxThreads * kBBoxUnroll - 1) / (kBBoxThreads * kBBoxUnroll);
     nbb = nbb < 1 ? 1 : (nbb > kBBoxBlocks ? kBBoxBlocks : nbb);
+    const bool far = ex->far_factor > 0.0;
     hipLaunchKernelGGL(k_bbox, dim3((unsigned)nbb, nr), dim3(kBBoxThreads), 0, s, x, y, z, h, ctx->run_p,
                        ctx->bbox_part, ctx->cell_count, ctx->total_keys, ex->dt, ex->vx, ex->vy,
-                       ex->vz, ex->fixed, ctx->flags);
+                       ex->vz, ex->fixed, (far && !ex->far_init) ? ctx->far_box : nullptr,
+                       ctx->flags);
     hipLaunchKernelGGL(k_grid, dim3(1), dim3(1024), 0, s, ctx->bbox_part, (int)nbb, ctx->run_p, nr, cell_min,
-                       ctx->cell_scale, ctx->max_cells, ctx->grid, ctx->total_keys, ctx->flags);
+                       ctx->cell_scale, ctx->max_cells, ctx->grid, ctx->total_keys,
+                       far ? ex->far_factor : 0.0, (far && ex->far_init) ? ctx->far_box : nullptr,
+                       ctx->flags);
     hipLaunchKernelGGL(k_keys, dim3(nb), dim3(tb), 0, s, n, x, y, z, ctx->run_p, nr, ctx->grid,
-                       ctx->total_keys, ctx->key, ctx->slot, ctx->cell_count);
+                       ctx->total_keys, far ? ctx->far_box : nullptr, ctx->key, ctx->slot,
+                       ctx->cell_count);
     sph_status st = scan<int32_t, int32_t>(ctx, ctx->cell_count, ctx->cell_start,
                                            ctx->total_keys, 0, s);
     if (st != SPH_OK) return st;
@@ -799,6 +864,7 @@ sph_status launch_build_cells(Ctx *ctx, int64_t n, double *x, double *y, double 
     SPH_HIP(hipGetLastError());
     ctx->n_built = n;
     ctx->n_runs_built = nr;
+    ctx->far_built = far;
     return SPH_OK;
 }
 

@@ -9,8 +9,14 @@
 //   level -1  the eight octants of each search cell (the cell build orders
 //             the members of a cell by octant).
 // Each node holds a monopole (mass and centre of mass, FP32, relative to the
-// run's grid origin).  Targets are grouped by level-1 node (2x2x2 cells); a
-// group walks the pyramid breadth first, one candidate node per lane: a
+// run's grid origin).  Targets are grouped by pyramid node: a node of level
+// up to kGroupTop (4x4x4 cells) whose particles number at most kGroupMax is
+// one group, a fuller one is split into its children, down to level 1 (2x2x2
+// cells), so sparse debris makes few walks and dense matter groups of a
+// few hundred (a larger top level lets the candidate lists of a group's walk
+// outgrow their kCand entries).  A node's cells form one range of Morton keys, hence its
+// particles one contiguous range of the sorted order.  A group walks the
+// pyramid breadth first, one candidate node per lane: a
 // node whose box is disjoint from the group's box and for which b < theta d
 // is used for every target of the group (b: distance from the node's centre
 // of mass to its farthest corner, d: from the centre of mass to the group's
@@ -29,13 +35,14 @@ constexpr int kIL = 128;      // accepted monopoles held before evaluation
 constexpr int kStage = 64;    // near-field source particles held before evaluation
 constexpr int kSlots = 8;     // targets per lane per pass
 constexpr int kEvalStep = 2;  // list entries evaluated together
+constexpr int kGroupTop = 2;    // highest pyramid level of a target group
+constexpr int kGroupMax = 256;  // particles of a group above level 1
 
 struct GravLevels {
     int32_t nlev;                      // levels 0 .. nlev-1
     int32_t nx[kGravLevels], ny[kGravLevels], nz[kGravLevels];
     int64_t off[kGravLevels];          // level k >= 1: first node in the upper array
-    int64_t grp_off;                   // first group of this run
-    int32_t grp_level;                 // 1, or 0 for a run of a single cell
+    int32_t grp_top;                   // highest level of this run's groups (0: one cell)
     double eps;                        // softening length
 };
 
@@ -63,17 +70,105 @@ __global__ void k_grav_layout(int nr, const GridDesc *__restrict__ grid,
             up += (int64_t)L.nx[k] * L.ny[k] * L.nz[k];
         }
         L.nlev = k + 1;
-        L.grp_level = L.nlev > 1 ? 1 : 0;
-        L.grp_off = groups;
-        groups += (int64_t)L.nx[L.grp_level] * L.ny[L.grp_level] * L.nz[L.grp_level];
+        const int top = kGroupTop < L.nlev - 1 ? kGroupTop : L.nlev - 1;
+        L.grp_top = top < 0 ? 0 : top;
         L.eps = eps_over_h * bbox_part[r * kBBoxBlocks].hmax;
         lev[r] = L;
+        groups += (int64_t)L.nx[L.grp_top] * L.ny[L.grp_top] * L.nz[L.grp_top];
     }
     totals[0] = up;
-    totals[1] = groups;
-    if (up > cap_upper) {
-        flags[FLAG_GRAV_OVERFLOW] = 1;
-        totals[1] = 0;  // nothing is evaluated
+    totals[1] = 0;       // groups written by k_grav_groups
+    totals[2] = groups;  // nodes of the groups' top levels
+    if (up > cap_upper) flags[FLAG_GRAV_OVERFLOW] = 1;
+}
+
+// Cells of the level-k node (x, y, z) of run g: the Morton keys [kb, kb +
+// 2^nb).  Below bit level k every axis that has such a bit varies over the
+// node, above it the node's coordinates fix the key, so the range is
+// contiguous (an axis with fewer than k bits lies whole in the node).
+__device__ __forceinline__ void node_keys(const GridDesc &g, int k, int x, int y, int z,
+                                          uint32_t &kb, int &nb) {
+    kb = (uint32_t)g.key_off + morton((uint32_t)x << k, (uint32_t)y << k, (uint32_t)z << k,
+                                      g.bx, g.by, g.bz);
+    nb = (k < g.bx ? k : g.bx) + (k < g.by ? k : g.by) + (k < g.bz ? k : g.bz);
+}
+
+// Particles of the level-k node (x, y, z) of run g: one contiguous range.
+__device__ __forceinline__ int32_t node_count(const GridDesc &g, const int32_t *cell_start, int k,
+                                              int x, int y, int z) {
+    uint32_t kb;
+    int nb;
+    node_keys(g, k, x, y, z, kb, nb);
+    return cell_start[kb + (1u << nb)] - cell_start[kb];
+}
+
+// Target groups: one thread per top-level node of a run.  A node of at most
+// kGroupMax particles (or of level 1, or the single cell of a run of one
+// cell) is a group; a fuller one hands over to its non-empty children.
+// Groups are appended with one atomic per node (their order does not
+// matter: each group's results are its own).
+__global__ void k_grav_groups(int nr, const GridDesc *__restrict__ grid,
+                              const GravLevels *__restrict__ lev, const int32_t *__restrict__ cell_start,
+                              int64_t *totals, int64_t cap_upper, int4 *groups, int64_t cap_groups,
+                              int32_t *flags) {
+    if (totals[0] > cap_upper) return;  // layout overflow (flagged): nothing is evaluated
+    const int64_t nodes = totals[2];
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < nodes;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        // run of node t: the runs' top-level node counts in turn
+        int r = 0;
+        int64_t base = 0;
+        for (;; ++r) {
+            const GravLevels &L = lev[r];
+            const int64_t c = (int64_t)L.nx[L.grp_top] * L.ny[L.grp_top] * L.nz[L.grp_top];
+            if (t < base + c || r == nr - 1) break;
+            base += c;
+        }
+        const GravLevels &L = lev[r];
+        const GridDesc g = grid[r];
+        const int top = L.grp_top;
+        const int64_t loc = t - base;
+        const int nx = L.nx[top], ny = L.ny[top];
+        const int x0 = (int)(loc % nx), y0 = (int)((loc / nx) % ny), z0 = (int)(loc / ((int64_t)nx * ny));
+        // the node's groups, visited twice: counted, then written at the
+        // place one atomic reserves
+        auto visit = [&](auto emit) {
+            const int c0 = node_count(g, cell_start, top, x0, y0, z0);
+            if (c0 == 0) return;
+            if (top <= 1 || c0 <= kGroupMax) {
+                emit(top, x0, y0, z0);
+                return;
+            }
+            for (int d = 0; d < 8; ++d) {
+                const int x1 = 2 * x0 + (d & 1), y1 = 2 * y0 + ((d >> 1) & 1), z1 = 2 * z0 + (d >> 2);
+                if (x1 >= L.nx[top - 1] || y1 >= L.ny[top - 1] || z1 >= L.nz[top - 1]) continue;
+                const int c1 = node_count(g, cell_start, top - 1, x1, y1, z1);
+                if (c1 == 0) continue;
+                if (top - 1 <= 1 || c1 <= kGroupMax) {
+                    emit(top - 1, x1, y1, z1);
+                    continue;
+                }
+                for (int e = 0; e < 8; ++e) {
+                    const int x2 = 2 * x1 + (e & 1), y2 = 2 * y1 + ((e >> 1) & 1),
+                              z2 = 2 * z1 + (e >> 2);
+                    if (x2 >= L.nx[top - 2] || y2 >= L.ny[top - 2] || z2 >= L.nz[top - 2]) continue;
+                    if (node_count(g, cell_start, top - 2, x2, y2, z2) > 0) emit(top - 2, x2, y2, z2);
+                }
+            }
+        };
+        int nout = 0;
+        visit([&](int, int, int, int) { ++nout; });
+        if (nout == 0) continue;
+        const int64_t at = (int64_t)atomicAdd((unsigned long long *)&totals[1],
+                                              (unsigned long long)nout);
+        if (at + nout > cap_groups) {
+            atomicOr(&flags[FLAG_GRAV_OVERFLOW], 1);
+            continue;
+        }
+        int q = 0;
+        visit([&](int k, int x, int y, int z) {
+            groups[at + q++] = make_int4(r, k, x | (y << 10) | (z << 20), 0);
+        });
     }
 }
 
@@ -186,7 +281,8 @@ struct Acc {
 
 __global__ __launch_bounds__(64) void k_grav_walk(
     int nr, const GridDesc *__restrict__ grid, const GravLevels *__restrict__ lev,
-    const int64_t *__restrict__ totals, const int32_t *__restrict__ cell_start,
+    const int64_t *__restrict__ totals, int64_t cap_upper, const int4 *__restrict__ groups,
+    int64_t cap_groups, const int32_t *__restrict__ cell_start,
     const int32_t *__restrict__ cell_count, const double4 *__restrict__ posh64,
     const uint8_t *__restrict__ octant, const double *__restrict__ m,
     const int32_t *__restrict__ active, const float4 *__restrict__ mom0,
@@ -199,45 +295,31 @@ __global__ __launch_bounds__(64) void k_grav_walk(
     __shared__ int32_t stg_j[kStage];
     __shared__ int32_t leaf_s[8], leaf_c[8];
     const int lane = threadIdx.x;
-    const int64_t ngroups = totals[1];
+    const int64_t ngroups = totals[0] > cap_upper ? 0 : (totals[1] < cap_groups ? totals[1] : cap_groups);
 
     for (int64_t grp = blockIdx.x; grp < ngroups; grp += gridDim.x) {
-        // ---- which run and which level-gl node
-        int r = 0;
-        {
-            int lo = 0, hi = nr;
-            while (hi - lo > 1) {
-                const int mid = (lo + hi) >> 1;
-                if (lev[mid].grp_off <= grp) lo = mid; else hi = mid;
-            }
-            r = lo;
-        }
+        // ---- the group's run, level gl and node; its particles are one
+        // contiguous range of the sorted order
+        const int4 gd = groups[grp];
+        const int r = gd.x, gl = gd.y;
         const GravLevels &L = lev[r];
         const GridDesc g = grid[r];
-        const int gl = L.grp_level;
-        const int64_t loc = grp - L.grp_off;
-        const int gnx = L.nx[gl], gny = L.ny[gl];
-        const int gx = (int)(loc % gnx), gy = (int)((loc / gnx) % gny),
-                  gz = (int)(loc / ((int64_t)gnx * gny));
-        // ---- target cells of the group (its level-0 cells)
+        const int gx = gd.z & 1023, gy = (gd.z >> 10) & 1023, gz = (gd.z >> 20) & 1023;
         __syncthreads();
         if (lane < 8) {
             int s = 0, c = 0;
-            const int span = gl == 1 ? 2 : 1;
-            const int x = gx * span + (lane & 1), y = gy * span + ((lane >> 1) & 1),
-                      z = gz * span + (lane >> 2);
-            const bool inside = (gl == 1 || lane == 0) && x < L.nx[0] && y < L.ny[0] && z < L.nz[0];
-            if (inside) {
-                const uint32_t key = (uint32_t)g.key_off + morton(x, y, z, g.bx, g.by, g.bz);
-                s = cell_start[key];
-                c = cell_count[key];
+            if (lane == 0) {
+                uint32_t kb;
+                int nb;
+                node_keys(g, gl, gx, gy, gz, kb, nb);
+                s = cell_start[kb];
+                c = cell_start[kb + (1u << nb)] - s;
             }
             leaf_s[lane] = s;
             leaf_c[lane] = c;
         }
         __syncthreads();
-        int nt = 0;
-        for (int q = 0; q < 8; ++q) nt += leaf_c[q];
+        const int nt = leaf_c[0];
         if (nt == 0) continue;
         const float edge_g = (float)(g.L * (double)(1 << gl));
         const float blo[3] = {gx * edge_g, gy * edge_g, gz * edge_g};
@@ -561,9 +643,13 @@ sph_status launch_gravity(Ctx *ctx, int64_t n, const double *m, const int32_t *a
         hipLaunchKernelGGL(k_grav_up, dim3(64, ry), dim3(256), 0, s, nr, k, ctx->grid,
                            (const GravLevels *)ctx->grav_lev, ctx->grav_totals,
                            ctx->grav_cap_upper, ctx->grav_mom0, ctx->grav_momU);
+    hipLaunchKernelGGL(k_grav_groups, dim3(256), dim3(256), 0, s, nr, ctx->grid,
+                       (const GravLevels *)ctx->grav_lev, ctx->cell_start, ctx->grav_totals,
+                       ctx->grav_cap_upper, ctx->grav_groups, ctx->grav_cap_groups, ctx->flags);
     hipLaunchKernelGGL(k_grav_walk, dim3(8192), dim3(64), 0, s, nr, ctx->grid,
                        (const GravLevels *)ctx->grav_lev,
-                       ctx->grav_totals, ctx->cell_start, ctx->cell_count, ctx->posh64,
+                       ctx->grav_totals, ctx->grav_cap_upper, ctx->grav_groups,
+                       ctx->grav_cap_groups, ctx->cell_start, ctx->cell_count, ctx->posh64,
                        ctx->octant, m, active, ctx->grav_mom0, ctx->grav_mom8, ctx->grav_momU,
                        (float)G, (float)theta, accumulate, ax, ay,
                        az, phi, ctx->flags, tmask);
@@ -580,10 +666,14 @@ namespace sph {
 
 constexpr int kBmBlocks = 64;  // partial sums per run
 
-__global__ void k_bm_fill(int64_t n, int32_t *bound) {
+// Every particle starts bound; the potential starts at zero, so a particle
+// the walk does not reach (outside its run's far cube) counts as unbound.
+__global__ void k_bm_fill(int64_t n, int32_t *bound, double *phi) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x)
+         i += (int64_t)gridDim.x * blockDim.x) {
         bound[i] = 1;
+        phi[i] = 0.0;
+    }
 }
 
 // Per (run, block) partial sums of m, m v over the bound particles; fixed
@@ -658,7 +748,7 @@ sph_status launch_bound_mass(Ctx *ctx, int64_t n, const double *vx, const double
                              double theta, int32_t max_iter, int32_t *bound, double *m_bound,
                              double *phi, double *acc3, int32_t *iterations, hipStream_t s) {
     const int nr = ctx->n_runs_built;
-    hipLaunchKernelGGL(k_bm_fill, dim3(1024), dim3(256), 0, s, n, bound);
+    hipLaunchKernelGGL(k_bm_fill, dim3(1024), dim3(256), 0, s, n, bound, phi);
     int32_t it = 0;
     for (; it < max_iter; ++it) {
         hipLaunchKernelGGL(k_bm_partial, dim3(kBmBlocks, nr), dim3(256), 0, s, ctx->run_p, vx, vy,

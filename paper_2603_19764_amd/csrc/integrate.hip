@@ -178,9 +178,16 @@ constexpr int kDtUnroll = 4;
 
 __global__ void k_dt_reduce(int64_t n, const int32_t *__restrict__ run_p,
                             const double *__restrict__ dtc, const int32_t *__restrict__ fixed,
+                            const GridDesc *__restrict__ far_grid,
+                            const int32_t *__restrict__ cell_count,
                             unsigned long long *bits_all, int32_t *__restrict__ flags) {
     const int r = blockIdx.y;
-    const int64_t a = run_p ? run_p[r] : 0, b = run_p ? run_p[r + 1] : n;
+    const int64_t a = run_p ? run_p[r] : 0;
+    int64_t b = run_p ? run_p[r + 1] : n;
+    if (far_grid) {  // the run's particles outside its far cube (sorted last) take no part
+        const GridDesc g = far_grid[r];
+        if (g.sink) b -= cell_count[far_key(g)];
+    }
     unsigned long long *bits = bits_all + r;
     unsigned long long best = 0x7ff0000000000000ull;
     bool bad = false;  // a NaN step (skipped by the minimum, reported)
@@ -229,7 +236,7 @@ __global__ void k_dt_final(int nr, unsigned long long *bits, double cap, double 
 
 sph_status launch_dt_reduce(Ctx *ctx, int64_t n, const double *dtc, const int32_t *fixed,
                             unsigned long long *bits, hipStream_t s, int32_t nr,
-                            const int32_t *run_p) {
+                            const int32_t *run_p, bool skip_far) {
     if (nr < 1 || nr > ctx->max_runs || (nr > 1 && !run_p)) return SPH_EINVAL;
     if (n > 0) {
         // about kDtUnroll elements per thread, at most 64 blocks (one atomic
@@ -238,7 +245,8 @@ sph_status launch_dt_reduce(Ctx *ctx, int64_t n, const double *dtc, const int32_
         const int cap_b = 64;
         nb = nb < 1 ? 1 : (nb > cap_b ? cap_b : nb);
         hipLaunchKernelGGL(k_dt_reduce, dim3(nb, nr), dim3(1024), 0, s, n, nr > 1 ? run_p : nullptr,
-                           dtc, fixed, bits, ctx->flags);
+                           dtc, fixed, (skip_far && ctx->far_built) ? ctx->grid : nullptr,
+                           ctx->cell_count, bits, ctx->flags);
     }
     SPH_HIP(hipGetLastError());
     return SPH_OK;

@@ -47,7 +47,15 @@ struct GridDesc {
     int32_t key_off;        // first key of this run in the global cell table
     int32_t key_count;      // 2^(bx+by+bz)
     int32_t p0, p1;         // particle range of the run (input order == sorted order by run)
+    int32_t sink;           // 1: key key_off + key_count holds the run's particles outside
+                            // its far cube (sph_params.far_factor), sorted after its cells
+    int32_t pad;
 };
+
+// Key of the far slot of run g (valid when g.sink).
+__host__ __device__ inline uint32_t far_key(const GridDesc &g) {
+    return (uint32_t)(g.key_off + g.key_count);
+}
 
 struct BBox {
     double lo[3], hi[3], hmax;
@@ -74,7 +82,9 @@ struct Ctx {
     int32_t build_tile = 256;         // candidates in the LDS tile of the pair-list build
     // self-gravity pyramid (allocated with the context)
     void *grav_lev = nullptr;        // per-run level layout (max_runs entries)
-    int64_t *grav_totals = nullptr;  // [upper nodes, groups]
+    int64_t *grav_totals = nullptr;  // [upper nodes, groups written, top-level group nodes]
+    int4 *grav_groups = nullptr;     // target groups of the walk (run, level, node)
+    int64_t grav_cap_groups = 0;
     float4 *grav_mom0 = nullptr;     // max_cells cell monopoles (by cell key)
     float4 *grav_mom8 = nullptr;     // 8 max_cells octant monopoles (by cell key, octant)
     float4 *grav_momU = nullptr;     // grav_cap_upper monopoles of levels >= 1
@@ -110,6 +120,7 @@ struct Ctx {
     unsigned long long *dtbits = nullptr;  // 3 * max_runs
     int32_t dt_parity = 0;
     double *diag = nullptr;         // diagnostics partial sums: 256 x 13 doubles
+    BBox *far_box = nullptr;        // max_runs: far cube of each run (sph_params.far_factor)
     // pair-pass records (array of structures, see the pair kernels)
     void *rec_d = nullptr;          // density: capacity * 32 bytes
     void *rec_g = nullptr;          // gradients: capacity * 96 bytes
@@ -124,6 +135,7 @@ struct Ctx {
     int64_t t_count[SPH_T_COUNT] = {0};
     // host state
     int64_t n_built = -1;           // particles of the last build
+    bool far_built = false;         // the last build kept far slots (sph_params.far_factor)
     int32_t n_runs_built = 0;
     char err[512] = {0};
 };
@@ -172,6 +184,8 @@ struct BuildExtras {
     const int32_t *fixed = nullptr;
     const double *m = nullptr;                   // write density records when set
     int32_t f32 = 0;                             // record arithmetic
+    double far_factor = 0.0;                     // > 0: far cubes in use (sph_params)
+    int32_t far_init = 0;                        // set the far cubes from this build's boxes
 };
 
 // Launch helpers implemented in the .hip files.
@@ -216,7 +230,7 @@ sph_status launch_dt_min(Ctx *ctx, int64_t n, const double *dtc, const int32_t *
 // Reduction only, into bits (the step's kick finishes it); see launch_step_kick.
 sph_status launch_dt_reduce(Ctx *ctx, int64_t n, const double *dtc, const int32_t *fixed,
                             unsigned long long *bits, hipStream_t s, int32_t nr,
-                            const int32_t *run_p);
+                            const int32_t *run_p, bool skip_far = false);
 
 // Self-gravity of every run at the last build (sorted order); see sph_gravity.
 // tmask (may be NULL): only the targets with tmask[i] != 0 receive outputs.

@@ -112,7 +112,7 @@ def default_params(**kw) -> dict:
     p = dict(av_alpha=1.0, av_beta=2.0, av_eps=0.01, eta_C=0.3, rot_sign=1.0,
              g=(0.0, 0.0, 0.0), box=(0.0, 0.0, 0.0), use_correction=1, omega_one=0,
              grav_G=0.0, grav_eps_over_h=0.5, grav_theta=0.6, adapt_ngb=0.0, adapt_skin=1.25,
-             eta_a=0.0, rungs=0)
+             eta_a=0.0, rungs=0, far_factor=0.0)
     p.update(kw)
     return p
 
@@ -334,15 +334,17 @@ def bcc_ball(n_target: int, radius: float):
 
 
 def impact_pair(n_target: int, gamma: float = 0.1, r_c1: float = 1.0e6, v_over_vesc: float = 2.0,
-                strength: bool = True, mat_id: int = 0, mat: dict | None = None) -> dict:
+                strength: bool = True, mat_id: int = 0, mat: dict | None = None,
+                cm_frame: bool = False) -> dict:
     """Head-on collision of two BCC spheres of one material with equal
     particle masses: target of ~n_target particles and projectile of mass
     ratio gamma = M_p / M_t.  The total mass is that of a sphere of radius
     r_c1 at 1000 kg/m^3; each body has the material's reference density.  The
     projectile starts one spacing from contact on the -x side and moves at
     v = v_over_vesc * v_esc along +x, with v_esc = sqrt(2 G M_tot / (R_t + R_p));
-    the target is at rest.  u = 0, S = 0.  ``strength`` only labels the run
-    (the material row at ``mat_id`` decides what the step computes)."""
+    the target is at rest (with ``cm_frame``, both move so that the total
+    momentum is zero).  u = 0, S = 0.  ``strength`` only labels the run (the
+    material row at ``mat_id`` decides what the step computes)."""
     mat = mat or granite_c3()
     rho = mat["rho0"]
     m_tot = 4.0 / 3.0 * math.pi * r_c1 ** 3 * 1000.0
@@ -360,6 +362,8 @@ def impact_pair(n_target: int, gamma: float = 0.1, r_c1: float = 1.0e6, v_over_v
     w.update(x=P[:, 0].copy(), y=P[:, 1].copy(), z=P[:, 2].copy(), m=np.full(n, mpart),
              h=np.full(n, 1.3 * sp))
     w["vx"][Pt.shape[0]:] = v_over_vesc * v_esc
+    if cm_frame:
+        w["vx"] -= w["vx"].sum() / n
     w["mat"][:] = mat_id
     w.update(mats=[mat], params=default_params(), n_target=int(Pt.shape[0]),
              name=f"impact_{Pt.shape[0]}+{Pp.shape[0]}",
@@ -369,13 +373,14 @@ def impact_pair(n_target: int, gamma: float = 0.1, r_c1: float = 1.0e6, v_over_v
 
 
 def scan_batch(n_runs: int = 64, seed: int = 5, n_min: int = 20_000, n_max: int = 300_000,
-               gamma: float = 0.1, scale: float = 1.0) -> dict:
+               gamma: float = 0.1, scale: float = 1.0, cm_frame: bool = False) -> dict:
     """A batched Q_RD* scan: n_runs head-on impacts with target particle counts
     log-uniform in [n_min, n_max] (times ``scale`` for small copies), mass
     ratio gamma, R_C1 log-uniform in [4.64e5, 4.64e6] m, v/v_esc log-uniform
     in [1, 10] and strength on or off with probability 1/2.  Material 0 is
     granite with strength, material 1 the same without; runs are concatenated
-    (``run_start``) and ``cases`` lists each run's parameters."""
+    (``run_start``) and ``cases`` lists each run's parameters; ``cm_frame``
+    puts each run in its centre-of-mass frame."""
     rng = np.random.Generator(np.random.PCG64(seed))
     strong = granite_impact()
     mats = [strong, fluid(strong)]
@@ -385,7 +390,8 @@ def scan_batch(n_runs: int = 64, seed: int = 5, n_min: int = 20_000, n_max: int 
         rc1 = math.exp(rng.uniform(math.log(4.64e5), math.log(4.64e6)))
         vv = math.exp(rng.uniform(0.0, math.log(10.0)))
         st = bool(rng.integers(0, 2))
-        w = impact_pair(max(nt, 8), gamma, rc1, vv, st, mat_id=0 if st else 1, mat=strong)
+        w = impact_pair(max(nt, 8), gamma, rc1, vv, st, mat_id=0 if st else 1, mat=strong,
+                        cm_frame=cm_frame)
         runs.append(w)
         cases.append(w["case"])
     b = concat_runs(runs)

@@ -26,7 +26,8 @@ def free_fall_time(rho: float) -> float:
 
 def run_to_end(b: dict, t_end, checkpoints=(1.0,), prec: int = sph.SPH_FP32_CELLREL,
                max_steps: int = 20000, check_every: int = 50, theta: float = 0.6,
-               max_neighbors: int = 256, log=None) -> dict:
+               max_neighbors: int = 256, log=None, max_cells: int = 1 << 24,
+               far_factor: float = 0.0) -> dict:
     """Advance a batch of runs (``b``: concatenated runs with ``run_start``,
     ``mats``) under self-gravity until every run has reached its t_end (one
     value per run), as replays of a two-step hipGraph with ``check_every``
@@ -35,14 +36,20 @@ def run_to_end(b: dict, t_end, checkpoints=(1.0,), prec: int = sph.SPH_FP32_CELL
     is taken (iterative removal of unbound particles) and its largest-remnant
     fraction f = M_bound / M_total recorded.  Returns {"f": {c: array},
     "t": {c: array} (the run's time when recorded), "m_tot", "steps",
-    "reached" (bool per run), "seconds"}."""
+    "reached" (bool per run), "seconds"}.  ``far_factor`` > 0 holds each
+    run's search grid to a cube of that many times its initial half-extent
+    (sph_params.far_factor): ejecta beyond it fly on ballistically and count
+    as unbound.  The runs take Omega = 1: with fixed smoothing lengths a
+    particle that loses its neighbours (ejecta, the edge of the far cube)
+    drives the defined Omega to zero, and the grad-h term is only consistent
+    with adapted lengths anyway."""
     import time
-    prm = inputs.default_params(grav_G=G, grav_theta=theta)
+    prm = inputs.default_params(grav_G=G, grav_theta=theta, far_factor=far_factor, omega_one=1)
     mats = b["mats"]
     rs = [int(v) for v in b["run_start"]]
     n, nr = int(b["x"].size), len(rs) - 1
     t_end = np.asarray(t_end, dtype=np.float64)
-    ctx = sph.Context(n, max_neighbors, max_cells=1 << 24, max_runs=nr)
+    ctx = sph.Context(n, max_neighbors, max_cells=max_cells, max_runs=nr)
     st = sph.State(b, run_start=rs)
     sph.sph_init(ctx, st, mats, prm, prec)   # the library sets each run's time to 0
     m = b["m"]
@@ -87,20 +94,36 @@ def run_to_end(b: dict, t_end, checkpoints=(1.0,), prec: int = sph.SPH_FP32_CELL
                 seconds=time.perf_counter() - t0)
 
 
-def end_times(cases, t_end_ff: float = 2.0):
-    """t_end of each run: t_end_ff free-fall times of the target material
-    plus the crossing time (R_t + R_p) / v."""
-    rho = inputs.granite_impact()["rho0"]
-    return np.array([t_end_ff * free_fall_time(rho) + (k["r_t"] + k["r_p"]) / k["v"]
-                     for k in cases])
+def end_times(cases, t_end_ff: float = 2.0, t_end_sound: float = 0.0):
+    """t_end of each run: the crossing time (R_t + R_p) / v plus t_end_ff
+    free-fall times 1/sqrt(G rho0) of the target material, or, when
+    ``t_end_sound`` > 0 and it is shorter, that many sound-crossing times
+    R_t / c0 of the target (c0 = sqrt(A / rho0), the bulk sound speed of the
+    Tillotson material): once the shock has crossed and pressure has
+    released the debris, each particle's energy relative to the remnant no
+    longer changes, and so neither does the bound mass."""
+    mat = inputs.granite_impact()
+    rho = mat["rho0"]
+    c0 = math.sqrt(mat["A"] / rho)
+    out = []
+    for k in cases:
+        settle = t_end_ff * free_fall_time(rho)
+        if t_end_sound > 0.0:
+            settle = min(settle, t_end_sound * k["r_t"] / c0)
+        out.append(settle + (k["r_t"] + k["r_p"]) / k["v"])
+    return np.array(out)
 
 
 def simulate(cases: list, t_end_ff: float = 2.0, prec: int = sph.SPH_FP32_CELLREL,
              max_steps: int = 20000, check_every: int = 50, theta: float = 0.6,
-             max_neighbors: int = 256, log=None, checkpoints=(1.0,)) -> dict:
+             max_neighbors: int = 256, log=None, checkpoints=(1.0,), t_end_sound: float = 0.0,
+             max_cells: int = 1 << 24, far_factor: float = 1.5) -> dict:
     """Run every case (dicts with n_target, gamma, r_c1, v_over_vesc, strength)
     to t_end = t_end_ff free-fall times of the target material plus the
-    crossing time (R_t + R_p) / v, then find the bound mass of each run.
+    crossing time (R_t + R_p) / v (or ``t_end_sound`` sound-crossing times of
+    the target, see ``end_times``), then find the bound mass of each run.
+    The bodies move in their centre-of-mass frame, so the remnant stays near
+    the centre of the run's far cube (``far_factor``, see ``run_to_end``).
     Returns {"f_lr", "m_tot", "steps", "t", "t_end", "seconds", "particles"}
     and, when 0.5 is among ``checkpoints``, "f_half" (f_lr at t_end / 2)."""
     strong = inputs.granite_impact()
@@ -109,14 +132,15 @@ def simulate(cases: list, t_end_ff: float = 2.0, prec: int = sph.SPH_FP32_CELLRE
     for c in cases:
         w = inputs.impact_pair(int(c["n_target"]), c.get("gamma", 0.1), c["r_c1"],
                                c["v_over_vesc"], bool(c["strength"]),
-                               mat_id=0 if c["strength"] else 1, mat=strong)
+                               mat_id=0 if c["strength"] else 1, mat=strong, cm_frame=True)
         runs.append(w)
     b = inputs.concat_runs(runs)
     b["mats"] = mats
-    t_end = end_times([w["case"] for w in runs], t_end_ff)
+    t_end = end_times([w["case"] for w in runs], t_end_ff, t_end_sound)
     cps = tuple(sorted(set(checkpoints) | {1.0}))
     r = run_to_end(b, t_end, cps, prec=prec, max_steps=max_steps, check_every=check_every,
-                   theta=theta, max_neighbors=max_neighbors, log=log)
+                   theta=theta, max_neighbors=max_neighbors, log=log, max_cells=max_cells,
+                   far_factor=far_factor)
     out = dict(f_lr=r["f"][1.0], m_tot=r["m_tot"], steps=r["steps"], t=r["t"][1.0],
                t_end=t_end, seconds=r["seconds"], particles=int(b["x"].size))
     if 0.5 in r["f"]:

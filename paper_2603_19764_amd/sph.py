@@ -62,7 +62,7 @@ class sph_params(C.Structure):
                 ("grav_G", C.c_double), ("grav_eps_over_h", C.c_double),
                 ("grav_theta", C.c_double), ("adapt_ngb", C.c_double),
                 ("adapt_skin", C.c_double), ("eta_a", C.c_double), ("rungs", C.c_int32),
-                ("rungs_pad", C.c_int32)]
+                ("rungs_pad", C.c_int32), ("far_factor", C.c_double)]
 
 
 class sph_state(C.Structure):
@@ -218,6 +218,7 @@ def make_params(d: dict) -> sph_params:
     p.adapt_skin = float(d.get("adapt_skin", 1.25))
     p.eta_a = float(d.get("eta_a", 0.0))
     p.rungs = int(d.get("rungs", 0))
+    p.far_factor = float(d.get("far_factor", 0.0))
     return p
 
 
