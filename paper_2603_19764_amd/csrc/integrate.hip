@@ -184,9 +184,10 @@ __global__ void k_dt_reduce(int64_t n, const int32_t *__restrict__ run_p,
     const int r = blockIdx.y;
     const int64_t a = run_p ? run_p[r] : 0;
     int64_t b = run_p ? run_p[r + 1] : n;
-    if (far_grid) {  // the run's particles outside its far cube (sorted last) take no part
+    if (far_grid) {  // the run's particles outside its far cube (sorted last) take no part,
+                     // unless no other is left (then they set the step of their flight)
         const GridDesc g = far_grid[r];
-        if (g.sink) b -= cell_count[far_key(g)];
+        if (g.sink && b - cell_count[far_key(g)] > a) b -= cell_count[far_key(g)];
     }
     unsigned long long *bits = bits_all + r;
     unsigned long long best = 0x7ff0000000000000ull;

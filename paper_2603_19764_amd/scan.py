@@ -71,7 +71,9 @@ def run_to_end(b: dict, t_end, checkpoints=(1.0,), prec: int = sph.SPH_FP32_CELL
         for _ in range(check_every // 2):
             graph.replay()
         steps += check_every
-        ctx.check(sph.lib().sph_sync_status(ctx.h, None))
+        code = sph.lib().sph_sync_status(ctx.h, None)
+        if code != sph.SPH_OK:
+            raise sph.SphError(code, f"after step {steps}: " + _run_report(st, rs, t_end))
         t_now = st.time.cpu().numpy()
         due = {c: np.flatnonzero(np.isnan(f[c]) & (t_now >= c * t_end)) for c in checkpoints}
         if any(d.size for d in due.values()):
@@ -92,6 +94,21 @@ def run_to_end(b: dict, t_end, checkpoints=(1.0,), prec: int = sph.SPH_FP32_CELL
     ctx.close()
     return dict(f=f, t=tr, m_tot=m_tot, steps=steps, reached=t_now >= t_end,
                 seconds=time.perf_counter() - t0)
+
+
+def _run_report(st, rs, t_end) -> str:
+    """Which runs of a batch hold non-finite values, with their steps and times."""
+    bad = []
+    x = np.stack([st.row(k).cpu().numpy() for k in (sph.SPH_X, sph.SPH_VX, sph.SPH_U)])
+    dt = st.dt.cpu().numpy()
+    tn = st.time.cpu().numpy()
+    for r in range(len(rs) - 1):
+        seg = x[:, rs[r]:rs[r + 1]]
+        nf = int((~np.isfinite(seg)).any(0).sum())
+        if nf or not np.isfinite(dt[r]):
+            bad.append(f"run {r}: {nf} particles non-finite, dt {dt[r]:.3g}, t/t_end "
+                       f"{tn[r] / t_end[r]:.3f}")
+    return "; ".join(bad) if bad else "no run holds a non-finite position, velocity or energy"
 
 
 def end_times(cases, t_end_ff: float = 2.0, t_end_sound: float = 0.0):
