@@ -275,8 +275,10 @@ def _round(state: dict, searches: list, predict, w: float, rng, log, judge_fn,
     for (key, lst), fv, fhv in zip(keyed.items(), f, fh):
         for k, src in lst:
             searches[k]["pts"].append([key[1], float(fv), src])
-    rec.update(phase=state["phase"], w=w,
-               f_change=float(np.nanmax(np.abs(np.asarray(f) - np.asarray(fh)))))
+    dfl = np.abs(np.asarray(f) - np.asarray(fh))
+    rec.update(phase=state["phase"], w=w, f_change=float(np.nanmax(dfl)),
+               f_change_median=float(np.nanmedian(dfl)),
+               f_change_p90=float(np.nanpercentile(dfl, 90)))
     state["rounds"].append(rec)
     if log:
         log(f"round {len(state['rounds'])} ({state['phase']}): {rec}")
@@ -366,7 +368,7 @@ def main(argv=None):
     ap.add_argument("--n-train", type=int, default=32)
     ap.add_argument("--n-held", type=int, default=16)
     ap.add_argument("--n-min", type=float, default=3.0e4)
-    ap.add_argument("--n-max", type=float, default=5.0e5)
+    ap.add_argument("--n-max", type=float, default=1.0e5)
     ap.add_argument("--train-rounds", type=int, default=8)
     ap.add_argument("--t-end-ff", type=float, default=2.0)
     ap.add_argument("--t-end-sound", type=float, default=6.0,

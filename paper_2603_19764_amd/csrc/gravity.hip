@@ -555,8 +555,20 @@ __global__ __launch_bounds__(64) void k_grav_walk(
                         }
                         continue;
                     }
-                    // children of opened nodes into the next level's list
+                    // children of opened nodes into the next level's list.  When
+                    // they would overflow it, the opened nodes disjoint from the
+                    // group's box are used as monopoles instead (the far field
+                    // then rests on coarser nodes than the opening angle asks
+                    // for) and only those overlapping the box are opened
                     {
+                        if (n_next + 8 * __popcll(__builtin_amdgcn_ballot_w64(open)) > kCand) {
+                            const float x0 = cx * edge, y0 = cy * edge, z0 = cz * edge;
+                            const bool disj = x0 >= bhi[0] || x0 + edge <= blo[0] ||
+                                              y0 >= bhi[1] || y0 + edge <= blo[1] ||
+                                              z0 >= bhi[2] || z0 + edge <= blo[2];
+                            push_il(open && disj, q);
+                            open = open && !disj;
+                        }
                         const uint64_t mk = __builtin_amdgcn_ballot_w64(open);
                         const int cnt = __popcll(mk);
                         if (n_next + 8 * cnt > kCand) {
