@@ -540,7 +540,9 @@ __global__ __launch_bounds__(64) void k_build_pairs(
     __shared__ double4 tpos[Tile];  // x, y, z, H_j^2
     __shared__ uint32_t tj[Tile];   // j | stencil code
     __shared__ int32_t st_start[27];
-    __shared__ int32_t st_off[28];
+    // first raw candidate index of each stencil cell; 27..31 hold INT_MAX so
+    // that the cell search below reads whole groups of eight
+    __shared__ __align__(16) int32_t st_off[32];
 
     const int lane = threadIdx.x;
     const uint32_t wg = xcd_block(blockIdx.x, gridDim.x);
@@ -593,14 +595,15 @@ __global__ __launch_bounds__(64) void k_build_pairs(
             const int v = __shfl_up(incl, o);
             if (lane >= o) incl += v;
         }
+        const int T = __shfl(incl, 26);  // raw candidates of the stencil
         __syncthreads();
         if (lane < 27) {
             st_start[lane] = start_t;
-            st_off[lane + 1] = incl;
+            st_off[lane] = incl - cnt_t;
+        } else if (lane < 32) {
+            st_off[lane] = 0x7fffffff;
         }
-        if (lane == 0) st_off[0] = 0;
         __syncthreads();
-        const int T = st_off[27];
 
         for (int64_t ib = i_lo; ib < i_hi; ib += kIBatch) {
             const int ni = (int)((i_hi - ib) < kIBatch ? (i_hi - ib) : kIBatch);
@@ -640,25 +643,22 @@ __global__ __launch_bounds__(64) void k_build_pairs(
                     const int left = (T - r0 + kWave - 1) / kWave;
                     nch = nch < left ? nch : left;
                     nch = nch < kFillChunks ? nch : kFillChunks;
-                    int g[kFillChunks], lo[kFillChunks], hi[kFillChunks];
+                    int g[kFillChunks], lo[kFillChunks];
+#pragma unroll
+                    for (int u = 0; u < kFillChunks; ++u) g[u] = r0 + u * kWave + lane;
+                    // stencil cell of each raw candidate: the largest t with
+                    // st_off[t] <= g, which (offsets do not decrease, st_off[0]
+                    // = 0) is the number of t >= 1 with st_off[t] <= g; counted
+                    // in two levels, first against st_off[8], [16], [24], then
+                    // against the seven entries after the chosen group's first
 #pragma unroll
                     for (int u = 0; u < kFillChunks; ++u) {
-                        g[u] = r0 + u * kWave + lane;
-                        lo[u] = 0;
-                        hi[u] = 27;
-                    }
-                    // stencil cell of each raw candidate: largest lo with
-                    // st_off[lo] <= g (five halvings cover 27 cells; once
-                    // hi - lo = 1, mid = lo and nothing changes)
-#pragma unroll
-                    for (int step = 0; step < 5; ++step) {
-#pragma unroll
-                        for (int u = 0; u < kFillChunks; ++u) {
-                            const int mid = (lo[u] + hi[u]) >> 1;
-                            const bool le = st_off[mid] <= g[u];
-                            lo[u] = le ? mid : lo[u];
-                            hi[u] = le ? hi[u] : mid;
-                        }
+                        const int b = (st_off[8] <= g[u]) + (st_off[16] <= g[u]) +
+                                      (st_off[24] <= g[u]);
+                        const int4 q0 = *reinterpret_cast<const int4 *>(&st_off[8 * b]);
+                        const int4 q1 = *reinterpret_cast<const int4 *>(&st_off[8 * b + 4]);
+                        lo[u] = 8 * b + (q0.y <= g[u]) + (q0.z <= g[u]) + (q0.w <= g[u]) +
+                                (q1.x <= g[u]) + (q1.y <= g[u]) + (q1.z <= g[u]) + (q1.w <= g[u]);
                     }
                     double4 c[kFillChunks];
                     uint32_t code[kFillChunks];
