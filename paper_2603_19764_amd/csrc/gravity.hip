@@ -26,6 +26,7 @@
 // eps_r = eps_over_h * max_i h_i of the run; sources inside the near field
 // exclude the target itself.
 #include "sph_internal.h"
+#include <type_traits>
 
 namespace sph {
 
@@ -352,7 +353,13 @@ __global__ __launch_bounds__(64) void k_grav_walk(
             int n_il = 0, n_st = 0;
             // Entries are evaluated kEvalStep at a time: per slot their
             // contributions are independent and are added in list order.
-            auto eval = [&](const float4 *lst, const int32_t *lj, int cnt) {
+            // Only near-field particles (pp) can be the target itself, whose
+            // term is left out; softened 1/r with eps^2 taken first.
+            auto rinv = [&](float dx, float dy, float dz) {
+                return __frsqrt_rn(fmaf(dz, dz, fmaf(dy, dy, fmaf(dx, dx, e2))));
+            };
+            auto eval = [&](auto pp, const float4 *lst, const int32_t *lj, int cnt) {
+                constexpr bool PP = decltype(pp)::value;
                 int e = 0;
                 for (; e + kEvalStep <= cnt; e += kEvalStep) {
                     float4 q[kEvalStep];
@@ -360,7 +367,7 @@ __global__ __launch_bounds__(64) void k_grav_walk(
 #pragma unroll
                     for (int u = 0; u < kEvalStep; ++u) {
                         q[u] = lst[e + u];
-                        j[u] = lj ? lj[e + u] : -1;
+                        j[u] = PP ? lj[e + u] : -1;
                     }
 #pragma unroll
                     for (int s = 0; s < kSlots; ++s) {
@@ -372,8 +379,8 @@ __global__ __launch_bounds__(64) void k_grav_walk(
                             dx[u] = q[u].x - A.tx[s];
                             dy[u] = q[u].y - A.ty[s];
                             dz[u] = q[u].z - A.tz[s];
-                            const float ri = __frsqrt_rn(dx[u] * dx[u] + dy[u] * dy[u] + dz[u] * dz[u] + e2);
-                            mr[u] = (j[u] == A.ti[s]) ? 0.f : q[u].w * ri;
+                            const float ri = rinv(dx[u], dy[u], dz[u]);
+                            mr[u] = (PP && j[u] == A.ti[s]) ? 0.f : q[u].w * ri;
                             m3[u] = mr[u] * ri * ri;
                         }
 #pragma unroll
@@ -387,13 +394,13 @@ __global__ __launch_bounds__(64) void k_grav_walk(
                 }
                 for (; e < cnt; ++e) {
                     const float4 q = lst[e];
-                    const int j = lj ? lj[e] : -1;
+                    const int j = PP ? lj[e] : -1;
 #pragma unroll
                     for (int s = 0; s < kSlots; ++s) {
                         if (s >= ns) break;
                         const float dx = q.x - A.tx[s], dy = q.y - A.ty[s], dz = q.z - A.tz[s];
-                        const float ri = __frsqrt_rn(dx * dx + dy * dy + dz * dz + e2);
-                        const float mr = (j == A.ti[s]) ? 0.f : q.w * ri;
+                        const float ri = rinv(dx, dy, dz);
+                        const float mr = (PP && j == A.ti[s]) ? 0.f : q.w * ri;
                         const float mr3 = mr * ri * ri;
                         A.ax[s] += mr3 * dx;
                         A.ay[s] += mr3 * dy;
@@ -404,13 +411,13 @@ __global__ __launch_bounds__(64) void k_grav_walk(
             };
             auto flush_il = [&]() {
                 __syncthreads();
-                eval(il, nullptr, n_il);
+                eval(std::false_type{}, il, nullptr, n_il);
                 n_il = 0;
                 __syncthreads();
             };
             auto flush_st = [&]() {
                 __syncthreads();
-                eval(stg, stg_j, n_st);
+                eval(std::true_type{}, stg, stg_j, n_st);
                 n_st = 0;
                 __syncthreads();
             };
