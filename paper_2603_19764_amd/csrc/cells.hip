@@ -715,6 +715,9 @@ __global__ __launch_bounds__(64) void k_build_pairs(
                         tj[fill + lane] = 0u;
                     }
                 }
+                // wave-uniform (keeps the column loop and the running counts
+                // in scalar registers)
+                cols = __builtin_amdgcn_readfirstlane(cols);
                 __syncthreads();
                 // ---- tests: G = 4 particles i at a time against every column
                 // of the tile (G = 2 or 1 for the last two or one of a batch).
@@ -751,18 +754,27 @@ __global__ __launch_bounds__(64) void k_build_pairs(
                         const uint32_t e = tj[col + lane];
                         const uint32_t jj = e & kIdxMask;
                         const uint32_t ed = e | kDensityBit;
+                        // all G tests first (their FP64 chains interleave),
+                        // then the G appends
+                        uint64_t md[G], m[G];
 #pragma unroll
                         for (int k = 0; k < G; ++k) {
                             const double r2 = sep2_exact(P[k].x, P[k].y, P[k].z, c.x, c.y, c.z);
-                            const uint64_t md = wave_ballot(r2 < H2[k]);   // density set of i
+                            md[k] = wave_ballot(r2 < H2[k]);                // density set of i
                             const uint64_t mj = wave_ballot(r2 < c.w);     // support of j
                             const uint64_t ms = wave_ballot(jj == self[k]);
-                            const uint64_t m = (md | mj) & ~ms;
+                            m[k] = (md[k] | mj) & ~ms;
+                        }
+#pragma unroll
+                        for (int k = 0; k < G; ++k) {
                             const int b = base[k];
                             const int at = b < K ? b : K;
-                            const uint32_t v = lane_bit(md) ? ed : e;
-                            if (lane_bit(m)) row[k][at + (int)lanes_below(m)] = v;
-                            base[k] = b + (int)__popcll(m);
+                            const uint32_t v = lane_bit(md[k]) ? ed : e;
+                            // wave-uniform base, unsigned lane offset: the
+                            // store takes a scalar base and a 32-bit offset
+                            uint32_t *dst = row[k] + at;
+                            if (lane_bit(m[k])) dst[lanes_below(m[k])] = v;
+                            base[k] = b + (int)__popcll(m[k]);
                         }
                     }
 #pragma unroll
