@@ -476,7 +476,14 @@ __global__ void k_place(int64_t n, const int32_t *__restrict__ arrived,
     if (*total_keys != 0) {
         const int32_t cs = cell_start[ko], c = cell_count[ko];
         int rank = 0;
-        for (int l = 0; l < c; ++l) rank += arrived[cs + l] < e;
+        // four loads in flight per step (a cell holds a few tens)
+        int l = 0;
+        for (; l + 4 <= c; l += 4) {
+            const int32_t a0 = arrived[cs + l], a1 = arrived[cs + l + 1];
+            const int32_t a2 = arrived[cs + l + 2], a3 = arrived[cs + l + 3];
+            rank += (a0 < e) + (a1 < e) + (a2 < e) + (a3 < e);
+        }
+        for (; l < c; ++l) rank += arrived[cs + l] < e;
         q = cs + rank;
         oct = (uint8_t)(e >> kIdxBits);
     }
@@ -515,7 +522,7 @@ __global__ void k_place(int64_t n, const int32_t *__restrict__ arrived,
 // each lane holds one candidate of a 64-wide column of the tile; one exact
 // test per lane, a ballot, and the hits are appended to i's list in
 // candidate order at offsets from mbcnt.  The lists are deterministic.
-constexpr int kFillChunks = 2;  // raw-candidate chunks whose loads overlap
+constexpr int kFillChunks = 3;  // raw-candidate chunks whose loads overlap
 constexpr int kIBatch = 64;
 constexpr double kCullMargin = 1.0 + 0x1p-40;
 
