@@ -355,6 +355,47 @@ def summary(state: dict) -> dict:
                 max_f_change=max((r["f_change"] for r in state["rounds"]), default=None))
 
 
+def settling(state: dict, factors=(0.5, 1.0, 2.0, 4.0), simulate=None, log=None,
+             **sim_kw) -> dict:
+    """Run the ends of every closed held-out bisection bracket on, past t_end:
+    f_lr at ``factors`` x t_end for the lower end (f > 1/2 at t_end) and the
+    upper end (f <= 1/2), all in one batch.  Reports per case whether the
+    ends still straddle 1/2 at each time and the threshold interpolated
+    between them (None once they do not), so that the drift of the bound
+    mass after t_end and its effect on Q_RD* are measured, not assumed."""
+    simulate = simulate or scan.simulate
+    specs, jobs = [], []
+    for s in state["held"]:
+        if s["method"] != "bisect" or s["status"] != "done":
+            continue
+        v_lo, _, v_hi, _ = _sides(s)
+        specs.append((s["spec"], v_lo, v_hi))
+        for v in (v_lo, v_hi):
+            c = case_of(s["spec"])
+            jobs.append(dict(n_target=s["spec"]["n_target"], gamma=s["spec"]["gamma"],
+                             r_c1=s["spec"]["r_c1"], v_over_vesc=v / c.v_esc,
+                             strength=s["spec"]["strength"]))
+    if not jobs:
+        return dict(factors=list(factors), cases=[])
+    r = simulate(jobs, checkpoints=tuple(factors), log=log, **sim_kw)
+    rows = []
+    for k, (spec, v_lo, v_hi) in enumerate(specs):
+        c = case_of(spec)
+        row = dict(m_tot=c.m_tot, strength=spec["strength"], n_target=spec["n_target"],
+                   q_lo=c.q(v_lo), q_hi=c.q(v_hi), f_lo=[], f_hi=[], straddles=[], q_rd=[])
+        for fac in factors:
+            f_lo = float(r["f_at"][fac][2 * k])
+            f_hi = float(r["f_at"][fac][2 * k + 1])
+            ok = f_lo > 0.5 >= f_hi
+            row["f_lo"].append(f_lo)
+            row["f_hi"].append(f_hi)
+            row["straddles"].append(bool(ok))
+            row["q_rd"].append(qrd.Bracket(c, v_lo, v_hi, f_lo, f_hi).q_rd() if ok else None)
+        rows.append(row)
+    return dict(factors=list(factors), cases=rows, steps=r["steps"], seconds=r["seconds"],
+                particles=r["particles"])
+
+
 def main(argv=None):
     """Run or resume a campaign whose state lives in a JSON file."""
     import argparse
@@ -377,6 +418,9 @@ def main(argv=None):
     ap.add_argument("--max-cells", type=int, default=1 << 26)
     ap.add_argument("--far-factor", type=float, default=1.5)
     ap.add_argument("--check-every", type=int, default=200)
+    ap.add_argument("--settling", metavar="OUT",
+                    help="instead of advancing the campaign, run the ends of the closed "
+                         "held-out bisection brackets to 4 t_end and write the result here")
     a = ap.parse_args(argv)
 
     def log(*x):
@@ -397,6 +441,14 @@ def main(argv=None):
 
     import torch
     torch.cuda.set_device(0)
+    if a.settling:
+        res = settling(state, log=log, t_end_ff=a.t_end_ff, t_end_sound=a.t_end_sound,
+                       check_every=a.check_every, max_cells=a.max_cells,
+                       far_factor=a.far_factor)
+        with open(a.settling, "w") as f:
+            json.dump(res, f)
+        print(json.dumps(res), flush=True)
+        return
     run(state, a.rounds, a.budget, log=log, train_rounds=a.train_rounds, save=save,
         t_end_ff=a.t_end_ff, t_end_sound=a.t_end_sound, check_every=a.check_every,
         max_cells=a.max_cells, far_factor=a.far_factor)

@@ -141,8 +141,9 @@ def simulate(cases: list, t_end_ff: float = 2.0, prec: int = sph.SPH_FP32_CELLRE
     the target, see ``end_times``), then find the bound mass of each run.
     The bodies move in their centre-of-mass frame, so the remnant stays near
     the centre of the run's far cube (``far_factor``, see ``run_to_end``).
-    Returns {"f_lr", "m_tot", "steps", "t", "t_end", "seconds", "particles"}
-    and, when 0.5 is among ``checkpoints``, "f_half" (f_lr at t_end / 2)."""
+    Returns {"f_lr", "m_tot", "steps", "t", "t_end", "seconds", "particles",
+    "f_at" (f_lr at every checkpoint c * t_end)} and, when 0.5 is among
+    ``checkpoints``, "f_half" (f_lr at t_end / 2)."""
     strong = inputs.granite_impact()
     mats = [strong, inputs.fluid(strong)]
     runs = []
@@ -159,7 +160,8 @@ def simulate(cases: list, t_end_ff: float = 2.0, prec: int = sph.SPH_FP32_CELLRE
                    theta=theta, max_neighbors=max_neighbors, log=log, max_cells=max_cells,
                    far_factor=far_factor)
     out = dict(f_lr=r["f"][1.0], m_tot=r["m_tot"], steps=r["steps"], t=r["t"][1.0],
-               t_end=t_end, seconds=r["seconds"], particles=int(b["x"].size))
+               t_end=t_end, seconds=r["seconds"], particles=int(b["x"].size),
+               f_at={c: r["f"][c] for c in cps})
     if 0.5 in r["f"]:
         out["f_half"] = r["f"][0.5]
     return out

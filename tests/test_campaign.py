@@ -155,3 +155,46 @@ def test_campaign_rounds_with_synthetic_judge():
     assert 0.03 <= state["w"] <= 0.5
     # rounds batch every open search: no more rounds than the slowest search
     assert out["rounds"] <= 8 + 12
+
+
+def test_settling_runs_the_bracket_ends_past_t_end():
+    """The settling check simulates both ends of every closed held-out
+    bisection bracket at several multiples of t_end; with a synthetic
+    outcome whose threshold drifts down by 3% per doubling of the time it
+    must report the truth at each time, and at t_end the campaign's own
+    thresholds."""
+    state = campaign.new_campaign(n_train=4, n_held=5, seed=8, n_min=1000, n_max=2000)
+
+    def trainer(searches):
+        return Exact([s["spec"] for s in state["train"] + state["held"]]), 0.0, 0
+
+    state = campaign.run(state, judge_fn=mock_judge, trainer=trainer)
+    drift = 0.97
+
+    def f_at(spec, v, fac):
+        c = campaign.case_of(spec)
+        return 1.0 / (1.0 + (c.q(v) / (q_star(spec) * drift ** math.log2(fac))) ** 4)
+
+    calls = []
+
+    def simulate(jobs, checkpoints, log=None, **kw):
+        calls.append((len(jobs), tuple(checkpoints)))
+        specs = [dict(n_target=j["n_target"], r_c1=j["r_c1"], strength=j["strength"],
+                      gamma=j["gamma"]) for j in jobs]
+        vs = [j["v_over_vesc"] * campaign.case_of(sp).v_esc for sp, j in zip(specs, jobs)]
+        f = {c: np.array([f_at(sp, v, c) for sp, v in zip(specs, vs)]) for c in checkpoints}
+        return dict(f_at=f, steps=0, seconds=0.0, particles=0)
+
+    res = campaign.settling(state, simulate=simulate)
+    closed = [s for s in state["held"] if s["method"] == "bisect" and s["status"] == "done"]
+    assert len(res["cases"]) == len(closed) >= 3
+    assert calls == [(2 * len(closed), (0.5, 1.0, 2.0, 4.0))]
+    k1 = res["factors"].index(1.0)
+    for row, s in zip(res["cases"], closed):
+        v_lo, _, v_hi, _ = campaign._sides(s)
+        assert row["straddles"][k1]
+        assert abs(row["q_rd"][k1] / campaign.q_rd(s) - 1.0) < 1e-12
+        for k, fac in enumerate(res["factors"]):
+            want = f_at(s["spec"], v_lo, fac) > 0.5 >= f_at(s["spec"], v_hi, fac)
+            assert row["straddles"][k] == want
+            assert (row["q_rd"][k] is None) == (not want)
