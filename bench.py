@@ -500,7 +500,7 @@ def run_batch(steps, warmup, gravity=True, tune=True):
             "dt_spread": float(dt.max() / dt.min())}
 
 
-def run_batch_outcomes(max_steps=12000, check_every=200, seed=5, scale=1.0, far_factor=1.5,
+def run_batch_outcomes(max_steps=12000, check_every=10, seed=5, scale=1.0, far_factor=3.0,
                        t_end_sound=6.0):
     """The 64-impact batch (FP32, self-gravity on; particle counts times
     ``scale``; each run in its centre-of-mass frame) run to every run's t_end

@@ -356,18 +356,21 @@ def summary(state: dict) -> dict:
 
 
 def settling(state: dict, factors=(0.5, 1.0, 2.0, 4.0), simulate=None, log=None,
-             **sim_kw) -> dict:
+             max_cases: int | None = None, **sim_kw) -> dict:
     """Run the ends of every closed held-out bisection bracket on, past t_end:
     f_lr at ``factors`` x t_end for the lower end (f > 1/2 at t_end) and the
     upper end (f <= 1/2), all in one batch.  Reports per case whether the
     ends still straddle 1/2 at each time and the threshold interpolated
     between them (None once they do not), so that the drift of the bound
-    mass after t_end and its effect on Q_RD* are measured, not assumed."""
+    mass after t_end and its effect on Q_RD* are measured, not assumed.
+    ``max_cases`` limits the check to the first that many closed brackets."""
     simulate = simulate or scan.simulate
     specs, jobs = [], []
     for s in state["held"]:
         if s["method"] != "bisect" or s["status"] != "done":
             continue
+        if max_cases is not None and len(specs) >= max_cases:
+            break
         v_lo, _, v_hi, _ = _sides(s)
         specs.append((s["spec"], v_lo, v_hi))
         for v in (v_lo, v_hi):
@@ -416,11 +419,13 @@ def main(argv=None):
                     help="end each run this many target sound-crossing times after contact "
                          "(0: use --t-end-ff free-fall times)")
     ap.add_argument("--max-cells", type=int, default=1 << 26)
-    ap.add_argument("--far-factor", type=float, default=1.5)
-    ap.add_argument("--check-every", type=int, default=200)
+    ap.add_argument("--far-factor", type=float, default=3.0)
+    ap.add_argument("--check-every", type=int, default=10)
     ap.add_argument("--settling", metavar="OUT",
                     help="instead of advancing the campaign, run the ends of the closed "
                          "held-out bisection brackets to 4 t_end and write the result here")
+    ap.add_argument("--settling-cases", type=int, default=None,
+                    help="settling check on the first this many closed brackets only")
     a = ap.parse_args(argv)
 
     def log(*x):
@@ -442,7 +447,8 @@ def main(argv=None):
     import torch
     torch.cuda.set_device(0)
     if a.settling:
-        res = settling(state, log=log, t_end_ff=a.t_end_ff, t_end_sound=a.t_end_sound,
+        res = settling(state, log=log, max_cases=a.settling_cases,
+                       t_end_ff=a.t_end_ff, t_end_sound=a.t_end_sound,
                        check_every=a.check_every, max_cells=a.max_cells,
                        far_factor=a.far_factor)
         with open(a.settling, "w") as f:

@@ -134,7 +134,7 @@ def end_times(cases, t_end_ff: float = 2.0, t_end_sound: float = 0.0):
 def simulate(cases: list, t_end_ff: float = 2.0, prec: int = sph.SPH_FP32_CELLREL,
              max_steps: int = 20000, check_every: int = 50, theta: float = 0.6,
              max_neighbors: int = 256, log=None, checkpoints=(1.0,), t_end_sound: float = 0.0,
-             max_cells: int = 1 << 24, far_factor: float = 1.5) -> dict:
+             max_cells: int = 1 << 24, far_factor: float = 3.0) -> dict:
     """Run every case (dicts with n_target, gamma, r_c1, v_over_vesc, strength)
     to t_end = t_end_ff free-fall times of the target material plus the
     crossing time (R_t + R_p) / v (or ``t_end_sound`` sound-crossing times of

@@ -20,7 +20,7 @@ def test_qrd_campaign_with_simulation_judge():
     from paper_2603_19764_amd import campaign
     t0 = time.perf_counter()
     state = campaign.new_campaign(n_train=8, n_held=4, seed=11, n_min=2000, n_max=2000)
-    campaign.run(state, log=say, train_rounds=8, t_end_ff=1.5, check_every=100)
+    campaign.run(state, log=say, train_rounds=8, t_end_ff=1.5, check_every=10)
     out = campaign.summary(state)
     say(f"campaign: {out}, {time.perf_counter() - t0:.0f} s")
     assert state["phase"] == "done"
