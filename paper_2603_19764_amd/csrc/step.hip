@@ -77,8 +77,13 @@ __global__ void k_reorder_predict(int64_t n, const int32_t *__restrict__ perm, S
 // (m Kn A xx yy zz xy) (m Kn A xz yz, rho/2, c/2)
 // (-m Kn/(2 Omega rho), m Kn/2, h/2, 1/m) with
 // A = (-P I + S_pred)/(Omega rho^2), Kn = -210/(pi H^5).
+// threads of a k_state block (its records staged in LDS: 24 KB in the
+// FP32 form, 20 KB in the FP64 form)
 template <bool F32>
-__global__ void k_state(int64_t n, const double4 *__restrict__ posh64,
+constexpr int kStateBlock = F32 ? 256 : 128;
+
+template <bool F32>
+__global__ __launch_bounds__(kStateBlock<F32>) void k_state(int64_t n, const double4 *__restrict__ posh64,
                         const float4 *__restrict__ posh32, const double *__restrict__ rho,
                         const double *__restrict__ omega, const double *__restrict__ up,
                         const double *__restrict__ vpx, const double *__restrict__ vpy,
@@ -92,8 +97,14 @@ __global__ void k_state(int64_t n, const double4 *__restrict__ posh64,
                         int32_t *__restrict__ flags) {
     using R = typename std::conditional<F32, float, double>::type;
     using R4 = typename std::conditional<F32, float4, double4>::type;
-    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i >= n) return;
+    constexpr int kS = kRecBothStride<F32>;
+    constexpr int kB = kStateBlock<F32>;
+    // records (96 B in the FP32 form, 160 B in the FP64 form) are assembled
+    // in LDS and written by the block as one contiguous span (each lane's
+    // slot stores would otherwise fall a record apart)
+    __shared__ R4 stg[kB * kS];
+    const int64_t i = blockIdx.x * (int64_t)kB + threadIdx.x;
+    if (i < n) {
     const sph_material &M = material_of(mt, mat, i);
     const double r = rho[i], om = omega[i];
     double p, c, t, y, gm;
@@ -125,7 +136,7 @@ __global__ void k_state(int64_t n, const double4 *__restrict__ posh64,
     const double mi = m[i];
     const double kn = -210.0 / (kPiD * H * H * H * H * H);
     const double sc = mi * kn / (om * r * r);
-    R4 *rf = (R4 *)rec_f_v + kRecBothStride<F32> * i;
+    R4 *rf = stg + kS * threadIdx.x;
     constexpr int o = kVelSlots<F32>;
     rf[0] = {px, py, pz, (R)(1.0 / H)};
     store_vm<F32>(rf + 1, vpx[i], vpy[i], vpz[i], mi);
@@ -134,6 +145,13 @@ __global__ void k_state(int64_t n, const double4 *__restrict__ posh64,
     rf[2 + o] = {(R)(sc * s[3]), (R)(sc * s[4]), (R)(0.5 * r), (R)(0.5 * c)};
     rf[3 + o] = {(R)(-0.5 * mi * kn / (om * r)), (R)(0.5 * mi * kn), (R)(0.5 * q64.w),
                  (R)(mi > 0.0 ? 1.0 / mi : 0.0)};
+    }
+    __syncthreads();
+    const int64_t b0 = blockIdx.x * (int64_t)kB;
+    const int64_t left = n - b0;
+    const int cnt = kS * (int)(left < kB ? left : kB);
+    R4 *dst = (R4 *)rec_f_v + kS * b0;
+    for (int q = threadIdx.x; q < cnt; q += kB) dst[q] = stg[q];
 }
 
 // ------------------------------------------- gradient epilogue + stress rate
@@ -357,13 +375,14 @@ sph_status launch_step_state(Ctx *ctx, int64_t n, sph_precision prec, const doub
     MatTable mt;
     mt.n = nmat;
     for (int k = 0; k < nmat; ++k) mt.m[k] = ctx->mats[k].m;
-    const unsigned nb = (unsigned)((n + 255) / 256);
     if (prec == SPH_FP32_CELLREL)
-        hipLaunchKernelGGL((k_state<true>), dim3(nb), dim3(256), 0, s, n, ctx->posh64,
+        hipLaunchKernelGGL((k_state<true>), dim3((unsigned)((n + 255) / 256)),
+                           dim3(kStateBlock<true>), 0, s, n, ctx->posh64,
                            ctx->posh32, rho, omega, up, vpx, vpy, vpz, m, mat, fixed, mt, tau,
                            S_half, Sdot, P, cs, T, Y, Gmod, S_pred, ctx->rec_f, ctx->flags);
     else
-        hipLaunchKernelGGL((k_state<false>), dim3(nb), dim3(256), 0, s, n, ctx->posh64,
+        hipLaunchKernelGGL((k_state<false>), dim3((unsigned)((n + 127) / 128)),
+                           dim3(kStateBlock<false>), 0, s, n, ctx->posh64,
                            ctx->posh32, rho, omega, up, vpx, vpy, vpz, m, mat, fixed, mt, tau,
                            S_half, Sdot, P, cs, T, Y, Gmod, S_pred, ctx->rec_f, ctx->flags);
     SPH_HIP(hipGetLastError());
