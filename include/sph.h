@@ -547,7 +547,8 @@ sph_status sph_timing_read(sph_ctx *ctx, int32_t which, double *total_ms, int64_
  *   SPH_TUNE_SWEEP_DEPTH neighbour records in flight per lane of the fused
  *                      gradient + force sweep of sph_step: 1 or 2 (per
  *                      precision; 2 hides more latency, 1 needs fewer
- *                      registers and so runs more waves per SIMD);
+ *                      registers and so runs more waves per SIMD; default
+ *                      2 in the FP32 form, 1 in the FP64 form);
  *   SPH_TUNE_BUILD_TILE candidates held in the local-memory tile of the
  *                      pair-list build: 128, 192 or 256 (precision ignored;
  *                      a smaller tile lets more work-groups share a CU). */

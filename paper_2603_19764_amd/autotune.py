@@ -20,7 +20,10 @@ from . import sph
 LANES = (8, 4, 16)   # default first
 CELL_SCALES = (1000, 1150, 1300)   # permille of 2 h_max
 BUILD_RANGES = (64, 32, 96, 128)   # sorted particles per pair-list build work-group (default first)
-SWEEP_DEPTHS = (2, 1)   # neighbour records in flight per lane of the fused sweep
+# neighbour records in flight per lane of the fused sweep, per precision
+# (default first): two in the FP32 form (104 VGPRs, four waves per SIMD), one
+# in the FP64 form (138 VGPRs, three waves; two records take 180, two waves)
+SWEEP_DEPTHS = {sph.SPH_FP64: (1, 2), sph.SPH_FP32_CELLREL: (2, 1)}
 BUILD_TILES = (256, 192, 128)   # candidates in the pair-list build's LDS tile
 
 # knob -> (timer whose per-launch time decides it, candidate values)
@@ -132,6 +135,8 @@ def tune(w: dict, prec: int, steps: int = 3, cache: TuneCache | None = None,
 
     settings, times = {}, {}
     for knob, timer, values in PLAN:
+        if isinstance(values, dict):
+            values = values[prec]
         best, t = choose(values, lambda v: measure(knob, timer, v))
         sph.sph_set_tuning(ctx, knob, prec, best)
         settings[KNOB_NAMES[knob]] = best

@@ -78,7 +78,7 @@ struct Ctx {
     int32_t lanes[4][2] = {{8, 8}, {8, 8}, {8, 8}, {8, 8}};
     double cell_scale = 1.0;
     int32_t build_range = 64;  // sorted particles per work-group of the pair-list build
-    int32_t sweep_depth[2] = {2, 2};  // records in flight per lane of the fused sweep [precision]
+    int32_t sweep_depth[2] = {1, 2};  // records in flight per lane of the fused sweep [FP64, FP32]
     int32_t build_tile = 256;         // candidates in the LDS tile of the pair-list build
     // self-gravity pyramid (allocated with the context)
     void *grav_lev = nullptr;        // per-run level layout (max_runs entries)

@@ -45,7 +45,7 @@ def test_every_knob_setting_gives_the_same_step(prec):
                   {sph.SPH_TUNE_LANES_STEP: 16, sph.SPH_TUNE_LANES_DENSITY: 4},
                   {sph.SPH_TUNE_CELL_SCALE: 1300},
                   {sph.SPH_TUNE_BUILD_RANGE: 32}, {sph.SPH_TUNE_BUILD_RANGE: 128},
-                  {sph.SPH_TUNE_SWEEP_DEPTH: 1},
+                  {sph.SPH_TUNE_SWEEP_DEPTH: 1}, {sph.SPH_TUNE_SWEEP_DEPTH: 2},
                   {sph.SPH_TUNE_BUILD_TILE: 128}, {sph.SPH_TUNE_BUILD_TILE: 192},
                   {sph.SPH_TUNE_SWEEP_DEPTH: 1, sph.SPH_TUNE_LANES_STEP: 4}):
         got = _steps(w, prec, knobs)
@@ -75,7 +75,7 @@ def test_tuner_returns_valid_settings(tmp_path):
     assert s["lanes_step"] in autotune.LANES and s["lanes_density"] in autotune.LANES
     assert s["cell_scale_permille"] in autotune.CELL_SCALES
     assert s["build_range"] in autotune.BUILD_RANGES
-    assert s["sweep_depth"] in autotune.SWEEP_DEPTHS
+    assert s["sweep_depth"] in autotune.SWEEP_DEPTHS[1]
     assert s["build_tile"] in autotune.BUILD_TILES
     again = autotune.tune(w, 1, steps=2, cache=cache)
     assert again["cached"] and again["settings"] == s
