@@ -710,6 +710,8 @@ def main():
     ap.add_argument("--batch-only", type=int, default=0, metavar="STEPS",
                     help="only the batched 64-impact scan, STEPS graph-replayed steps "
                          "(profiling)")
+    ap.add_argument("--outcomes-only", type=float, default=0.0, metavar="SCALE",
+                    help="only the 64-impact batch run to t_end (see --batch-outcomes)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -724,6 +726,9 @@ def main():
         copy_calibration(args.copy_calibration)
     if args.batch_only:
         print(json.dumps(run_batch(args.batch_only, 4, tune=not args.no_tune)), flush=True)
+        return
+    if args.outcomes_only > 0:
+        print(json.dumps(run_batch_outcomes(scale=args.outcomes_only)), flush=True)
         return
     w = inputs.c3_impact()
     n = int(w["x"].size)
