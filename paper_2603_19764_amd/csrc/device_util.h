@@ -69,6 +69,12 @@ __device__ __forceinline__ float group_sum(float v) {
     return v;
 }
 template <int L>
+__device__ __forceinline__ int group_sum(int v) {
+#pragma unroll
+    for (int o = L / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, L);
+    return v;
+}
+template <int L>
 __device__ __forceinline__ double group_sum(double v) {
 #pragma unroll
     for (int o = L / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, L);

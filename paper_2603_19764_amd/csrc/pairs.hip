@@ -119,7 +119,8 @@ __global__ __launch_bounds__(kBlock) void k_density(
     const int64_t i = (int64_t)xcd_block(blockIdx.x, gridDim.x) * (kBlock / L) + threadIdx.x / L;
     const int lg = threadIdx.x % L;
     const bool active = i < n;
-    double sw = 0.0, sd = 0.0, nd = 0.0;  // nd: members of the density set other than i
+    double sw = 0.0, sd = 0.0;
+    int nd = 0;  // members of the density set other than i
     double hi = 0.0;
     R4 pi = {0, 0, 0, 0};
     if (active) {
@@ -149,7 +150,7 @@ __global__ __launch_bounds__(kBlock) void k_density(
             const R dh = mj * (t3 * ((R)3 + q * ((R)9 - (R)32 * q)));
             sw += (double)w;
             sd += (double)dh;
-            nd += in_d ? 1.0 : 0.0;
+            nd += in_d ? 1 : 0;
         };
         auto entry = [&](int k) -> uint32_t {
             const uint32_t v = row[k < K ? k : K - 1];
@@ -184,7 +185,7 @@ __global__ __launch_bounds__(kBlock) void k_density(
         const double dsum = Dn * (3.0 * mi + sd);  // self term dW/dh(0) = 3 Dn
         // a density set of i alone gives Omega = 0 by the definition (the
         // self term cancels the 1): such a particle takes Omega = 1
-        const double om = (omega_one || nd == 0.0) ? 1.0 : 1.0 + hi / (3.0 * r) * dsum;
+        const double om = (omega_one || nd == 0) ? 1.0 : 1.0 + hi / (3.0 * r) * dsum;
         rho[i] = r;
         omega[i] = om;
         bad = nonfinite(r, om);
