@@ -32,16 +32,16 @@ if ROOT not in sys.path:
 
 METRIC = "SPH strength-step pair interactions/s (FP32 vs FP64 plain, 1 GPU) at 1e-5 rel err"
 PEAK_FP32_VALU = 157.3e12   # MI355X FP32 vector, published (packed instructions)
-PEAK_FP32_UNPACKED = 78.6e12  # the same pipes without packed FP32 (this build's code)
+PEAK_FP32_UNPACKED = 78.6e12  # the same pipes without packed FP32 (the library is compiled so)
 PEAK_FP64_VALU = 78.6e12
 PEAK_HBM = 8.0e12
 
 # Algorithmic flops per ordered pair of the fused gradient + force sweep.
-# The scope table's estimates per pass (FMA = 2, sqrt and division 1 each):
-# gradients ~60, forces ~110 plus ~25 when the pair approaches (the AV
-# term); both passes' work is credited, each with its own separation,
-# square root and kernel factors, as a two-pass code would do it.
-SURVEY_GRADIENTS, SURVEY_FORCES, SURVEY_AV = 60.0, 110.0, 25.0
+# Estimates per pass (FMA = 2, sqrt and division 1 each): gradients ~60
+# (the corrected velocity-gradient sums), forces ~110 plus ~25 when the pair
+# approaches (the AV term); both passes' work is credited, each with its own
+# separation, square root and kernel factors, as a two-pass code would do it.
+EST_GRADIENTS, EST_FORCES, EST_AV = 60.0, 110.0, 25.0
 # The same work counted from the fused pair term, shared parts once:
 # separation 3, r^2 5, sqrt 1, kernel factors t_i^3, t_j^3 with Kn 10, v_ij 3;
 # gradient weight 8, C^-1 sums 12, F sums 18; (K A)_i x and (K A)_j x 30,
@@ -714,7 +714,7 @@ def main():
                     help="only the 64-impact batch run to t_end (see --batch-outcomes)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
               "(--gpus must be 1)", file=sys.stderr)
         sys.exit(2)
 
@@ -766,9 +766,9 @@ def main():
         ms, cnt = r32["kernels"]["grad_forces"]
         avg_s = ms / cnt * 1e-3
         ppl = r32["pairs"] / r32["steps"]
-        fl_survey = SURVEY_GRADIENTS + SURVEY_FORCES + SURVEY_AV * f_av
+        fl_est = EST_GRADIENTS + EST_FORCES + EST_AV * f_av
         fl_recount = RECOUNT + RECOUNT_AV * f_av
-        achieved = fl_survey * ppl / avg_s
+        achieved = fl_est * ppl / avg_s
         lanes = (tuned[1] or {}).get("lanes_step", 8)
         depth = (tuned[1] or {}).get("sweep_depth", 2)
         kname = f"k_grad_forces<{lanes},fp32,{depth}>"
@@ -776,7 +776,7 @@ def main():
                     unit="TFLOP/s", frac=achieved / PEAK_FP32_VALU,
                     frac_unpacked=achieved / PEAK_FP32_UNPACKED,
                     traffic=measured_traffic(kname), kernel=kname, avg_launch_us=avg_s * 1e6,
-                    pairs_per_launch=ppl, flops_per_pair=fl_survey,
+                    pairs_per_launch=ppl, flops_per_pair=fl_est,
                     flops_per_pair_recount=fl_recount,
                     frac_recount=fl_recount * ppl / avg_s / PEAK_FP32_VALU,
                     approaching_pair_fraction=f_av,

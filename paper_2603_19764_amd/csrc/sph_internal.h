@@ -185,7 +185,7 @@ struct BuildExtras {
     const double *m = nullptr;                   // write density records when set
     int32_t f32 = 0;                             // record arithmetic
     double far_factor = 0.0;                     // > 0: far cubes in use (sph_params)
-    int32_t far_init = 0;                        // set the far cubes from this build's boxes
+    int32_t far_init = 0;                        // set the far cubes from this search's boxes
 };
 
 // Launch helpers implemented in the .hip files.
