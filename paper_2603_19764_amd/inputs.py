@@ -339,7 +339,12 @@ def impact_pair(n_target: int, gamma: float = 0.1, r_c1: float = 1.0e6, v_over_v
     """Head-on collision of two BCC spheres of one material with equal
     particle masses: target of ~n_target particles and projectile of mass
     ratio gamma = M_p / M_t.  The total mass is that of a sphere of radius
-    r_c1 at 1000 kg/m^3; each body has the material's reference density.  The
+    r_c1 at 1000 kg/m^3; each body's radius is that of its nominal mass at
+    the material's reference density.  The target holds exactly M_t; the
+    projectile is the BCC lattice clipped to R_p with about gamma times the
+    target's count (within a few percent), so its mass and density are
+    gamma M_t and rho0 to within as much (the case records the nominal
+    masses, which Q_R uses).  The
     projectile starts one spacing from contact on the -x side and moves at
     v = v_over_vesc * v_esc along +x, with v_esc = sqrt(2 G M_tot / (R_t + R_p));
     the target is at rest (with ``cm_frame``, both move so that the total
