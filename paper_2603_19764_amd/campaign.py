@@ -426,6 +426,8 @@ def main(argv=None):
                          "held-out bisection brackets to 4 t_end and write the result here")
     ap.add_argument("--settling-cases", type=int, default=None,
                     help="settling check on the first this many closed brackets only")
+    ap.add_argument("--settling-factors", default="0.5,1,2,4",
+                    help="multiples of t_end at which the settling check takes f_lr")
     a = ap.parse_args(argv)
 
     def log(*x):
@@ -448,6 +450,7 @@ def main(argv=None):
     torch.cuda.set_device(0)
     if a.settling:
         res = settling(state, log=log, max_cases=a.settling_cases,
+                       factors=tuple(float(x) for x in a.settling_factors.split(",")),
                        t_end_ff=a.t_end_ff, t_end_sound=a.t_end_sound,
                        check_every=a.check_every, max_cells=a.max_cells,
                        far_factor=a.far_factor)
