@@ -41,3 +41,18 @@ def test_cache_round_trip(tmp_path):
 
 def test_knob_names_cover_plan():
     assert {autotune.KNOB_NAMES[k] for k, _, _ in autotune.PLAN} == set(autotune.KNOB_NAMES.values())
+
+
+def test_per_precision_candidates_start_with_the_library_default():
+    """Knobs with per-precision candidates list both precisions, with the
+    same values in each and the library's default for that precision first
+    (the choice keeps it unless another value is clearly faster)."""
+    from paper_2603_19764_amd import sph
+    defaults = {sph.SPH_FP64: 1, sph.SPH_FP32_CELLREL: 2}   # fused-sweep depth
+    for knob, _, values in autotune.PLAN:
+        if isinstance(values, dict):
+            assert set(values) == {sph.SPH_FP64, sph.SPH_FP32_CELLREL}
+            assert sorted(values[0]) == sorted(values[1])
+            if knob == sph.SPH_TUNE_SWEEP_DEPTH:
+                for prec, first in defaults.items():
+                    assert values[prec][0] == first
